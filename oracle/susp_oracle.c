@@ -1,0 +1,961 @@
+/*
+ * susp_oracle.c -- plain FP64 CPU reference of the sheared-suspension LBM + DEM step.
+ *
+ * TEST INFRASTRUCTURE ONLY: the GPU library never includes, links or calls this file.
+ * It is written for a reader checking it against Pradipto & Hayakawa (arXiv:1904.02929):
+ *   equations of motion             eq. (1)
+ *   contact force / torque           eqs. (11), (11t) and the spring-dashpot text of Sec. 2
+ *   contact / DLVO stress            eqs. (12), (14)
+ *   DLVO repulsion                   eq. (13)
+ *   total stress                     eq. (15)
+ *   oscillatory strain, G', G''      eqs. (16)-(18)
+ *   LB update, moments, collision    App. A eqs. (3)-(5) (collision taken as single-time BGK)
+ *   moving bounce-back, link force   App. A eqs. (6)-(8); force and torque sums eqs. (9)-(10)
+ *   mapped radius, lubrication       App. A (mapped radius 0.95 a; grand-resistance matrix
+ *                                    with the leading-order scalar functions)
+ * The Lees-Edwards boundary is not in the paper; it follows the interpolated, Galilean
+ * corrected ghost-row scheme of Wagner & Pagonabarraga (2002).
+ * Compile with -ffp-contract=off: every geometric predicate is evaluated left to right.
+ */
+#include "susp_oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------- D3Q19 lattice (App. A: weights 1/3, 1/18, 1/36) ---------------- */
+static const int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+static double WQ(int q) { return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+static int OPP(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+/* directions entering row y=0 from below (c_y=+1) and row y=ly-1 from above (c_y=-1) */
+static const int UPQ[5] = {3, 7, 10, 15, 17};
+static const int DNQ[5] = {4, 8, 9, 16, 18};
+
+void orc_lattice(int32_t *cx, int32_t *cy, int32_t *cz, double *w, int32_t *opp) {
+  for (int q = 0; q < 19; ++q) {
+    cx[q] = CX[q]; cy[q] = CY[q]; cz[q] = CZ[q]; w[q] = WQ(q); opp[q] = OPP(q);
+  }
+}
+
+static const double PI = 3.14159265358979323846;
+
+/* Second-order equilibrium (the standard D3Q19 form; the paper defers to Succi). */
+void orc_feq(double rho, double ux, double uy, double uz, double out[19]) {
+  double uu = ux * ux + uy * uy + uz * uz;
+  for (int q = 0; q < 19; ++q) {
+    double cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
+    out[q] = WQ(q) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+  }
+}
+static double feq1(int q, double rho, double ux, double uy, double uz) {
+  double uu = ux * ux + uy * uy + uz * uz;
+  double cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
+  return WQ(q) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
+/* ---------------- geometry ---------------- */
+/* Minimum-image displacement d = point - particle under Lees-Edwards in y (offset s) and
+ * periodicity in x, z.  k is the image index of the particle: the image sits at
+ * R + k (s, ly, 0) and moves with U + k U_LE x.                                          */
+void orc_minimage(const orc_params *p, double s, double dx, double dy, double dz,
+                  double out[3], int32_t *k) {
+  double Lx = p->lx, Ly = p->ly, Lz = p->lz;
+  int kk = 0;
+  if (dy > 0.5 * Ly) { dy -= Ly; dx -= s; kk = 1; }
+  else if (dy < -0.5 * Ly) { dy += Ly; dx += s; kk = -1; }
+  while (dx > 0.5 * Lx) dx -= Lx;
+  while (dx < -0.5 * Lx) dx += Lx;
+  while (dz > 0.5 * Lz) dz -= Lz;
+  while (dz < -0.5 * Lz) dz += Lz;
+  out[0] = dx; out[1] = dy; out[2] = dz;
+  if (k) *k = kk;
+}
+
+static int wrapi(int i, int L) { i %= L; return i < 0 ? i + L : i; }
+
+/* ---------------- shear protocol: eq. (16) and its rate ---------------- */
+void orc_protocol(const orc_params *p, int64_t t, double *s, double *ule) {
+  double Lx = p->lx, Ly = p->ly;
+  if (p->shear_kind == 1) {
+    double u = p->gamma_dot * Ly;
+    double x = (double)t * u;
+    *s = x - Lx * floor(x / Lx);
+    *ule = u;
+  } else if (p->shear_kind == 2) {
+    int64_t P = p->period;
+    int64_t tI = (int64_t)p->ncyc_I * P;
+    double g0 = t < tI ? p->g0_I : p->g0_F;
+    int64_t tp = t < tI ? t : t - tI;
+    double om = 2.0 * PI / (double)P;
+    double ph = om * (double)tp + p->theta;
+    double gam = g0 * (cos(p->theta) - cos(ph));
+    double gdot = om * g0 * sin(ph);
+    double x = Ly * gam;
+    *s = x - Lx * floor(x / Lx);
+    *ule = Ly * gdot;
+  } else {
+    *s = 0.0; *ule = 0.0;
+  }
+}
+
+/* ---------------- derived constants (Sec. 2) ---------------- */
+int orc_resolve(const orc_params *p, int32_t np, const double *radius, orc_derived *d) {
+  double amin = 0, amax = 0, msum = 0;
+  for (int i = 0; i < np; ++i) {
+    double a = radius[i];
+    if (i == 0 || a < amin) amin = a;
+    if (i == 0 || a > amax) amax = a;
+    msum += p->rho_p * (4.0 / 3.0) * PI * a * a * a;
+  }
+  d->a_min = amin; d->a_max = amax;
+  d->m0 = np > 0 ? msum / np : 0.0;
+  /* dt = 0.6 tau_c with tau_c = sqrt(m0/kn) and dt = 1 gives kn = 0.36 m0 */
+  d->kn = p->kn > 0 ? p->kn : 0.36 * d->m0;
+  d->kt = p->kt_ratio * d->kn;
+  d->eta_n = p->eta_n >= 0 ? p->eta_n : sqrt(d->m0 * d->kn);
+  d->lub_delta = p->lub_delta >= 0 ? p->lub_delta : 0.01 * amin;
+  d->debye_lambda = p->debye_lambda > 0 ? p->debye_lambda : 0.02 * amin;
+  d->F0 = p->F0 >= 0 ? p->F0 : 2e-4 * d->kn;
+  d->eta0 = p->rho0 * (p->tau - 0.5) / 3.0;
+  return 0;
+}
+
+/* ---------------- pair interactions ---------------- */
+static void cross(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Linear spring-dashpot normal force, Cundall-Strack tangential spring with Coulomb cap
+ * (Sec. 2: F_nor = (kn delta_n + eta_n u_n) n, kt spring, |F_tan| <= mu |F_nor|), torque
+ * eq. (11t).  n points from j to i; the contact point of i is R_i - a_i n.               */
+int orc_contact(const orc_params *p, const orc_derived *d, double ai, double aj,
+                const double dv[3], const double Ui[3], const double Uj[3],
+                const double Wi[3], const double Wj[3], double dt, double xi[3],
+                double Fi[3], double Ti[3], double Tj[3], double Fn_out[3]) {
+  double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+  double r = sqrt(r2);
+  double h = r - ai - aj;
+  for (int c = 0; c < 3; ++c) { Fi[c] = 0; Ti[c] = 0; Tj[c] = 0; Fn_out[c] = 0; }
+  if (!(h < 0.0)) { xi[0] = xi[1] = xi[2] = 0.0; return 0; }
+  double n[3] = {dv[0] / r, dv[1] / r, dv[2] / r};
+  double Uij[3] = {Ui[0] - Uj[0], Ui[1] - Uj[1], Ui[2] - Uj[2]};
+  double vn = -dot(Uij, n);                   /* approach speed */
+  double fnm = d->kn * (-h) + d->eta_n * vn;  /* signed normal magnitude, along n */
+  double Fn[3] = {fnm * n[0], fnm * n[1], fnm * n[2]};
+  /* relative velocity of the contact points */
+  double aw[3] = {ai * Wi[0] + aj * Wj[0], ai * Wi[1] + aj * Wj[1], ai * Wi[2] + aj * Wj[2]};
+  double awn[3];
+  cross(aw, n, awn);
+  double v[3] = {Uij[0] - awn[0], Uij[1] - awn[1], Uij[2] - awn[2]};
+  double vdn = dot(v, n);
+  double vt[3] = {v[0] - vdn * n[0], v[1] - vdn * n[1], v[2] - vdn * n[2]};
+  /* rotate the spring into the current tangent plane, keeping its length */
+  double xn = dot(xi, n);
+  double xp[3] = {xi[0] - xn * n[0], xi[1] - xn * n[1], xi[2] - xn * n[2]};
+  double mo = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+  double mp = sqrt(xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2]);
+  if (mp > 0.0) {
+    double sc = mo / mp;
+    xi[0] = xp[0] * sc; xi[1] = xp[1] * sc; xi[2] = xp[2] * sc;
+  } else {
+    xi[0] = xp[0]; xi[1] = xp[1]; xi[2] = xp[2];
+  }
+  xi[0] += vt[0] * dt; xi[1] += vt[1] * dt; xi[2] += vt[2] * dt;
+  double Ft[3] = {-d->kt * xi[0], -d->kt * xi[1], -d->kt * xi[2]};
+  double ftm = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+  double cap = p->mu * fabs(fnm);
+  if (ftm > cap) {
+    double sc = cap / ftm;
+    Ft[0] *= sc; Ft[1] *= sc; Ft[2] *= sc;
+    xi[0] = -Ft[0] / d->kt; xi[1] = -Ft[1] / d->kt; xi[2] = -Ft[2] / d->kt;
+  }
+  for (int c = 0; c < 3; ++c) { Fi[c] = Fn[c] + Ft[c]; Fn_out[c] = Fn[c]; }
+  double li[3] = {-ai * n[0], -ai * n[1], -ai * n[2]};
+  double lj[3] = {-aj * n[0], -aj * n[1], -aj * n[2]};
+  cross(li, Ft, Ti);
+  cross(lj, Ft, Tj);
+  return 1;
+}
+
+/* eq. (13): F_r = F0 exp(-h/lambda) n, with the gap clamped at 0. */
+void orc_dlvo(const orc_params *p, const orc_derived *d, double ai, double aj,
+              const double dv[3], double Fi[3]) {
+  double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+  double r = sqrt(r2);
+  double h = r - ai - aj;
+  Fi[0] = Fi[1] = Fi[2] = 0.0;
+  if (!(h < p->pair_cutoff)) return;
+  double hh = h > 0.0 ? h : 0.0;
+  double f = d->F0 * exp(-hh / d->debye_lambda);
+  Fi[0] = f * dv[0] / r; Fi[1] = f * dv[1] / r; Fi[2] = f * dv[2] / r;
+}
+
+/* Leading-order scalar resistance functions of App. A for the block of sphere "a" with
+ * partner ratio b (b = partner radius / own radius); inv = 1/xi, lg = ln(1/xi) terms.    */
+typedef struct { double XA, YA, YB, XG, YG, YC, YCp, YH, YHp; } lubfun;
+static lubfun lub_block(double a, double b, double inv, double lg) {
+  lubfun f;
+  double b1 = 1.0 + b;
+  f.XA = 6.0 * PI * a * (2.0 * b * b / (b1 * b1 * b1)) * inv;
+  f.YA = 6.0 * PI * a * (4.0 * b * (2.0 + b + 2.0 * b * b) / (15.0 * b1 * b1 * b1)) * lg;
+  f.YB = 4.0 * PI * a * a * (b * (4.0 + b) / (5.0 * b1 * b1)) * lg;
+  f.XG = 4.0 * PI * a * a * (3.0 * b * b / (b1 * b1 * b1)) * inv;
+  f.YG = 4.0 * PI * a * a * (b * (4.0 - b + 7.0 * b * b) / (10.0 * b1 * b1 * b1)) * lg;
+  f.YC = 8.0 * PI * a * a * a * (2.0 * b / (5.0 * b1)) * lg;
+  f.YCp = 8.0 * PI * a * a * a * (b * b / (10.0 * b1)) * lg;            /* C_ij */
+  f.YH = 8.0 * PI * a * a * a * (b * (2.0 - b) / (10.0 * b1 * b1)) * lg;
+  f.YHp = 8.0 * PI * a * a * a * (b * b * (1.0 + 7.0 * b) / (20.0 * b1 * b1)) * lg; /* H_ij */
+  return f;
+}
+
+static void sym6(const double a[3], const double b[3], double w, double o[6]) {
+  /* o += w (a b + b a) */
+  o[0] += w * (2.0 * a[0] * b[0]);
+  o[1] += w * (2.0 * a[1] * b[1]);
+  o[2] += w * (2.0 * a[2] * b[2]);
+  o[3] += w * (a[0] * b[1] + b[0] * a[1]);
+  o[4] += w * (a[0] * b[2] + b[0] * a[2]);
+  o[5] += w * (a[1] * b[2] + b[1] * a[2]);
+}
+
+/* Grand-resistance lubrication correction (App. A).  Readings: n points from j to i in
+ * the force/torque rows; the stresslet rows carry the sign that makes a closing pair
+ * compressive; beta of the ii block is a_j/a_i; every function is evaluated at
+ * xi = 2(h+delta)/(a_i+a_j) and, with lub_subtract_hc, minus its value at h = h_c.      */
+void orc_lubrication(const orc_params *p, const orc_derived *d, double ai, double aj,
+                     const double dv[3], const double Ui[3], const double Uj[3],
+                     const double Wi[3], const double Wj[3], double Fi[3], double Ti[3],
+                     double Tj[3], double Si[6], double Sj[6]) {
+  for (int c = 0; c < 3; ++c) { Fi[c] = 0; Ti[c] = 0; Tj[c] = 0; }
+  for (int c = 0; c < 6; ++c) { Si[c] = 0; Sj[c] = 0; }
+  double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+  double r = sqrt(r2);
+  double h = r - ai - aj;
+  if (!(h < p->lub_hc)) return;
+  double n[3] = {dv[0] / r, dv[1] / r, dv[2] / r};
+  double hh = h > 0.0 ? h : 0.0;
+  double xg = 2.0 * (hh + d->lub_delta) / (ai + aj);
+  double inv = 1.0 / xg, lg = log(1.0 / xg);
+  if (p->lub_subtract_hc) {
+    double xc = 2.0 * (p->lub_hc + d->lub_delta) / (ai + aj);
+    inv = inv - 1.0 / xc;
+    lg = lg - log(1.0 / xc);
+  }
+  lubfun fi = lub_block(ai, aj / ai, inv, lg);
+  lubfun fj = lub_block(aj, ai / aj, inv, lg);
+  double eta = d->eta0;
+  double U[3] = {Ui[0] - Uj[0], Ui[1] - Uj[1], Ui[2] - Uj[2]};
+  double un = dot(U, n);
+  double Wixn[3], Wjxn[3], Uxn[3];
+  cross(Wi, n, Wixn);
+  cross(Wj, n, Wjxn);
+  cross(U, n, Uxn);
+  double wi_n = dot(Wi, n), wj_n = dot(Wj, n);
+  for (int c = 0; c < 3; ++c) {
+    double AU = fi.XA * un * n[c] + fi.YA * (U[c] - un * n[c]);
+    /* F_i = -eta (A_ii U - B_ii W_i + B_jj W_j); B(n) W = YB (W x n), B_jj uses -n */
+    Fi[c] = -eta * (AU - fi.YB * Wixn[c] - fj.YB * Wjxn[c]);
+    double Wip = Wi[c] - wi_n * n[c], Wjp = Wj[c] - wj_n * n[c];
+    /* T_i = -eta (B_ii U + C_ii W_i + C_ij W_j) */
+    Ti[c] = -eta * (fi.YB * Uxn[c] + fi.YC * Wip + fi.YCp * Wjp);
+    /* T_j = -eta (-B_jj U + C_ij W_i + C_jj W_j) */
+    Tj[c] = -eta * (fj.YB * Uxn[c] + fi.YCp * Wip + fj.YC * Wjp);
+  }
+  /* stresslets: S = -eta (G U + H W + H' W'), G odd in its normal, H even. */
+  double s1[6] = {0, 0, 0, 0, 0, 0}; /* (n n - I/3)(n.U) */
+  double s2[6] = {0, 0, 0, 0, 0, 0}; /* n U + U n - 2 n n (n.U) */
+  double hi[6] = {0, 0, 0, 0, 0, 0}; /* (W_i x n) n + n (W_i x n) */
+  double hj[6] = {0, 0, 0, 0, 0, 0};
+  sym6(n, n, 0.5 * un, s1);
+  s1[0] -= un / 3.0; s1[1] -= un / 3.0; s1[2] -= un / 3.0;
+  sym6(n, U, 1.0, s2);
+  sym6(n, n, -un, s2);
+  sym6(Wixn, n, 1.0, hi);
+  sym6(Wjxn, n, 1.0, hj);
+  for (int c = 0; c < 6; ++c) {
+    /* G_ii evaluated with the normal from i to j (= -n) */
+    double Gi = -(fi.XG * s1[c] + fi.YG * s2[c]);
+    Si[c] = -eta * (Gi + fi.YH * hi[c] + fi.YHp * hj[c]);
+    /* -G_jj with the normal from j to i (= n) */
+    double Gj = -(fj.XG * s1[c] + fj.YG * s2[c]);
+    Sj[c] = -eta * (Gj + fj.YHp * hi[c] + fj.YH * hj[c]);
+  }
+}
+
+/* ---------------- simulation object ---------------- */
+static void *xcalloc(size_t n, size_t sz) {
+  void *q = calloc(n ? n : 1, sz);
+  return q;
+}
+
+static void quat_step(double *Q, const double W[3], double dt) {
+  /* q <- normalize(q + dt/2 (0, W) (x) q) */
+  double qw = Q[0], qx = Q[1], qy = Q[2], qz = Q[3];
+  double dw = -(W[0] * qx + W[1] * qy + W[2] * qz);
+  double dx = W[0] * qw + (W[1] * qz - W[2] * qy);
+  double dy = W[1] * qw + (W[2] * qx - W[0] * qz);
+  double dz = W[2] * qw + (W[0] * qy - W[1] * qx);
+  qw += 0.5 * dt * dw; qx += 0.5 * dt * dx; qy += 0.5 * dt * dy; qz += 0.5 * dt * dz;
+  double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  Q[0] = qw / nn; Q[1] = qx / nn; Q[2] = qy / nn; Q[3] = qz / nn;
+}
+
+/* Candidate integer range around centre c with half-width r (superset of the sphere). */
+static void cand_range(double c, double r, int L, int *lo, int *hi) {
+  int a = (int)ceil(c - r - 1e-6), b = (int)floor(c + r + 1e-6);
+  if (b - a + 1 >= L) { a = 0; b = L - 1; }
+  *lo = a; *hi = b;
+}
+
+/* Mapped-sphere membership of a lattice point (x,y,z) (y may be -1 or ly) for particle p
+ * at position Rp = R[3p..3p+2] under offset s: strict |d|^2 < a_map^2.                    */
+static int inside(const orc_sim *S, const double *R, int p, double s, double x, double y, double z) {
+  double d[3];
+  orc_minimage(&S->p, s, x - R[3 * p], y - R[3 * p + 1], z - R[3 * p + 2], d, NULL);
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  return r2 < S->amap[p] * S->amap[p];
+}
+
+/* Visit every node of particle p's mapped sphere (all images), calling fn(node). */
+typedef void (*node_fn)(orc_sim *S, int p, int64_t node, int x, int y, int z, void *ctx);
+static void for_footprint(orc_sim *S, const double *R, int p, double s, node_fn fn, void *ctx) {
+  const orc_params *P = &S->p;
+  double r = S->amap[p];
+  for (int k = -1; k <= 1; ++k) {
+    double cy = R[3 * p + 1] + k * (double)P->ly;
+    double cx = R[3 * p] + k * s;
+    int ylo = (int)ceil(cy - r - 1e-6), yhi = (int)floor(cy + r + 1e-6);
+    if (ylo < 0) ylo = 0;
+    if (yhi > P->ly - 1) yhi = P->ly - 1;
+    if (ylo > yhi) continue;
+    int xlo, xhi, zlo, zhi;
+    cand_range(cx, r, P->lx, &xlo, &xhi);
+    cand_range(R[3 * p + 2], r, P->lz, &zlo, &zhi);
+    for (int zz = zlo; zz <= zhi; ++zz)
+      for (int yy = ylo; yy <= yhi; ++yy)
+        for (int xu = xlo; xu <= xhi; ++xu) {
+          int x = wrapi(xu, P->lx), z = wrapi(zz, P->lz);
+          int32_t kk;
+          double dd[3];
+          orc_minimage(P, s, x - R[3 * p], yy - R[3 * p + 1], z - R[3 * p + 2], dd, &kk);
+          if (kk != k) continue; /* reached through a different image box */
+          if (!(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] < S->amap[p] * S->amap[p])) continue;
+          int64_t node = x + (int64_t)P->lx * (yy + (int64_t)P->ly * z);
+          fn(S, p, node, x, yy, z, ctx);
+        }
+  }
+}
+
+static void claim_fn(orc_sim *S, int p, int64_t node, int x, int y, int z, void *ctx) {
+  (void)x; (void)y; (void)z;
+  int32_t *own = (int32_t *)ctx;
+  if (own[node] == -2) return;
+  if (own[node] >= 0 && own[node] != p) {
+    S->flags |= 1;
+    if (p < own[node]) own[node] = p;
+    return;
+  }
+  own[node] = p;
+}
+
+static void build_map(orc_sim *S, int32_t *own, const double *R, double s) {
+  const orc_params *P = &S->p;
+  for (int64_t i = 0; i < S->nodes; ++i) own[i] = -1;
+  if (P->wall_y)
+    for (int z = 0; z < P->lz; ++z)
+      for (int x = 0; x < P->lx; ++x) {
+        own[x + (int64_t)P->lx * (0 + (int64_t)P->ly * z)] = -2;
+        own[x + (int64_t)P->lx * ((P->ly - 1) + (int64_t)P->ly * z)] = -2;
+      }
+  for (int p = 0; p < S->np; ++p) for_footprint(S, R, p, s, claim_fn, own);
+}
+
+int orc_remap(orc_sim *S) {
+  S->flags = 0;
+  build_map(S, S->own, S->R, S->s_next);
+  return 0;
+}
+
+orc_sim *orc_create(const orc_params *p, int32_t np, const double *pos, const double *vel,
+                    const double *omega, const double *radius) {
+  orc_sim *S = (orc_sim *)xcalloc(1, sizeof(orc_sim));
+  S->p = *p;
+  orc_resolve(p, np, radius, &S->d);
+  S->nodes = (int64_t)p->lx * p->ly * p->lz;
+  S->f = (double *)xcalloc((size_t)19 * S->nodes, sizeof(double));
+  S->fn = (double *)xcalloc((size_t)19 * S->nodes, sizeof(double));
+  S->own = (int32_t *)xcalloc((size_t)S->nodes, sizeof(int32_t));
+  S->np = np;
+  S->R = (double *)xcalloc(3 * (size_t)np, sizeof(double));
+  S->U = (double *)xcalloc(3 * (size_t)np, sizeof(double));
+  S->W = (double *)xcalloc(3 * (size_t)np, sizeof(double));
+  S->Q = (double *)xcalloc(4 * (size_t)np, sizeof(double));
+  S->a = (double *)xcalloc((size_t)np, sizeof(double));
+  S->m = (double *)xcalloc((size_t)np, sizeof(double));
+  S->I = (double *)xcalloc((size_t)np, sizeof(double));
+  S->amap = (double *)xcalloc((size_t)np, sizeof(double));
+  S->Fh = (double *)xcalloc(3 * (size_t)np, sizeof(double));
+  S->Th = (double *)xcalloc(3 * (size_t)np, sizeof(double));
+  S->Sh = (double *)xcalloc(9 * (size_t)np, sizeof(double));
+  S->nlinks = (int32_t *)xcalloc((size_t)np, sizeof(int32_t));
+  S->gown = (int32_t *)xcalloc(2 * (size_t)p->lx * p->lz, sizeof(int32_t));
+  for (int i = 0; i < np; ++i) {
+    for (int c = 0; c < 3; ++c) {
+      S->R[3 * i + c] = pos[3 * i + c];
+      S->U[3 * i + c] = vel ? vel[3 * i + c] : 0.0;
+      S->W[3 * i + c] = omega ? omega[3 * i + c] : 0.0;
+    }
+    S->Q[4 * i] = 1.0;
+    double a = radius[i];
+    S->a[i] = a;
+    S->m[i] = p->rho_p * (4.0 / 3.0) * PI * a * a * a;
+    S->I[i] = 0.4 * S->m[i] * a * a;
+    S->amap[i] = p->map_ratio * a;
+  }
+#ifdef _OPENMP
+  S->nthreads = omp_get_max_threads();
+#else
+  S->nthreads = 1;
+#endif
+  /* initial fluid: equilibrium at rho0 and the affine profile of the shear at t = 0 */
+  double s0, u0;
+  orc_protocol(p, 0, &s0, &u0);
+  S->s_next = s0;
+  double gd = u0 / (double)p->ly;
+  for (int z = 0; z < p->lz; ++z)
+    for (int y = 0; y < p->ly; ++y)
+      for (int x = 0; x < p->lx; ++x) {
+        int64_t node = x + (int64_t)p->lx * (y + (int64_t)p->ly * z);
+        double ux = gd * ((double)y - 0.5 * (double)(p->ly - 1));
+        double fe[19];
+        orc_feq(p->rho0, ux, 0.0, 0.0, fe);
+        for (int q = 0; q < 19; ++q) S->f[q * S->nodes + node] = fe[q];
+      }
+  build_map(S, S->own, S->R, S->s_next);
+  return S;
+}
+
+void orc_destroy(orc_sim *S) {
+  if (!S) return;
+  free(S->f); free(S->fn); free(S->own); free(S->R); free(S->U); free(S->W); free(S->Q);
+  free(S->a); free(S->m); free(S->I); free(S->amap); free(S->Fh); free(S->Th); free(S->Sh);
+  free(S->nlinks); free(S->pi); free(S->pj); free(S->hi); free(S->hj); free(S->hxi);
+  free(S->gown);
+  free(S);
+}
+
+int orc_set_history(orc_sim *S, int32_t n, const int32_t *i, const int32_t *j, const double *xi) {
+  free(S->hi); free(S->hj); free(S->hxi);
+  S->nhist = n; S->hist_cap = n;
+  S->hi = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+  S->hj = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+  S->hxi = (double *)xcalloc(3 * (size_t)n, sizeof(double));
+  for (int k = 0; k < n; ++k) {
+    S->hi[k] = i[k]; S->hj[k] = j[k];
+    S->hxi[3 * k] = xi[3 * k]; S->hxi[3 * k + 1] = xi[3 * k + 1]; S->hxi[3 * k + 2] = xi[3 * k + 2];
+  }
+  return 0;
+}
+
+/* ---------------- ghost planes for the Lees-Edwards boundary ---------------- */
+typedef struct {
+  double *val;   /* [2][5][lz][lx] interpolated, Galilean-corrected populations */
+} ghost_t;
+
+/* Galilean-corrected post-collision value of direction q at node (x,yrow,z) as seen from the
+ * image box: sgn=+1 for the box below (velocity shifted by -U_LE), -1 for the box above.  */
+static double nhat(const orc_sim *S, int q, int x, int yrow, int z, double s, double ule, int sgn) {
+  const orc_params *P = &S->p;
+  int64_t node = x + (int64_t)P->lx * (yrow + (int64_t)P->ly * z);
+  int o = S->own[node];
+  if (o >= 0) {
+    double d[3]; int32_t k;
+    orc_minimage(P, s, x - S->R[3 * o], yrow - S->R[3 * o + 1], z - S->R[3 * o + 2], d, &k);
+    const double *W = &S->W[3 * o];
+    double ub[3] = {S->U[3 * o] + k * ule + (W[1] * d[2] - W[2] * d[1]),
+                    S->U[3 * o + 1] + (W[2] * d[0] - W[0] * d[2]),
+                    S->U[3 * o + 2] + (W[0] * d[1] - W[1] * d[0])};
+    return feq1(q, P->rho0, ub[0] - sgn * ule, ub[1], ub[2]);
+  }
+  double rho = 0, jx = 0, jy = 0, jz = 0;
+  for (int r = 0; r < 19; ++r) {
+    double v = S->f[r * S->nodes + node];
+    rho += v; jx += v * CX[r]; jy += v * CY[r]; jz += v * CZ[r];
+  }
+  double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  double fq = S->f[q * S->nodes + node];
+  return fq + (feq1(q, rho, ux - sgn * ule, uy, uz) - feq1(q, rho, ux, uy, uz));
+}
+
+static void build_ghosts(orc_sim *S, double s, double ule, ghost_t *G) {
+  const orc_params *P = &S->p;
+  int lx = P->lx, lz = P->lz;
+  for (int i = 0; i < 2 * lx * lz; ++i) S->gown[i] = -1;
+  /* owners: geometric test of the points (x,-1,z) and (x,ly,z) against particle images */
+  for (int p = 0; p < S->np; ++p) {
+    double r = S->amap[p];
+    for (int g = 0; g < 2; ++g) {
+      double gy = g == 0 ? -1.0 : (double)P->ly;
+      for (int k = -1; k <= 1; ++k) {
+        double cy = S->R[3 * p + 1] + k * (double)P->ly;
+        if (!(fabs(gy - cy) < r + 1e-6)) continue;
+        double cx = S->R[3 * p] + k * s;
+        int xlo, xhi, zlo, zhi;
+        cand_range(cx, r, lx, &xlo, &xhi);
+        cand_range(S->R[3 * p + 2], r, lz, &zlo, &zhi);
+        for (int zz = zlo; zz <= zhi; ++zz)
+          for (int xu = xlo; xu <= xhi; ++xu) {
+            int x = wrapi(xu, lx), z = wrapi(zz, lz);
+            if (!inside(S, S->R, p, s, x, gy, z)) continue;
+            int32_t *o = &S->gown[g * lx * lz + z * lx + x];
+            if (*o >= 0 && *o != p) { S->flags |= 1; if (p < *o) *o = p; }
+            else *o = p;
+          }
+      }
+    }
+  }
+  /* values at fluid ghost points: linear interpolation along x of the shifted row */
+  for (int g = 0; g < 2; ++g) {
+    const int *qs = g == 0 ? UPQ : DNQ;
+    int yrow = g == 0 ? P->ly - 1 : 0;
+    int sgn = g == 0 ? 1 : -1;
+    for (int z = 0; z < lz; ++z)
+      for (int x = 0; x < lx; ++x) {
+        double xs = (double)x + sgn * s;
+        double x0f = floor(xs);
+        double fr = xs - x0f;
+        int i0 = wrapi((int)x0f, lx), i1 = wrapi((int)x0f + 1, lx);
+        for (int m = 0; m < 5; ++m) {
+          double v0 = nhat(S, qs[m], i0, yrow, z, s, ule, sgn);
+          double v1 = nhat(S, qs[m], i1, yrow, z, s, ule, sgn);
+          G->val[((g * 5 + m) * lz + z) * lx + x] = (1.0 - fr) * v0 + fr * v1;
+        }
+      }
+  }
+}
+
+/* ---------------- one LB step of the fluid with particle links ---------------- */
+static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, double pineq[6]) {
+  const orc_params *P = &S->p;
+  const int lx = P->lx, ly = P->ly, lz = P->lz, np = S->np;
+  const int64_t nodes = S->nodes;
+  const double rho0 = P->rho0, tau = P->tau;
+  int nt = S->nthreads;
+  double *acc = (double *)xcalloc((size_t)nt * (np > 0 ? np : 1) * 16, sizeof(double));
+  double *pacc = (double *)xcalloc((size_t)nt * 6, sizeof(double));
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double *A = acc + (size_t)tid * (np > 0 ? np : 1) * 16;
+    double *pa = pacc + 6 * tid;
+#pragma omp for schedule(static)
+    for (int z = 0; z < lz; ++z)
+      for (int y = 0; y < ly; ++y)
+        for (int x = 0; x < lx; ++x) {
+          int64_t X = x + (int64_t)lx * (y + (int64_t)ly * z);
+          if (S->own[X] != -1) continue;
+          double n[19];
+          n[0] = S->f[X];
+          for (int q = 1; q < 19; ++q) {
+            int px = x - CX[q], py = y - CY[q], pz = z - CZ[q];
+            int wx = wrapi(px, lx), wz = wrapi(pz, lz);
+            int owner;
+            double val = 0.0;
+            if (py < 0 || py >= ly) {
+              int g = py < 0 ? 0 : 1;
+              owner = S->gown[g * lx * lz + wz * lx + wx];
+              if (owner < 0) {
+                int m = 0;
+                const int *qs = g == 0 ? UPQ : DNQ;
+                while (qs[m] != q) ++m;
+                val = G->val[((g * 5 + m) * lz + wz) * lx + wx];
+              }
+            } else {
+              int64_t Ps = wx + (int64_t)lx * (py + (int64_t)ly * wz);
+              owner = S->own[Ps];
+              if (owner == -1) val = S->f[q * nodes + Ps];
+            }
+            int co = OPP(q);
+            double fo = S->f[co * nodes + X];
+            if (owner == -1) {
+              n[q] = val;
+            } else if (owner == -2) {
+              /* test-only static/moving wall */
+              double uw = py <= 0 ? P->wall_u_bot : P->wall_u_top;
+              double ubc = uw * CX[co];
+              n[q] = fo - 6.0 * WQ(co) * rho0 * ubc;
+            } else {
+              /* eq. (7)-(8): bounce-back from the moving sphere surface halfway along the link */
+              int p = owner;
+              double d[3]; int32_t k;
+              orc_minimage(P, s, px - S->R[3 * p], py - S->R[3 * p + 1], pz - S->R[3 * p + 2], d, &k);
+              double lev[3] = {d[0] + 0.5 * CX[q], d[1] + 0.5 * CY[q], d[2] + 0.5 * CZ[q]};
+              const double *Wp = &S->W[3 * p];
+              double ub[3] = {S->U[3 * p] + k * ule + (Wp[1] * lev[2] - Wp[2] * lev[1]),
+                              S->U[3 * p + 1] + (Wp[2] * lev[0] - Wp[0] * lev[2]),
+                              S->U[3 * p + 2] + (Wp[0] * lev[1] - Wp[1] * lev[0])};
+              double ubc = ub[0] * CX[co] + ub[1] * CY[co] + ub[2] * CZ[co];
+              double corr = 6.0 * WQ(co) * rho0 * ubc;
+              n[q] = fo - corr;
+              /* eq. (6) (one factor 2): momentum exchanged across the link */
+              double fm = 2.0 * fo - corr;
+              double fl[3] = {fm * CX[co], fm * CY[co], fm * CZ[co]};
+              double fc = 2.0 * fo - corr - 2.0 * WQ(co) * rho0; /* minus the rest state */
+              double fs[3] = {fc * CX[co], fc * CY[co], fc * CZ[co]};
+              double *a = A + 16 * (size_t)p;
+              a[0] += fl[0]; a[1] += fl[1]; a[2] += fl[2];
+              a[3] += lev[1] * fl[2] - lev[2] * fl[1];
+              a[4] += lev[2] * fl[0] - lev[0] * fl[2];
+              a[5] += lev[0] * fl[1] - lev[1] * fl[0];
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) a[6 + 3 * r + c] += lev[r] * fs[c];
+              a[15] += 1.0;
+            }
+          }
+          /* eq. (4) moments, BGK collision (eq. (5) with a single eigenvalue -1/tau) */
+          double rho = 0, jx = 0, jy = 0, jz = 0;
+          for (int q = 0; q < 19; ++q) {
+            rho += n[q]; jx += n[q] * CX[q]; jy += n[q] * CY[q]; jz += n[q] * CZ[q];
+          }
+          double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+          double fe[19];
+          orc_feq(rho, ux, uy, uz, fe);
+          for (int q = 0; q < 19; ++q) {
+            double ne = n[q] - fe[q];
+            pa[0] += ne * CX[q] * CX[q]; pa[1] += ne * CY[q] * CY[q]; pa[2] += ne * CZ[q] * CZ[q];
+            pa[3] += ne * CX[q] * CY[q]; pa[4] += ne * CX[q] * CZ[q]; pa[5] += ne * CY[q] * CZ[q];
+            double v = n[q] - ne / tau;
+            if (P->gx != 0.0 || P->gy != 0.0 || P->gz != 0.0)
+              v += 3.0 * WQ(q) * (CX[q] * P->gx + CY[q] * P->gy + CZ[q] * P->gz);
+            S->fn[q * nodes + X] = v;
+          }
+        }
+  }
+  /* fixed-order reduction of the per-thread partials */
+  for (int p = 0; p < np; ++p) {
+    double t[16] = {0};
+    for (int th = 0; th < nt; ++th)
+      for (int c = 0; c < 16; ++c) t[c] += acc[((size_t)th * np + p) * 16 + c];
+    for (int c = 0; c < 3; ++c) { S->Fh[3 * p + c] = t[c]; S->Th[3 * p + c] = t[3 + c]; }
+    for (int c = 0; c < 9; ++c) S->Sh[9 * p + c] = t[6 + c];
+    S->nlinks[p] = (int32_t)t[15];
+  }
+  for (int c = 0; c < 6; ++c) {
+    pineq[c] = 0;
+    for (int th = 0; th < nt; ++th) pineq[c] += pacc[6 * th + c];
+  }
+  free(acc);
+  free(pacc);
+  double *t = S->f; S->f = S->fn; S->fn = t;
+}
+
+/* ---------------- pairs ---------------- */
+static void build_pairs(orc_sim *S, double s) {
+  const int np = S->np;
+  const double hl = S->p.pair_cutoff;
+  int32_t *cnt = (int32_t *)xcalloc((size_t)np + 1, sizeof(int32_t));
+  int32_t **lst = (int32_t **)xcalloc((size_t)np, sizeof(int32_t *));
+  int ovl = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : ovl)
+  for (int i = 0; i < np; ++i) {
+    int cap = 16, c = 0;
+    int32_t *L = (int32_t *)malloc(cap * sizeof(int32_t));
+    for (int j = i + 1; j < np; ++j) {
+      double d[3];
+      orc_minimage(&S->p, s, S->R[3 * i] - S->R[3 * j], S->R[3 * i + 1] - S->R[3 * j + 1],
+                   S->R[3 * i + 2] - S->R[3 * j + 2], d, NULL);
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      double rc = S->a[i] + S->a[j] + hl;
+      if (r2 < rc * rc) {
+        if (c == cap) { cap *= 2; L = (int32_t *)realloc(L, cap * sizeof(int32_t)); }
+        L[c++] = j;
+        double rm = S->amap[i] + S->amap[j];
+        if (r2 < rm * rm) ovl = 1;
+      }
+    }
+    lst[i] = L; cnt[i] = c;
+  }
+  if (ovl) S->flags |= 1;
+  int64_t tot = 0;
+  for (int i = 0; i < np; ++i) tot += cnt[i];
+  if (tot > S->pairs_cap) {
+    free(S->pi); free(S->pj);
+    S->pairs_cap = (int32_t)tot;
+    S->pi = (int32_t *)xcalloc((size_t)tot, sizeof(int32_t));
+    S->pj = (int32_t *)xcalloc((size_t)tot, sizeof(int32_t));
+  }
+  int64_t k = 0;
+  for (int i = 0; i < np; ++i) {
+    for (int c = 0; c < cnt[i]; ++c) { S->pi[k] = i; S->pj[k] = lst[i][c]; ++k; }
+    free(lst[i]);
+  }
+  S->npairs = (int32_t)tot;
+  free(lst);
+  free(cnt);
+}
+
+static int find_hist(const orc_sim *S, int i, int j) {
+  int lo = 0, hi = S->nhist - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) / 2;
+    int a = S->hi[mid], b = S->hj[mid];
+    if (a == i && b == j) return mid;
+    if (a < i || (a == i && b < j)) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/* ---------------- map update: covered and uncovered nodes ---------------- */
+typedef struct {
+  const int32_t *own_other; /* covers: map before the move; uncovers: map after the move */
+  const double *R, *U, *W;  /* particle state after the move */
+  double s, ule;            /* offset and sliding velocity after the move */
+  double *dp;               /* [7 np]: momentum, angular momentum, fluid mass */
+} remap_ctx;
+
+/* A node that was fluid and is now inside particle p: its fluid is absorbed. */
+static void cover_fn(orc_sim *S, int p, int64_t node, int x, int y, int z, void *vctx) {
+  remap_ctx *c = (remap_ctx *)vctx;
+  if (c->own_other[node] != -1) return;
+  double rho = 0, j[3] = {0, 0, 0};
+  for (int q = 0; q < 19; ++q) {
+    double v = S->f[q * S->nodes + node];
+    rho += v; j[0] += v * CX[q]; j[1] += v * CY[q]; j[2] += v * CZ[q];
+  }
+  double d[3]; int32_t k;
+  orc_minimage(&S->p, c->s, x - c->R[3 * p], y - c->R[3 * p + 1], z - c->R[3 * p + 2], d, &k);
+  j[0] -= rho * k * c->ule; /* momentum seen from the particle's own image frame */
+  double *a = c->dp + 7 * (size_t)p;
+  a[0] += j[0]; a[1] += j[1]; a[2] += j[2];
+  a[3] += d[1] * j[2] - d[2] * j[1];
+  a[4] += d[2] * j[0] - d[0] * j[2];
+  a[5] += d[0] * j[1] - d[1] * j[0];
+  a[6] += rho;
+}
+
+/* A node inside particle p before the move and fluid after it: refilled with the
+ * equilibrium at rho0 and the surface velocity; the particle pays that momentum.     */
+static void uncover_fn(orc_sim *S, int p, int64_t node, int x, int y, int z, void *vctx) {
+  remap_ctx *c = (remap_ctx *)vctx;
+  if (c->own_other[node] != -1) return;
+  double d[3]; int32_t k;
+  orc_minimage(&S->p, c->s, x - c->R[3 * p], y - c->R[3 * p + 1], z - c->R[3 * p + 2], d, &k);
+  const double *W = &c->W[3 * p];
+  double ub[3] = {c->U[3 * p] + (W[1] * d[2] - W[2] * d[1]),
+                  c->U[3 * p + 1] + (W[2] * d[0] - W[0] * d[2]),
+                  c->U[3 * p + 2] + (W[0] * d[1] - W[1] * d[0])};
+  double fe[19];
+  orc_feq(S->p.rho0, ub[0] + k * c->ule, ub[1], ub[2], fe);
+  for (int q = 0; q < 19; ++q) S->f[q * S->nodes + node] = fe[q];
+  double r0 = S->p.rho0;
+  double j[3] = {r0 * ub[0], r0 * ub[1], r0 * ub[2]};
+  double *a = c->dp + 7 * (size_t)p;
+  a[0] -= j[0]; a[1] -= j[1]; a[2] -= j[2];
+  a[3] -= d[1] * j[2] - d[2] * j[1];
+  a[4] -= d[2] * j[0] - d[0] * j[2];
+  a[5] -= d[0] * j[1] - d[1] * j[0];
+  a[6] -= r0;
+}
+
+static int finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+/* ---------------- the full step ---------------- */
+static void one_step(orc_sim *S) {
+  orc_params *P = &S->p;
+  const int np = S->np;
+  const size_t npa = np > 0 ? (size_t)np : 1;
+  double s, ule, s1, ule1;
+  orc_protocol(P, S->step, &s, &ule);
+  orc_protocol(P, S->step + 1, &s1, &ule1);
+  S->s = s; S->ule = ule;
+  const double V = (double)P->lx * P->ly * P->lz;
+  double *R0 = (double *)xcalloc(3 * npa, sizeof(double));
+  memcpy(R0, S->R, 3 * sizeof(double) * (size_t)np);
+
+  /* neighbour list from the positions at the start of the step, history carried over */
+  build_pairs(S, s);
+  size_t npp = S->npairs > 0 ? (size_t)S->npairs : 1;
+  double *pxi = (double *)xcalloc(3 * npp, sizeof(double));
+  int32_t *pon = (int32_t *)xcalloc(npp, sizeof(int32_t));
+  for (int k = 0; k < S->npairs; ++k) {
+    int h = find_hist(S, S->pi[k], S->pj[k]);
+    if (h >= 0) {
+      pxi[3 * k] = S->hxi[3 * h]; pxi[3 * k + 1] = S->hxi[3 * h + 1]; pxi[3 * k + 2] = S->hxi[3 * h + 2];
+      pon[k] = 1;
+    }
+  }
+
+  /* fluid: Lees-Edwards ghosts, then stream + bounce-back + collide with link forces */
+  ghost_t G;
+  G.val = (double *)xcalloc((size_t)2 * 5 * P->lx * P->lz, sizeof(double));
+  build_ghosts(S, s, ule, &G);
+  double pineq[6];
+  fluid_step(S, s, ule, &G, pineq);
+  free(G.val);
+
+  /* DEM substeps: eq. (1) with the hydrodynamic force and torque frozen over the step */
+  double *Fp = (double *)xcalloc(3 * npa, sizeof(double));
+  double *Tp = (double *)xcalloc(3 * npa, sizeof(double));
+  double sc[6] = {0}, sr[6] = {0}, sl[6] = {0};
+  const int ns = P->n_sub;
+  const double dts = 1.0 / (double)ns;
+  for (int sub = 0; sub < ns; ++sub) {
+    memset(Fp, 0, 3 * sizeof(double) * npa);
+    memset(Tp, 0, 3 * sizeof(double) * npa);
+    for (int k = 0; k < S->npairs; ++k) {
+      int i = S->pi[k], j = S->pj[k];
+      double d[3]; int32_t kk;
+      orc_minimage(P, s, S->R[3 * i] - S->R[3 * j], S->R[3 * i + 1] - S->R[3 * j + 1],
+                   S->R[3 * i + 2] - S->R[3 * j + 2], d, &kk);
+      double Uj[3] = {S->U[3 * j] + kk * ule, S->U[3 * j + 1], S->U[3 * j + 2]};
+      const double *Ui = &S->U[3 * i], *Wi = &S->W[3 * i], *Wj = &S->W[3 * j];
+      double Fc[3], Tci[3], Tcj[3], Fn[3], Fr[3], Fl[3], Tli[3], Tlj[3], Si[6], Sj[6];
+      pon[k] = orc_contact(P, &S->d, S->a[i], S->a[j], d, Ui, Uj, Wi, Wj, dts, &pxi[3 * k],
+                           Fc, Tci, Tcj, Fn);
+      orc_dlvo(P, &S->d, S->a[i], S->a[j], d, Fr);
+      orc_lubrication(P, &S->d, S->a[i], S->a[j], d, Ui, Uj, Wi, Wj, Fl, Tli, Tlj, Si, Sj);
+      for (int c = 0; c < 3; ++c) {
+        double F = Fc[c] + Fr[c] + Fl[c];
+        Fp[3 * i + c] += F; Fp[3 * j + c] -= F;
+        Tp[3 * i + c] += Tci[c] + Tli[c];
+        Tp[3 * j + c] += Tcj[c] + Tlj[c];
+      }
+      /* eqs. (12), (14) counted once per pair: -(1/V) sym(r_ij (x) F_ij); stresslets + */
+      sym6(d, Fc, -0.5 / V, sc);
+      sym6(d, Fr, -0.5 / V, sr);
+      for (int c = 0; c < 6; ++c) sl[c] += (Si[c] + Sj[c]) / V;
+    }
+    for (int i = 0; i < np; ++i) {
+      double *U = &S->U[3 * i], *W = &S->W[3 * i], *R = &S->R[3 * i];
+      for (int c = 0; c < 3; ++c) {
+        U[c] += dts * (S->Fh[3 * i + c] + Fp[3 * i + c]) / S->m[i];
+        W[c] += dts * (S->Th[3 * i + c] + Tp[3 * i + c]) / S->I[i];
+      }
+      if (P->quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
+      for (int c = 0; c < 3; ++c) R[c] += dts * U[c];
+      quat_step(&S->Q[4 * i], W, dts);
+    }
+  }
+  free(Fp);
+  free(Tp);
+  /* surviving contacts become the new history (already in (i,j) order) */
+  int nh = 0;
+  for (int k = 0; k < S->npairs; ++k) nh += pon[k] ? 1 : 0;
+  free(S->hi); free(S->hj); free(S->hxi);
+  S->hi = (int32_t *)xcalloc((size_t)nh, sizeof(int32_t));
+  S->hj = (int32_t *)xcalloc((size_t)nh, sizeof(int32_t));
+  S->hxi = (double *)xcalloc(3 * (size_t)nh, sizeof(double));
+  S->nhist = nh; S->hist_cap = nh;
+  nh = 0;
+  for (int k = 0; k < S->npairs; ++k)
+    if (pon[k]) {
+      S->hi[nh] = S->pi[k]; S->hj[nh] = S->pj[k];
+      S->hxi[3 * nh] = pxi[3 * k]; S->hxi[3 * nh + 1] = pxi[3 * k + 1]; S->hxi[3 * nh + 2] = pxi[3 * k + 2];
+      ++nh;
+    }
+  free(pxi);
+  free(pon);
+
+  /* Lees-Edwards wrap of the particles with the offset of the next step */
+  for (int i = 0; i < np; ++i) {
+    double *R = &S->R[3 * i], *U = &S->U[3 * i];
+    if (R[1] >= P->ly) { R[1] -= P->ly; R[0] -= s1; U[0] -= ule1; }
+    else if (R[1] < 0.0) { R[1] += P->ly; R[0] += s1; U[0] += ule1; }
+    while (R[0] >= P->lx) R[0] -= P->lx;
+    while (R[0] < 0.0) R[0] += P->lx;
+    while (R[2] >= P->lz) R[2] -= P->lz;
+    while (R[2] < 0.0) R[2] += P->lz;
+  }
+
+  /* map update: new footprints absorb fluid nodes, old footprints release nodes */
+  if (np > 0) {
+    int32_t *own_new = (int32_t *)xcalloc((size_t)S->nodes, sizeof(int32_t));
+    build_map(S, own_new, S->R, s1);
+    double *dp = (double *)xcalloc(7 * npa, sizeof(double));
+    remap_ctx cc = {S->own, S->R, S->U, S->W, s1, ule1, dp};
+    for (int p = 0; p < np; ++p) for_footprint(S, S->R, p, s1, cover_fn, &cc);
+    remap_ctx uc = {own_new, S->R, S->U, S->W, s1, ule1, dp};
+    for (int p = 0; p < np; ++p) for_footprint(S, R0, p, s, uncover_fn, &uc);
+    for (int p = 0; p < np; ++p) {
+      const double *a = dp + 7 * (size_t)p;
+      for (int c = 0; c < 3; ++c) {
+        S->U[3 * p + c] += a[c] / S->m[p];
+        S->W[3 * p + c] += a[3 + c] / S->I[p];
+      }
+      if (P->quasi2d) { S->U[3 * p + 2] = 0.0; S->W[3 * p] = 0.0; S->W[3 * p + 1] = 0.0; }
+      S->ledger += a[6];
+    }
+    free(S->own);
+    S->own = own_new;
+    free(dp);
+  }
+  free(R0);
+  for (int i = 0; i < np; ++i)
+    if (!finite3(&S->R[3 * i]) || !finite3(&S->U[3 * i]) || !finite3(&S->W[3 * i])) S->flags |= 2;
+
+  /* stress of this step, eq. (15) with the fluid, particle and lubrication parts */
+  double sig[5][6];
+  double cf = -(1.0 - 0.5 / P->tau) / V;
+  for (int c = 0; c < 6; ++c) sig[0][c] = cf * pineq[c];
+  double sh[6] = {0, 0, 0, 0, 0, 0};
+  for (int p = 0; p < np; ++p) {
+    const double *m = &S->Sh[9 * p];
+    sh[0] += m[0]; sh[1] += m[4]; sh[2] += m[8];
+    sh[3] += 0.5 * (m[1] + m[3]); sh[4] += 0.5 * (m[2] + m[6]); sh[5] += 0.5 * (m[5] + m[7]);
+  }
+  for (int c = 0; c < 6; ++c) {
+    sig[1][c] = sh[c] / V;
+    sig[2][c] = sl[c] / ns;
+    sig[3][c] = sc[c] / ns;
+    sig[4][c] = sr[c] / ns;
+  }
+  for (int k = 0; k < 5; ++k)
+    for (int c = 0; c < 6; ++c) { S->sig_last[k][c] = sig[k][c]; S->sig_sum[k][c] += sig[k][c]; }
+  S->sig_count += 1;
+  /* G', G'' (eqs. 17-18, rectangle rule over the observation periods) */
+  if (P->shear_kind == 2) {
+    int64_t tI = (int64_t)P->ncyc_I * P->period, tF = tI + (int64_t)P->ncyc_F * P->period;
+    if (S->step >= tI && S->step < tF) {
+      double om = 2.0 * PI / (double)P->period;
+      double ph = om * (double)(S->step - tI) + P->theta;
+      double sxy = sig[0][3] + sig[1][3] + sig[2][3] + sig[3][3] + sig[4][3];
+      S->gp_cos += sxy * cos(ph);
+      S->gp_sin += sxy * sin(ph);
+      S->gp_count += 1;
+    }
+  }
+  S->step += 1;
+  S->s_next = s1;
+}
+
+int orc_step(orc_sim *S, int64_t nsteps) {
+  for (int64_t t = 0; t < nsteps; ++t) {
+    one_step(S);
+    if (S->flags) return -4;
+  }
+  return 0;
+}
+
+void orc_stress(orc_sim *S, double out[5][6], double gg[2]) {
+  double n = S->sig_count > 0 ? (double)S->sig_count : 1.0;
+  for (int k = 0; k < 5; ++k)
+    for (int c = 0; c < 6; ++c) { out[k][c] = S->sig_sum[k][c] / n; S->sig_sum[k][c] = 0.0; }
+  S->sig_count = 0;
+  if (S->gp_count > 0 && S->p.g0_F != 0.0) {
+    double c = 2.0 / ((double)S->gp_count * S->p.g0_F);
+    gg[0] = -c * S->gp_cos;
+    gg[1] = c * S->gp_sin;
+  } else {
+    gg[0] = 0.0; gg[1] = 0.0;
+  }
+}
