@@ -1,0 +1,183 @@
+/*
+ * susp.h -- C ABI of the MI355X lattice-Boltzmann + DEM library for sheared, frictional,
+ * non-Brownian suspensions (Pradipto & Hayakawa, arXiv:1904.02929).
+ *
+ * One call of susp_step advances the coupled system by whole lattice-Boltzmann steps:
+ *   - D3Q19 collide-and-stream (App. A, eqs. 3-5; collision taken as single-time BGK)
+ *     with a Lees-Edwards sliding boundary in y (interpolated, Galilean-corrected ghost
+ *     rows; periodic in x and z),
+ *   - moving-sphere bounce-back on links cut by the mapped spheres (App. A, eqs. 7-8),
+ *     with the exchanged momentum (eq. 6) summed into force, torque and stresslet per
+ *     particle (eqs. 9-10),
+ *   - cell-list neighbour search and pair forces: linear spring-dashpot normal contact,
+ *     Cundall-Strack tangential spring with Coulomb cap (Sec. 2, eqs. 11, 11t), DLVO
+ *     repulsion (eq. 13) and the leading-order lubrication correction (App. A),
+ *   - the particle equations of motion (eq. 1) with DEM substeps,
+ *   - the mapped-sphere node update (nodes covered and released as spheres move),
+ *   - the stress of eq. (15) split into fluid, particle-surface, lubrication, contact and
+ *     DLVO parts, and the G', G'' quadratures of eqs. (17)-(18).
+ *
+ * Units: lattice units, dx = dt = 1.  Node (x,y,z) has linear index x + lx*(y + ly*z).
+ * Directions q = 0..18: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (+1,+1,0), (-1,-1,0),
+ * (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1), (-1,0,+1), (0,+1,+1),
+ * (0,-1,-1), (0,+1,-1), (0,-1,+1); the opposite of odd q is q+1.
+ *
+ * Conventions common to every call:
+ *   - Return value: a susp_status; 0 on success.  No exception or abort crosses the ABI.
+ *     susp_last_error() gives a human-readable text for the calling thread's last error.
+ *   - Host pointers are owned by the caller and only read or written during the call.
+ *   - Device state is owned by the simulation object, carved out of one device block that
+ *     the library allocates at susp_create, or out of a caller-provided workspace of at least
+ *     susp_footprint_bytes() bytes (which then stays owned by the caller and must outlive the
+ *     simulation).
+ *   - All device work is enqueued on the HIP stream given at creation (NULL: the null
+ *     stream).  susp_step is asynchronous except for the instability check at its end; the
+ *     getters, setters and susp_stress synchronise the stream.
+ */
+#ifndef SUSP_H
+#define SUSP_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct susp_sim susp_sim;
+
+typedef enum {
+  SUSP_OK = 0,
+  SUSP_EINVAL = -1,     /* a parameter or argument is out of range                      */
+  SUSP_ENOMEM = -2,     /* device allocation failed or workspace too small             */
+  SUSP_EDEVICE = -3,    /* a HIP call failed                                            */
+  SUSP_EUNSTABLE = -4,  /* mapped spheres overlap, non-finite particle state, or a
+                           particle exceeded the neighbour capacity                     */
+  SUSP_ESTATE = -5      /* a state buffer does not match the simulation                */
+} susp_status;
+
+typedef enum {
+  SUSP_FP64 = 0,        /* populations stored and collided in FP64                      */
+  SUSP_FP32 = 1,        /* deviations n_q - w_q rho0 stored in FP32, FP32 collision     */
+  SUSP_FP16STORE = 2    /* deviations stored as FP16 of (n_q - w_q rho0)/w_q * 2^k,
+                           FP32 collision                                               */
+} susp_precision;
+
+/* Problem statement (Sec. 2, Sec. 4.1, App. A).  A value below zero for kn, eta_n,
+ * lub_delta, F0 or debye_lambda selects the paper's default:
+ *   kn = 0.36 m0 (dt = 0.6 sqrt(m0/kn) with dt = 1), eta_n = sqrt(m0 kn),
+ *   lub_delta = 0.01 a_min, F0 = 2e-4 kn, debye_lambda = 0.02 a_min,
+ * with m0 the mean particle mass and a_min the smallest contact radius.                   */
+typedef struct {
+  int32_t lx, ly, lz;        /* lattice size; all >= 8, ly >= 3 (2 a_max + pair_cutoff)  */
+  int32_t precision;         /* susp_precision                                           */
+  double tau, rho0;          /* BGK relaxation time (> 0.5), reference density          */
+  int32_t n;                 /* number of spheres (0 allowed)                            */
+  const double *pos;         /* [n][3] centres, inside [0,lx) x [0,ly) x [0,lz)          */
+  const double *vel;         /* [n][3] or NULL (zero)                                    */
+  const double *omega;       /* [n][3] or NULL (zero)                                    */
+  const double *radius;      /* [n] contact radii                                        */
+  double map_ratio;          /* mapped radius / contact radius (paper: 0.95)             */
+  double rho_p;              /* particle density                                         */
+  double kn, kt_ratio, mu, eta_n;
+  double lub_delta, lub_hc;  /* roughness length; lubrication acts for gaps below lub_hc */
+  int32_t lub_subtract_hc;   /* 1: each resistance function minus its value at lub_hc   */
+  double F0, debye_lambda;
+  double pair_cutoff;        /* neighbour-list gap cutoff; DLVO acts below it            */
+  int32_t n_sub;             /* DEM substeps per lattice step (>= 1)                     */
+  int32_t quasi2d;           /* 1: monolayer, U_z = Omega_x = Omega_y = 0 (Sec. 4.1)     */
+  int32_t shear_kind;        /* 0 none, 1 simple (gamma_dot), 2 oscillatory (eq. 16)     */
+  double gamma_dot;
+  double g0_I, g0_F;         /* strain amplitude of the initial and observation cycles  */
+  int32_t period;            /* steps per oscillation period (omega = 2 pi / period)     */
+  double theta;              /* initial phase Theta                                      */
+  int32_t ncyc_I, ncyc_F;    /* initial and observation cycles                           */
+  int32_t fp16_exp;          /* k of the FP16 storage scale 2^k (SUSP_FP16STORE only)    */
+} susp_params;
+
+/* Fill *p with the paper's defaults (tau 1, rho0 1, map_ratio 0.95, rho_p 1, kt 0.5 kn,
+ * mu 1, lub_hc 0.5 with subtraction, pair_cutoff 1, n_sub 8, FP32, no shear).           */
+void susp_default_params(susp_params *p);
+
+/* Exact device bytes a simulation of these parameters needs (workspace size).  Returns 0
+ * and sets the last error if the parameters are invalid.                                  */
+size_t susp_footprint_bytes(const susp_params *p);
+
+/* Create a simulation: validate, upload the spheres, fill the fluid with the equilibrium
+ * of the imposed shear profile u_x = gdot(0) (y - (ly-1)/2) and map the spheres.
+ * stream: a hipStream_t (NULL: null stream).  workspace: device memory of at least
+ * ws_bytes >= susp_footprint_bytes(p), 256-byte aligned, or NULL to let the library
+ * allocate.  On success *out receives the handle.                                         */
+int susp_create(const susp_params *p, void *stream, void *workspace, size_t ws_bytes,
+                susp_sim **out);
+
+/* Advance nsteps lattice steps (nsteps >= 0).  Returns SUSP_EUNSTABLE if any of those
+ * steps found overlapping mapped spheres, a non-finite particle state or a neighbour-list
+ * overflow (the state has still been advanced).                                            */
+int susp_step(susp_sim *s, int64_t nsteps);
+
+/* Stress averaged over the steps since the previous call (or creation), then reset:
+ * out[k][c], k = fluid, particle surface, lubrication, contact, DLVO; c = xx yy zz xy xz
+ * yz, each divided by the box volume (eqs. 12, 14, 15).  gg = {G', G''} from eqs. (17)-(18)
+ * over the observation steps completed so far (0 if none).  Synchronises.                */
+int susp_stress(susp_sim *s, double out[5][6], double gg[2]);
+
+/* Release the simulation (and its device block unless it came from a workspace). */
+int susp_destroy(susp_sim *s);
+
+/* ---- state access (synchronising); used for checkpoints and parity checks ---- */
+/* Populations as full FP64 values n_q, [19][lz][ly][lx]; entries of solid nodes are
+ * undefined on get and ignored on set.  Set rounds to the storage precision.             */
+int susp_get_populations(susp_sim *s, double *host);
+int susp_set_populations(susp_sim *s, const double *host);
+/* Particle state: positions, velocities, angular velocities [n][3], orientations [n][4]
+ * (any pointer may be NULL on get).  Set re-maps the spheres (no cover/uncover).         */
+int susp_get_particles(susp_sim *s, double *pos, double *vel, double *omega, double *quat);
+int susp_set_particles(susp_sim *s, const double *pos, const double *vel, const double *omega,
+                       const double *quat);
+/* Tangential-spring history: the pairs (i<j) in contact and their spring vectors.
+ * Get: *count receives the number of pairs; i, j, xi may be NULL to query the count;
+ * otherwise they must hold cap entries.  Set replaces the history.                        */
+int susp_get_history(susp_sim *s, int32_t cap, int32_t *count, int32_t *i, int32_t *j,
+                     double *xi);
+int susp_set_history(susp_sim *s, int32_t count, const int32_t *i, const int32_t *j,
+                     const double *xi);
+/* Step counter and Lees-Edwards offset of the current state; the counter drives eq. (16).
+ * Setting the clock re-maps the spheres with the new offset; an overlap this creates is
+ * reported by the next susp_set_particles or susp_step, so set the clock first when
+ * restoring a state.                                                                     */
+int susp_get_clock(susp_sim *s, int64_t *step, double *offset);
+int susp_set_clock(susp_sim *s, int64_t step);
+
+/* Per-particle hydrodynamic results of the last step: force [n][3], torque [n][3],
+ * symmetric stresslet [n][6] (xx yy zz xy xz yz; link momentum minus that of the uniform
+ * rest state) and boundary-link count [n].  Any pointer may be NULL.                      */
+int susp_get_hydro(susp_sim *s, double *force, double *torque, double *stresslet,
+                   int32_t *nlinks);
+
+/* Lists, for bit-exact checks.  kind selects:
+ *   SUSP_LIST_OWNER   int32 [lz][ly][lx] owner sphere of every node (-1 fluid)
+ *   SUSP_LIST_GHOST   int32 [2][lz][lx] owner of the ghost points (x,-1,z), (x,ly,z)
+ *                     used by the last step
+ *   SUSP_LIST_CELLS   int32 cell_start[ncell+1] followed by sphere ids [n] of the cell
+ *                     list of the last step (cells x fastest, ids ascending in a cell)
+ *   SUSP_LIST_PAIRS   int32 [npairs][2] neighbour pairs (i<j) of the last step, sorted
+ *   SUSP_LIST_CONTACTS int32 [m][2] pairs of the last step's list in contact (gap < 0)
+ *                     at its start, sorted
+ *   SUSP_LIST_LINKS   int32 [nlinks][3] (node, q, sphere) of every link from a fluid
+ *                     node whose pull source x - c_q is solid, for the current map and
+ *                     offset, sorted by (node, q)
+ * *bytes is in/out: capacity of host on entry, bytes needed on return.  host may be NULL
+ * to query the size.                                                                       */
+enum { SUSP_LIST_OWNER = 0, SUSP_LIST_GHOST = 1, SUSP_LIST_CELLS = 2, SUSP_LIST_PAIRS = 3,
+       SUSP_LIST_CONTACTS = 4, SUSP_LIST_LINKS = 5 };
+int susp_get_lists(susp_sim *s, int32_t kind, void *host, size_t *bytes);
+
+/* Resolved constants: {m0, kn, kt, eta_n, lub_delta, F0, debye_lambda, eta0, a_min, a_max}. */
+int susp_get_derived(susp_sim *s, double out[10]);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *susp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

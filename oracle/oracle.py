@@ -62,7 +62,7 @@ class Sim(C.Structure):
         ("f", _PD), ("fn", _PD), ("own", _PI), ("np", C.c_int32),
         ("R", _PD), ("U", _PD), ("W", _PD), ("Q", _PD), ("a", _PD),
         ("m", _PD), ("I", _PD), ("amap", _PD),
-        ("Fh", _PD), ("Th", _PD), ("Sh", _PD), ("nlinks", _PI),
+        ("Fh", _PD), ("Th", _PD), ("Sh", _PD), ("nlinks", _PI), ("Frest", _PD), ("Trest", _PD),
         ("npairs", C.c_int32), ("pairs_cap", C.c_int32), ("pi", _PI), ("pj", _PI),
         ("nhist", C.c_int32), ("hist_cap", C.c_int32), ("hi", _PI), ("hj", _PI), ("hxi", _PD),
         ("gown", _PI),
@@ -240,7 +240,7 @@ class Oracle:
 
     def part(self, name):
         width = {"R": 3, "U": 3, "W": 3, "Q": 4, "a": None, "m": None, "I": None, "amap": None,
-                 "Fh": 3, "Th": 3, "Sh": 9}[name]
+                 "Fh": 3, "Th": 3, "Sh": 9, "Frest": 3, "Trest": 3}[name]
         shape = (self.s.np,) if width is None else (self.s.np, width)
         return self._arr(getattr(self.s, name), shape)
 

@@ -67,10 +67,10 @@ void orc_minimage(const orc_params *p, double s, double dx, double dy, double dz
   int kk = 0;
   if (dy > 0.5 * Ly) { dy -= Ly; dx -= s; kk = 1; }
   else if (dy < -0.5 * Ly) { dy += Ly; dx += s; kk = -1; }
-  while (dx > 0.5 * Lx) dx -= Lx;
-  while (dx < -0.5 * Lx) dx += Lx;
-  while (dz > 0.5 * Lz) dz -= Lz;
-  while (dz < -0.5 * Lz) dz += Lz;
+  for (int it = 0; it < 4 && dx > 0.5 * Lx; ++it) dx -= Lx;
+  for (int it = 0; it < 4 && dx < -0.5 * Lx; ++it) dx += Lx;
+  for (int it = 0; it < 4 && dz > 0.5 * Lz; ++it) dz -= Lz;
+  for (int it = 0; it < 4 && dz < -0.5 * Lz; ++it) dz += Lz;
   out[0] = dx; out[1] = dy; out[2] = dz;
   if (k) *k = kk;
 }
@@ -405,6 +405,8 @@ orc_sim *orc_create(const orc_params *p, int32_t np, const double *pos, const do
   S->Th = (double *)xcalloc(3 * (size_t)np, sizeof(double));
   S->Sh = (double *)xcalloc(9 * (size_t)np, sizeof(double));
   S->nlinks = (int32_t *)xcalloc((size_t)np, sizeof(int32_t));
+  S->Frest = (double *)xcalloc(3 * (size_t)np, sizeof(double));
+  S->Trest = (double *)xcalloc(3 * (size_t)np, sizeof(double));
   S->gown = (int32_t *)xcalloc(2 * (size_t)p->lx * p->lz, sizeof(int32_t));
   for (int i = 0; i < np; ++i) {
     for (int c = 0; c < 3; ++c) {
@@ -446,7 +448,7 @@ void orc_destroy(orc_sim *S) {
   if (!S) return;
   free(S->f); free(S->fn); free(S->own); free(S->R); free(S->U); free(S->W); free(S->Q);
   free(S->a); free(S->m); free(S->I); free(S->amap); free(S->Fh); free(S->Th); free(S->Sh);
-  free(S->nlinks); free(S->pi); free(S->pj); free(S->hi); free(S->hj); free(S->hxi);
+  free(S->nlinks); free(S->Frest); free(S->Trest); free(S->pi); free(S->pj); free(S->hi); free(S->hj); free(S->hxi);
   free(S->gown);
   free(S);
 }
@@ -542,13 +544,16 @@ static void build_ghosts(orc_sim *S, double s, double ule, ghost_t *G) {
 }
 
 /* ---------------- one LB step of the fluid with particle links ---------------- */
+/* per-particle link sums: F[3] T[3] S[9] count, rest-state force[3] and torque[3] */
+#define ACC 22
+
 static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, double pineq[6]) {
   const orc_params *P = &S->p;
   const int lx = P->lx, ly = P->ly, lz = P->lz, np = S->np;
   const int64_t nodes = S->nodes;
   const double rho0 = P->rho0, tau = P->tau;
   int nt = S->nthreads;
-  double *acc = (double *)xcalloc((size_t)nt * (np > 0 ? np : 1) * 16, sizeof(double));
+  double *acc = (double *)xcalloc((size_t)nt * (np > 0 ? np : 1) * ACC, sizeof(double));
   double *pacc = (double *)xcalloc((size_t)nt * 6, sizeof(double));
 #pragma omp parallel num_threads(nt)
   {
@@ -556,7 +561,7 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
 #ifdef _OPENMP
     tid = omp_get_thread_num();
 #endif
-    double *A = acc + (size_t)tid * (np > 0 ? np : 1) * 16;
+    double *A = acc + (size_t)tid * (np > 0 ? np : 1) * ACC;
     double *pa = pacc + 6 * tid;
 #pragma omp for schedule(static)
     for (int z = 0; z < lz; ++z)
@@ -607,19 +612,25 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
               double ubc = ub[0] * CX[co] + ub[1] * CY[co] + ub[2] * CZ[co];
               double corr = 6.0 * WQ(co) * rho0 * ubc;
               n[q] = fo - corr;
-              /* eq. (6) (one factor 2): momentum exchanged across the link */
+              /* eq. (6) (one factor 2): momentum exchanged across the link, measured from
+               * the uniform rest state rho0 (whose part 2 w rho0 c is kept apart) */
               double fm = 2.0 * fo - corr;
-              double fl[3] = {fm * CX[co], fm * CY[co], fm * CZ[co]};
-              double fc = 2.0 * fo - corr - 2.0 * WQ(co) * rho0; /* minus the rest state */
-              double fs[3] = {fc * CX[co], fc * CY[co], fc * CZ[co]};
-              double *a = A + 16 * (size_t)p;
+              double fr = 2.0 * WQ(co) * rho0;
+              double fc = fm - fr;
+              double fl[3] = {fc * CX[co], fc * CY[co], fc * CZ[co]};
+              double rl[3] = {fr * CX[co], fr * CY[co], fr * CZ[co]};
+              double *a = A + ACC * (size_t)p;
               a[0] += fl[0]; a[1] += fl[1]; a[2] += fl[2];
               a[3] += lev[1] * fl[2] - lev[2] * fl[1];
               a[4] += lev[2] * fl[0] - lev[0] * fl[2];
               a[5] += lev[0] * fl[1] - lev[1] * fl[0];
               for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) a[6 + 3 * r + c] += lev[r] * fs[c];
+                for (int c = 0; c < 3; ++c) a[6 + 3 * r + c] += lev[r] * fl[c];
               a[15] += 1.0;
+              a[16] += rl[0]; a[17] += rl[1]; a[18] += rl[2];
+              a[19] += lev[1] * rl[2] - lev[2] * rl[1];
+              a[20] += lev[2] * rl[0] - lev[0] * rl[2];
+              a[21] += lev[0] * rl[1] - lev[1] * rl[0];
             }
           }
           /* eq. (4) moments, BGK collision (eq. (5) with a single eigenvalue -1/tau) */
@@ -643,12 +654,13 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
   }
   /* fixed-order reduction of the per-thread partials */
   for (int p = 0; p < np; ++p) {
-    double t[16] = {0};
+    double t[ACC] = {0};
     for (int th = 0; th < nt; ++th)
-      for (int c = 0; c < 16; ++c) t[c] += acc[((size_t)th * np + p) * 16 + c];
+      for (int c = 0; c < ACC; ++c) t[c] += acc[((size_t)th * np + p) * ACC + c];
     for (int c = 0; c < 3; ++c) { S->Fh[3 * p + c] = t[c]; S->Th[3 * p + c] = t[3 + c]; }
     for (int c = 0; c < 9; ++c) S->Sh[9 * p + c] = t[6 + c];
     S->nlinks[p] = (int32_t)t[15];
+    for (int c = 0; c < 3; ++c) { S->Frest[3 * p + c] = t[16 + c]; S->Trest[3 * p + c] = t[19 + c]; }
   }
   for (int c = 0; c < 6; ++c) {
     pineq[c] = 0;
@@ -871,10 +883,10 @@ static void one_step(orc_sim *S) {
     double *R = &S->R[3 * i], *U = &S->U[3 * i];
     if (R[1] >= P->ly) { R[1] -= P->ly; R[0] -= s1; U[0] -= ule1; }
     else if (R[1] < 0.0) { R[1] += P->ly; R[0] += s1; U[0] += ule1; }
-    while (R[0] >= P->lx) R[0] -= P->lx;
-    while (R[0] < 0.0) R[0] += P->lx;
-    while (R[2] >= P->lz) R[2] -= P->lz;
-    while (R[2] < 0.0) R[2] += P->lz;
+    for (int it = 0; it < 4 && R[0] >= P->lx; ++it) R[0] -= P->lx;
+    for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += P->lx;
+    for (int it = 0; it < 4 && R[2] >= P->lz; ++it) R[2] -= P->lz;
+    for (int it = 0; it < 4 && R[2] < 0.0; ++it) R[2] += P->lz;
   }
 
   /* map update: new footprints absorb fluid nodes, old footprints release nodes */

@@ -64,6 +64,8 @@ typedef struct {
   /* per-step hydrodynamic results */
   double *Fh, *Th, *Sh;      /* [3np] [3np] [9np] (Sh row-major lever (x) force)       */
   int32_t *nlinks;           /* [np] boundary links per particle in the last step      */
+  double *Frest, *Trest;     /* [3np] rest-state part 2 w rho0 c of the link momentum,
+                                excluded from Fh, Th, Sh (see fluid_step)              */
   /* neighbour list (step start): pairs i<j, sorted by (i,j) */
   int32_t npairs, pairs_cap;
   int32_t *pi, *pj;

@@ -1,0 +1,656 @@
+// api.hip -- host side of the C ABI declared in include/susp.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/susp.h"
+#include "susp_impl.h"
+
+using namespace susp;
+
+struct susp_sim {
+  Sim s;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(SUSP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+extern "C" const char *susp_last_error(void) { return g_err.c_str(); }
+
+extern "C" void susp_default_params(susp_params *p) {
+  memset(p, 0, sizeof *p);
+  p->precision = SUSP_FP32;
+  p->tau = 1.0;
+  p->rho0 = 1.0;
+  p->map_ratio = 0.95;
+  p->rho_p = 1.0;
+  p->kn = -1.0;
+  p->kt_ratio = 0.5;
+  p->mu = 1.0;
+  p->eta_n = -1.0;
+  p->lub_delta = -1.0;
+  p->lub_hc = 0.5;
+  p->lub_subtract_hc = 1;
+  p->F0 = -1.0;
+  p->debye_lambda = -1.0;
+  p->pair_cutoff = 1.0;
+  p->n_sub = 8;
+  p->period = 1;
+  p->fp16_exp = 10;
+}
+
+// ---------------------------------------------------------------------------------------
+// Shear protocol: offset and sliding velocity of the image box above at step t
+// (simple shear, or eq. (16) with the amplitude switched after ncyc_I periods).
+static void protocol(const Sim &s, int64_t t, double *off, double *ule) {
+  const double Lx = s.lx, Ly = s.ly;
+  if (s.shear_kind == 1) {
+    const double u = s.gamma_dot * Ly;
+    const double x = (double)t * u;
+    *off = x - Lx * floor(x / Lx);
+    *ule = u;
+  } else if (s.shear_kind == 2) {
+    const int64_t P = s.period;
+    const int64_t tI = (int64_t)s.ncyc_I * P;
+    const double g0 = t < tI ? s.g0_I : s.g0_F;
+    const int64_t tp = t < tI ? t : t - tI;
+    const double om = 2.0 * 3.14159265358979323846 / (double)P;
+    const double ph = om * (double)tp + s.theta;
+    const double gam = g0 * (cos(s.theta) - cos(ph));
+    const double gdot = om * g0 * sin(ph);
+    const double x = Ly * gam;
+    *off = x - Lx * floor(x / Lx);
+    *ule = Ly * gdot;
+  } else {
+    *off = 0.0;
+    *ule = 0.0;
+  }
+}
+
+static Box make_box(const Sim &s, double off, double ule) {
+  Box b;
+  b.lx = s.lx; b.ly = s.ly; b.lz = s.lz;
+  b.Lx = s.lx; b.Ly = s.ly; b.Lz = s.lz;
+  b.s = off; b.ule = ule;
+  return b;
+}
+
+// ---------------------------------------------------------------------------------------
+static int resolve(const susp_params *p, Sim &s) {
+  if (!p) return fail(SUSP_EINVAL, "params is NULL");
+  if (p->lx < 8 || p->ly < 8 || p->lz < 8) return fail(SUSP_EINVAL, "lattice must be at least 8^3");
+  if ((int64_t)p->lx * p->ly * p->lz > (int64_t)1 << 31)
+    return fail(SUSP_EINVAL, "lattice larger than 2^31 nodes");
+  if (p->precision < 0 || p->precision > 2) return fail(SUSP_EINVAL, "bad precision");
+  if (!(p->tau > 0.5)) return fail(SUSP_EINVAL, "tau must exceed 1/2");
+  if (!(p->rho0 > 0)) return fail(SUSP_EINVAL, "rho0 must be positive");
+  if (p->n < 0) return fail(SUSP_EINVAL, "negative sphere count");
+  if (p->n > 0 && (!p->pos || !p->radius)) return fail(SUSP_EINVAL, "pos/radius missing");
+  if (p->n_sub < 1) return fail(SUSP_EINVAL, "n_sub must be >= 1");
+  if (p->shear_kind < 0 || p->shear_kind > 2) return fail(SUSP_EINVAL, "bad shear_kind");
+  if (p->shear_kind == 2 && p->period < 1) return fail(SUSP_EINVAL, "period must be >= 1");
+  if (!(p->map_ratio > 0 && p->map_ratio <= 1)) return fail(SUSP_EINVAL, "map_ratio in (0,1]");
+  if (!(p->pair_cutoff >= p->lub_hc) || !(p->pair_cutoff > 0))
+    return fail(SUSP_EINVAL, "pair_cutoff must be positive and >= lub_hc");
+  s.lx = p->lx; s.ly = p->ly; s.lz = p->lz;
+  s.precision = p->precision;
+  s.nodes = (int64_t)p->lx * p->ly * p->lz;
+  s.plane = (size_t)((s.nodes + 255) / 256 * 256);
+  s.n = p->n;
+  s.tau = p->tau; s.rho0 = p->rho0;
+  s.map_ratio = p->map_ratio; s.rho_p = p->rho_p;
+  const double PI = 3.14159265358979323846;
+  double amin = 0, amax = 0, msum = 0;
+  for (int i = 0; i < p->n; ++i) {
+    const double a = p->radius[i];
+    if (!(a > 0)) return fail(SUSP_EINVAL, "radius %d not positive", i);
+    if (i == 0 || a < amin) amin = a;
+    if (i == 0 || a > amax) amax = a;
+    msum += p->rho_p * (4.0 / 3.0) * PI * a * a * a;
+    for (int c = 0; c < 3; ++c) {
+      const double L = c == 0 ? p->lx : (c == 1 ? p->ly : p->lz);
+      const double x = p->pos[3 * i + c];
+      if (!(x >= 0.0 && x < L)) return fail(SUSP_EINVAL, "sphere %d outside the box", i);
+    }
+  }
+  s.a_min = amin; s.a_max = amax;
+  s.m0 = p->n > 0 ? msum / p->n : 0.0;
+  s.kn = p->kn > 0 ? p->kn : 0.36 * s.m0;  // dt = 0.6 sqrt(m0/kn), dt = 1
+  s.kt = p->kt_ratio * s.kn;
+  s.eta_n = p->eta_n >= 0 ? p->eta_n : sqrt(s.m0 * s.kn);
+  s.lub_delta = p->lub_delta >= 0 ? p->lub_delta : 0.01 * amin;
+  s.lambda = p->debye_lambda > 0 ? p->debye_lambda : 0.02 * amin;
+  s.F0 = p->F0 >= 0 ? p->F0 : 2e-4 * s.kn;
+  s.eta0 = p->rho0 * (p->tau - 0.5) / 3.0;
+  s.mu = p->mu; s.lub_hc = p->lub_hc; s.pair_cutoff = p->pair_cutoff;
+  s.lub_sub = p->lub_subtract_hc; s.n_sub = p->n_sub; s.quasi2d = p->quasi2d;
+  s.shear_kind = p->shear_kind;
+  s.gamma_dot = p->gamma_dot; s.g0_I = p->g0_I; s.g0_F = p->g0_F; s.theta = p->theta;
+  s.period = p->period; s.ncyc_I = p->ncyc_I; s.ncyc_F = p->ncyc_F;
+  s.fp16_exp = p->fp16_exp;
+  for (int q = 0; q < NQ; ++q) {
+    s.fp16_tab[q] = (float)(wq(q) * ldexp(1.0, -p->fp16_exp));     // storage -> deviation
+    s.fp16_tab[NQ + q] = (float)(ldexp(1.0, p->fp16_exp) / wq(q));  // deviation -> storage
+  }
+  // cell grid: width >= 2 a_max + cutoff, at least 3 cells across the sliding direction
+  const double rc = 2.0 * amax * (p->n > 0 ? 1.0 : 0.0) + p->pair_cutoff + 1e-6;
+  const int L[3] = {p->lx, p->ly, p->lz};
+  int nc[3];
+  for (int c = 0; c < 3; ++c) {
+    nc[c] = (int)floor(L[c] / rc);
+    if (nc[c] < 1) nc[c] = 1;
+    if (nc[c] > 64) nc[c] = 64;
+  }
+  if (p->n > 0 && nc[1] < 3)
+    return fail(SUSP_EINVAL, "ly must hold 3 cells of 2 a_max + pair_cutoff");
+  const double amap = p->map_ratio * amax;
+  if (p->n > 0 && (p->lx <= 2 * amap || p->lz <= 2 * amap))
+    return fail(SUSP_EINVAL, "lx and lz must exceed the mapped diameter");
+  s.cells.nx = nc[0]; s.cells.ny = nc[1]; s.cells.nz = nc[2];
+  s.cells.ix = nc[0] / (double)p->lx;
+  s.cells.iy = nc[1] / (double)p->ly;
+  s.cells.iz = nc[2] / (double)p->lz;
+  s.ncell = nc[0] * nc[1] * nc[2];
+  s.lbm_blocks = (int)((s.nodes + LBM_BLOCK - 1) / LBM_BLOCK);
+  return SUSP_OK;
+}
+
+// Carve (or size) the device block.  With base == NULL only the size is computed.
+static size_t carve(Sim &s, char *base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    void *p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    if (bytes == 0) off += 256;
+    return p;
+  };
+  const size_t es = s.precision == 0 ? 8 : (s.precision == 1 ? 4 : 2);
+  const size_t cs = s.precision == 0 ? 8 : 4;
+  const size_t n = (size_t)s.n;
+  for (int b = 0; b < 2; ++b) s.f[b] = take(NQ * s.plane * es);
+  for (int b = 0; b < 2; ++b) s.own[b] = (int32_t *)take((size_t)s.nodes * 4);
+  s.gown = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
+  s.gval = take((size_t)2 * 5 * s.lx * s.lz * cs);
+  for (int b = 0; b < 2; ++b) {
+    s.R[b] = (double *)take(n * 3 * 8);
+    s.U[b] = (double *)take(n * 3 * 8);
+    s.W[b] = (double *)take(n * 3 * 8);
+    s.Q[b] = (double *)take(n * 4 * 8);
+    s.hyd[b] = (double *)take(n * HYD * 8);
+  }
+  s.R0 = (double *)take(n * 3 * 8);
+  s.a = (double *)take(n * 8);
+  s.m = (double *)take(n * 8);
+  s.I = (double *)take(n * 8);
+  s.amap = (double *)take(n * 8);
+  s.pst = (double *)take(n * PST * 8);
+  s.dp = (double *)take(n * 8 * 8);
+  s.cell_start = (int32_t *)take((size_t)(s.ncell + 1) * 4);
+  s.cell_ids = (int32_t *)take(n * 4);
+  s.cell_scr = (int32_t *)take((size_t)s.ncell * 4);
+  for (int b = 0; b < 2; ++b) {
+    s.ncnt[b] = (int32_t *)take(n * 4);
+    s.nj[b] = (int32_t *)take(n * NCAP * 4);
+    s.hxi[b] = (double *)take(n * NCAP * 3 * 8);
+    s.hon[b] = (int32_t *)take(n * NCAP * 4);
+  }
+  s.hstart = (int32_t *)take(n * NCAP * 4);
+  s.pineq = (double *)take((size_t)s.lbm_blocks * 6 * 8);
+  s.acc = (double *)take((size_t)(128 + 128 * 32) * 8);
+  s.flags = (int32_t *)take(256);
+  return off;
+}
+
+extern "C" size_t susp_footprint_bytes(const susp_params *p) {
+  Sim s;
+  memset(&s, 0, sizeof s);
+  if (resolve(p, s) != SUSP_OK) return 0;
+  return carve(s, nullptr);
+}
+
+static int remap(Sim &s) {
+  // both maps to fluid, then claim the current footprints (no cover/uncover)
+  HIPCHK(launch_fill_i32(s.own[0], (size_t)s.nodes, -1, s.stream));
+  HIPCHK(launch_fill_i32(s.own[1], (size_t)s.nodes, -1, s.stream));
+  double off, ule;
+  protocol(s, s.step, &off, &ule);
+  HIPCHK(launch_map_claim(&s, make_box(s, off, ule), 0));
+  s.own_cur = 1 - s.own_cur;
+  return SUSP_OK;
+}
+
+static int read_flags(Sim &s, int32_t *out) {
+  HIPCHK(hipMemcpyAsync(out, s.flags, 4, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  HIPCHK(launch_fill_i32(s.flags, 1, 0, s.stream));
+  return SUSP_OK;
+}
+
+extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, size_t ws_bytes,
+                           susp_sim **out) {
+  if (!out) return fail(SUSP_EINVAL, "out is NULL");
+  *out = nullptr;
+  susp_sim *h = new susp_sim;
+  Sim &s = h->s;
+  memset(&s, 0, sizeof s);
+  int rc = resolve(p, s);
+  if (rc) { delete h; return rc; }
+  s.stream = (hipStream_t)stream;
+  const size_t need = carve(s, nullptr);
+  char *base = nullptr;
+  if (workspace) {
+    if (ws_bytes < need) { delete h; return fail(SUSP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need); }
+    if (((uintptr_t)workspace & 255) != 0) { delete h; return fail(SUSP_EINVAL, "workspace not 256-byte aligned"); }
+    base = (char *)workspace;
+    s.owns_block = 0;
+  } else {
+    hipError_t e = hipMalloc((void **)&base, need);
+    if (e != hipSuccess) { delete h; return fail(SUSP_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e)); }
+    s.owns_block = 1;
+  }
+  s.block = base;
+  carve(s, base);
+  auto bail = [&](int code) { susp_destroy(h); return code; };
+  const size_t n = (size_t)s.n;
+  if (n) {
+    std::vector<double> v(n * 4, 0.0), a(n), m(n), I(n), am(n);
+    const double PI = 3.14159265358979323846;
+    for (size_t i = 0; i < n; ++i) {
+      a[i] = p->radius[i];
+      m[i] = p->rho_p * (4.0 / 3.0) * PI * a[i] * a[i] * a[i];
+      I[i] = 0.4 * m[i] * a[i] * a[i];
+      am[i] = p->map_ratio * a[i];
+    }
+    for (int b = 0; b < 2; ++b) {
+      if (hipMemcpyAsync(s.R[b], p->pos, n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
+      std::vector<double> z(n * 3, 0.0);
+      if (hipMemcpyAsync(s.U[b], p->vel ? p->vel : z.data(), n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
+      if (hipMemcpyAsync(s.W[b], p->omega ? p->omega : z.data(), n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
+      for (size_t i = 0; i < n; ++i) v[4 * i] = 1.0;
+      if (hipMemcpyAsync(s.Q[b], v.data(), n * 32, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
+      if (hipStreamSynchronize(s.stream)) return bail(fail(SUSP_EDEVICE, "sync"));
+    }
+    if (hipMemcpy(s.a, a.data(), n * 8, hipMemcpyHostToDevice) || hipMemcpy(s.m, m.data(), n * 8, hipMemcpyHostToDevice) ||
+        hipMemcpy(s.I, I.data(), n * 8, hipMemcpyHostToDevice) || hipMemcpy(s.amap, am.data(), n * 8, hipMemcpyHostToDevice))
+      return bail(fail(SUSP_EDEVICE, "upload of radii"));
+  }
+  s.cur = 0; s.pcur = 0; s.hcur = 0; s.lcur = 0; s.hfin = 0; s.own_cur = 0; s.step = 0;
+  if (launch_init_populations(&s)) return bail(fail(SUSP_EDEVICE, "init populations"));
+  if (launch_fill_i32(s.gown, (size_t)2 * s.lx * s.lz, -1, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  for (int b = 0; b < 2; ++b) {
+    if (n && (launch_fill_f64(s.hyd[b], n * HYD, 0.0, s.stream) || launch_fill_i32(s.ncnt[b], n, 0, s.stream) ||
+              launch_fill_i32(s.hon[b], n * NCAP, 0, s.stream)))
+      return bail(fail(SUSP_EDEVICE, "fill"));
+  }
+  if (n && (launch_fill_f64(s.pst, n * PST, 0.0, s.stream) || launch_fill_f64(s.dp, n * 8, 0.0, s.stream) ||
+            launch_fill_i32(s.hstart, n * NCAP, 0, s.stream)))
+    return bail(fail(SUSP_EDEVICE, "fill"));
+  if (launch_fill_f64(s.acc, 128 + 128 * 32, 0.0, s.stream) || launch_fill_i32(s.flags, 64, 0, s.stream) ||
+      launch_fill_f64(s.pineq, (size_t)s.lbm_blocks * 6, 0.0, s.stream))
+    return bail(fail(SUSP_EDEVICE, "fill"));
+  if (launch_fill_i32(s.cell_start, (size_t)s.ncell + 1, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  rc = remap(s);
+  if (rc) return bail(rc);
+  int32_t fl = 0;
+  rc = read_flags(s, &fl);
+  if (rc) return bail(rc);
+  if (fl & 1) return bail(fail(SUSP_EUNSTABLE, "mapped spheres overlap in the initial state"));
+  *out = h;
+  return SUSP_OK;
+}
+
+extern "C" int susp_destroy(susp_sim *h) {
+  if (!h) return SUSP_OK;
+  if (h->s.owns_block && h->s.block) {
+    (void)hipStreamSynchronize(h->s.stream);
+    (void)hipFree(h->s.block);
+  }
+  delete h;
+  return SUSP_OK;
+}
+
+// One lattice step (see the header for the order of the parts).
+static int one_step(Sim &s) {
+  const int64_t t = s.step;
+  double off, ule, off1, ule1;
+  protocol(s, t, &off, &ule);
+  protocol(s, t + 1, &off1, &ule1);
+  const Box b = make_box(s, off, ule), b1 = make_box(s, off1, ule1);
+  s.hcur ^= 1;
+  if (s.n) HIPCHK(launch_fill_f64(s.hyd[s.hcur], (size_t)s.n * HYD, 0.0, s.stream));
+  if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
+  HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1));
+  HIPCHK(launch_lbm(&s, b));
+  s.cur ^= 1;
+  if (s.n) {
+    HIPCHK(launch_pairs(&s, b));
+    s.lcur ^= 1;
+    for (int k = 0; k < s.n_sub; ++k) {
+      HIPCHK(launch_substep(&s, b, k, off1, ule1));
+      s.pcur ^= 1;
+    }
+    s.hfin = (1 - s.hfin + s.n_sub) & 1;
+    HIPCHK(launch_map_claim(&s, b1, 1));
+    HIPCHK(launch_map_release(&s, b, b1));
+    s.own_cur ^= 1;
+  }
+  int gphase = 0;
+  double gc = 0, gsn = 0;
+  if (s.shear_kind == 2) {
+    const int64_t tI = (int64_t)s.ncyc_I * s.period, tF = tI + (int64_t)s.ncyc_F * s.period;
+    if (t >= tI && t < tF) {
+      const double om = 2.0 * 3.14159265358979323846 / (double)s.period;
+      const double ph = om * (double)(t - tI) + s.theta;
+      gphase = 1;
+      gc = cos(ph);
+      gsn = sin(ph);
+    }
+  }
+  HIPCHK(launch_stress(&s, gphase, gc, gsn));
+  s.step = t + 1;
+  return SUSP_OK;
+}
+
+extern "C" int susp_step(susp_sim *h, int64_t nsteps) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  if (nsteps < 0) return fail(SUSP_EINVAL, "negative step count");
+  Sim &s = h->s;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    int rc = one_step(s);
+    if (rc) return rc;
+  }
+  int32_t fl = 0;
+  int rc = read_flags(s, &fl);
+  if (rc) return rc;
+  if (fl) {
+    return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite, 4 neighbour overflow)", fl);
+  }
+  return SUSP_OK;
+}
+
+extern "C" int susp_stress(susp_sim *h, double out[5][6], double gg[2]) {
+  if (!h || !out || !gg) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  double acc[65];
+  HIPCHK(hipMemcpyAsync(acc, s.acc, sizeof acc, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  const double n = acc[60] > 0 ? acc[60] : 1.0;
+  for (int k = 0; k < 5; ++k)
+    for (int c = 0; c < 6; ++c) out[k][c] = acc[30 + 6 * k + c] / n;
+  if (acc[63] > 0 && s.g0_F != 0.0) {
+    const double cf = 2.0 / (acc[63] * s.g0_F);
+    gg[0] = -cf * acc[61];
+    gg[1] = cf * acc[62];
+  } else {
+    gg[0] = 0.0;
+    gg[1] = 0.0;
+  }
+  HIPCHK(launch_fill_f64(s.acc + 30, 31, 0.0, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+extern "C" int susp_get_populations(susp_sim *h, double *host) {
+  if (!h || !host) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  double *tmp = nullptr;
+  const size_t bytes = (size_t)NQ * s.nodes * 8;
+  HIPCHK(hipMalloc((void **)&tmp, bytes));
+  hipError_t e = launch_pop_convert(&s, tmp, 0);
+  if (!e) e = hipMemcpyAsync(host, tmp, bytes, hipMemcpyDeviceToHost, s.stream);
+  if (!e) e = hipStreamSynchronize(s.stream);
+  (void)hipFree(tmp);
+  if (e) return fail(SUSP_EDEVICE, "get_populations: %s", hipGetErrorString(e));
+  return SUSP_OK;
+}
+
+extern "C" int susp_set_populations(susp_sim *h, const double *host) {
+  if (!h || !host) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  double *tmp = nullptr;
+  const size_t bytes = (size_t)NQ * s.nodes * 8;
+  HIPCHK(hipStreamSynchronize(s.stream));
+  HIPCHK(hipMalloc((void **)&tmp, bytes));
+  hipError_t e = hipMemcpyAsync(tmp, host, bytes, hipMemcpyHostToDevice, s.stream);
+  if (!e) e = launch_pop_convert(&s, tmp, 1);
+  if (!e) e = hipStreamSynchronize(s.stream);
+  (void)hipFree(tmp);
+  if (e) return fail(SUSP_EDEVICE, "set_populations: %s", hipGetErrorString(e));
+  return SUSP_OK;
+}
+
+extern "C" int susp_get_particles(susp_sim *h, double *pos, double *vel, double *omega, double *quat) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  Sim &s = h->s;
+  const size_t n = (size_t)s.n;
+  if (!n) return SUSP_OK;
+  if (pos) HIPCHK(hipMemcpyAsync(pos, s.R[s.pcur], n * 24, hipMemcpyDeviceToHost, s.stream));
+  if (vel) HIPCHK(hipMemcpyAsync(vel, s.U[s.pcur], n * 24, hipMemcpyDeviceToHost, s.stream));
+  if (omega) HIPCHK(hipMemcpyAsync(omega, s.W[s.pcur], n * 24, hipMemcpyDeviceToHost, s.stream));
+  if (quat) HIPCHK(hipMemcpyAsync(quat, s.Q[s.pcur], n * 32, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+extern "C" int susp_set_particles(susp_sim *h, const double *pos, const double *vel,
+                                  const double *omega, const double *quat) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  Sim &s = h->s;
+  const size_t n = (size_t)s.n;
+  if (!n) return SUSP_OK;
+  if (pos)
+    for (size_t i = 0; i < n; ++i)
+      for (int c = 0; c < 3; ++c) {
+        const double L = c == 0 ? s.lx : (c == 1 ? s.ly : s.lz);
+        if (!(pos[3 * i + c] >= 0.0 && pos[3 * i + c] < L)) return fail(SUSP_EINVAL, "sphere %zu outside the box", i);
+      }
+  HIPCHK(hipStreamSynchronize(s.stream));
+  if (pos) HIPCHK(hipMemcpy(s.R[s.pcur], pos, n * 24, hipMemcpyHostToDevice));
+  if (vel) HIPCHK(hipMemcpy(s.U[s.pcur], vel, n * 24, hipMemcpyHostToDevice));
+  if (omega) HIPCHK(hipMemcpy(s.W[s.pcur], omega, n * 24, hipMemcpyHostToDevice));
+  if (quat) HIPCHK(hipMemcpy(s.Q[s.pcur], quat, n * 32, hipMemcpyHostToDevice));
+  int rc = remap(s);
+  if (rc) return rc;
+  int32_t fl = 0;
+  rc = read_flags(s, &fl);
+  if (rc) return rc;
+  if (fl & 1) return fail(SUSP_EUNSTABLE, "mapped spheres overlap");
+  return SUSP_OK;
+}
+
+extern "C" int susp_get_history(susp_sim *h, int32_t cap, int32_t *count, int32_t *oi, int32_t *oj,
+                                double *xi) {
+  if (!h || !count) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  const size_t n = (size_t)s.n;
+  *count = 0;
+  if (!n) return SUSP_OK;
+  std::vector<int32_t> cnt(n), nj(n * NCAP), on(n * NCAP);
+  std::vector<double> hx(n * NCAP * 3);
+  HIPCHK(hipMemcpyAsync(cnt.data(), s.ncnt[s.lcur], n * 4, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipMemcpyAsync(nj.data(), s.nj[s.lcur], n * NCAP * 4, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipMemcpyAsync(on.data(), s.hon[s.hfin], n * NCAP * 4, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipMemcpyAsync(hx.data(), s.hxi[s.hfin], n * NCAP * 24, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  int32_t k = 0;
+  for (size_t i = 0; i < n; ++i)
+    for (int u = 0; u < cnt[i]; ++u) {
+      const size_t e = i * NCAP + u;
+      if (nj[e] <= (int32_t)i || !on[e]) continue;
+      if (oi && k < cap) {
+        oi[k] = (int32_t)i;
+        if (oj) oj[k] = nj[e];
+        if (xi) { xi[3 * k] = hx[3 * e]; xi[3 * k + 1] = hx[3 * e + 1]; xi[3 * k + 2] = hx[3 * e + 2]; }
+      }
+      ++k;
+    }
+  *count = k;
+  return SUSP_OK;
+}
+
+extern "C" int susp_set_history(susp_sim *h, int32_t count, const int32_t *hi, const int32_t *hj,
+                                const double *xi) {
+  if (!h || count < 0 || (count > 0 && (!hi || !hj || !xi))) return fail(SUSP_EINVAL, "bad arguments");
+  Sim &s = h->s;
+  const size_t n = (size_t)s.n;
+  if (!n) return count ? fail(SUSP_EINVAL, "no spheres") : SUSP_OK;
+  std::vector<int32_t> cnt(n, 0), nj(n * NCAP, 0), on(n * NCAP, 0);
+  std::vector<double> hx(n * NCAP * 3, 0.0);
+  for (int32_t k = 0; k < count; ++k) {
+    const int32_t i = hi[k], j = hj[k];
+    if (i < 0 || j <= i || j >= (int32_t)n) return fail(SUSP_EINVAL, "history pair %d invalid", k);
+    if (cnt[i] >= NCAP) return fail(SUSP_EINVAL, "too many history pairs for sphere %d", i);
+    const size_t e = (size_t)i * NCAP + cnt[i]++;
+    nj[e] = j;
+    on[e] = 1;
+    hx[3 * e] = xi[3 * k]; hx[3 * e + 1] = xi[3 * k + 1]; hx[3 * e + 2] = xi[3 * k + 2];
+  }
+  HIPCHK(hipStreamSynchronize(s.stream));
+  HIPCHK(hipMemcpy(s.ncnt[s.lcur], cnt.data(), n * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s.nj[s.lcur], nj.data(), n * NCAP * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s.hon[s.hfin], on.data(), n * NCAP * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s.hxi[s.hfin], hx.data(), n * NCAP * 24, hipMemcpyHostToDevice));
+  return SUSP_OK;
+}
+
+extern "C" int susp_get_clock(susp_sim *h, int64_t *step, double *offset) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  double off, ule;
+  protocol(h->s, h->s.step, &off, &ule);
+  if (step) *step = h->s.step;
+  if (offset) *offset = off;
+  return SUSP_OK;
+}
+
+extern "C" int susp_set_clock(susp_sim *h, int64_t step) {
+  if (!h || step < 0) return fail(SUSP_EINVAL, "bad arguments");
+  HIPCHK(hipStreamSynchronize(h->s.stream));
+  h->s.step = step;
+  // re-map with the offset of the new clock; overlaps are reported by the next
+  // susp_set_particles or susp_step (positions are usually replaced right after)
+  int rc = remap(h->s);
+  if (rc) return rc;
+  int32_t fl = 0;
+  return read_flags(h->s, &fl);
+}
+
+extern "C" int susp_get_hydro(susp_sim *h, double *force, double *torque, double *stresslet,
+                              int32_t *nlinks) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  Sim &s = h->s;
+  const size_t n = (size_t)s.n;
+  if (!n) return SUSP_OK;
+  std::vector<double> v(n * HYD);
+  HIPCHK(hipMemcpyAsync(v.data(), s.hyd[s.hcur], n * HYD * 8, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  for (size_t i = 0; i < n; ++i) {
+    const double *a = &v[i * HYD];
+    for (int c = 0; c < 3; ++c) {
+      if (force) force[3 * i + c] = a[c];
+      if (torque) torque[3 * i + c] = a[3 + c];
+    }
+    for (int c = 0; c < 6; ++c)
+      if (stresslet) stresslet[6 * i + c] = a[6 + c];
+    if (nlinks) nlinks[i] = (int32_t)llround(a[12]);
+  }
+  return SUSP_OK;
+}
+
+extern "C" int susp_get_derived(susp_sim *h, double out[10]) {
+  if (!h || !out) return fail(SUSP_EINVAL, "NULL argument");
+  const Sim &s = h->s;
+  const double v[10] = {s.m0, s.kn, s.kt, s.eta_n, s.lub_delta, s.F0, s.lambda, s.eta0, s.a_min, s.a_max};
+  memcpy(out, v, sizeof v);
+  return SUSP_OK;
+}
+
+extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *bytes) {
+  if (!h || !bytes) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  const size_t n = (size_t)s.n;
+  std::vector<int32_t> out;
+  HIPCHK(hipStreamSynchronize(s.stream));
+  if (kind == SUSP_LIST_OWNER) {
+    out.resize((size_t)s.nodes);
+    HIPCHK(hipMemcpy(out.data(), s.own[s.own_cur], out.size() * 4, hipMemcpyDeviceToHost));
+  } else if (kind == SUSP_LIST_GHOST) {
+    out.resize((size_t)2 * s.lx * s.lz);
+    HIPCHK(hipMemcpy(out.data(), s.gown, out.size() * 4, hipMemcpyDeviceToHost));
+  } else if (kind == SUSP_LIST_CELLS) {
+    out.resize((size_t)s.ncell + 1 + n);
+    HIPCHK(hipMemcpy(out.data(), s.cell_start, ((size_t)s.ncell + 1) * 4, hipMemcpyDeviceToHost));
+    if (n) HIPCHK(hipMemcpy(out.data() + s.ncell + 1, s.cell_ids, n * 4, hipMemcpyDeviceToHost));
+  } else if (kind == SUSP_LIST_PAIRS || kind == SUSP_LIST_CONTACTS) {
+    if (n) {
+      std::vector<int32_t> cnt(n), nj(n * NCAP), hs(n * NCAP);
+      HIPCHK(hipMemcpy(cnt.data(), s.ncnt[s.lcur], n * 4, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(nj.data(), s.nj[s.lcur], n * NCAP * 4, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(hs.data(), s.hstart, n * NCAP * 4, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n; ++i)
+        for (int u = 0; u < cnt[i] && u < NCAP; ++u) {
+          const size_t e = i * NCAP + u;
+          if (nj[e] <= (int32_t)i) continue;
+          if (kind == SUSP_LIST_CONTACTS && !hs[e]) continue;
+          out.push_back((int32_t)i);
+          out.push_back(nj[e]);
+        }
+    }
+  } else if (kind == SUSP_LIST_LINKS) {
+    double off, ule;
+    protocol(s, s.step, &off, &ule);
+    const Box b = make_box(s, off, ule);
+    int32_t *g = nullptr, *lk = nullptr;
+    HIPCHK(hipMalloc((void **)&g, (size_t)2 * s.lx * s.lz * 4));
+    hipError_t e = hipMalloc((void **)&lk, (size_t)NQ * s.nodes * 4);
+    if (!e && n) e = launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr);
+    if (!e) e = n ? launch_ghosts(&s, b, g, s.gval, 0) : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
+    if (!e) e = launch_link_enum(&s, g, lk, b);
+    std::vector<int32_t> all;
+    if (!e) {
+      all.resize((size_t)NQ * s.nodes);
+      e = hipMemcpyAsync(all.data(), lk, all.size() * 4, hipMemcpyDeviceToHost, s.stream);
+    }
+    if (!e) e = hipStreamSynchronize(s.stream);
+    (void)hipFree(g);
+    (void)hipFree(lk);
+    if (e) return fail(SUSP_EDEVICE, "link enumeration: %s", hipGetErrorString(e));
+    for (int64_t node = 0; node < s.nodes; ++node)
+      for (int q = 1; q < NQ; ++q) {
+        const int32_t o = all[(size_t)q * s.nodes + node];
+        if (o >= 0) { out.push_back((int32_t)node); out.push_back(q); out.push_back(o); }
+      }
+  } else {
+    return fail(SUSP_EINVAL, "unknown list kind %d", kind);
+  }
+  const size_t need = out.size() * 4;
+  const size_t cap = *bytes;
+  *bytes = need;
+  if (host) {
+    if (cap < need) return fail(SUSP_EINVAL, "buffer of %zu bytes < %zu", cap, need);
+    memcpy(host, out.data(), need);
+  }
+  return SUSP_OK;
+}

@@ -1,0 +1,799 @@
+// particles.hip -- sphere-side kernels for gfx950 (all geometry and forces in FP64).
+//
+//  k_cells         cell list: cell of each sphere, counting sort, ascending ids per cell
+//  k_pairs         Lees-Edwards cell search -> neighbour list (ascending ids, both
+//                  directions), contact-at-start flags, spring history carried over
+//  k_substep       one DEM substep per sphere: contact (spring-dashpot + Cundall-Strack with
+//                  Coulomb cap, Sec. 2), DLVO (eq. 13), lubrication (App. A), eq. (1)
+//  k_map_claim     new mapped-sphere footprints; fluid nodes covered by a sphere give it
+//                  their mass and momentum
+//  k_map_release   old footprints; released nodes are refilled at equilibrium with the
+//                  surface velocity, the sphere pays that momentum; impulses applied
+//  k_reduce1/2     deterministic two-stage stress reduction (eqs. 12, 14, 15) and the
+//                  G', G'' quadratures (eqs. 17-18)
+#include "susp_impl.h"
+
+namespace susp {
+
+__global__ void k_fill_i32(int32_t *p, size_t n, int32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f64(double *p, size_t n, double v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st) {
+  if (!n) return hipSuccess;
+  size_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st) {
+  if (!n) return hipSuccess;
+  size_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+__device__ inline int cell_of(const Cells &C, double x, double y, double z) {
+  int a = (int)floor(x * C.ix), b = (int)floor(y * C.iy), c = (int)floor(z * C.iz);
+  a = a < 0 ? 0 : (a >= C.nx ? C.nx - 1 : a);
+  b = b < 0 ? 0 : (b >= C.ny ? C.ny - 1 : b);
+  c = c < 0 ? 0 : (c >= C.nz ? C.nz - 1 : c);
+  return a + C.nx * (b + C.ny * c);
+}
+
+// One work-group builds the whole cell list (counting sort, then ids sorted inside cells).
+__global__ __launch_bounds__(1024) void k_cells(const double *R, int n, Cells C, int ncell,
+                                                int32_t *start, int32_t *ids, int32_t *cnt) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int c = t; c < ncell; c += nt) cnt[c] = 0;
+  __syncthreads();
+  for (int i = t; i < n; i += nt) {
+    const int c = cell_of(C, R[3 * i], R[3 * i + 1], R[3 * i + 2]);
+    atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  // exclusive scan of cnt into start (chunked block scan)
+  __shared__ int32_t part[1024];
+  const int per = (ncell + nt - 1) / nt;
+  const int c0 = t * per, c1 = min(ncell, c0 + per);
+  int32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += cnt[c];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    int32_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = t > 0 ? part[t - 1] : 0;
+  for (int c = c0; c < c1; ++c) {
+    const int32_t k = cnt[c];
+    start[c] = run;
+    cnt[c] = run;  // becomes the fill cursor
+    run += k;
+  }
+  if (t == nt - 1) start[ncell] = part[nt - 1];
+  __syncthreads();
+  for (int i = t; i < n; i += nt) {
+    const int c = cell_of(C, R[3 * i], R[3 * i + 1], R[3 * i + 2]);
+    const int pos = atomicAdd(&cnt[c], 1);
+    ids[pos] = i;
+  }
+  __syncthreads();
+  for (int c = t; c < ncell; c += nt) {  // insertion sort inside each cell
+    const int a = start[c], b = start[c + 1];
+    for (int u = a + 1; u < b; ++u) {
+      const int32_t v = ids[u];
+      int w = u - 1;
+      while (w >= a && ids[w] > v) { ids[w + 1] = ids[w]; --w; }
+      ids[w + 1] = v;
+    }
+  }
+}
+
+hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch) {
+  hipLaunchKernelGGL(k_cells, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n, s->cells,
+                     s->ncell, cell_start, cell_ids, scratch);
+  return hipGetLastError();
+}
+
+// Visit the distinct cells that can hold spheres within one cell width of (px,py,pz).
+template <class F>
+__device__ inline void near_cells(const Cells &C, const Box &b, double px, double py, double pz,
+                                  F fn) {
+  int ccy = (int)floor(py * C.iy);
+  ccy = ccy < 0 ? 0 : (ccy >= C.ny ? C.ny - 1 : ccy);
+  int ccz = (int)floor(pz * C.iz);
+  ccz = ccz < 0 ? 0 : (ccz >= C.nz ? C.nz - 1 : ccz);
+  const int zn = C.nz >= 3 ? 3 : C.nz;
+  const int xn = C.nx >= 3 ? 3 : C.nx;
+  for (int dy = -1; dy <= 1; ++dy) {
+    int ny = ccy + dy;
+    double xs = px;
+    if (ny < 0) { ny += C.ny; xs = px + b.s; }
+    else if (ny >= C.ny) { ny -= C.ny; xs = px - b.s; }
+    xs = xs - b.Lx * floor(xs / b.Lx);
+    int ccx = (int)floor(xs * C.ix);
+    ccx = ccx < 0 ? 0 : (ccx >= C.nx ? C.nx - 1 : ccx);
+    for (int iz = 0; iz < zn; ++iz) {
+      int nz = C.nz >= 3 ? ccz + iz - 1 : iz;
+      nz = nz < 0 ? nz + C.nz : (nz >= C.nz ? nz - C.nz : nz);
+      for (int ix = 0; ix < xn; ++ix) {
+        int nx = C.nx >= 3 ? ccx + ix - 1 : ix;
+        nx = nx < 0 ? nx + C.nx : (nx >= C.nx ? nx - C.nx : nx);
+        fn(nx + C.nx * (ny + C.ny * nz));
+      }
+    }
+  }
+}
+
+// Pair geometry in the canonical order lo < hi: d = R_lo - R_hi (minimum image), k = image
+// index of hi.  Both spheres of a pair evaluate exactly the same expression.
+__device__ inline double pair_geo(const Box &b, const double *R, int lo, int hi, double &dx,
+                                  double &dy, double &dz, int &k) {
+  minimage(b, R[3 * lo] - R[3 * hi], R[3 * lo + 1] - R[3 * hi + 1], R[3 * lo + 2] - R[3 * hi + 2],
+           dx, dy, dz, k);
+  return dx * dx + dy * dy + dz * dz;
+}
+
+struct PairArgs {
+  const double *R, *a, *amap;
+  const int32_t *cell_start, *cell_ids;
+  Cells C;
+  Box b;
+  int n;
+  double cutoff;
+  int32_t *cnt, *nj;                 // new list
+  const int32_t *ocnt, *onj;         // list of the previous step
+  const double *oxi;                 // its final spring history
+  const int32_t *oon;
+  double *xi;                        // carried history for this step
+  int32_t *on, *hstart;
+  int32_t *flags;
+};
+
+__global__ void k_pairs(PairArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  int32_t js[NCAP];
+  int c = 0, over = 0, ovl = 0;
+  const double *R = A.R;
+  near_cells(A.C, A.b, R[3 * i], R[3 * i + 1], R[3 * i + 2], [&](int cell) {
+    for (int t = A.cell_start[cell]; t < A.cell_start[cell + 1]; ++t) {
+      const int j = A.cell_ids[t];
+      if (j == i) continue;
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      double dx, dy, dz;
+      int k;
+      const double r2 = pair_geo(A.b, R, lo, hi, dx, dy, dz, k);
+      const double rc = A.a[lo] + A.a[hi] + A.cutoff;
+      if (r2 < rc * rc) {
+        if (c < NCAP) js[c++] = j; else over = 1;
+        const double rm = A.amap[lo] + A.amap[hi];
+        if (r2 < rm * rm) ovl = 1;
+      }
+    }
+  });
+  for (int u = 1; u < c; ++u) {  // ascending partner ids
+    const int32_t v = js[u];
+    int w = u - 1;
+    while (w >= 0 && js[w] > v) { js[w + 1] = js[w]; --w; }
+    js[w + 1] = v;
+  }
+  if (over) atomicOr(A.flags, 4);
+  if (ovl) atomicOr(A.flags, 1);
+  A.cnt[i] = c;
+  const int oc = A.ocnt[i];
+  for (int u = 0; u < c; ++u) {
+    const int j = js[u];
+    const size_t e = (size_t)i * NCAP + u;
+    A.nj[e] = j;
+    if (j < i) continue;  // the history of a pair lives with its lower id
+    double x0 = 0, x1 = 0, x2 = 0;
+    int on = 0;
+    for (int v = 0; v < oc; ++v)
+      if (A.onj[(size_t)i * NCAP + v] == j) {
+        const size_t oe = (size_t)i * NCAP + v;
+        if (A.oon[oe]) { x0 = A.oxi[3 * oe]; x1 = A.oxi[3 * oe + 1]; x2 = A.oxi[3 * oe + 2]; on = 1; }
+        break;
+      }
+    A.xi[3 * e] = x0; A.xi[3 * e + 1] = x1; A.xi[3 * e + 2] = x2;
+    A.on[e] = on;
+    double dx, dy, dz;
+    int k;
+    const double r2 = pair_geo(A.b, R, i, j, dx, dy, dz, k);
+    A.hstart[e] = (sqrt(r2) - A.a[i] - A.a[j]) < 0.0 ? 1 : 0;
+  }
+}
+
+hipError_t launch_pairs(Sim *s, const Box &b) {
+  PairArgs A;
+  A.R = s->R[s->pcur]; A.a = s->a; A.amap = s->amap;
+  A.cell_start = s->cell_start; A.cell_ids = s->cell_ids;
+  A.C = s->cells; A.b = b; A.n = s->n; A.cutoff = s->pair_cutoff;
+  const int nl = 1 - s->lcur;
+  A.cnt = s->ncnt[nl]; A.nj = s->nj[nl];
+  A.ocnt = s->ncnt[s->lcur]; A.onj = s->nj[s->lcur];
+  A.oxi = s->hxi[s->hfin]; A.oon = s->hon[s->hfin];
+  A.xi = s->hxi[1 - s->hfin]; A.on = s->hon[1 - s->hfin];
+  A.hstart = s->hstart;
+  A.flags = s->flags;
+  if (s->n > 0)
+    hipLaunchKernelGGL(k_pairs, dim3((s->n + 127) / 128), dim3(128), 0, s->stream, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+struct Phys {
+  double kn, kt, eta_n, mu, delta, hc, F0, lambda, eta0, cutoff;
+  int lub_sub;
+};
+
+__device__ inline void crs(double ax, double ay, double az, double bx, double by, double bz,
+                           double &cx_, double &cy_, double &cz_) {
+  cx_ = ay * bz - az * by;
+  cy_ = az * bx - ax * bz;
+  cz_ = ax * by - ay * bx;
+}
+
+// Scalar resistance functions of App. A for the block of a sphere of radius a with partner
+// ratio b, at 1/xi (inv) and ln(1/xi) (lg).
+struct LubF {
+  double XA, YA, YB, XG, YG, YC, YCp, YH, YHp;
+};
+__device__ inline LubF lubf(double a, double b, double inv, double lg) {
+  const double PI = 3.14159265358979323846;
+  const double b1 = 1.0 + b;
+  LubF f;
+  f.XA = 6.0 * PI * a * (2.0 * b * b / (b1 * b1 * b1)) * inv;
+  f.YA = 6.0 * PI * a * (4.0 * b * (2.0 + b + 2.0 * b * b) / (15.0 * b1 * b1 * b1)) * lg;
+  f.YB = 4.0 * PI * a * a * (b * (4.0 + b) / (5.0 * b1 * b1)) * lg;
+  f.XG = 4.0 * PI * a * a * (3.0 * b * b / (b1 * b1 * b1)) * inv;
+  f.YG = 4.0 * PI * a * a * (b * (4.0 - b + 7.0 * b * b) / (10.0 * b1 * b1 * b1)) * lg;
+  f.YC = 8.0 * PI * a * a * a * (2.0 * b / (5.0 * b1)) * lg;
+  f.YCp = 8.0 * PI * a * a * a * (b * b / (10.0 * b1)) * lg;
+  f.YH = 8.0 * PI * a * a * a * (b * (2.0 - b) / (10.0 * b1 * b1)) * lg;
+  f.YHp = 8.0 * PI * a * a * a * (b * b * (1.0 + 7.0 * b) / (20.0 * b1 * b1)) * lg;
+  return f;
+}
+
+// All pair forces of (lo, hi): force on lo F, torques Tl, Th, spring update, stresses.
+struct PairOut {
+  double F[3], Tl[3], Th[3];
+  double vc[6], vr[6], sl[6];  // contact virial, DLVO virial (x -1/2 sym), stresslet sum
+  int on;
+};
+
+__device__ inline void sym_add(double *o, const double *a, const double *b, double w) {
+  o[0] += w * (2.0 * a[0] * b[0]);
+  o[1] += w * (2.0 * a[1] * b[1]);
+  o[2] += w * (2.0 * a[2] * b[2]);
+  o[3] += w * (a[0] * b[1] + b[0] * a[1]);
+  o[4] += w * (a[0] * b[2] + b[0] * a[2]);
+  o[5] += w * (a[1] * b[2] + b[1] * a[2]);
+}
+
+__device__ void pair_forces(const Phys &P, double ai, double aj, const double d[3],
+                            const double *Ui, const double Uj[3], const double *Wi,
+                            const double *Wj, double dt, double xi[3], int on_in, PairOut &o) {
+  for (int c = 0; c < 3; ++c) { o.F[c] = 0; o.Tl[c] = 0; o.Th[c] = 0; }
+  for (int c = 0; c < 6; ++c) { o.vc[c] = 0; o.vr[c] = 0; o.sl[c] = 0; }
+  (void)on_in;
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const double r = sqrt(r2);
+  const double h = r - ai - aj;
+  const double n[3] = {d[0] / r, d[1] / r, d[2] / r};
+  const double Uij[3] = {Ui[0] - Uj[0], Ui[1] - Uj[1], Ui[2] - Uj[2]};
+  double Fc[3] = {0, 0, 0};
+  // ---- contact: normal spring-dashpot, tangential spring with Coulomb cap ----
+  if (h < 0.0) {
+    const double vn = -(Uij[0] * n[0] + Uij[1] * n[1] + Uij[2] * n[2]);
+    const double fnm = P.kn * (-h) + P.eta_n * vn;
+    const double Fn[3] = {fnm * n[0], fnm * n[1], fnm * n[2]};
+    double awx = ai * Wi[0] + aj * Wj[0], awy = ai * Wi[1] + aj * Wj[1], awz = ai * Wi[2] + aj * Wj[2];
+    double wnx, wny, wnz;
+    crs(awx, awy, awz, n[0], n[1], n[2], wnx, wny, wnz);
+    const double v[3] = {Uij[0] - wnx, Uij[1] - wny, Uij[2] - wnz};
+    const double vdn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+    const double vt[3] = {v[0] - vdn * n[0], v[1] - vdn * n[1], v[2] - vdn * n[2]};
+    const double xn = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2];
+    const double xp[3] = {xi[0] - xn * n[0], xi[1] - xn * n[1], xi[2] - xn * n[2]};
+    const double mo = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+    const double mp = sqrt(xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2]);
+    if (mp > 0.0) {
+      const double sc = mo / mp;
+      xi[0] = xp[0] * sc; xi[1] = xp[1] * sc; xi[2] = xp[2] * sc;
+    } else {
+      xi[0] = xp[0]; xi[1] = xp[1]; xi[2] = xp[2];
+    }
+    xi[0] += vt[0] * dt; xi[1] += vt[1] * dt; xi[2] += vt[2] * dt;
+    double Ft[3] = {-P.kt * xi[0], -P.kt * xi[1], -P.kt * xi[2]};
+    const double ftm = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+    const double cap = P.mu * fabs(fnm);
+    if (ftm > cap) {
+      const double sc = cap / ftm;
+      Ft[0] *= sc; Ft[1] *= sc; Ft[2] *= sc;
+      xi[0] = -Ft[0] / P.kt; xi[1] = -Ft[1] / P.kt; xi[2] = -Ft[2] / P.kt;
+    }
+    for (int c = 0; c < 3; ++c) Fc[c] = Fn[c] + Ft[c];
+    crs(-ai * n[0], -ai * n[1], -ai * n[2], Ft[0], Ft[1], Ft[2], o.Tl[0], o.Tl[1], o.Tl[2]);
+    crs(-aj * n[0], -aj * n[1], -aj * n[2], Ft[0], Ft[1], Ft[2], o.Th[0], o.Th[1], o.Th[2]);
+    o.on = 1;
+  } else {
+    xi[0] = xi[1] = xi[2] = 0.0;
+    o.on = 0;
+  }
+  // ---- DLVO double-layer repulsion (eq. 13), gap clamped at contact ----
+  double Fr[3] = {0, 0, 0};
+  if (h < P.cutoff) {
+    const double hh = h > 0.0 ? h : 0.0;
+    const double f = P.F0 * exp(-hh / P.lambda);
+    Fr[0] = f * d[0] / r; Fr[1] = f * d[1] / r; Fr[2] = f * d[2] / r;
+  }
+  // ---- lubrication correction (App. A grand-resistance matrix, leading order) ----
+  double Fl[3] = {0, 0, 0};
+  if (h < P.hc) {
+    const double hh = h > 0.0 ? h : 0.0;
+    const double xg = 2.0 * (hh + P.delta) / (ai + aj);
+    double inv = 1.0 / xg, lg = log(1.0 / xg);
+    if (P.lub_sub) {
+      const double xc = 2.0 * (P.hc + P.delta) / (ai + aj);
+      inv = inv - 1.0 / xc;
+      lg = lg - log(1.0 / xc);
+    }
+    const LubF fi = lubf(ai, aj / ai, inv, lg);
+    const LubF fj = lubf(aj, ai / aj, inv, lg);
+    const double un = Uij[0] * n[0] + Uij[1] * n[1] + Uij[2] * n[2];
+    double wix, wiy, wiz, wjx, wjy, wjz, ux_, uy_, uz_;
+    crs(Wi[0], Wi[1], Wi[2], n[0], n[1], n[2], wix, wiy, wiz);
+    crs(Wj[0], Wj[1], Wj[2], n[0], n[1], n[2], wjx, wjy, wjz);
+    crs(Uij[0], Uij[1], Uij[2], n[0], n[1], n[2], ux_, uy_, uz_);
+    const double Wixn[3] = {wix, wiy, wiz}, Wjxn[3] = {wjx, wjy, wjz}, Uxn[3] = {ux_, uy_, uz_};
+    const double win = Wi[0] * n[0] + Wi[1] * n[1] + Wi[2] * n[2];
+    const double wjn = Wj[0] * n[0] + Wj[1] * n[1] + Wj[2] * n[2];
+    const double eta = P.eta0;
+    for (int c = 0; c < 3; ++c) {
+      const double AU = fi.XA * un * n[c] + fi.YA * (Uij[c] - un * n[c]);
+      Fl[c] = -eta * (AU - fi.YB * Wixn[c] - fj.YB * Wjxn[c]);
+      const double wip = Wi[c] - win * n[c], wjp = Wj[c] - wjn * n[c];
+      o.Tl[c] += -eta * (fi.YB * Uxn[c] + fi.YC * wip + fi.YCp * wjp);
+      o.Th[c] += -eta * (fj.YB * Uxn[c] + fi.YCp * wip + fj.YC * wjp);
+    }
+    double s1[6] = {0, 0, 0, 0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0};
+    double hi_[6] = {0, 0, 0, 0, 0, 0}, hj_[6] = {0, 0, 0, 0, 0, 0};
+    sym_add(s1, n, n, 0.5 * un);
+    s1[0] -= un / 3.0; s1[1] -= un / 3.0; s1[2] -= un / 3.0;
+    sym_add(s2, n, Uij, 1.0);
+    sym_add(s2, n, n, -un);
+    sym_add(hi_, Wixn, n, 1.0);
+    sym_add(hj_, Wjxn, n, 1.0);
+    for (int c = 0; c < 6; ++c) {
+      const double Si = -eta * (-(fi.XG * s1[c] + fi.YG * s2[c]) + fi.YH * hi_[c] + fi.YHp * hj_[c]);
+      const double Sj = -eta * (-(fj.XG * s1[c] + fj.YG * s2[c]) + fj.YHp * hi_[c] + fj.YH * hj_[c]);
+      o.sl[c] = Si + Sj;
+    }
+  }
+  for (int c = 0; c < 3; ++c) o.F[c] = Fc[c] + Fr[c] + Fl[c];
+  sym_add(o.vc, d, Fc, -0.5);
+  sym_add(o.vr, d, Fr, -0.5);
+}
+
+struct SubArgs {
+  const double *Ri, *Ui, *Wi, *Qi;
+  double *Ro, *Uo, *Wo, *Qo;
+  double *R0;
+  const double *a, *m, *I;
+  const double *hyd;
+  const int32_t *cnt, *nj;
+  const double *xin;
+  const int32_t *onin;
+  double *xout;
+  int32_t *onout;
+  double *pst;
+  Phys P;
+  Box b;
+  double dts, s1, ule1;
+  int n, sub, last, quasi2d;
+  int32_t *flags;
+};
+
+__global__ void k_substep(SubArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double Fp[3] = {0, 0, 0}, Tp[3] = {0, 0, 0};
+  double st[PST];
+  if (A.sub == 0) {
+    for (int c = 0; c < PST; ++c) st[c] = 0.0;
+    A.R0[3 * i] = A.Ri[3 * i]; A.R0[3 * i + 1] = A.Ri[3 * i + 1]; A.R0[3 * i + 2] = A.Ri[3 * i + 2];
+  } else {
+    for (int c = 0; c < PST; ++c) st[c] = A.pst[(size_t)i * PST + c];
+  }
+  const int c_i = A.cnt[i];
+  for (int u = 0; u < c_i; ++u) {
+    const int j = A.nj[(size_t)i * NCAP + u];
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    size_t e = (size_t)i * NCAP + u;
+    if (i != lo) {  // locate the entry of this pair in the lower sphere's list
+      const int cl = A.cnt[lo];
+      for (int v = 0; v < cl; ++v)
+        if (A.nj[(size_t)lo * NCAP + v] == i) { e = (size_t)lo * NCAP + v; break; }
+    }
+    double d[3];
+    int k;
+    pair_geo(A.b, A.Ri, lo, hi, d[0], d[1], d[2], k);
+    const double Uh[3] = {A.Ui[3 * hi] + k * A.b.ule, A.Ui[3 * hi + 1], A.Ui[3 * hi + 2]};
+    double xi[3] = {A.xin[3 * e], A.xin[3 * e + 1], A.xin[3 * e + 2]};
+    PairOut o;
+    pair_forces(A.P, A.a[lo], A.a[hi], d, &A.Ui[3 * lo], Uh, &A.Wi[3 * lo], &A.Wi[3 * hi], A.dts,
+                xi, A.onin[e], o);
+    if (i == lo) {
+      for (int c = 0; c < 3; ++c) { Fp[c] += o.F[c]; Tp[c] += o.Tl[c]; }
+      A.xout[3 * e] = xi[0]; A.xout[3 * e + 1] = xi[1]; A.xout[3 * e + 2] = xi[2];
+      A.onout[e] = o.on;
+      for (int c = 0; c < 6; ++c) { st[c] += o.sl[c]; st[6 + c] += o.vc[c]; st[12 + c] += o.vr[c]; }
+    } else {
+      for (int c = 0; c < 3; ++c) { Fp[c] -= o.F[c]; Tp[c] += o.Th[c]; }
+    }
+  }
+  for (int c = 0; c < PST; ++c) A.pst[(size_t)i * PST + c] = st[c];
+  // eq. (1), symplectic Euler with the hydrodynamic force and torque of this step
+  double U[3], W[3], R[3];
+  for (int c = 0; c < 3; ++c) {
+    U[c] = A.Ui[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + c] + Fp[c]) / A.m[i];
+    W[c] = A.Wi[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + 3 + c] + Tp[c]) / A.I[i];
+  }
+  if (A.quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
+  for (int c = 0; c < 3; ++c) R[c] = A.Ri[3 * i + c] + A.dts * U[c];
+  // orientation: q <- normalize(q + dt/2 (0, W) (x) q)
+  double qw = A.Qi[4 * i], qx = A.Qi[4 * i + 1], qy = A.Qi[4 * i + 2], qz = A.Qi[4 * i + 3];
+  const double dw = -(W[0] * qx + W[1] * qy + W[2] * qz);
+  const double dx = W[0] * qw + (W[1] * qz - W[2] * qy);
+  const double dy = W[1] * qw + (W[2] * qx - W[0] * qz);
+  const double dz = W[2] * qw + (W[0] * qy - W[1] * qx);
+  qw += 0.5 * A.dts * dw; qx += 0.5 * A.dts * dx; qy += 0.5 * A.dts * dy; qz += 0.5 * A.dts * dz;
+  const double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  if (A.last) {  // Lees-Edwards wrap with the offset of the next step
+    if (R[1] >= A.b.Ly) { R[1] -= A.b.Ly; R[0] -= A.s1; U[0] -= A.ule1; }
+    else if (R[1] < 0.0) { R[1] += A.b.Ly; R[0] += A.s1; U[0] += A.ule1; }
+    for (int it = 0; it < 4 && R[0] >= A.b.Lx; ++it) R[0] -= A.b.Lx;
+    for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += A.b.Lx;
+    for (int it = 0; it < 4 && R[2] >= A.b.Lz; ++it) R[2] -= A.b.Lz;
+    for (int it = 0; it < 4 && R[2] < 0.0; ++it) R[2] += A.b.Lz;
+  }
+  for (int c = 0; c < 3; ++c) { A.Uo[3 * i + c] = U[c]; A.Wo[3 * i + c] = W[c]; A.Ro[3 * i + c] = R[c]; }
+  A.Qo[4 * i] = qw / nn; A.Qo[4 * i + 1] = qx / nn; A.Qo[4 * i + 2] = qy / nn; A.Qo[4 * i + 3] = qz / nn;
+  if (A.last) {
+    bool ok = true;
+    for (int c = 0; c < 3; ++c) ok = ok && isfinite(R[c]) && isfinite(U[c]) && isfinite(W[c]);
+    if (!ok) atomicOr(A.flags, 2);
+  }
+}
+
+hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1) {
+  SubArgs A;
+  const int pi = s->pcur, po = 1 - s->pcur;
+  A.Ri = s->R[pi]; A.Ui = s->U[pi]; A.Wi = s->W[pi]; A.Qi = s->Q[pi];
+  A.Ro = s->R[po]; A.Uo = s->U[po]; A.Wo = s->W[po]; A.Qo = s->Q[po];
+  A.R0 = s->R0;
+  A.a = s->a; A.m = s->m; A.I = s->I;
+  A.hyd = s->hyd[s->hcur];
+  A.cnt = s->ncnt[s->lcur]; A.nj = s->nj[s->lcur];
+  // history ping-pong: substep k reads buffer (start + k) % 2
+  const int hin = (1 - s->hfin + sub) & 1;
+  A.xin = s->hxi[hin]; A.onin = s->hon[hin];
+  A.xout = s->hxi[1 - hin]; A.onout = s->hon[1 - hin];
+  A.pst = s->pst;
+  A.P.kn = s->kn; A.P.kt = s->kt; A.P.eta_n = s->eta_n; A.P.mu = s->mu;
+  A.P.delta = s->lub_delta; A.P.hc = s->lub_hc; A.P.F0 = s->F0; A.P.lambda = s->lambda;
+  A.P.eta0 = s->eta0; A.P.cutoff = s->pair_cutoff; A.P.lub_sub = s->lub_sub;
+  A.b = b;
+  A.dts = 1.0 / (double)s->n_sub;
+  A.s1 = s1; A.ule1 = ule1;
+  A.n = s->n; A.sub = sub; A.last = sub == s->n_sub - 1; A.quasi2d = s->quasi2d;
+  A.flags = s->flags;
+  if (s->n > 0)
+    hipLaunchKernelGGL(k_substep, dim3((s->n + 63) / 64), dim3(64), 0, s->stream, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Candidate boxes of a sphere's mapped footprint: three Lees-Edwards image boxes.
+struct Foot {
+  int xlo[3], nxk[3], ylo[3], nyk[3], zlo, nzk;
+  int tot[3];
+};
+
+__device__ inline void cand(double c, double r, int L, int &lo, int &cnt) {
+  int a = (int)ceil(c - r - 1e-6), b = (int)floor(c + r + 1e-6);
+  if (b - a + 1 >= L) { a = 0; b = L - 1; }
+  lo = a;
+  cnt = b - a + 1;
+}
+
+__device__ inline void footprint(const Box &bx, const double *R, int p, double r, Foot &f) {
+  cand(R[3 * p + 2], r, bx.lz, f.zlo, f.nzk);
+  for (int k = -1; k <= 1; ++k) {
+    const double cyy = R[3 * p + 1] + k * bx.Ly;
+    const double cxx = R[3 * p] + k * bx.s;
+    int ylo = (int)ceil(cyy - r - 1e-6), yhi = (int)floor(cyy + r + 1e-6);
+    if (ylo < 0) ylo = 0;
+    if (yhi > bx.ly - 1) yhi = bx.ly - 1;
+    const int t = k + 1;
+    f.ylo[t] = ylo;
+    f.nyk[t] = yhi >= ylo ? yhi - ylo + 1 : 0;
+    cand(cxx, r, bx.lx, f.xlo[t], f.nxk[t]);
+    f.tot[t] = f.nyk[t] * f.nxk[t] * f.nzk;
+  }
+}
+
+// Decode candidate t; returns true with the node and its displacement if inside sphere p.
+__device__ inline bool foot_node(const Box &bx, const double *R, int p, double r, const Foot &f,
+                                 int t, int64_t &node, double d[3], int &kk) {
+  int k = 0;
+  while (t >= f.tot[k]) { t -= f.tot[k]; ++k; }
+  const int nx = f.nxk[k], ny = f.nyk[k];
+  const int ix = t % nx;
+  const int iy = (t / nx) % ny;
+  const int iz = t / (nx * ny);
+  int x = f.xlo[k] + ix, y = f.ylo[k] + iy, z = f.zlo + iz;
+  x %= bx.lx; x = x < 0 ? x + bx.lx : x;
+  z %= bx.lz; z = z < 0 ? z + bx.lz : z;
+  minimage(bx, (double)x - R[3 * p], (double)y - R[3 * p + 1], (double)z - R[3 * p + 2], d[0],
+           d[1], d[2], kk);
+  if (kk != k - 1) return false;
+  if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < r * r)) return false;
+  node = x + (int64_t)bx.lx * (y + (int64_t)bx.ly * z);
+  return true;
+}
+
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *sh /*[NV][blockDim/64]*/) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = 0; c < NV; ++c) {
+    double x = v[c];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sh[c * 16 + wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < NV; ++c) {
+      double x = 0;
+      for (int w = 0; w < nw; ++w) x += sh[c * 16 + w];
+      v[c] = x;
+    }
+  __syncthreads();
+}
+
+template <class ST>
+__device__ inline double ldpop(const void *f, size_t i, int q, const float *tab) {
+  return (double)Store<ST>::ld((const ST *)f, i, q, tab);
+}
+
+struct MapArgs {
+  const double *R, *U, *W;  // state after the move
+  const double *R0;         // state before the move (release only)
+  const double *amap, *m, *I;
+  double *Uw, *Ww;          // written by release (impulses)
+  int32_t *own_new;
+  int32_t *own_old;
+  void *f;
+  size_t plane;
+  Box bnew, bold;
+  double rho0;
+  int covers, quasi2d;
+  double *dp;
+  int32_t *flags;
+  float tab[2 * NQ];
+};
+
+template <class ST>
+__global__ __launch_bounds__(256) void k_map_claim(MapArgs A) {
+  const int p = blockIdx.x;
+  const double r = A.amap[p];
+  if (!(isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2]))) {
+    if (threadIdx.x == 0) atomicOr(A.flags, 2);
+    return;
+  }
+  Foot f;
+  footprint(A.bnew, A.R, p, r, f);
+  const int tot = f.tot[0] + f.tot[1] + f.tot[2];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    int64_t node;
+    double d[3];
+    int kk;
+    if (!foot_node(A.bnew, A.R, p, r, f, t, node, d, kk)) continue;
+    const int32_t old = atomicCAS(&A.own_new[node], -1, p);
+    if (old != -1 && old != p) { atomicMin(&A.own_new[node], p); atomicOr(A.flags, 1); }
+    if (!A.covers || A.own_old[node] != -1) continue;
+    // covered: the node's fluid mass and momentum go to the sphere
+    double rho = 0, j0 = 0, j1 = 0, j2 = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double v = wq(q) * A.rho0 + ldpop<ST>(A.f, (size_t)q * A.plane + node, q, A.tab);
+      rho += v; j0 += v * cx(q); j1 += v * cy(q); j2 += v * cz(q);
+    }
+    j0 -= rho * kk * A.bnew.ule;
+    acc[0] += j0; acc[1] += j1; acc[2] += j2;
+    acc[3] += d[1] * j2 - d[2] * j1;
+    acc[4] += d[2] * j0 - d[0] * j2;
+    acc[5] += d[0] * j1 - d[1] * j0;
+    acc[6] += rho;
+  }
+  __shared__ double sh[7 * 16];
+  block_sum<7>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 7; ++c) A.dp[(size_t)p * 8 + c] = acc[c];
+}
+
+template <class ST>
+__global__ __launch_bounds__(256) void k_map_release(MapArgs A) {
+  using CT = typename Store<ST>::CT;
+  const int p = blockIdx.x;
+  const double r = A.amap[p];
+  if (!(isfinite(A.R0[3 * p]) && isfinite(A.R0[3 * p + 1]) && isfinite(A.R0[3 * p + 2]) &&
+        isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2]))) {
+    if (threadIdx.x == 0) atomicOr(A.flags, 2);
+    return;
+  }
+  Foot f;
+  footprint(A.bold, A.R0, p, r, f);
+  const int tot = f.tot[0] + f.tot[1] + f.tot[2];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    int64_t node;
+    double d0[3];
+    int k0;
+    if (!foot_node(A.bold, A.R0, p, r, f, t, node, d0, k0)) continue;
+    if (A.own_new[node] == -1) {
+      // released: equilibrium at rho0 and the surface velocity of the moved sphere
+      double d[3];
+      int k;
+      minimage(A.bnew, (double)(node % A.bnew.lx) - A.R[3 * p],
+               (double)((node / A.bnew.lx) % A.bnew.ly) - A.R[3 * p + 1],
+               (double)(node / ((int64_t)A.bnew.lx * A.bnew.ly)) - A.R[3 * p + 2], d[0], d[1],
+               d[2], k);
+      const double *W = &A.W[3 * p];
+      const double ub0 = A.U[3 * p] + (W[1] * d[2] - W[2] * d[1]);
+      const double ub1 = A.U[3 * p + 1] + (W[2] * d[0] - W[0] * d[2]);
+      const double ub2 = A.U[3 * p + 2] + (W[0] * d[1] - W[1] * d[0]);
+      const double ux = ub0 + k * A.bnew.ule;
+      const double uu = ux * ux + ub1 * ub1 + ub2 * ub2;
+      ST *fs = (ST *)A.f;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double cu = cx(q) * ux + cy(q) * ub1 + cz(q) * ub2;
+        const double dv = wq(q) * A.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        Store<ST>::st(fs, (size_t)q * A.plane + node, (CT)dv, q, A.tab);
+      }
+      const double j0 = A.rho0 * ub0, j1 = A.rho0 * ub1, j2 = A.rho0 * ub2;
+      acc[0] -= j0; acc[1] -= j1; acc[2] -= j2;
+      acc[3] -= d[1] * j2 - d[2] * j1;
+      acc[4] -= d[2] * j0 - d[0] * j2;
+      acc[5] -= d[0] * j1 - d[1] * j0;
+      acc[6] -= A.rho0;
+    }
+    A.own_old[node] = -1;  // the old map becomes the next spare (all fluid)
+  }
+  __shared__ double sh[7 * 16];
+  block_sum<7>(acc, sh);
+  if (threadIdx.x == 0) {
+    double *dp = &A.dp[(size_t)p * 8];
+    for (int c = 0; c < 7; ++c) dp[c] += acc[c];
+    double U[3], W[3];
+    for (int c = 0; c < 3; ++c) {
+      U[c] = A.U[3 * p + c] + dp[c] / A.m[p];
+      W[c] = A.W[3 * p + c] + dp[3 + c] / A.I[p];
+    }
+    if (A.quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
+    for (int c = 0; c < 3; ++c) { A.Uw[3 * p + c] = U[c]; A.Ww[3 * p + c] = W[c]; }
+  }
+}
+
+hipError_t launch_map_claim(Sim *s, const Box &bnew, int covers) {
+  MapArgs A;
+  A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
+  A.R0 = s->R0; A.amap = s->amap; A.m = s->m; A.I = s->I;
+  A.Uw = s->U[s->pcur]; A.Ww = s->W[s->pcur];
+  A.own_new = s->own[1 - s->own_cur];
+  A.own_old = s->own[s->own_cur];
+  A.f = s->f[s->cur]; A.plane = s->plane;
+  A.bnew = bnew; A.bold = bnew;
+  A.rho0 = s->rho0; A.covers = covers; A.quasi2d = s->quasi2d;
+  A.dp = s->dp; A.flags = s->flags;
+  for (int i = 0; i < 2 * NQ; ++i) A.tab[i] = s->fp16_tab[i];
+  if (s->n == 0) return hipSuccess;
+  if (s->precision == 0) hipLaunchKernelGGL(k_map_claim<double>, dim3(s->n), dim3(256), 0, s->stream, A);
+  else if (s->precision == 1) hipLaunchKernelGGL(k_map_claim<float>, dim3(s->n), dim3(256), 0, s->stream, A);
+  else hipLaunchKernelGGL(k_map_claim<__half>, dim3(s->n), dim3(256), 0, s->stream, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_release(Sim *s, const Box &bold, const Box &bnew) {
+  MapArgs A;
+  A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
+  A.R0 = s->R0; A.amap = s->amap; A.m = s->m; A.I = s->I;
+  A.Uw = s->U[s->pcur]; A.Ww = s->W[s->pcur];
+  A.own_new = s->own[1 - s->own_cur];
+  A.own_old = s->own[s->own_cur];
+  A.f = s->f[s->cur]; A.plane = s->plane;
+  A.bnew = bnew; A.bold = bold;
+  A.rho0 = s->rho0; A.covers = 1; A.quasi2d = s->quasi2d;
+  A.dp = s->dp; A.flags = s->flags;
+  for (int i = 0; i < 2 * NQ; ++i) A.tab[i] = s->fp16_tab[i];
+  if (s->n == 0) return hipSuccess;
+  if (s->precision == 0) hipLaunchKernelGGL(k_map_release<double>, dim3(s->n), dim3(256), 0, s->stream, A);
+  else if (s->precision == 1) hipLaunchKernelGGL(k_map_release<float>, dim3(s->n), dim3(256), 0, s->stream, A);
+  else hipLaunchKernelGGL(k_map_release<__half>, dim3(s->n), dim3(256), 0, s->stream, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Stress reduction.  Stage 1: block b sums a contiguous slice of the lattice-block partials
+// and of the spheres into part[b][32]; stage 2 (one block) adds the slices in order.
+constexpr int RED_BLOCKS = 128;
+constexpr int RED_W = 32;  // pineq 6 | hydro stresslet 6 | pair 18 | ledger 1 | pad
+
+__global__ __launch_bounds__(256) void k_reduce1(const double *pineq, int nblk, const double *hyd,
+                                                 const double *pst, const double *dp, int n,
+                                                 double *part) {
+  double v[31];
+  for (int c = 0; c < 31; ++c) v[c] = 0.0;
+  const int b = blockIdx.x;
+  const int pb0 = (int)((int64_t)nblk * b / RED_BLOCKS), pb1 = (int)((int64_t)nblk * (b + 1) / RED_BLOCKS);
+  for (int t = pb0 + threadIdx.x; t < pb1; t += blockDim.x)
+    for (int c = 0; c < 6; ++c) v[c] += pineq[(size_t)t * 6 + c];
+  const int s0 = (int)((int64_t)n * b / RED_BLOCKS), s1 = (int)((int64_t)n * (b + 1) / RED_BLOCKS);
+  for (int p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
+    for (int c = 0; c < 6; ++c) v[6 + c] += hyd[(size_t)p * HYD + 6 + c];
+    for (int c = 0; c < PST; ++c) v[12 + c] += pst[(size_t)p * PST + c];
+    v[30] += dp[(size_t)p * 8 + 6];
+  }
+  __shared__ double sh[31 * 16];
+  block_sum<31>(v, sh);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 31; ++c) part[(size_t)b * RED_W + c] = v[c];
+}
+
+// acc layout: [0,30) sig_last, [30,60) sig_sum, 60 count, 61 gp_cos, 62 gp_sin, 63 gp_count,
+// 64 ledger
+__global__ void k_reduce2(const double *part, double *acc, double cf, double invV, double invns,
+                          int gphase, double gcos, double gsin, int has_particles) {
+  if (threadIdx.x != 0) return;
+  double v[31];
+  for (int c = 0; c < 31; ++c) v[c] = 0.0;
+  for (int b = 0; b < RED_BLOCKS; ++b)
+    for (int c = 0; c < 31; ++c) v[c] += part[(size_t)b * RED_W + c];
+  double sig[30];
+  for (int c = 0; c < 6; ++c) {
+    sig[c] = cf * v[c];
+    sig[6 + c] = has_particles ? v[6 + c] * invV : 0.0;
+    sig[12 + c] = v[12 + c] * invV * invns;  // lubrication
+    sig[18 + c] = v[18 + c] * invV * invns;  // contact
+    sig[24 + c] = v[24 + c] * invV * invns;  // DLVO
+  }
+  double sxy = 0;
+  for (int k = 0; k < 5; ++k) sxy += sig[6 * k + 3];
+  for (int c = 0; c < 30; ++c) { acc[c] = sig[c]; acc[30 + c] += sig[c]; }
+  acc[60] += 1.0;
+  if (gphase) { acc[61] += sxy * gcos; acc[62] += sxy * gsin; acc[63] += 1.0; }
+  acc[64] += v[30];
+}
+
+hipError_t launch_stress(Sim *s, int gphase, double gcos, double gsin) {
+  double *part = s->acc + 128;
+  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, s->stream, s->pineq,
+                     s->lbm_blocks, s->hyd[s->hcur], s->pst, s->dp, s->n, part);
+  const double V = (double)s->lx * s->ly * s->lz;
+  const double cf = -(1.0 - 0.5 / s->tau) / V;
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, 1.0 / V,
+                     1.0 / (double)s->n_sub, gphase, gcos, gsin, s->n > 0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace susp

@@ -1,0 +1,177 @@
+// susp_impl.h -- internal declarations of the MI355X suspension library (not installed).
+//
+// Device layout of one simulation (all carved from one 256-byte aligned block):
+//   populations   2 x 19 planes x nodes, storage type (double | float | half), each plane
+//                 padded to 256 B; a plane holds deviations d_q = n_q - w_q rho0 (FP16:
+//                 d_q / w_q * 2^k) of the post-collision state, x fastest.
+//   owner maps    2 x nodes int32 (current map, spare map kept all -1)
+//   ghost planes  owner int32 [2][lz][lx]; values [2][5][lz][lx] in compute precision
+//   particles     FP64 arrays (positions, velocities, spins, quaternions, radii, ...)
+//   lists         cell list, fixed-capacity neighbour lists (NCAP per sphere), spring
+//                 history per neighbour entry
+//   reductions    per-block fluid stress partials, per-sphere hydrodynamic and pair-stress
+//                 accumulators, global stress/G' accumulators, flags
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace susp {
+
+constexpr int NQ = 19;
+constexpr int NCAP = 48;        // neighbour capacity per sphere
+constexpr int LBM_BLOCK = 256;  // nodes per lattice block
+constexpr int HYD = 13;         // F[3] T[3] S[6] nlinks  (per-sphere hydrodynamic sums)
+constexpr int PST = 18;         // lubrication, contact, DLVO stress partials (6 each)
+
+// D3Q19: 0 rest, 1..6 axes, 7..18 face diagonals; opposite of odd q is q+1.
+__host__ __device__ constexpr int cx(int q) {
+  return q == 1 || q == 7 || q == 9 || q == 11 || q == 13 ? 1
+       : q == 2 || q == 8 || q == 10 || q == 12 || q == 14 ? -1 : 0;
+}
+__host__ __device__ constexpr int cy(int q) {
+  return q == 3 || q == 7 || q == 10 || q == 15 || q == 17 ? 1
+       : q == 4 || q == 8 || q == 9 || q == 16 || q == 18 ? -1 : 0;
+}
+__host__ __device__ constexpr int cz(int q) {
+  return q == 5 || q == 11 || q == 14 || q == 15 || q == 18 ? 1
+       : q == 6 || q == 12 || q == 13 || q == 16 || q == 17 ? -1 : 0;
+}
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr double wq(int q) { return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// slot of q among the five directions crossing the y boundary (c_y = +1 or -1)
+__host__ __device__ constexpr int gslot(int q) {
+  return q == 3 || q == 4 ? 0 : q == 7 || q == 8 ? 1 : q == 10 || q == 9 ? 2 : q == 15 || q == 16 ? 3 : 4;
+}
+__host__ __device__ constexpr int gdir(int g, int m) {  // g=0: c_y=+1 set, g=1: c_y=-1 set
+  return g == 0 ? (m == 0 ? 3 : m == 1 ? 7 : m == 2 ? 10 : m == 3 ? 15 : 17)
+                : (m == 0 ? 4 : m == 1 ? 8 : m == 2 ? 9 : m == 3 ? 16 : 18);
+}
+
+// Box and Lees-Edwards state for geometric predicates (FP64, fixed operation order).
+struct Box {
+  int lx, ly, lz;
+  double Lx, Ly, Lz;
+  double s;    // offset of the image above (x shift of the box at +Ly)
+  double ule;  // its velocity
+};
+
+// Minimum-image displacement d = point - particle; k = image index of the particle
+// (its image sits at R + k (s, Ly, 0) and moves with U + k ule x).
+__host__ __device__ inline void minimage(const Box &b, double dx, double dy, double dz,
+                                         double &ox, double &oy, double &oz, int &k) {
+  k = 0;
+  if (dy > 0.5 * b.Ly) { dy -= b.Ly; dx -= b.s; k = 1; }
+  else if (dy < -0.5 * b.Ly) { dy += b.Ly; dx += b.s; k = -1; }
+  // at most a few periods apart for finite input; the bound keeps non-finite input finite-time
+  for (int it = 0; it < 4 && dx > 0.5 * b.Lx; ++it) dx -= b.Lx;
+  for (int it = 0; it < 4 && dx < -0.5 * b.Lx; ++it) dx += b.Lx;
+  for (int it = 0; it < 4 && dz > 0.5 * b.Lz; ++it) dz -= b.Lz;
+  for (int it = 0; it < 4 && dz < -0.5 * b.Lz; ++it) dz += b.Lz;
+  ox = dx; oy = dy; oz = dz;
+}
+
+// Storage of population deviations.
+template <class ST> struct Store;
+template <> struct Store<double> {
+  using CT = double;
+  __device__ static double ld(const double *p, size_t i, int, const float *) { return p[i]; }
+  __device__ static void st(double *p, size_t i, double v, int, const float *) { p[i] = v; }
+};
+template <> struct Store<float> {
+  using CT = float;
+  __device__ static float ld(const float *p, size_t i, int, const float *) { return p[i]; }
+  __device__ static void st(float *p, size_t i, float v, int, const float *) { p[i] = v; }
+};
+// FP16: h = half(d * sc[q]) with sc[q] = 2^k / w_q; d = float(h) * isc[q].
+template <> struct Store<__half> {
+  using CT = float;
+  __device__ static float ld(const __half *p, size_t i, int q, const float *isc) {
+    return __half2float(p[i]) * isc[q];
+  }
+  __device__ static void st(__half *p, size_t i, float v, int q, const float *sc) {
+    p[i] = __float2half_rn(v * sc[NQ + q]);
+  }
+};
+
+// Cell grid for the neighbour search.
+struct Cells {
+  int nx, ny, nz;
+  double ix, iy, iz;  // cells per unit length (n / L)
+};
+
+struct Sim;
+
+// ---- launchers (fluid.hip) ----
+hipError_t launch_init_populations(Sim *s);
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values);
+hipError_t launch_lbm(Sim *s, const Box &b);
+hipError_t launch_pop_convert(Sim *s, double *dev64, int to_storage);
+hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[19][nodes]*/, const Box &b);
+// ---- launchers (particles.hip) ----
+hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch);
+hipError_t launch_pairs(Sim *s, const Box &b);
+hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1);
+hipError_t launch_map_claim(Sim *s, const Box &bnew, int covers);
+hipError_t launch_map_release(Sim *s, const Box &bold, const Box &bnew);
+hipError_t launch_stress(Sim *s, int gphase, double gcos, double gsin);
+hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
+
+struct Sim {
+  // problem
+  int lx, ly, lz, precision;
+  int64_t nodes;
+  size_t plane;  // elements per population plane (padded)
+  int n;
+  double tau, rho0;
+  double map_ratio, rho_p;
+  double m0, kn, kt, eta_n, lub_delta, F0, lambda, eta0, a_min, a_max;
+  double mu, lub_hc, pair_cutoff;
+  int lub_sub, n_sub, quasi2d;
+  int shear_kind;
+  double gamma_dot, g0_I, g0_F, theta;
+  int period, ncyc_I, ncyc_F;
+  int fp16_exp;
+  float fp16_tab[2 * NQ];  // isc[19], sc[19]
+  Cells cells;
+  int ncell;
+  int lbm_blocks;
+  // device block
+  void *block;
+  int owns_block;
+  hipStream_t stream;
+  // populations
+  void *f[2];
+  int cur;  // index of the buffer holding the current state
+  int32_t *own[2];
+  int own_cur;
+  int32_t *gown;
+  void *gval;
+  // particles (FP64)
+  double *R[2], *U[2], *W[2], *Q[2];
+  int pcur;  // current particle buffer
+  double *R0;
+  double *a, *m, *I, *amap;
+  double *hyd[2];
+  int hcur;
+  double *pst;   // [n][PST]
+  double *dp;    // [n][8] cover/uncover momentum, angular momentum, mass
+  // lists
+  int32_t *cell_start, *cell_ids, *cell_scr;
+  int32_t *ncnt[2], *nj[2];  // neighbour count [n], neighbour ids [n][NCAP]
+  int lcur;                  // list of the last step
+  double *hxi[3];            // spring vector per entry [n][NCAP][3]
+  int32_t *hon[3];           // contact flag per entry
+  int32_t *hstart;           // contact at the start of the step per entry
+  int hfin;                  // history buffer holding the final state of the last step
+  // reductions
+  double *pineq;  // [lbm_blocks][6]
+  double *acc;    // sig_last[30] sig_sum[30] count gp_cos gp_sin gp_count ledger
+  int32_t *flags;
+  // clock
+  int64_t step;
+};
+
+}  // namespace susp

@@ -1,0 +1,184 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+One-step parity starts both sides from the same oracle-made state, rounded on the host to
+the storage precision exactly as the library stores it, and compares:
+  - lists bit-exactly: owner map, ghost owners, cell list, neighbour pairs, contacts at the
+    start of the step, per-sphere boundary-link counts, the link list;
+  - fields to the per-step tolerance: 1e-12 (FP64), 1e-6 (FP32), 1e-3 (FP16 storage) on
+    density, velocity, particle force/torque/velocity, spring history and stress.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import parity_util as PU
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-6, 2: 1e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_02929_amd import susp
+    susp.lib()
+    yield
+
+
+def _announce(msg):
+    print("\n[parity] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _one_step_parity(box, pos, vel, om, rad, kw, precision, presteps):
+    from paper_1904_02929_amd import susp
+    o = PU.oracle_for(box, kw, pos, vel, om, rad)
+    assert o.step(presteps) == 0
+    g = PU.gpu_for(box, kw, pos, vel, om, rad, precision)
+    PU.load_oracle_state(o, g, precision)
+    R0 = o.part("R").copy()
+    s0 = o.s.s_next
+    o.stress(); g.stress()
+    _announce("one step from oracle step %d, precision %d, box %s, n=%d" % (o.s.step, precision, box, len(rad)))
+    # link list of the start state vs an enumeration of the oracle's map and ghost points
+    links_g = g.lists(susp.LIST_LINKS)
+    rc_o = o.step(1)
+    rc_g = g.step(1, check=False)
+    assert rc_o == 0 and rc_g == 0, susp.lib().susp_last_error()
+    tol = TOL[precision]
+    # ---- lists, bit-exact ----
+    assert np.array_equal(g.lists(susp.LIST_OWNER), o.own)
+    assert np.array_equal(g.lists(susp.LIST_GHOST), o.gown)
+    pi, pj = o.pairs()
+    gp = g.lists(susp.LIST_PAIRS)
+    assert np.array_equal(gp, np.stack([pi, pj], 1).reshape(-1, 2))
+    exp_c = PU.contacts_at_start(o.params, R0, rad, s0, zip(pi, pj))
+    assert [tuple(x) for x in g.lists(susp.LIST_CONTACTS).tolist()] == exp_c
+    if len(rad):
+        cs = g.lists(susp.LIST_CELLS)
+        st, ids = PU.cell_list(box, R0, rad)
+        assert np.array_equal(cs[: len(st)], st) and np.array_equal(cs[len(st):], ids)
+    F, T, S, nl = g.hydro()
+    assert np.array_equal(nl, o.nlinks)
+    assert int(nl.sum()) == len(links_g)
+    # ---- fields ----
+    own = o.own
+    fluid = own == -1
+    fg = g.get_populations()[:, fluid]
+    fo = o.f[:, fluid]
+    rg, ug = PU.moments(fg)
+    ro, uo = PU.moments(fo)
+    e_rho = float(np.abs(rg - ro).max())
+    e_u = PU.rel(ug, uo)
+    _announce("e_rho %.3e e_u %.3e" % (e_rho, e_u))
+    assert e_rho <= tol and e_u <= tol
+    if len(rad):
+        Fo, To = o.part("Fh"), o.part("Th")
+        So = o.part("Sh").reshape(-1, 3, 3)
+        So = 0.5 * (So + So.transpose(0, 2, 1))
+        So6 = np.stack([So[:, 0, 0], So[:, 1, 1], So[:, 2, 2], So[:, 0, 1], So[:, 0, 2], So[:, 1, 2]], 1)
+        # floors: hydrodynamic forces/torques below 1e-4 (a centred sphere in shear has
+        # none) are compared in absolute terms
+        e_F, e_T, e_S = PU.rel(F, Fo, 1e-4), PU.rel(T, To, 1e-4), PU.rel(S, So6, 1e-4)
+        Rg, Ug, Wg, Qg = g.get_particles()
+        e_R = float(np.abs(Rg - o.part("R")).max())
+        e_U = PU.rel(Ug, o.part("U"), 1e-6)
+        e_W = PU.rel(Wg, o.part("W"), 1e-7)
+        _announce("e_F %.3e e_T %.3e e_S %.3e e_R %.3e e_U %.3e e_W %.3e" % (e_F, e_T, e_S, e_R, e_U, e_W))
+        assert max(e_F, e_T, e_S, e_U, e_W) <= max(tol, 1e-10) and e_R <= 1e-10
+        hi, hj, hx = g.get_history()
+        oi, oj, ox = o.history()
+        assert np.array_equal(hi, oi) and np.array_equal(hj, oj)
+        if len(ox):
+            assert PU.rel(hx, ox) <= max(tol, 1e-10)
+    sg, gg = g.stress()
+    so, go = o.stress()
+    for k in range(5):
+        assert PU.rel(sg[k], so[k]) <= max(tol, 1e-9), (k, sg[k], so[k])
+    return o, g
+
+
+def test_single_sphere_fp64():
+    w = __import__("paper_1904_02929_amd.synth", fromlist=["x"]).single_sphere(32, 4.5, 1e-4)
+    _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params), 0, presteps=20)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_dense_one_step(precision):
+    box, pos, vel, om, rad, kw = PU.dense_workload()
+    o, g = _one_step_parity(box, pos, vel, om, rad, kw, precision, presteps=40)
+    assert o.s.nhist > 0  # contacts are active in the compared step
+
+
+def test_dense_straddling_le_plane_fp32():
+    # spheres placed across the sliding plane and across the x and z faces
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=3)
+    pos = pos.copy()
+    pos[0] = [0.3, 0.2, 36.8]     # across x, y (sliding plane) and z faces
+    pos[1] = [20.5, 47.7, 18.0]   # across the sliding plane only
+    L = np.array(box, float)
+    keep = [0, 1]
+    for i in range(2, len(pos)):
+        ok = True
+        for k in keep:
+            d = pos[i] - pos[k]
+            d -= L * np.round(d / L)
+            ok &= np.linalg.norm(d) > rad[i] + rad[k] + 0.2
+        if ok:
+            keep.append(i)
+    pos, vel, om, rad = pos[keep], vel[keep], om[keep], rad[keep]
+    _one_step_parity(box, pos, vel, om, rad, kw, 1, presteps=15)
+
+
+def test_monolayer_oscillatory_fp32():
+    from paper_1904_02929_amd import synth
+    w = synth.monolayer(64, 10, 0.7, seed=2, g0_I=0.2, period=400, ncyc_I=1, ncyc_F=1)
+    _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params), 1, presteps=30)
+
+
+def test_pure_fluid_le_fp32():
+    kw = dict(shear_kind=1, gamma_dot=2e-3)
+    _one_step_parity((24, 40, 17), np.zeros((0, 3)), None, None, np.zeros(0), kw, 1, presteps=25)
+
+
+def test_multistep_fp64_from_create():
+    # both sides start from their own initial state and run 25 steps
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=11)
+    o = PU.oracle_for(box, kw, pos, vel, om, rad)
+    g = PU.gpu_for(box, kw, pos, vel, om, rad, 0)
+    assert o.step(25) == 0
+    g.step(25)
+    Rg, Ug, Wg, _ = g.get_particles()
+    assert np.abs(Rg - o.part("R")).max() < 1e-9
+    assert PU.rel(Ug, o.part("U")) < 1e-8
+    fluid = o.own == -1
+    assert np.array_equal(g.lists(__import__("paper_1904_02929_amd.susp", fromlist=["x"]).LIST_OWNER), o.own)
+    _, ug = PU.moments(g.get_populations()[:, fluid])
+    _, uo = PU.moments(o.f[:, fluid])
+    assert PU.rel(ug, uo) < 1e-9
+
+
+def test_overlap_is_reported():
+    from paper_1904_02929_amd import susp
+    box = (32, 48, 32)
+    pos = np.array([[10.0, 20.0, 10.0], [18.0, 20.0, 10.0]])  # gap -1: mapped spheres overlap
+    rad = np.array([4.5, 4.5])
+    with pytest.raises(susp.SuspError) as ei:
+        PU.gpu_for(box, {}, pos, None, None, rad, 1)
+    assert ei.value.code == susp.EUNSTABLE
+    o = PU.oracle_for(box, {}, pos, None, None, rad)
+    assert o.step(1) == -4
+
+
+def test_invalid_parameters():
+    from paper_1904_02929_amd import susp
+    with pytest.raises(susp.SuspError) as ei:
+        PU.gpu_for((32, 20, 32), {}, np.array([[5.0, 5.0, 5.0]]), None, None, np.array([4.5]), 1)
+    assert ei.value.code == susp.EINVAL
+    with pytest.raises(susp.SuspError):
+        PU.gpu_for((32, 48, 32), {}, np.array([[5.0, 50.0, 5.0]]), None, None, np.array([4.5]), 1)

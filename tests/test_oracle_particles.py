@@ -19,15 +19,29 @@ def _params(orc, **kw):
 
 # ----------------------------------------------------------------------------- coupling
 def test_rest_state_link_constant_cancels(orc):
-    # eqs. (6), (9), (10): in the uniform rest state every link carries 2 w rho0 c; the
-    # entry and exit links of each lattice line cancel, so force and torque vanish.
-    p = _params(orc)
-    o = orc.Oracle(p, pos=[[11.37, 12.81, 10.09]], radius=[4.5])
+    # eqs. (6), (9), (10): in the uniform rest state every link carries 2 w rho0 c.  For a
+    # sphere away from the sliding plane the entry and exit links of each lattice line
+    # cancel, so the literal sum is zero and measuring link momentum from the rest state
+    # changes nothing.  A sphere straddling the Lees-Edwards plane is seen through the
+    # integer lattice on one side and the offset ghost points on the other: there the
+    # rest-state part does not cancel, which is why it is kept out of the force.
+    # eq. (16) with period 2: at t = 1 the phase is pi, so the offset 2 g0 ly is generic and
+    # the sliding velocity vanishes; fluid and spheres at rest
+    p = _params(orc, shear_kind=2, period=2, g0_I=0.1119, ncyc_I=10)
+    o = orc.Oracle(p, pos=[[11.37, 12.81, 10.09], [5.2, 23.6, 15.3]], radius=[4.5, 4.5])
     o.step(1)
-    Fh, Th = o.part("Fh")[0], o.part("Th")[0]
-    assert o.nlinks[0] > 500
-    assert np.abs(Fh).max() < 1e-13 and np.abs(Th).max() < 1e-12
-    assert np.abs(o.part("Sh")[0]).max() < 1e-13
+    s, ule = orc.protocol(p, 1)
+    assert abs(s - 2 * 0.1119 * 24) < 1e-12 and abs(ule) < 1e-13
+    o.f[...] = orc.feq(1.0, [0, 0, 0])[:, None, None, None]
+    U = o.part("U"); U[...] = 0.0
+    W = o.part("W"); W[...] = 0.0
+    o.step(1)
+    Fh, Th, Fr, Tr = o.part("Fh"), o.part("Th"), o.part("Frest"), o.part("Trest")
+    assert o.nlinks[0] > 500 and o.nlinks[1] > 500
+    assert np.abs(Fh).max() < 1e-12 and np.abs(Th).max() < 1e-11
+    assert np.abs(o.part("Sh")).max() < 1e-11
+    assert np.abs(Fr[0]).max() < 1e-13 and np.abs(Tr[0]).max() < 1e-12
+    assert np.abs(Fr[1]).max() > 1e-2
 
 
 def _totals(o, orc):
