@@ -1,0 +1,196 @@
+#!/usr/bin/env python
+"""Benchmark of one coupled lattice-Boltzmann + DEM step on one MI355X.
+
+Workload (default): large 3D bulk suspension, 256^3 D3Q19 lattice, Lees-Edwards simple
+shear at 1e-4, bidisperse spheres of radii 4.5/6.3 (1:1) at volume fraction 0.55, i.e.
+12,914 spheres, seeded synthetic packing; FP32 populations (FP64 particles).
+
+Prints one JSON line: whole-step throughput in MLUPS (all lattice nodes per second), the
+roofline of the dominant kernel (the fused stream/bounce-back/collide kernel, timed with HIP
+events on the simulation's stream), and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline; batched jobs/hr + p99 latency vs plain loop"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per fluid node update: 19 populations read + 19 written + owner word
+BYTES_PER_FLUID = {"fp64": 38 * 8 + 4, "fp32": 38 * 4 + 4, "fp16store": 38 * 2 + 4}
+PREC = {"fp64": 0, "fp32": 1, "fp16store": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16store": "f32 (f16 storage)"}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_1904_02929_amd import synth
+    if name == "large3d":
+        w = synth.bulk3d(256, 0.55, 1e-4, seed=1)
+        return w, "large_3d_bulk_256cube_phi0.55"
+    if name == "bulk96":
+        w = synth.bulk3d(96, 0.55, 1e-3, seed=1)
+        return w, "bulk_3d_96cube_phi0.55"
+    if name == "empty256":
+        from paper_1904_02929_amd.synth import Workload
+        import numpy as np
+        w = Workload("empty256", (256, 256, 256), np.zeros((0, 3)), np.zeros((0, 3)),
+                     np.zeros((0, 3)), np.zeros(0), dict(shear_kind=1, gamma_dot=1e-4))
+        return w, "pure_fluid_256cube"
+    raise SystemExit("unknown workload " + name)
+
+
+def traffic_for(kernel_key, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", kernel_key + "_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_sha256") != src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, steps):
+    import numpy as np
+    from oracle import oracle as O
+    p = O.make_params(lx=w.box[0], ly=w.box[1], lz=w.box[2], **w.params)
+    t0 = time.perf_counter()
+    o = O.Oracle(p, w.pos, w.vel, w.omega, w.radius)
+    t1 = time.perf_counter()
+    rc = o.step(steps)
+    t2 = time.perf_counter()
+    nodes = float(np.prod(w.box))
+    return {
+        "value": round(nodes * steps / (t2 - t1) / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": int(o.s.nthreads),
+        "kind": "oracle",
+        "sample": "%d steps of the same workload (FP64, all lattice nodes), after a %.1f s "
+                  "set-up; %.2f s per step; status %d" % (steps, t1 - t0, (t2 - t1) / steps, rc),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
+    ap.add_argument("--workload", default="large3d", choices=["large3d", "bulk96", "empty256"])
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the lattice would "
+              "shard into z-slabs with halo exchange over RCCL; see DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1904_02929_amd import susp
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    w, wname = workload(args.workload)
+    log("workload %s: box %s, %d spheres (%.1f s to generate)" % (wname, w.box, w.n, time.perf_counter() - t))
+    p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
+                         precision=PREC[args.precision], **w.params)
+    sim = susp.Simulation(p)
+    stream = sim.stream
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    log("warmup %d steps done" % args.warmup)
+    sim.profile(True)
+    sim.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rc = sim.step(args.steps, check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k_ms, k_n = sim.profile_read()
+    sim.profile(False)
+    log("timed %d steps in %.1f ms (status %d)" % (args.steps, ms, rc))
+
+    nodes = int(np.prod(w.box))
+    own = sim.lists(susp.LIST_OWNER)
+    n_fluid = int((own == -1).sum())
+    n_solid = nodes - n_fluid
+    per_step = ms / args.steps
+    mlups = nodes * args.steps / (ms / 1e3) / 1e6
+    k_avg_ms = k_ms / max(1, k_n)
+    alg_bytes = n_fluid * BYTES_PER_FLUID[args.precision] + n_solid * 4
+    achieved = alg_bytes / (k_avg_ms / 1e3) / 1e9
+    with open(os.path.join(ROOT, "paper_1904_02929_amd", "csrc", "fluid.hip"), "rb") as fh:
+        src_hash = hashlib.sha256(fh.read()).hexdigest()
+    kernel_key = "k_lbm_%s_%s" % (wname, args.precision)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on %d steps" % args.cpu_steps)
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": wname,
+            "lattice": list(w.box),
+            "spheres": int(w.n),
+            "radii": [4.5, 6.3] if w.n else [],
+            "phi": 0.55 if w.n else 0.0,
+            "shear_rate": w.params.get("gamma_dot"),
+            "precision": args.precision,
+            "n_sub": int(p.n_sub),
+            "status": int(rc),
+        },
+        "fluid_mlups": round(n_fluid * args.steps / (ms / 1e3) / 1e6, 2),
+        "particle_steps_per_s": round(w.n * args.steps / (ms / 1e3), 1),
+        "roofline": {
+            "kernel": "k_lbm (fused pull-stream, bounce-back, BGK collision, link forces)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(kernel_key, src_hash),
+            "avg_kernel_ms": round(k_avg_ms, 5),
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "fluid_nodes": n_fluid,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,13 @@ int susp_get_lists(susp_sim *s, int32_t kind, void *host, size_t *bytes);
 /* Resolved constants: {m0, kn, kt, eta_n, lub_delta, F0, debye_lambda, eta0, a_min, a_max}. */
 int susp_get_derived(susp_sim *s, double out[10]);
 
+/* Timing of the lattice kernel (fused stream/bounce-back/collide): while enabled, every
+ * step records a pair of HIP events around that kernel on the simulation's stream.
+ * susp_profile_read synchronises, returns the summed kernel time in milliseconds and the
+ * number of timed launches since the previous read, and resets both.                     */
+int susp_profile(susp_sim *s, int32_t enable);
+int susp_profile_read(susp_sim *s, double *ms_total, int64_t *launches);
+
 /* Text of the calling thread's last error ("" if none). */
 const char *susp_last_error(void);
 

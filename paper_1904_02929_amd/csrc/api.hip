@@ -150,10 +150,10 @@ static int resolve(const susp_params *p, Sim &s) {
   s.gamma_dot = p->gamma_dot; s.g0_I = p->g0_I; s.g0_F = p->g0_F; s.theta = p->theta;
   s.period = p->period; s.ncyc_I = p->ncyc_I; s.ncyc_F = p->ncyc_F;
   s.fp16_exp = p->fp16_exp;
-  for (int q = 0; q < NQ; ++q) {
-    s.fp16_tab[q] = (float)(wq(q) * ldexp(1.0, -p->fp16_exp));     // storage -> deviation
-    s.fp16_tab[NQ + q] = (float)(ldexp(1.0, p->fp16_exp) / wq(q));  // deviation -> storage
-  }
+  if (p->precision == 2 && (p->fp16_exp < -20 || p->fp16_exp > 20))
+    return fail(SUSP_EINVAL, "fp16_exp out of [-20, 20]");
+  s.h16.up = (float)ldexp(1.0, p->fp16_exp);  // deviation -> storage: d / w_q * 2^k
+  s.h16.dn = (float)ldexp(1.0, -p->fp16_exp);
   // cell grid: width >= 2 a_max + cutoff, at least 3 cells across the sliding direction
   const double rc = 2.0 * amax * (p->n > 0 ? 1.0 : 0.0) + p->pair_cutoff + 1e-6;
   const int L[3] = {p->lx, p->ly, p->lz};
@@ -173,7 +173,20 @@ static int resolve(const susp_params *p, Sim &s) {
   s.cells.iy = nc[1] / (double)p->ly;
   s.cells.iz = nc[2] / (double)p->lz;
   s.ncell = nc[0] * nc[1] * nc[2];
-  s.lbm_blocks = (int)((s.nodes + LBM_BLOCK - 1) / LBM_BLOCK);
+  // bricks of 64 x BY x BZ nodes for the lattice kernel: as large as possible while
+  // leaving about 2048 of them to spread over the 256 compute units
+  s.bxn = (p->lx + 63) / 64;
+  s.BY = 16; s.BZ = 16;
+  auto nbr = [&]() { return s.bxn * ((p->ly + s.BY - 1) / s.BY) * ((p->lz + s.BZ - 1) / s.BZ); };
+  while (nbr() < 2048 && (s.BY > 4 || s.BZ > 1)) {
+    if (s.BZ >= s.BY && s.BZ > 1) s.BZ /= 2;
+    else if (s.BY > 4) s.BY /= 2;
+    else s.BZ /= 2;
+  }
+  s.byn = (p->ly + s.BY - 1) / s.BY;
+  s.bzn = (p->lz + s.BZ - 1) / s.BZ;
+  s.nbricks = nbr();
+  s.lbm_blocks = s.nbricks;
   return SUSP_OK;
 }
 
@@ -190,7 +203,7 @@ static size_t carve(Sim &s, char *base) {
   const size_t cs = s.precision == 0 ? 8 : 4;
   const size_t n = (size_t)s.n;
   for (int b = 0; b < 2; ++b) s.f[b] = take(NQ * s.plane * es);
-  for (int b = 0; b < 2; ++b) s.own[b] = (int32_t *)take((size_t)s.nodes * 4);
+  s.own = (int32_t *)take((size_t)s.nodes * 4);
   s.gown = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
   s.gval = take((size_t)2 * 5 * s.lx * s.lz * cs);
   for (int b = 0; b < 2; ++b) {
@@ -201,6 +214,9 @@ static size_t carve(Sim &s, char *base) {
     s.hyd[b] = (double *)take(n * HYD * 8);
   }
   s.R0 = (double *)take(n * 3 * 8);
+  s.bt_key = (int32_t *)take((size_t)s.nbricks * 128 * 4);
+  s.bt_val = (double *)take((size_t)s.nbricks * 128 * HYD * 8);
+  s.hyd_fb = (double *)take(n * HYD * 8);
   s.a = (double *)take(n * 8);
   s.m = (double *)take(n * 8);
   s.I = (double *)take(n * 8);
@@ -217,6 +233,7 @@ static size_t carve(Sim &s, char *base) {
     s.hon[b] = (int32_t *)take(n * NCAP * 4);
   }
   s.hstart = (int32_t *)take(n * NCAP * 4);
+  s.rev = (int32_t *)take(n * NCAP * 4);
   s.pineq = (double *)take((size_t)s.lbm_blocks * 6 * 8);
   s.acc = (double *)take((size_t)(128 + 128 * 32) * 8);
   s.flags = (int32_t *)take(256);
@@ -232,12 +249,10 @@ extern "C" size_t susp_footprint_bytes(const susp_params *p) {
 
 static int remap(Sim &s) {
   // both maps to fluid, then claim the current footprints (no cover/uncover)
-  HIPCHK(launch_fill_i32(s.own[0], (size_t)s.nodes, -1, s.stream));
-  HIPCHK(launch_fill_i32(s.own[1], (size_t)s.nodes, -1, s.stream));
+  HIPCHK(launch_fill_i32(s.own, (size_t)s.nodes, -1, s.stream));
   double off, ule;
   protocol(s, s.step, &off, &ule);
-  HIPCHK(launch_map_claim(&s, make_box(s, off, ule), 0));
-  s.own_cur = 1 - s.own_cur;
+  HIPCHK(launch_map_full(&s, make_box(s, off, ule)));
   return SUSP_OK;
 }
 
@@ -296,7 +311,7 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
         hipMemcpy(s.I, I.data(), n * 8, hipMemcpyHostToDevice) || hipMemcpy(s.amap, am.data(), n * 8, hipMemcpyHostToDevice))
       return bail(fail(SUSP_EDEVICE, "upload of radii"));
   }
-  s.cur = 0; s.pcur = 0; s.hcur = 0; s.lcur = 0; s.hfin = 0; s.own_cur = 0; s.step = 0;
+  s.cur = 0; s.pcur = 0; s.hcur = 0; s.lcur = 0; s.hfin = 0; s.step = 0;
   if (launch_init_populations(&s)) return bail(fail(SUSP_EDEVICE, "init populations"));
   if (launch_fill_i32(s.gown, (size_t)2 * s.lx * s.lz, -1, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   for (int b = 0; b < 2; ++b) {
@@ -304,6 +319,7 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
               launch_fill_i32(s.hon[b], n * NCAP, 0, s.stream)))
       return bail(fail(SUSP_EDEVICE, "fill"));
   }
+  if (n && launch_fill_f64(s.hyd_fb, n * HYD, 0.0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   if (n && (launch_fill_f64(s.pst, n * PST, 0.0, s.stream) || launch_fill_f64(s.dp, n * 8, 0.0, s.stream) ||
             launch_fill_i32(s.hstart, n * NCAP, 0, s.stream)))
     return bail(fail(SUSP_EDEVICE, "fill"));
@@ -323,6 +339,8 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
 
 extern "C" int susp_destroy(susp_sim *h) {
   if (!h) return SUSP_OK;
+  for (int i = 0; i < 2 * h->s.prof_cap; ++i) (void)hipEventDestroy(h->s.prof_ev[i]);
+  free(h->s.prof_ev);
   if (h->s.owns_block && h->s.block) {
     (void)hipStreamSynchronize(h->s.stream);
     (void)hipFree(h->s.block);
@@ -339,22 +357,36 @@ static int one_step(Sim &s) {
   protocol(s, t + 1, &off1, &ule1);
   const Box b = make_box(s, off, ule), b1 = make_box(s, off1, ule1);
   s.hcur ^= 1;
-  if (s.n) HIPCHK(launch_fill_f64(s.hyd[s.hcur], (size_t)s.n * HYD, 0.0, s.stream));
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
   HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1));
+  hipEvent_t *ev = nullptr;
+  if (s.prof_on) {
+    if (s.prof_used == s.prof_cap) {
+      const int cap = s.prof_cap ? 2 * s.prof_cap : 256;
+      hipEvent_t *nev = (hipEvent_t *)realloc(s.prof_ev, sizeof(hipEvent_t) * 2 * cap);
+      if (!nev) return fail(SUSP_ENOMEM, "event pool");
+      for (int i = 2 * s.prof_cap; i < 2 * cap; ++i) HIPCHK(hipEventCreate(&nev[i]));
+      s.prof_ev = nev;
+      s.prof_cap = cap;
+    }
+    ev = &s.prof_ev[2 * s.prof_used++];
+    HIPCHK(hipEventRecord(ev[0], s.stream));
+  }
   HIPCHK(launch_lbm(&s, b));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s.stream));
+  HIPCHK(launch_hydro_gather(&s, b));
   s.cur ^= 1;
   if (s.n) {
     HIPCHK(launch_pairs(&s, b));
     s.lcur ^= 1;
+    HIPCHK(launch_pair_rev(&s));
     for (int k = 0; k < s.n_sub; ++k) {
       HIPCHK(launch_substep(&s, b, k, off1, ule1));
       s.pcur ^= 1;
     }
     s.hfin = (1 - s.hfin + s.n_sub) & 1;
-    HIPCHK(launch_map_claim(&s, b1, 1));
-    HIPCHK(launch_map_release(&s, b, b1));
-    s.own_cur ^= 1;
+    HIPCHK(launch_map_update(&s, b, b1, 1));
+    HIPCHK(launch_map_update(&s, b, b1, 2));
   }
   int gphase = 0;
   double gc = 0, gsn = 0;
@@ -385,7 +417,8 @@ extern "C" int susp_step(susp_sim *h, int64_t nsteps) {
   int rc = read_flags(s, &fl);
   if (rc) return rc;
   if (fl) {
-    return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite, 4 neighbour overflow)", fl);
+    return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite, 4 neighbour "
+                "overflow, 8 node touching more than six spheres)", fl);
   }
   return SUSP_OK;
 }
@@ -595,7 +628,7 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
   HIPCHK(hipStreamSynchronize(s.stream));
   if (kind == SUSP_LIST_OWNER) {
     out.resize((size_t)s.nodes);
-    HIPCHK(hipMemcpy(out.data(), s.own[s.own_cur], out.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(out.data(), s.own, out.size() * 4, hipMemcpyDeviceToHost));
   } else if (kind == SUSP_LIST_GHOST) {
     out.resize((size_t)2 * s.lx * s.lz);
     HIPCHK(hipMemcpy(out.data(), s.gown, out.size() * 4, hipMemcpyDeviceToHost));
@@ -652,5 +685,27 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     if (cap < need) return fail(SUSP_EINVAL, "buffer of %zu bytes < %zu", cap, need);
     memcpy(host, out.data(), need);
   }
+  return SUSP_OK;
+}
+
+extern "C" int susp_profile(susp_sim *h, int32_t enable) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  h->s.prof_on = enable ? 1 : 0;
+  return SUSP_OK;
+}
+
+extern "C" int susp_profile_read(susp_sim *h, double *ms_total, int64_t *launches) {
+  if (!h || !ms_total || !launches) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  HIPCHK(hipStreamSynchronize(s.stream));
+  double tot = 0.0;
+  for (int i = 0; i < s.prof_used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, s.prof_ev[2 * i], s.prof_ev[2 * i + 1]));
+    tot += ms;
+  }
+  *ms_total = tot;
+  *launches = s.prof_used;
+  s.prof_used = 0;
   return SUSP_OK;
 }

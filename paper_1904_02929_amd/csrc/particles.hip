@@ -96,9 +96,62 @@ __global__ __launch_bounds__(1024) void k_cells(const double *R, int n, Cells C,
   }
 }
 
+// Same construction with the counters, the scan and the fill cursors in LDS (used when
+// the cell grid fits: ncell <= LDS_CELLS).
+constexpr int LDS_CELLS = 12288;
+__global__ __launch_bounds__(1024) void k_cells_lds(const double *R, int n, Cells C, int ncell,
+                                                    int32_t *start, int32_t *ids) {
+  __shared__ int32_t cnt[LDS_CELLS];
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int c = t; c < ncell; c += nt) cnt[c] = 0;
+  __syncthreads();
+  for (int i = t; i < n; i += nt) atomicAdd(&cnt[cell_of(C, R[3 * i], R[3 * i + 1], R[3 * i + 2])], 1);
+  __syncthreads();
+  const int per = (ncell + nt - 1) / nt;
+  const int c0 = t * per, c1 = min(ncell, c0 + per);
+  int32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += cnt[c];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    int32_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = t > 0 ? part[t - 1] : 0;
+  for (int c = c0; c < c1; ++c) {
+    const int32_t k = cnt[c];
+    start[c] = run;
+    cnt[c] = run;
+    run += k;
+  }
+  if (t == nt - 1) start[ncell] = part[nt - 1];
+  __syncthreads();
+  for (int i = t; i < n; i += nt) {
+    const int pos = atomicAdd(&cnt[cell_of(C, R[3 * i], R[3 * i + 1], R[3 * i + 2])], 1);
+    ids[pos] = i;
+  }
+  __syncthreads();
+  for (int c = t; c < ncell; c += nt) {  // insertion sort inside each cell
+    const int a = start[c], b = start[c + 1];
+    for (int u = a + 1; u < b; ++u) {
+      const int32_t v = ids[u];
+      int w = u - 1;
+      while (w >= a && ids[w] > v) { ids[w + 1] = ids[w]; --w; }
+      ids[w + 1] = v;
+    }
+  }
+}
+
 hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch) {
-  hipLaunchKernelGGL(k_cells, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n, s->cells,
-                     s->ncell, cell_start, cell_ids, scratch);
+  if (s->ncell <= LDS_CELLS)
+    hipLaunchKernelGGL(k_cells_lds, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n,
+                       s->cells, s->ncell, cell_start, cell_ids);
+  else
+    hipLaunchKernelGGL(k_cells, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n, s->cells,
+                       s->ncell, cell_start, cell_ids, scratch);
   return hipGetLastError();
 }
 
@@ -157,7 +210,7 @@ struct PairArgs {
   int32_t *flags;
 };
 
-__global__ void k_pairs(PairArgs A) {
+__global__ __launch_bounds__(128) void k_pairs(PairArgs A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   int32_t js[NCAP];
@@ -383,13 +436,40 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
   sym_add(o.vr, d, Fr, -0.5);
 }
 
+// Entry of each neighbour-list slot that holds the pair's spring history (the slot of the
+// lower id); one wave per sphere, lanes over its neighbour slots.
+__global__ __launch_bounds__(256) void k_pair_rev(const int32_t *cnt, const int32_t *nj, int32_t *rev,
+                                                  int n) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int u = threadIdx.x & 63;
+  if (i >= n || u >= NCAP) return;
+  if (u >= cnt[i]) return;
+  const size_t e = (size_t)i * NCAP + u;
+  const int j = nj[e];
+  int r = (int)e;
+  if (j < i) {
+    const int cj = cnt[j];
+    r = -1;
+    for (int v = 0; v < cj; ++v)
+      if (nj[(size_t)j * NCAP + v] == i) { r = j * NCAP + v; break; }
+  }
+  rev[e] = r;
+}
+
+hipError_t launch_pair_rev(Sim *s) {
+  if (s->n > 0)
+    hipLaunchKernelGGL(k_pair_rev, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, s->ncnt[s->lcur],
+                       s->nj[s->lcur], s->rev, s->n);
+  return hipGetLastError();
+}
+
 struct SubArgs {
   const double *Ri, *Ui, *Wi, *Qi;
   double *Ro, *Uo, *Wo, *Qo;
   double *R0;
   const double *a, *m, *I;
   const double *hyd;
-  const int32_t *cnt, *nj;
+  const int32_t *cnt, *nj, *rev;
   const double *xin;
   const int32_t *onin;
   double *xout;
@@ -402,27 +482,37 @@ struct SubArgs {
   int32_t *flags;
 };
 
-__global__ void k_substep(SubArgs A) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
-  double Fp[3] = {0, 0, 0}, Tp[3] = {0, 0, 0};
-  double st[PST];
-  if (A.sub == 0) {
-    for (int c = 0; c < PST; ++c) st[c] = 0.0;
-    A.R0[3 * i] = A.Ri[3 * i]; A.R0[3 * i + 1] = A.Ri[3 * i + 1]; A.R0[3 * i + 2] = A.Ri[3 * i + 2];
-  } else {
-    for (int c = 0; c < PST; ++c) st[c] = A.pst[(size_t)i * PST + c];
-  }
-  const int c_i = A.cnt[i];
-  for (int u = 0; u < c_i; ++u) {
-    const int j = A.nj[(size_t)i * NCAP + u];
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sum over the 16 lanes of a lane group (xor offsets stay inside the group)
+__device__ inline double gsum16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One DEM substep; 16 lanes per sphere (four spheres per wave), the lanes striding over
+// the sphere's neighbours.  Both spheres of a pair evaluate the identical pair expression;
+// the lower id owns the spring history and the pair's stress.
+__global__ __launch_bounds__(256) void k_substep(SubArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l = lane & 15;
+  const bool ok = i < A.n;
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0}, st[PST];
+#pragma unroll
+  for (int c = 0; c < PST; ++c) st[c] = 0.0;
+  const int c_i = ok ? A.cnt[i] : 0;
+  for (int u = l; u < c_i; u += 16) {
+    const size_t own_e = (size_t)i * NCAP + u;
+    const int j = A.nj[own_e];
     const int lo = i < j ? i : j, hi = i < j ? j : i;
-    size_t e = (size_t)i * NCAP + u;
-    if (i != lo) {  // locate the entry of this pair in the lower sphere's list
-      const int cl = A.cnt[lo];
-      for (int v = 0; v < cl; ++v)
-        if (A.nj[(size_t)lo * NCAP + v] == i) { e = (size_t)lo * NCAP + v; break; }
-    }
+    const int re = A.rev[own_e];
+    const size_t e = re >= 0 ? (size_t)re : own_e;
     double d[3];
     int k;
     pair_geo(A.b, A.Ri, lo, hi, d[0], d[1], d[2], k);
@@ -432,20 +522,30 @@ __global__ void k_substep(SubArgs A) {
     pair_forces(A.P, A.a[lo], A.a[hi], d, &A.Ui[3 * lo], Uh, &A.Wi[3 * lo], &A.Wi[3 * hi], A.dts,
                 xi, A.onin[e], o);
     if (i == lo) {
-      for (int c = 0; c < 3; ++c) { Fp[c] += o.F[c]; Tp[c] += o.Tl[c]; }
+      for (int c = 0; c < 3; ++c) { F[c] += o.F[c]; T[c] += o.Tl[c]; }
       A.xout[3 * e] = xi[0]; A.xout[3 * e + 1] = xi[1]; A.xout[3 * e + 2] = xi[2];
       A.onout[e] = o.on;
       for (int c = 0; c < 6; ++c) { st[c] += o.sl[c]; st[6 + c] += o.vc[c]; st[12 + c] += o.vr[c]; }
     } else {
-      for (int c = 0; c < 3; ++c) { Fp[c] -= o.F[c]; Tp[c] += o.Th[c]; }
+      for (int c = 0; c < 3; ++c) { F[c] -= o.F[c]; T[c] += o.Th[c]; }
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { F[c] = gsum16(F[c]); T[c] = gsum16(T[c]); }
+#pragma unroll
+  for (int c = 0; c < PST; ++c) st[c] = gsum16(st[c]);
+  if (!ok || l != 0) return;
+  if (A.sub == 0) {
+    for (int c = 0; c < 3; ++c) A.R0[3 * i + c] = A.Ri[3 * i + c];
+  } else {
+    for (int c = 0; c < PST; ++c) st[c] += A.pst[(size_t)i * PST + c];
   }
   for (int c = 0; c < PST; ++c) A.pst[(size_t)i * PST + c] = st[c];
   // eq. (1), symplectic Euler with the hydrodynamic force and torque of this step
   double U[3], W[3], R[3];
   for (int c = 0; c < 3; ++c) {
-    U[c] = A.Ui[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + c] + Fp[c]) / A.m[i];
-    W[c] = A.Wi[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + 3 + c] + Tp[c]) / A.I[i];
+    U[c] = A.Ui[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + c] + F[c]) / A.m[i];
+    W[c] = A.Wi[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + 3 + c] + T[c]) / A.I[i];
   }
   if (A.quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
   for (int c = 0; c < 3; ++c) R[c] = A.Ri[3 * i + c] + A.dts * U[c];
@@ -482,7 +582,7 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1)
   A.R0 = s->R0;
   A.a = s->a; A.m = s->m; A.I = s->I;
   A.hyd = s->hyd[s->hcur];
-  A.cnt = s->ncnt[s->lcur]; A.nj = s->nj[s->lcur];
+  A.cnt = s->ncnt[s->lcur]; A.nj = s->nj[s->lcur]; A.rev = s->rev;
   // history ping-pong: substep k reads buffer (start + k) % 2
   const int hin = (1 - s->hfin + sub) & 1;
   A.xin = s->hxi[hin]; A.onin = s->hon[hin];
@@ -497,7 +597,7 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1)
   A.n = s->n; A.sub = sub; A.last = sub == s->n_sub - 1; A.quasi2d = s->quasi2d;
   A.flags = s->flags;
   if (s->n > 0)
-    hipLaunchKernelGGL(k_substep, dim3((s->n + 63) / 64), dim3(64), 0, s->stream, A);
+    hipLaunchKernelGGL(k_substep, dim3((s->n + 15) / 16), dim3(256), 0, s->stream, A);
   return hipGetLastError();
 }
 
@@ -569,30 +669,15 @@ __device__ inline void block_sum(double (&v)[NV], double *sh /*[NV][blockDim/64]
   __syncthreads();
 }
 
-template <class ST>
-__device__ inline double ldpop(const void *f, size_t i, int q, const float *tab) {
-  return (double)Store<ST>::ld((const ST *)f, i, q, tab);
-}
-
-struct MapArgs {
-  const double *R, *U, *W;  // state after the move
-  const double *R0;         // state before the move (release only)
-  const double *amap, *m, *I;
-  double *Uw, *Ww;          // written by release (impulses)
-  int32_t *own_new;
-  int32_t *own_old;
-  void *f;
-  size_t plane;
-  Box bnew, bold;
-  double rho0;
-  int covers, quasi2d;
-  double *dp;
+// Full mapping of every sphere into an all-fluid map (creation and state loads).
+struct MapFullArgs {
+  const double *R, *amap;
+  int32_t *own;
+  Box b;
   int32_t *flags;
-  float tab[2 * NQ];
 };
 
-template <class ST>
-__global__ __launch_bounds__(256) void k_map_claim(MapArgs A) {
+__global__ __launch_bounds__(256) void k_map_full(MapFullArgs A) {
   const int p = blockIdx.x;
   const double r = A.amap[p];
   if (!(isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2]))) {
@@ -600,136 +685,231 @@ __global__ __launch_bounds__(256) void k_map_claim(MapArgs A) {
     return;
   }
   Foot f;
-  footprint(A.bnew, A.R, p, r, f);
+  footprint(A.b, A.R, p, r, f);
   const int tot = f.tot[0] + f.tot[1] + f.tot[2];
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < tot; t += blockDim.x) {
     int64_t node;
     double d[3];
     int kk;
-    if (!foot_node(A.bnew, A.R, p, r, f, t, node, d, kk)) continue;
-    const int32_t old = atomicCAS(&A.own_new[node], -1, p);
-    if (old != -1 && old != p) { atomicMin(&A.own_new[node], p); atomicOr(A.flags, 1); }
-    if (!A.covers || A.own_old[node] != -1) continue;
-    // covered: the node's fluid mass and momentum go to the sphere
-    double rho = 0, j0 = 0, j1 = 0, j2 = 0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double v = wq(q) * A.rho0 + ldpop<ST>(A.f, (size_t)q * A.plane + node, q, A.tab);
-      rho += v; j0 += v * cx(q); j1 += v * cy(q); j2 += v * cz(q);
-    }
-    j0 -= rho * kk * A.bnew.ule;
-    acc[0] += j0; acc[1] += j1; acc[2] += j2;
-    acc[3] += d[1] * j2 - d[2] * j1;
-    acc[4] += d[2] * j0 - d[0] * j2;
-    acc[5] += d[0] * j1 - d[1] * j0;
-    acc[6] += rho;
-  }
-  __shared__ double sh[7 * 16];
-  block_sum<7>(acc, sh);
-  if (threadIdx.x == 0)
-    for (int c = 0; c < 7; ++c) A.dp[(size_t)p * 8 + c] = acc[c];
-}
-
-template <class ST>
-__global__ __launch_bounds__(256) void k_map_release(MapArgs A) {
-  using CT = typename Store<ST>::CT;
-  const int p = blockIdx.x;
-  const double r = A.amap[p];
-  if (!(isfinite(A.R0[3 * p]) && isfinite(A.R0[3 * p + 1]) && isfinite(A.R0[3 * p + 2]) &&
-        isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2]))) {
-    if (threadIdx.x == 0) atomicOr(A.flags, 2);
-    return;
-  }
-  Foot f;
-  footprint(A.bold, A.R0, p, r, f);
-  const int tot = f.tot[0] + f.tot[1] + f.tot[2];
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    int64_t node;
-    double d0[3];
-    int k0;
-    if (!foot_node(A.bold, A.R0, p, r, f, t, node, d0, k0)) continue;
-    if (A.own_new[node] == -1) {
-      // released: equilibrium at rho0 and the surface velocity of the moved sphere
-      double d[3];
-      int k;
-      minimage(A.bnew, (double)(node % A.bnew.lx) - A.R[3 * p],
-               (double)((node / A.bnew.lx) % A.bnew.ly) - A.R[3 * p + 1],
-               (double)(node / ((int64_t)A.bnew.lx * A.bnew.ly)) - A.R[3 * p + 2], d[0], d[1],
-               d[2], k);
-      const double *W = &A.W[3 * p];
-      const double ub0 = A.U[3 * p] + (W[1] * d[2] - W[2] * d[1]);
-      const double ub1 = A.U[3 * p + 1] + (W[2] * d[0] - W[0] * d[2]);
-      const double ub2 = A.U[3 * p + 2] + (W[0] * d[1] - W[1] * d[0]);
-      const double ux = ub0 + k * A.bnew.ule;
-      const double uu = ux * ux + ub1 * ub1 + ub2 * ub2;
-      ST *fs = (ST *)A.f;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const double cu = cx(q) * ux + cy(q) * ub1 + cz(q) * ub2;
-        const double dv = wq(q) * A.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        Store<ST>::st(fs, (size_t)q * A.plane + node, (CT)dv, q, A.tab);
-      }
-      const double j0 = A.rho0 * ub0, j1 = A.rho0 * ub1, j2 = A.rho0 * ub2;
-      acc[0] -= j0; acc[1] -= j1; acc[2] -= j2;
-      acc[3] -= d[1] * j2 - d[2] * j1;
-      acc[4] -= d[2] * j0 - d[0] * j2;
-      acc[5] -= d[0] * j1 - d[1] * j0;
-      acc[6] -= A.rho0;
-    }
-    A.own_old[node] = -1;  // the old map becomes the next spare (all fluid)
-  }
-  __shared__ double sh[7 * 16];
-  block_sum<7>(acc, sh);
-  if (threadIdx.x == 0) {
-    double *dp = &A.dp[(size_t)p * 8];
-    for (int c = 0; c < 7; ++c) dp[c] += acc[c];
-    double U[3], W[3];
-    for (int c = 0; c < 3; ++c) {
-      U[c] = A.U[3 * p + c] + dp[c] / A.m[p];
-      W[c] = A.W[3 * p + c] + dp[3 + c] / A.I[p];
-    }
-    if (A.quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
-    for (int c = 0; c < 3; ++c) { A.Uw[3 * p + c] = U[c]; A.Ww[3 * p + c] = W[c]; }
+    if (!foot_node(A.b, A.R, p, r, f, t, node, d, kk)) continue;
+    const int32_t old = atomicCAS(&A.own[node], -1, p);
+    if (old != -1 && old != p) { atomicMin(&A.own[node], p); atomicOr(A.flags, 1); }
   }
 }
 
-hipError_t launch_map_claim(Sim *s, const Box &bnew, int covers) {
-  MapArgs A;
-  A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
-  A.R0 = s->R0; A.amap = s->amap; A.m = s->m; A.I = s->I;
-  A.Uw = s->U[s->pcur]; A.Ww = s->W[s->pcur];
-  A.own_new = s->own[1 - s->own_cur];
-  A.own_old = s->own[s->own_cur];
-  A.f = s->f[s->cur]; A.plane = s->plane;
-  A.bnew = bnew; A.bold = bnew;
-  A.rho0 = s->rho0; A.covers = covers; A.quasi2d = s->quasi2d;
-  A.dp = s->dp; A.flags = s->flags;
-  for (int i = 0; i < 2 * NQ; ++i) A.tab[i] = s->fp16_tab[i];
-  if (s->n == 0) return hipSuccess;
-  if (s->precision == 0) hipLaunchKernelGGL(k_map_claim<double>, dim3(s->n), dim3(256), 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_map_claim<float>, dim3(s->n), dim3(256), 0, s->stream, A);
-  else hipLaunchKernelGGL(k_map_claim<__half>, dim3(s->n), dim3(256), 0, s->stream, A);
+hipError_t launch_map_full(Sim *s, const Box &b) {
+  MapFullArgs A;
+  A.R = s->R[s->pcur]; A.amap = s->amap; A.own = s->own; A.b = b; A.flags = s->flags;
+  if (s->n > 0) hipLaunchKernelGGL(k_map_full, dim3(s->n), dim3(256), 0, s->stream, A);
   return hipGetLastError();
 }
 
-hipError_t launch_map_release(Sim *s, const Box &bold, const Box &bnew) {
+// In-place map update after the spheres moved.  A node can change owner only if its
+// distance d from (an image of) a sphere lies within delta of the mapped radius, delta
+// = the sphere's displacement plus the change of the Lees-Edwards offset; each sphere
+// visits that shell row by row (two short x-intervals per row) through its new images.
+// Phase 1 claims nodes that entered the sphere: a fluid node is covered (its fluid mass
+// and momentum go to the sphere); a node handed over by a sphere that left it changes
+// owner without a fluid event.  Phase 2 releases nodes that left the sphere and were not
+// claimed: they are refilled with the equilibrium at rho0 and the surface velocity, which
+// the sphere pays; then the impulses of both phases are applied.
+struct MapArgs {
+  const double *R, *U, *W;  // state after the move
+  const double *R0;         // positions before the move
+  const double *amap, *m, *I;
+  double *Uw, *Ww;
+  int32_t *own;
+  void *f;
+  size_t plane;
+  Box bnew, bold;
+  double rho0;
+  int quasi2d;
+  double *dp;
+  int32_t *flags;
+  H16 h16;
+};
+
+__device__ inline bool inside_new(const MapArgs &A, int v, double x, double y, double z) {
+  double d0, d1, d2;
+  int k;
+  minimage(A.bnew, x - A.R[3 * v], y - A.R[3 * v + 1], z - A.R[3 * v + 2], d0, d1, d2, k);
+  return d0 * d0 + d1 * d1 + d2 * d2 < A.amap[v] * A.amap[v];
+}
+
+template <class ST, int PHASE>
+__global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
+  using CT = typename Store<ST>::CT;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double *Rn = &A.R[3 * p], *Ro = &A.R0[3 * p];
+  if (!(isfinite(Rn[0]) && isfinite(Rn[1]) && isfinite(Rn[2]) && isfinite(Ro[0]) &&
+        isfinite(Ro[1]) && isfinite(Ro[2]))) {
+    if (lane == 0) atomicOr(A.flags, 2);
+    return;
+  }
+  const double a = A.amap[p];
+  const double a2 = a * a;
+  double e0, e1, e2;
+  int ke;
+  minimage(A.bnew, Rn[0] - Ro[0], Rn[1] - Ro[1], Rn[2] - Ro[2], e0, e1, e2, ke);
+  const double delta = sqrt(e0 * e0 + e1 * e1 + e2 * e2) + fabs(A.bnew.s - A.bold.s) + 1e-6;
+  const double ro = a + delta, ri = a - delta;
+  const Box &B = A.bnew;
+  // rows (y, z) of the shell around each image of the new position
+  int zlo = (int)floor(Rn[2] - ro), zhi = (int)ceil(Rn[2] + ro);
+  const bool zall = zhi - zlo + 1 >= B.lz;
+  if (zall) { zlo = 0; zhi = B.lz - 1; }
+  const int nz = zhi - zlo + 1;
+  int ylo[3], ny[3];
+  int rows = 0;
+  for (int k = -1; k <= 1; ++k) {
+    const double cyy = Rn[1] + k * B.Ly;
+    int lo = (int)floor(cyy - ro), hi = (int)ceil(cyy + ro);
+    if (lo < 0) lo = 0;
+    if (hi > B.ly - 1) hi = B.ly - 1;
+    ylo[k + 1] = lo;
+    ny[k + 1] = hi >= lo ? hi - lo + 1 : 0;
+    rows += ny[k + 1] * nz;
+  }
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int r = lane; r < rows; r += 64) {
+    int t = r, kb = 0;
+    while (t >= ny[kb] * nz) { t -= ny[kb] * nz; ++kb; }
+    const int k = kb - 1;
+    const int y = ylo[kb] + t % ny[kb];
+    const int zu = zlo + t / ny[kb];
+    int z = zu % B.lz;
+    z = z < 0 ? z + B.lz : z;
+    const double cxx = Rn[0] + k * B.s;
+    const double dyy = (double)y - (Rn[1] + k * B.Ly);
+    const double dzz = zall ? 0.0 : (double)zu - Rn[2];
+    const double oo = ro * ro - dyy * dyy - dzz * dzz;
+    if (!zall && oo < 0.0) continue;
+    // candidate x-intervals of this row (all x when the row is not bounded)
+    int xa0, xa1, xb0 = 1, xb1 = 0;
+    if (zall) {
+      xa0 = (int)ceil(cxx - ro - 1e-6); xa1 = (int)floor(cxx + ro + 1e-6);
+    } else {
+      const double xo = sqrt(oo);
+      const double ii = ri > 0.0 ? ri * ri - dyy * dyy - dzz * dzz : -1.0;
+      if (ii <= 0.0) {
+        xa0 = (int)ceil(cxx - xo - 1e-6); xa1 = (int)floor(cxx + xo + 1e-6);
+      } else {
+        const double xi = sqrt(ii);
+        xa0 = (int)ceil(cxx - xo - 1e-6); xa1 = (int)floor(cxx - xi + 1e-6);
+        xb0 = (int)ceil(cxx + xi - 1e-6); xb1 = (int)floor(cxx + xo + 1e-6);
+      }
+    }
+    if (xa1 - xa0 + 1 >= B.lx || (xb1 >= xb0 && xb1 - xa0 + 1 >= B.lx)) {
+      xa0 = 0; xa1 = B.lx - 1; xb0 = 1; xb1 = 0;  // whole row, once
+    }
+    for (int seg = 0; seg < 2; ++seg) {
+      const int x0 = seg == 0 ? xa0 : xb0, x1 = seg == 0 ? xa1 : xb1;
+      for (int xu = x0; xu <= x1; ++xu) {
+        int x = xu % B.lx;
+        x = x < 0 ? x + B.lx : x;
+        double dn[3];
+        int kn;
+        minimage(B, (double)x - Rn[0], (double)y - Rn[1], (double)z - Rn[2], dn[0], dn[1], dn[2], kn);
+        if (kn != k) continue;  // reached through another image box
+        const bool in_new = dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2] < a2;
+        double dd0, dd1, dd2;
+        int ko;
+        minimage(A.bold, (double)x - Ro[0], (double)y - Ro[1], (double)z - Ro[2], dd0, dd1, dd2, ko);
+        const bool in_old = dd0 * dd0 + dd1 * dd1 + dd2 * dd2 < a2;
+        const int64_t node = x + (int64_t)B.lx * (y + (int64_t)B.ly * z);
+        if (PHASE == 1 && in_new && !in_old) {
+          const int32_t v = atomicCAS(&A.own[node], -1, p);
+          if (v == -1) {
+            // covered: the node's fluid mass and momentum go to the sphere
+            double rho = 0, j0 = 0, j1 = 0, j2 = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const double fv = wq(q) * A.rho0 +
+                                (double)Store<ST>::ld((const ST *)A.f + (size_t)q * A.plane, node, q, A.h16);
+              rho += fv; j0 += fv * cx(q); j1 += fv * cy(q); j2 += fv * cz(q);
+            }
+            j0 -= rho * kn * B.ule;
+            acc[0] += j0; acc[1] += j1; acc[2] += j2;
+            acc[3] += dn[1] * j2 - dn[2] * j1;
+            acc[4] += dn[2] * j0 - dn[0] * j2;
+            acc[5] += dn[0] * j1 - dn[1] * j0;
+            acc[6] += rho;
+          } else if (v != p) {
+            if (inside_new(A, v, x, y, z)) {  // both spheres hold the node: overlap
+              atomicMin(&A.own[node], p);
+              atomicOr(A.flags, 1);
+            } else if (atomicCAS(&A.own[node], v, p) != v) {  // v left it; a third claim is an overlap
+              atomicMin(&A.own[node], p);
+              atomicOr(A.flags, 1);
+            }
+          }
+        }
+        if (PHASE == 2 && in_old && !in_new && A.own[node] == p) {
+          // released: equilibrium at rho0 and the surface velocity of the moved sphere
+          A.own[node] = -1;
+          const double *W = &A.W[3 * p];
+          const double ub0 = A.U[3 * p] + (W[1] * dn[2] - W[2] * dn[1]);
+          const double ub1 = A.U[3 * p + 1] + (W[2] * dn[0] - W[0] * dn[2]);
+          const double ub2 = A.U[3 * p + 2] + (W[0] * dn[1] - W[1] * dn[0]);
+          const double ux = ub0 + kn * B.ule;
+          const double uu = ux * ux + ub1 * ub1 + ub2 * ub2;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const double cu = cx(q) * ux + cy(q) * ub1 + cz(q) * ub2;
+            const double dv = wq(q) * A.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            Store<ST>::st((ST *)A.f + (size_t)q * A.plane, node, (CT)dv, q, A.h16);
+          }
+          const double j0 = A.rho0 * ub0, j1 = A.rho0 * ub1, j2 = A.rho0 * ub2;
+          acc[0] -= j0; acc[1] -= j1; acc[2] -= j2;
+          acc[3] -= dn[1] * j2 - dn[2] * j1;
+          acc[4] -= dn[2] * j0 - dn[0] * j2;
+          acc[5] -= dn[0] * j1 - dn[1] * j0;
+          acc[6] -= A.rho0;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 7; ++c) acc[c] = wsum(acc[c]);
+  if (lane != 0) return;
+  double *dp = &A.dp[(size_t)p * 8];
+  if (PHASE == 1) {
+    for (int c = 0; c < 7; ++c) dp[c] = acc[c];
+    return;
+  }
+  for (int c = 0; c < 7; ++c) dp[c] += acc[c];
+  double U[3], W[3];
+  for (int c = 0; c < 3; ++c) {
+    U[c] = A.U[3 * p + c] + dp[c] / A.m[p];
+    W[c] = A.W[3 * p + c] + dp[3 + c] / A.I[p];
+  }
+  if (A.quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
+  for (int c = 0; c < 3; ++c) { A.Uw[3 * p + c] = U[c]; A.Ww[3 * p + c] = W[c]; }
+}
+
+hipError_t launch_map_update(Sim *s, const Box &bold, const Box &bnew, int phase) {
   MapArgs A;
   A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
   A.R0 = s->R0; A.amap = s->amap; A.m = s->m; A.I = s->I;
   A.Uw = s->U[s->pcur]; A.Ww = s->W[s->pcur];
-  A.own_new = s->own[1 - s->own_cur];
-  A.own_old = s->own[s->own_cur];
+  A.own = s->own;
   A.f = s->f[s->cur]; A.plane = s->plane;
   A.bnew = bnew; A.bold = bold;
-  A.rho0 = s->rho0; A.covers = 1; A.quasi2d = s->quasi2d;
+  A.rho0 = s->rho0; A.quasi2d = s->quasi2d;
   A.dp = s->dp; A.flags = s->flags;
-  for (int i = 0; i < 2 * NQ; ++i) A.tab[i] = s->fp16_tab[i];
+  A.h16 = s->h16;
   if (s->n == 0) return hipSuccess;
-  if (s->precision == 0) hipLaunchKernelGGL(k_map_release<double>, dim3(s->n), dim3(256), 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_map_release<float>, dim3(s->n), dim3(256), 0, s->stream, A);
-  else hipLaunchKernelGGL(k_map_release<__half>, dim3(s->n), dim3(256), 0, s->stream, A);
+  dim3 g(s->n), b(64);
+  if (phase == 1) {
+    if (s->precision == 0) hipLaunchKernelGGL((k_map_update<double, 1>), g, b, 0, s->stream, A);
+    else if (s->precision == 1) hipLaunchKernelGGL((k_map_update<float, 1>), g, b, 0, s->stream, A);
+    else hipLaunchKernelGGL((k_map_update<__half, 1>), g, b, 0, s->stream, A);
+  } else {
+    if (s->precision == 0) hipLaunchKernelGGL((k_map_update<double, 2>), g, b, 0, s->stream, A);
+    else if (s->precision == 1) hipLaunchKernelGGL((k_map_update<float, 2>), g, b, 0, s->stream, A);
+    else hipLaunchKernelGGL((k_map_update<__half, 2>), g, b, 0, s->stream, A);
+  }
   return hipGetLastError();
 }
 
@@ -764,22 +944,26 @@ __global__ __launch_bounds__(256) void k_reduce1(const double *pineq, int nblk, 
 // 64 ledger
 __global__ void k_reduce2(const double *part, double *acc, double cf, double invV, double invns,
                           int gphase, double gcos, double gsin, int has_particles) {
-  if (threadIdx.x != 0) return;
-  double v[31];
-  for (int c = 0; c < 31; ++c) v[c] = 0.0;
-  for (int b = 0; b < RED_BLOCKS; ++b)
-    for (int c = 0; c < 31; ++c) v[c] += part[(size_t)b * RED_W + c];
+  __shared__ double v[32];
+  const int c = threadIdx.x;
+  if (c < 31) {
+    double x = 0.0;
+    for (int b = 0; b < RED_BLOCKS; ++b) x += part[(size_t)b * RED_W + c];  // fixed order
+    v[c] = x;
+  }
+  __syncthreads();
+  if (c != 0) return;
   double sig[30];
-  for (int c = 0; c < 6; ++c) {
-    sig[c] = cf * v[c];
-    sig[6 + c] = has_particles ? v[6 + c] * invV : 0.0;
-    sig[12 + c] = v[12 + c] * invV * invns;  // lubrication
-    sig[18 + c] = v[18 + c] * invV * invns;  // contact
-    sig[24 + c] = v[24 + c] * invV * invns;  // DLVO
+  for (int k = 0; k < 6; ++k) {
+    sig[k] = cf * v[k];
+    sig[6 + k] = has_particles ? v[6 + k] * invV : 0.0;
+    sig[12 + k] = v[12 + k] * invV * invns;  // lubrication
+    sig[18 + k] = v[18 + k] * invV * invns;  // contact
+    sig[24 + k] = v[24 + k] * invV * invns;  // DLVO
   }
   double sxy = 0;
   for (int k = 0; k < 5; ++k) sxy += sig[6 * k + 3];
-  for (int c = 0; c < 30; ++c) { acc[c] = sig[c]; acc[30 + c] += sig[c]; }
+  for (int k = 0; k < 30; ++k) { acc[k] = sig[k]; acc[30 + k] += sig[k]; }
   acc[60] += 1.0;
   if (gphase) { acc[61] += sxy * gcos; acc[62] += sxy * gsin; acc[63] += 1.0; }
   acc[64] += v[30];

@@ -4,7 +4,7 @@
 //   populations   2 x 19 planes x nodes, storage type (double | float | half), each plane
 //                 padded to 256 B; a plane holds deviations d_q = n_q - w_q rho0 (FP16:
 //                 d_q / w_q * 2^k) of the post-collision state, x fastest.
-//   owner maps    2 x nodes int32 (current map, spare map kept all -1)
+//   owner map     nodes int32 (sphere id, -1 fluid), updated in place
 //   ghost planes  owner int32 [2][lz][lx]; values [2][5][lz][lx] in compute precision
 //   particles     FP64 arrays (positions, velocities, spins, quaternions, radii, ...)
 //   lists         cell list, fixed-capacity neighbour lists (NCAP per sphere), spring
@@ -21,7 +21,6 @@ namespace susp {
 
 constexpr int NQ = 19;
 constexpr int NCAP = 48;        // neighbour capacity per sphere
-constexpr int LBM_BLOCK = 256;  // nodes per lattice block
 constexpr int HYD = 13;         // F[3] T[3] S[6] nlinks  (per-sphere hydrodynamic sums)
 constexpr int PST = 18;         // lubrication, contact, DLVO stress partials (6 each)
 
@@ -72,26 +71,30 @@ __host__ __device__ inline void minimage(const Box &b, double dx, double dy, dou
   ox = dx; oy = dy; oz = dz;
 }
 
-// Storage of population deviations.
+// Storage of population deviations.  FP16 keeps h = half(d / w_q * 2^k); the factors
+// 2^k / w_q (= 2^k times 3, 18 or 36) and w_q 2^-k are formed exactly from the scalars
+// up = 2^k and dn = 2^-k.
+struct H16 {
+  float up, dn;
+};
 template <class ST> struct Store;
 template <> struct Store<double> {
   using CT = double;
-  __device__ static double ld(const double *p, size_t i, int, const float *) { return p[i]; }
-  __device__ static void st(double *p, size_t i, double v, int, const float *) { p[i] = v; }
+  __device__ static double ld(const double *p, size_t i, int, H16) { return p[i]; }
+  __device__ static void st(double *p, size_t i, double v, int, H16) { p[i] = v; }
 };
 template <> struct Store<float> {
   using CT = float;
-  __device__ static float ld(const float *p, size_t i, int, const float *) { return p[i]; }
-  __device__ static void st(float *p, size_t i, float v, int, const float *) { p[i] = v; }
+  __device__ static float ld(const float *p, size_t i, int, H16) { return p[i]; }
+  __device__ static void st(float *p, size_t i, float v, int, H16) { p[i] = v; }
 };
-// FP16: h = half(d * sc[q]) with sc[q] = 2^k / w_q; d = float(h) * isc[q].
 template <> struct Store<__half> {
   using CT = float;
-  __device__ static float ld(const __half *p, size_t i, int q, const float *isc) {
-    return __half2float(p[i]) * isc[q];
+  __device__ static float ld(const __half *p, size_t i, int q, H16 h) {
+    return __half2float(p[i]) * ((float)wq(q) * h.dn);
   }
-  __device__ static void st(__half *p, size_t i, float v, int q, const float *sc) {
-    p[i] = __float2half_rn(v * sc[NQ + q]);
+  __device__ static void st(__half *p, size_t i, float v, int q, H16 h) {
+    p[i] = __float2half_rn(v * ((float)(1.0 / wq(q)) * h.up));
   }
 };
 
@@ -107,14 +110,16 @@ struct Sim;
 hipError_t launch_init_populations(Sim *s);
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values);
 hipError_t launch_lbm(Sim *s, const Box &b);
+hipError_t launch_hydro_gather(Sim *s, const Box &b);
 hipError_t launch_pop_convert(Sim *s, double *dev64, int to_storage);
 hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[19][nodes]*/, const Box &b);
 // ---- launchers (particles.hip) ----
 hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch);
 hipError_t launch_pairs(Sim *s, const Box &b);
+hipError_t launch_pair_rev(Sim *s);
 hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1);
-hipError_t launch_map_claim(Sim *s, const Box &bnew, int covers);
-hipError_t launch_map_release(Sim *s, const Box &bold, const Box &bnew);
+hipError_t launch_map_full(Sim *s, const Box &b);
+hipError_t launch_map_update(Sim *s, const Box &bold, const Box &bnew, int phase);
 hipError_t launch_stress(Sim *s, int gphase, double gcos, double gsin);
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
@@ -134,10 +139,11 @@ struct Sim {
   double gamma_dot, g0_I, g0_F, theta;
   int period, ncyc_I, ncyc_F;
   int fp16_exp;
-  float fp16_tab[2 * NQ];  // isc[19], sc[19]
+  H16 h16;                 // FP16 storage scale 2^k and its inverse
   Cells cells;
   int ncell;
-  int lbm_blocks;
+  int lbm_blocks;  // lattice bricks (= partial sums of the fluid stress)
+  int bxn, byn, bzn, BY, BZ, nbricks;
   // device block
   void *block;
   int owns_block;
@@ -145,8 +151,7 @@ struct Sim {
   // populations
   void *f[2];
   int cur;  // index of the buffer holding the current state
-  int32_t *own[2];
-  int own_cur;
+  int32_t *own;  // owner map: sphere id of every node, -1 fluid
   int32_t *gown;
   void *gval;
   // particles (FP64)
@@ -156,6 +161,9 @@ struct Sim {
   double *a, *m, *I, *amap;
   double *hyd[2];
   int hcur;
+  int32_t *bt_key;  // [nbricks][128] sphere ids of each brick's link table (-1 empty)
+  double *bt_val;   // [nbricks][128][HYD]
+  double *hyd_fb;   // [n][HYD] overflow of full brick tables
   double *pst;   // [n][PST]
   double *dp;    // [n][8] cover/uncover momentum, angular momentum, mass
   // lists
@@ -165,6 +173,7 @@ struct Sim {
   double *hxi[3];            // spring vector per entry [n][NCAP][3]
   int32_t *hon[3];           // contact flag per entry
   int32_t *hstart;           // contact at the start of the step per entry
+  int32_t *rev;              // per entry: entry (of the lower id) holding the pair's history
   int hfin;                  // history buffer holding the final state of the last step
   // reductions
   double *pineq;  // [lbm_blocks][6]
@@ -172,6 +181,10 @@ struct Sim {
   int32_t *flags;
   // clock
   int64_t step;
+  // optional timing of the lattice kernel with HIP events on the simulation's stream
+  int prof_on;
+  int prof_used, prof_cap;
+  hipEvent_t *prof_ev;  // [2 * prof_cap]: start, end of each timed launch
 };
 
 }  // namespace susp

@@ -73,6 +73,8 @@ def lib():
         L.susp_get_hydro.argtypes = [vp, _PD, _PD, _PD, _PI]
         L.susp_get_lists.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_size_t)]
         L.susp_get_derived.argtypes = [vp, _PD]
+        L.susp_profile.argtypes = [vp, C.c_int32]
+        L.susp_profile_read.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
         L.susp_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -170,6 +172,15 @@ class Simulation:
         if check:
             _chk(rc)
         return rc
+
+    def profile(self, enable=True):
+        _chk(lib().susp_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed lattice-kernel milliseconds, number of launches) since the last read."""
+        ms = C.c_double(); n = C.c_int64()
+        _chk(lib().susp_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def stress(self):
         out = np.zeros((5, 6)); gg = np.zeros(2)
