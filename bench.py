@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--workload", default="large3d", choices=["large3d", "bulk96", "empty256"])
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device-to-device copy of 1 GiB five times (the "
+                         "reference kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the lattice would "
@@ -107,6 +110,15 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": src.numel() * 4,
+                          "copy_bytes_written_per_launch": src.numel() * 4, "launches": 5}))
+        return
     t = time.perf_counter()
     w, wname = workload(args.workload)
     log("workload %s: box %s, %d spheres (%.1f s to generate)" % (wname, w.box, w.n, time.perf_counter() - t))
