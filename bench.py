@@ -98,8 +98,8 @@ def main():
                          "reference kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the lattice would "
-              "shard into z-slabs with halo exchange over RCCL; see DESIGN.md). Run with --gpus 1.",
+        print("bench.py measures one GPU: there is no multi-GPU path (the lattice would shard "
+              "into z-slabs with halo planes exchanged over RCCL). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -103,6 +103,8 @@ size_t susp_footprint_bytes(const susp_params *p);
 
 /* Create a simulation: validate, upload the spheres, fill the fluid with the equilibrium
  * of the imposed shear profile u_x = gdot(0) (y - (ly-1)/2) and map the spheres.
+ * Limits (SUSP_EINVAL beyond them): every edge >= 8 nodes; one population array
+ * (19 x nodes x storage bytes) < 4 GiB, i.e. up to ~56M nodes in FP32, ~28M in FP64.
  * stream: a hipStream_t (NULL: null stream).  workspace: device memory of at least
  * ws_bytes >= susp_footprint_bytes(p), 256-byte aligned, or NULL to let the library
  * allocate.  On success *out receives the handle.                                         */

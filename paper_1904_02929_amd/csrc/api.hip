@@ -118,6 +118,13 @@ static int resolve(const susp_params *p, Sim &s) {
   s.precision = p->precision;
   s.nodes = (int64_t)p->lx * p->ly * p->lz;
   s.plane = (size_t)((s.nodes + 255) / 256 * 256);
+  {
+    // the lattice kernel addresses one population array with 32-bit byte offsets
+    const size_t es = p->precision == 0 ? 8 : p->precision == 1 ? 4 : 2;
+    if ((size_t)NQ * s.plane * es > 0xffffffffull)
+      return fail(SUSP_EINVAL, "one population array would exceed 4 GiB (%zu nodes, %zu-byte storage)",
+                  (size_t)s.nodes, es);
+  }
   s.n = p->n;
   s.tau = p->tau; s.rho0 = p->rho0;
   s.map_ratio = p->map_ratio; s.rho_p = p->rho_p;

@@ -28,28 +28,36 @@ template <class T> __device__ inline T wave_sum(T v) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Fused lattice kernel.
-//
-// A work-group owns one brick of TX x BY x BZ nodes and walks it in tiles of TX x TY
-// (one wave per 64-node row segment).  Per tile the owner map with a one-node halo is
-// staged in LDS (halo rows outside the box come from the Lees-Edwards ghost planes), so
-// every pull source is classified from LDS.
+// Lattice kernel k_lbm: pull-stream, moving bounce-back, link sums, BGK collision and the
+// fluid stress partials in one pass.  The lattice is walked in bricks of TX x BY x BZ
+// nodes, one work-group per brick: its four waves take four consecutive rows (one 64-node
+// x segment each) and walk the brick's z range together.  The owner map of planes z-1, z,
+// z+1 (rows y-1 .. y+4 with a one-node x halo; rows beyond the box edges come from the
+// Lees-Edwards ghost owner planes) sits in a ring of four LDS planes; each z step fetches
+// one new plane, one step ahead.  Row and plane of every pull source are uniform over a
+// wave, so a population load is a uniform row pointer plus the lane's (periodically
+// wrapped) x.
 //
 // Links: with lever r_b - R = D - c_q/2 (D = node minus sphere centre, minimum image) the
 // surface velocity along the link is u_b.c_q = u(X).c_q, because (W x c).c = 0; hence one
 // FP64 minimum image and one rigid-body velocity per node and sphere, and per link only
 //   corr = -6 w_q rho0 u(X).c_q,  n_q = n*_qbar - corr,  m = 2 n*_qbar - corr.
 // The node's sums are F = -sum m c_q, T = D x F, S = sym(D (x) F) + 1/2 sum m c_q c_q
-// (exactly the link sums of eqs. 6, 9, 10 regrouped).  Per-sphere sums of the brick are
-// accumulated in an LDS hash table (two copies to halve atomic contention) and written
-// once per brick; k_hydro_gather adds a sphere's brick entries in a fixed order.
+// (exactly the link sums of eqs. 6, 9, 10 regrouped).  A sphere is convex, so of two
+// opposite directions at most one links the node to the same sphere; the sums are formed
+// per opposite pair, in FP64 (torque and stresslet cancel strongly over a surface).
+// Per-sphere sums of the brick are accumulated in an LDS hash table (two copies to halve
+// atomic contention) and written once per brick; k_hydro_gather adds a sphere's brick
+// entries in a fixed order.
 constexpr int TX = 64, TY = 4;
 constexpr int TSLOT = 128;
+constexpr int SROW = TX + 2, SPLANE = (TY + 2) * SROW;  // staged owner plane: 6 rows of 66
 
 struct LbmArgs {
   const void *fin;
   void *fout;
   size_t plane;
+  uint32_t pop_bytes, gval_bytes;  // bytes of one population array (< 4 GiB), of gval
   const int32_t *own;
   const int32_t *gown;
   const void *gval;
@@ -64,6 +72,7 @@ struct LbmArgs {
   int nbricks, per_xcd;
   Box b;
   double rho0, omega;
+  double kax, kdg;  // -6 w_q rho0 of the axis and of the diagonal directions
   H16 h16;
 };
 
@@ -79,141 +88,308 @@ __device__ inline int table_slot(int32_t *skey, int p) {
   return -1;
 }
 
+// c_q . (ax, ay, az) for a compile-time q, summed x, y, z in order without the zero terms.
+template <class T> __device__ inline T cdot(int q, T ax, T ay, T az) {
+  T s = 0;
+  bool first = true;
+  if (cx(q) != 0) { s = cx(q) > 0 ? ax : -ax; first = false; }
+  if (cy(q) != 0) { const T v = cy(q) > 0 ? ay : -ay; s = first ? v : s + v; first = false; }
+  if (cz(q) != 0) { const T v = cz(q) > 0 ? az : -az; s = first ? v : s + v; }
+  return s;
+}
+// acc += c * v for c in {-1, 0, 1} known at compile time
+template <class T> __device__ inline void addc(T &acc, int c, T v) {
+  if (c > 0) acc += v;
+  else if (c < 0) acc -= v;
+}
+__device__ inline float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
+// Population access through a buffer resource over a whole array (< 4 GiB): the 32-bit
+// byte offset is the sum of a uniform part (plane and row, scalar registers) and the lane's
+// x; an offset past the array reads 0 and writes nothing.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <class ST> struct RowIO;
+template <> struct RowIO<double> {
+  __device__ static double ld(__amdgpu_buffer_rsrc_t r, uint32_t off, int, H16) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, int, H16) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  }
+};
+template <> struct RowIO<float> {
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, int, H16) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, int, H16) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+  }
+};
+// FP16 storage: same scaling as Store<__half>
+template <> struct RowIO<__half> {
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, int q, H16 h) {
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    return __half2float(__builtin_bit_cast(__half, b)) * ((float)wq(q) * h.dn);
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, int q, H16 h) {
+    const __half hv = __float2half_rn(v * ((float)(1.0 / wq(q)) * h.up));
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hv), r, off, 0, 0);
+  }
+};
+
+// Work-group barrier that orders LDS only: the lattice kernel's global stores are never
+// read back within the kernel, so waiting for them at every z step would only add latency.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// A wave-uniform value the compiler must treat as unknown at this point: row pointers built
+// from it are formed where they are used, instead of being hoisted out of the loops into
+// dozens of live scalar registers.
+__device__ inline int opaque_uniform(int v) {
+  v = __builtin_amdgcn_readfirstlane(v);
+  asm volatile("" : "+s"(v));
+  return v;
+}
+template <class T> __device__ inline T *opaque_uniform(T *p) {
+  const uint64_t u = (uint64_t)p;
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+// One thread's view of its brick: the lane's column, the staged entries of the owner ring.
+struct BrickView {
+  int brick, t, lane, wv;
+  int x, z_lo, z_hi, y_lo, y_hi;
+  bool xin;
+  uint32_t xc, xm, xp;  // x of the node and of the pull sources c_x = +1, -1 (periodic)
+};
+
+// Brick of this work-group (XCD-aware order: hardware blocks are dealt round-robin to the 8
+// XCDs; each XCD gets a contiguous range of bricks, z-major, so neighbouring bricks share
+// its L2).  False for the surplus blocks of the last round.
+__device__ inline bool brick_view(const LbmArgs &A, BrickView &V) {
+  V.brick = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
+  if (V.brick >= A.nbricks) return false;
+  const int bxi = V.brick % A.bxn;
+  const int byi = (V.brick / A.bxn) % A.byn;
+  const int bzi = V.brick / (A.bxn * A.byn);
+  V.t = threadIdx.x;
+  V.lane = V.t & 63;
+  V.wv = __builtin_amdgcn_readfirstlane(V.t >> 6);
+  V.x = bxi * TX + V.lane;
+  V.xin = V.x < A.lx;
+  // lanes past the box end use the last column for loads (their results are not stored)
+  V.xc = V.xin ? V.x : A.lx - 1;
+  V.xm = V.xc == 0 ? A.lx - 1 : V.xc - 1;
+  V.xp = V.xc == (uint32_t)(A.lx - 1) ? 0 : V.xc + 1;
+  V.z_lo = bzi * A.BZ;
+  V.z_hi = min(A.lz, V.z_lo + A.BZ);
+  V.y_lo = byi * A.BY;
+  V.y_hi = min(A.ly, V.y_lo + A.BY);
+  return true;
+}
+
+// Walk the brick: for every z step and row band call node(y, z, sm, s0, sp, cen) in every
+// wave, with the staged owner planes z-1, z, z+1 and the lane's centre entry (y may be
+// >= ly in the last band of a box whose ly is not a multiple of TY).
+template <class Fn>
+__device__ inline void walk_brick(const LbmArgs &A, const BrickView &V, int32_t (*smap)[SPLANE], Fn &&node) {
+  const int lx = A.lx, ly = A.ly, lz = A.lz, t = V.t;
+  // the staged entries (row, column of a staged plane) of this thread: t and t + 256
+  const bool two = t + 256 < SPLANE;
+  const int e1 = two ? t + 256 : t;
+  const int x0 = V.x - V.lane;
+  int gx0 = (x0 - 1 + t % SROW) % lx, gx1 = (x0 - 1 + e1 % SROW) % lx;
+  gx0 += gx0 < 0 ? lx : 0;
+  gx1 += gx1 < 0 ? lx : 0;
+  for (int y0 = V.y_lo; y0 < V.y_hi; y0 += TY) {
+    // source of each staged entry: a row of the owner map, or a ghost owner plane beyond
+    // y = -1 and y = ly (rows past ly only feed lanes that do nothing)
+    const int gy0 = y0 - 1 + t / SROW, gy1 = y0 - 1 + e1 / SROW;
+    const int32_t *ep0 = gy0 < 0 ? A.gown + gx0
+                       : gy0 >= ly ? A.gown + (size_t)lz * lx + gx0
+                                   : A.own + gx0 + (size_t)lx * gy0;
+    const int32_t *ep1 = gy1 < 0 ? A.gown + gx1
+                       : gy1 >= ly ? A.gown + (size_t)lz * lx + gx1
+                                   : A.own + gx1 + (size_t)lx * gy1;
+    const int es0 = (gy0 < 0 || gy0 >= ly) ? lx : lx * ly;
+    const int es1 = (gy1 < 0 || gy1 >= ly) ? lx : lx * ly;
+    auto fetch = [&](int zz, int32_t &v0, int32_t &v1) {
+      zz = zz < 0 ? zz + lz : (zz >= lz ? zz - lz : zz);
+      v0 = ep0[zz * es0];
+      v1 = ep1[zz * es1];
+    };
+    {
+      int32_t a0, a1, b0, b1, c0, c1;
+      fetch(V.z_lo - 1, a0, a1);
+      fetch(V.z_lo, b0, b1);
+      fetch(V.z_lo + 1, c0, c1);
+      __syncthreads();  // the previous row band is done with the ring
+      smap[0][t] = a0; smap[1][t] = b0; smap[2][t] = c0;
+      if (two) { smap[0][e1] = a1; smap[1][e1] = b1; smap[2][e1] = c1; }
+    }
+    const int yb = y0 + V.wv;  // this wave's row (uniform)
+    for (int zb = V.z_lo; zb < V.z_hi; ++zb) {
+      lds_barrier();  // plane z+1 is staged; plane z-2's slot is free
+      const int r = zb - V.z_lo + 1;  // ring index of plane zb
+      // plane z+2 for the next step (past the brick's last plane it is fetched but unused)
+      int32_t f0, f1;
+      fetch(zb + 2, f0, f1);
+      node(yb, zb, smap[(r - 1) & 3], smap[r & 3], smap[(r + 1) & 3], (V.wv + 1) * SROW + V.lane + 1);
+      smap[(r + 2) & 3][t] = f0;
+      if (two) smap[(r + 2) & 3][e1] = f1;
+    }
+  }
+}
+
+// Owner of the source X - c_q of direction q, from the staged planes z-1, z, z+1.
+__device__ inline int src_owner(int q, const int32_t *sm, const int32_t *s0, const int32_t *sp, int cen) {
+  const int32_t *spl = cz(q) == 1 ? sm : (cz(q) == -1 ? sp : s0);
+  return spl[cen - cy(q) * SROW - cx(q)];
+}
+
+// The node's links: bit q of the result is set if the source X - c_q is solid; *ph = the
+// largest owner among them (-1 if none).
+__device__ inline uint32_t link_bits(const int32_t *sm, const int32_t *s0, const int32_t *sp, int cen, int *ph) {
+  uint32_t all = 0;
+  int h = -1;
+#pragma unroll
+  for (int q = 1; q < NQ; ++q) {
+    const int o = src_owner(q, sm, s0, sp, cen);
+    all |= o >= 0 ? 1u << q : 0u;
+    h = max(h, o);
+  }
+  *ph = h;
+  return all;
+}
+
+// Spheres linked to a node, visited in descending id order; fn(p, m) handles sphere p
+// whose links are the bits of m.  False if links were left over (more than six spheres).
+template <class Fn>
+__device__ inline bool for_each_sphere(const int32_t *sm, const int32_t *s0, const int32_t *sp, int cen,
+                                       uint32_t all, int ph, Fn &&fn) {
+  uint32_t rem = all;
+  int p = ph;
+  for (int it = 0; rem != 0 && it < 6; ++it) {
+    uint32_t m = 0;
+    int nx = -1;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      const int o = src_owner(q, sm, s0, sp, cen);
+      if (o == p) m |= 1u << q;
+      else if ((rem >> q) & 1u) nx = max(nx, o);
+    }
+    fn(p, m);
+    rem &= ~m;
+    p = nx;
+  }
+  return rem == 0;
+}
+
+// Every link source X - c_q lies in the image of X itself unless X is within one node of
+// half a period from the centre (boxes thin compared with the sphere); then each link
+// finds its own image.
+__device__ inline bool same_image(const Box &b, double Dx, double Dy, double Dz) {
+  return fabs(Dx) <= 0.5 * b.Lx - 1.000001 && fabs(Dy) <= 0.5 * b.Ly - 1.000001 &&
+         fabs(Dz) <= 0.5 * b.Lz - 1.000001;
+}
+
+// ---- k_lbm: pull (eq. 3), bounce-back on moving spheres (eq. 7) with the link sums
+//      (eqs. 6, 9, 10), BGK collision (eq. 4) on the deviations, non-equilibrium momentum
+//      flux per brick ----
 template <class ST>
-__global__ __launch_bounds__(256, 3) void k_lbm(LbmArgs A) {
+__global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   using CT = typename Store<ST>::CT;
-  const ST *fin = (const ST *)A.fin;
-  ST *fout = (ST *)A.fout;
-  const CT *gval = (const CT *)A.gval;
-  __shared__ int32_t smap[3][TY + 2][TX + 2];
+  constexpr bool kPlain = std::is_same<ST, CT>::value;  // ghost rows share the storage type
+  __shared__ int32_t smap[4][SPLANE];
   __shared__ int32_t skey[TSLOT];
   __shared__ double sval[2][TSLOT][HYD];
-  __shared__ double red[4][6];
-  // XCD-aware brick order: hardware blocks are dealt round-robin to the 8 XCDs; each XCD
-  // gets a contiguous range of bricks (z-major), so neighbouring bricks share its L2
-  const int hb = blockIdx.x;
-  int brick = (hb & 7) * A.per_xcd + (hb >> 3);
-  const bool bok = brick < A.nbricks;
-  if (!bok) brick = 0;
-  const int bxi = brick % A.bxn;
-  const int byi = (brick / A.bxn) % A.byn;
-  const int bzi = brick / (A.bxn * A.byn);
-  const int t = threadIdx.x;
-  const int tx = t & 63, tyl = t >> 6;
+  __shared__ double spn[6][256];  // per-thread fluid stress partials
+  BrickView V;
+  if (!brick_view(A, V)) return;  // the whole work-group
+  const int t = V.t, lane = V.lane;
   const int lx = A.lx, ly = A.ly, lz = A.lz;
+  const size_t plane = A.plane;
   for (int i = t; i < TSLOT; i += 256) skey[i] = -1;
   for (int i = t; i < 2 * TSLOT * HYD; i += 256) (&sval[0][0][0])[i] = 0.0;
-  double pn[6] = {0, 0, 0, 0, 0, 0};
-  const int x0 = bxi * TX;
-  const int x = x0 + tx;
-  const int z_end = min(lz, (bzi + 1) * A.BZ), y_end = min(ly, (byi + 1) * A.BY);
-  for (int z = bzi * A.BZ; bok && z < z_end; ++z) {
-    for (int y0 = byi * A.BY; y0 < y_end; y0 += TY) {
-      __syncthreads();  // previous tile done with smap (and table initialised)
-      for (int i = t; i < 3 * (TY + 2) * (TX + 2); i += 256) {
-        const int dx = i % (TX + 2), dy = (i / (TX + 2)) % (TY + 2), dz = i / ((TX + 2) * (TY + 2));
-        int gx = (x0 - 1 + dx) % lx;
-        gx = gx < 0 ? gx + lx : gx;
-        int gz = (z - 1 + dz) % lz;
-        gz = gz < 0 ? gz + lz : gz;
-        const int gy = y0 - 1 + dy;
-        int v;
-        if (gy < 0) v = A.gown[(0 * lz + gz) * lx + gx];
-        else if (gy >= ly) v = A.gown[(1 * lz + gz) * lx + gx];
-        else v = A.own[gx + (int64_t)lx * (gy + (int64_t)ly * gz)];
-        smap[dz][dy][dx] = v;
-      }
-      __syncthreads();
-      const int y = y0 + tyl;
-      const bool valid = x < lx && y < ly;
-      const int own = valid ? smap[1][tyl + 1][tx + 1] : -2;
-      if (own == -2) continue;
-      const int node = x + lx * (y + ly * z);  // < 2^31 nodes (checked at creation)
-      if (own >= 0) {
-        // solid node: its populations are never read (a released node is refilled); store
-        // the rest state so that the wave writes whole cache lines
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) Store<ST>::st(fout + (size_t)q * A.plane, node, (CT)0, q, A.h16);
-        continue;
-      }
-      CT n[NQ];
-      uint32_t lmask = 0, m2 = 0;  // links; links to a sphere other than p1
-      int p1 = -1;
-      n[0] = Store<ST>::ld(fin, node, 0, A.h16);
+  for (int c = 0; c < 6; ++c) spn[c][t] = 0.0;
+  const CT om = (CT)A.omega;
+  const CT rho0 = (CT)A.rho0;
+  constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
+  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(A.fin, A.pop_bytes), rout = buf_rsrc(A.fout, A.pop_bytes);
+  const __amdgpu_buffer_rsrc_t rgh = buf_rsrc(A.gval, A.gval_bytes);
+  // byte offsets of the lane's column and of its pull sources c_x = +1, -1
+  const uint32_t xcb = V.xc * es, xmb = V.xm * es, xpb = V.xp * es;
+  const uint32_t xcg = V.xc * ges, xmg = V.xm * ges, xpg = V.xp * ges;
+  walk_brick(A, V, smap, [&](int yb, int zb, const int32_t *sm, const int32_t *s0, const int32_t *sp, int cen) {
+    if (yb >= ly) return;
+    const int y = opaque_uniform(yb), z = opaque_uniform(zb);
+    const uint32_t pb = (uint32_t)opaque_uniform((int)(plane * es));  // plane stride, bytes
+    const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
+    const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
+    CT n[NQ];  // populations in, post-collision populations out (0 = rest state if solid)
+    uint32_t all = 0;  // link directions of a fluid node (bit q: X - c_q is solid)
+    int ph = -1;       // the largest sphere id among them
+    if (V.xin && s0[cen] == -1) {
+      n[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
+      // ---- pull ----
 #pragma unroll
       for (int q = 1; q < NQ; ++q) {
-        const int so = smap[1 - cz(q)][tyl + 1 - cy(q)][tx + 1 - cx(q)];
-        if (so >= 0) {
-          if (p1 < 0) p1 = so;
-          else if (so != p1) m2 |= 1u << q;
-        }
-        // exactly one independent load per direction: the pulled population if the
-        // source is fluid, else this node's own opposite population (bounced back below)
-        CT val;
-        if (so < 0) {
-          int px = x - cx(q), pz = z - cz(q);
-          const int py = y - cy(q);
-          px = px < 0 ? px + lx : (px >= lx ? px - lx : px);
-          pz = pz < 0 ? pz + lz : (pz >= lz ? pz - lz : pz);
-          if (cy(q) != 0 && (py < 0 || py >= ly))
-            val = gval[((((py < 0 ? 0 : 1) * 5 + gslot(q)) * lz + pz) * lx + px)];
-          else
-            val = Store<ST>::ld(fin + (size_t)q * A.plane, px + lx * (py + ly * pz), q, A.h16);
+        const int ys = y - cy(q);
+        const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
+        const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
+        const bool gh = cy(q) != 0 && (ys < 0 || ys >= ly);
+        if (gh) {  // uniform: a Lees-Edwards ghost row
+          const uint32_t xsg = cx(q) == 1 ? xmg : (cx(q) == -1 ? xpg : xcg);
+          n[q] = RowIO<CT>::ld(rgh, (uint32_t)((((ys < 0 ? 0 : 1) * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
         } else {
-          lmask |= 1u << q;
-          val = Store<ST>::ld(fin + (size_t)opp(q) * A.plane, node, opp(q), A.h16);
+          n[q] = RowIO<ST>::ld(rin, q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb, q, A.h16);
         }
-        n[q] = val;
       }
-      // ---- links, one sphere at a time (a node rarely touches more than two) ----
-      for (int it = 0; it < 6 && lmask; ++it) {
-        // first pass: sphere p1 (links lmask & ~m2, no map reads); later passes: the
-        // sphere of the lowest remaining link
-        int p = p1;
-        uint32_t mine = lmask & ~m2;
-        if (it > 0) {
-          p = -1;
+      // ---- links: the node's own opposite population, bounced back ----
+      all = link_bits(sm, s0, sp, cen, &ph);
 #pragma unroll
-          for (int q = NQ - 1; q >= 1; --q)
-            if ((lmask >> q) & 1u) p = smap[1 - cz(q)][tyl + 1 - cy(q)][tx + 1 - cx(q)];
-          mine = 0;
-#pragma unroll
-          for (int q = 1; q < NQ; ++q)
-            if (((lmask >> q) & 1u) && smap[1 - cz(q)][tyl + 1 - cy(q)][tx + 1 - cx(q)] == p) mine |= 1u << q;
-        }
+      for (int q = 1; q < NQ; ++q)
+        if ((all >> q) & 1u)
+          n[q] = RowIO<ST>::ld(rin, opp(q) * pb + rowc + xcb, opp(q), A.h16);
+      const int x = V.x;
+      const bool done = for_each_sphere(sm, s0, sp, cen, all, ph, [&](int p, uint32_t m) {
+        // the sphere's state, all loads issued together
+        const double Rx = A.R[3 * p], Ry = A.R[3 * p + 1], Rz = A.R[3 * p + 2];
+        const double U0 = A.U[3 * p], U1 = A.U[3 * p + 1], U2 = A.U[3 * p + 2];
+        const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
         double Dx, Dy, Dz;
         int k;
-        minimage(A.b, (double)x - A.R[3 * p], (double)y - A.R[3 * p + 1], (double)z - A.R[3 * p + 2],
-                 Dx, Dy, Dz, k);
-        const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
-        const double U0 = A.U[3 * p], U1 = A.U[3 * p + 1], U2 = A.U[3 * p + 2];
-        const int slot = table_slot(skey, p);
-        double *dst = slot >= 0 ? &sval[t & 1][slot][0] : &A.hyd_fb[(size_t)p * HYD];
-        // every link source X - c_q lies in the image of X itself unless X is within one
-        // node of half a period from the centre (thin boxes); then each link finds its own
-        const bool same_image = fabs(Dx) <= 0.5 * A.b.Lx - 1.000001 &&
-                                fabs(Dy) <= 0.5 * A.b.Ly - 1.000001 &&
-                                fabs(Dz) <= 0.5 * A.b.Lz - 1.000001;
-        if (same_image) {
+        minimage(A.b, (double)x - Rx, (double)y - Ry, (double)z - Rz, Dx, Dy, Dz, k);
+        double v[HYD];
+        if (same_image(A.b, Dx, Dy, Dz)) {
+          // rigid-body velocity at the node (eq. 8)
           const double ux = U0 + k * A.b.ule + (w1 * Dz - w2 * Dy);
           const double uy = U1 + (w2 * Dx - w0 * Dz);
           const double uz = U2 + (w0 * Dy - w1 * Dx);
-          double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0, cnt = 0;
+          double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
 #pragma unroll
-          for (int q = 1; q < NQ; ++q) {
-            if ((mine >> q) & 1u) {
-              const double fo = (double)n[q];
-              const double ucq = cx(q) * ux + cy(q) * uy + cz(q) * uz;
-              const double corr = -6.0 * wq(q) * A.rho0 * ucq;
-              n[q] = (CT)(fo - corr);
-              const double m = 2.0 * fo - corr;
-              g0 += cx(q) * m; g1 += cy(q) * m; g2 += cz(q) * m;
-              mxx += cx(q) * cx(q) * m; myy += cy(q) * cy(q) * m; mzz += cz(q) * cz(q) * m;
-              mxy += cx(q) * cy(q) * m; mxz += cx(q) * cz(q) * m; myz += cy(q) * cz(q) * m;
-              cnt += 1.0;
-            }
+          for (int pi = 0; pi < 9; ++pi) {
+            const int q = 2 * pi + 1, b = q + 1;
+            const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
+            const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
+            const double fq = (double)n[q], fb = (double)n[b];
+            const double mq = lq ? fma(2.0, fq, -corr) : 0.0;
+            const double mb = lb ? fma(2.0, fb, corr) : 0.0;
+            const double sm2 = mq + mb, df = mq - mb;
+            addc(g0, cx(q), df); addc(g1, cy(q), df); addc(g2, cz(q), df);
+            if (cx(q) != 0) mxx += sm2;
+            if (cy(q) != 0) myy += sm2;
+            if (cz(q) != 0) mzz += sm2;
+            addc(mxy, cx(q) * cy(q), sm2); addc(mxz, cx(q) * cz(q), sm2); addc(myz, cy(q) * cz(q), sm2);
+            if (lq) n[q] = (CT)(fq - corr);
+            if (lb) n[b] = (CT)(fb + corr);
           }
-          double v[HYD];
           v[0] = -g0; v[1] = -g1; v[2] = -g2;
           v[3] = Dy * v[2] - Dz * v[1];
           v[4] = Dz * v[0] - Dx * v[2];
@@ -224,102 +400,134 @@ __global__ __launch_bounds__(256, 3) void k_lbm(LbmArgs A) {
           v[9] = 0.5 * (Dx * v[1] + Dy * v[0]) + 0.5 * mxy;
           v[10] = 0.5 * (Dx * v[2] + Dz * v[0]) + 0.5 * mxz;
           v[11] = 0.5 * (Dy * v[2] + Dz * v[1]) + 0.5 * myz;
-          v[12] = cnt;
-#pragma unroll
-          for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&dst[c], v[c]);
         } else {
+          // rare: each link with the lever of the image that holds its solid end (eq. 8)
+#pragma unroll
+          for (int c = 0; c < 12; ++c) v[c] = 0.0;
 #pragma unroll
           for (int q = 1; q < NQ; ++q) {
-            if ((mine >> q) & 1u) {
-              // lever of this link from the image that holds its solid end (eq. 8)
+            if ((m >> q) & 1u) {
               double ex, ey, ez;
               int kq;
-              minimage(A.b, (double)(x - cx(q)) - A.R[3 * p], (double)(y - cy(q)) - A.R[3 * p + 1],
-                       (double)(z - cz(q)) - A.R[3 * p + 2], ex, ey, ez, kq);
+              minimage(A.b, (double)(x - cx(q)) - Rx, (double)(y - cy(q)) - Ry, (double)(z - cz(q)) - Rz,
+                       ex, ey, ez, kq);
               const double lvx = ex + 0.5 * cx(q), lvy = ey + 0.5 * cy(q), lvz = ez + 0.5 * cz(q);
               const double ubx = U0 + kq * A.b.ule + (w1 * lvz - w2 * lvy);
               const double uby = U1 + (w2 * lvx - w0 * lvz);
               const double ubz = U2 + (w0 * lvy - w1 * lvx);
+              const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ubx, uby, ubz);
               const double fo = (double)n[q];
-              const double corr = -6.0 * wq(q) * A.rho0 * (cx(q) * ubx + cy(q) * uby + cz(q) * ubz);
               n[q] = (CT)(fo - corr);
-              const double m = 2.0 * fo - corr;
-              const double fx = -cx(q) * m, fy = -cy(q) * m, fz = -cz(q) * m;
-              double v[HYD];
-              v[0] = fx; v[1] = fy; v[2] = fz;
-              v[3] = lvy * fz - lvz * fy;
-              v[4] = lvz * fx - lvx * fz;
-              v[5] = lvx * fy - lvy * fx;
-              v[6] = lvx * fx; v[7] = lvy * fy; v[8] = lvz * fz;
-              v[9] = 0.5 * (lvx * fy + lvy * fx);
-              v[10] = 0.5 * (lvx * fz + lvz * fx);
-              v[11] = 0.5 * (lvy * fz + lvz * fy);
-              v[12] = 1.0;
-#pragma unroll
-              for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&dst[c], v[c]);
+              const double mm = fma(2.0, fo, -corr);
+              double f[3] = {0.0, 0.0, 0.0};
+              addc(f[0], -cx(q), mm); addc(f[1], -cy(q), mm); addc(f[2], -cz(q), mm);
+              v[0] += f[0]; v[1] += f[1]; v[2] += f[2];
+              v[3] += lvy * f[2] - lvz * f[1];
+              v[4] += lvz * f[0] - lvx * f[2];
+              v[5] += lvx * f[1] - lvy * f[0];
+              v[6] += lvx * f[0]; v[7] += lvy * f[1]; v[8] += lvz * f[2];
+              v[9] += 0.5 * (lvx * f[1] + lvy * f[0]);
+              v[10] += 0.5 * (lvx * f[2] + lvz * f[0]);
+              v[11] += 0.5 * (lvy * f[2] + lvz * f[1]);
             }
           }
         }
-        lmask &= ~mine;
-      }
-      if (lmask) atomicOr(A.flags, 8);
-      // ---- eq. (4) moments and BGK collision on the deviations d_q = n_q - w_q rho0 ----
-      CT rd = 0, jx = 0, jy = 0, jz = 0;
+        v[12] = (double)__builtin_popcount(m);
+        const int slot = table_slot(skey, p);
+        double *dst = slot >= 0 ? &sval[t & 1][slot][0] : &A.hyd_fb[(size_t)p * HYD];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        rd += n[q];
-        jx += n[q] * (CT)cx(q);
-        jy += n[q] * (CT)cy(q);
-        jz += n[q] * (CT)cz(q);
+        for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&dst[c], v[c]);
+      });
+      if (!done) atomicOr(A.flags, 8);
+      // ---- moments and BGK collision on the deviations d_q = n_q - w_q rho0, opposite
+      //      directions paired: feq_q,qbar = w (a + 4.5 rho cu^2) +- 3 w rho cu ----
+      CT rd = n[0], jx = 0, jy = 0, jz = 0;
+#pragma unroll
+      for (int pi = 0; pi < 9; ++pi) {
+        const int q = 2 * pi + 1;
+        const CT dq = n[q] - n[q + 1];
+        rd += n[q] + n[q + 1];
+        addc(jx, cx(q), dq); addc(jy, cy(q), dq); addc(jz, cz(q), dq);
       }
-      const CT rho = (CT)A.rho0 + rd;
-      const CT ux = jx / rho, uy = jy / rho, uz = jz / rho;
+      const CT rho = rho0 + rd;
+      const CT ir = (CT)1 / rho;
+      const CT ux = jx * ir, uy = jy * ir, uz = jz * ir;
       const CT uu = ux * ux + uy * uy + uz * uz;
-      const CT om = (CT)A.omega;
-      CT s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+      const CT a = rd - (CT)1.5 * rho * uu;
+      const CT w0 = (CT)(1.0 / 3.0), w1 = (CT)(1.0 / 18.0), w2 = (CT)(1.0 / 36.0);
+      const CT a1 = w1 * a, a2 = w2 * a;
+      const CT b1 = (CT)4.5 * w1 * rho, b2 = (CT)4.5 * w2 * rho;
+      const CT c1 = (CT)3 * w1 * rho, c2 = (CT)3 * w2 * rho;
+      n[0] = fmaT(-om, n[0] - w0 * a, n[0]);
+      CT ps[9];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const CT cu = (CT)cx(q) * ux + (CT)cy(q) * uy + (CT)cz(q) * uz;
-        const CT feqd = (CT)wq(q) * (rd + rho * ((CT)3 * cu + (CT)4.5 * cu * cu - (CT)1.5 * uu));
-        const CT ne = n[q] - feqd;
-        if (cx(q) != 0) s0 += ne;
-        if (cy(q) != 0) s1 += ne;
-        if (cz(q) != 0) s2 += ne;
-        if (cx(q) * cy(q) != 0) s3 += ne * (CT)(cx(q) * cy(q));
-        if (cx(q) * cz(q) != 0) s4 += ne * (CT)(cx(q) * cz(q));
-        if (cy(q) * cz(q) != 0) s5 += ne * (CT)(cy(q) * cz(q));
-        Store<ST>::st(fout + (size_t)q * A.plane, node, n[q] - om * ne, q, A.h16);
+      for (int pi = 0; pi < 9; ++pi) {
+        const int q = 2 * pi + 1, b = q + 1;
+        const CT cu = cdot<CT>(q, ux, uy, uz);
+        const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+        const CT anti = (q <= 6 ? c1 : c2) * cu;
+        const CT neq = n[q] - (sym + anti), neb = n[b] - (sym - anti);
+        ps[pi] = neq + neb;
+        n[q] = fmaT(-om, neq, n[q]);
+        n[b] = fmaT(-om, neb, n[b]);
       }
-      pn[0] += (double)s0; pn[1] += (double)s1; pn[2] += (double)s2;
-      pn[3] += (double)s3; pn[4] += (double)s4; pn[5] += (double)s5;
+      // non-equilibrium momentum flux Pi^neq = sum_q (n_q - feq_q) c_q c_q (pairs add)
+      CT s[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int pi = 0; pi < 9; ++pi) {
+        const int q = 2 * pi + 1;
+        if (cx(q) != 0) s[0] += ps[pi];
+        if (cy(q) != 0) s[1] += ps[pi];
+        if (cz(q) != 0) s[2] += ps[pi];
+        addc(s[3], cx(q) * cy(q), ps[pi]);
+        addc(s[4], cx(q) * cz(q), ps[pi]);
+        addc(s[5], cy(q) * cz(q), ps[pi]);
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) spn[c][t] += (double)s[c];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) n[q] = 0;
     }
-  }
+    // every node of the row is stored, so that the wave writes whole cache lines (HBM3E
+    // has no write mask: a partly written line costs a read-modify-write)
+    if (V.xin) {  // (lanes past the box end would alias the last column through xc)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        RowIO<ST>::st(rout, q * pb + rowc + xcb, n[q], q, A.h16);
+    }
+  });
   __syncthreads();
   // ---- brick table out ----
-  if (bok)
-    for (int i = t; i < TSLOT; i += 256) {
-      const int key = skey[i];
-      A.bt_key[(size_t)brick * TSLOT + i] = key;
-      if (key >= 0)
-        for (int c = 0; c < HYD; ++c)
-          A.bt_val[((size_t)brick * TSLOT + i) * HYD + c] = sval[0][i][c] + sval[1][i][c];
-    }
-  // ---- brick partial of the non-equilibrium momentum flux (fluid stress) ----
-  const int lane = t & 63, wv = t >> 6;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    double v = wave_sum(pn[c]);
-    if (lane == 0) red[wv][c] = v;
+  for (int i = t; i < TSLOT; i += 256) {
+    const int key = skey[i];
+    A.bt_key[(size_t)V.brick * TSLOT + i] = key;
+    if (key >= 0)
+      for (int c = 0; c < HYD; ++c)
+        A.bt_val[((size_t)V.brick * TSLOT + i) * HYD + c] = sval[0][i][c] + sval[1][i][c];
   }
-  __syncthreads();
-  if (t < 6 && bok) A.pineq[(size_t)brick * 6 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  // ---- brick partial of the non-equilibrium momentum flux (fluid stress): the 256
+  //      per-thread partials of each component summed by one wave in a fixed order ----
+  if (V.wv == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double v = wave_sum(spn[c][lane] + spn[c][lane + 64] + spn[c][lane + 128] + spn[c][lane + 192]);
+      if (lane == 0) A.pineq[(size_t)V.brick * 6 + c] = v;
+    }
+  }
 }
 
-hipError_t launch_lbm(Sim *s, const Box &b) {
+static LbmArgs lbm_args(Sim *s, const Box &b) {
   LbmArgs A;
   A.fin = s->f[s->cur];
   A.fout = s->f[1 - s->cur];
   A.plane = s->plane;
+  {
+    const size_t es = s->precision == 0 ? 8 : s->precision == 1 ? 4 : 2;
+    const size_t ges = s->precision == 0 ? 8 : 4;
+    A.pop_bytes = (uint32_t)(NQ * s->plane * es);  // < 2^32, checked at creation
+    A.gval_bytes = (uint32_t)(10 * (size_t)s->lx * s->lz * ges);
+  }
   A.own = s->own;
   A.gown = s->gown;
   A.gval = s->gval;
@@ -338,7 +546,14 @@ hipError_t launch_lbm(Sim *s, const Box &b) {
   A.b = b;
   A.rho0 = s->rho0;
   A.omega = 1.0 / s->tau;
+  A.kax = -6.0 * wq(1) * s->rho0;
+  A.kdg = -6.0 * wq(7) * s->rho0;
   A.h16 = s->h16;
+  return A;
+}
+
+hipError_t launch_lbm(Sim *s, const Box &b) {
+  const LbmArgs A = lbm_args(s, b);
   dim3 grid(A.per_xcd * 8), blk(256);
   if (s->precision == 0) hipLaunchKernelGGL(k_lbm<double>, grid, blk, 0, s->stream, A);
   else if (s->precision == 1) hipLaunchKernelGGL(k_lbm<float>, grid, blk, 0, s->stream, A);
