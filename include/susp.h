@@ -176,6 +176,14 @@ int susp_get_lists(susp_sim *s, int32_t kind, void *host, size_t *bytes);
 /* Resolved constants: {m0, kn, kt, eta_n, lub_delta, F0, debye_lambda, eta0, a_min, a_max}. */
 int susp_get_derived(susp_sim *s, double out[10]);
 
+/* Graph replay of steps (default on).  On a stream other than the null stream, susp_step
+ * records two consecutive steps once as a HIP graph and replays it for pairs of steps
+ * (the buffer parities repeat every two steps; the shear protocol is read from a device
+ * table that susp_step uploads ahead of the steps).  Results are bit-identical to plain
+ * launches.  Off, or on the null stream, or while profiling, every kernel is launched
+ * one by one.                                                                              */
+int susp_use_graphs(susp_sim *s, int32_t enable);
+
 /* Timing of the lattice kernel (fused stream/bounce-back/collide): while enabled, every
  * step records a pair of HIP events around that kernel on the simulation's stream.
  * susp_profile_read synchronises, returns the summed kernel time in milliseconds and the

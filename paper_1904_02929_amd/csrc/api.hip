@@ -244,6 +244,8 @@ static size_t carve(Sim &s, char *base) {
   s.pineq = (double *)take((size_t)s.lbm_blocks * 6 * 8);
   s.acc = (double *)take((size_t)(128 + 128 * 32) * 8);
   s.flags = (int32_t *)take(256);
+  s.clk_tab = (ClockEntry *)take((size_t)CLK_CAP * sizeof(ClockEntry));
+  s.clk = (Clock *)take(sizeof(Clock));
   return off;
 }
 
@@ -295,6 +297,9 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
   s.block = base;
   carve(s, base);
   auto bail = [&](int code) { susp_destroy(h); return code; };
+  if (hipHostMalloc((void **)&s.clk_host, (size_t)CLK_CAP * sizeof(ClockEntry), hipHostMallocDefault))
+    return bail(fail(SUSP_ENOMEM, "pinned clock table"));
+  if (launch_fill_i32((int32_t *)s.clk, sizeof(Clock) / 4, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   const size_t n = (size_t)s.n;
   if (n) {
     std::vector<double> v(n * 4, 0.0), a(n), m(n), I(n), am(n);
@@ -319,6 +324,7 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       return bail(fail(SUSP_EDEVICE, "upload of radii"));
   }
   s.cur = 0; s.pcur = 0; s.hcur = 0; s.lcur = 0; s.hfin = 0; s.step = 0;
+  s.graph_on = 1;
   if (launch_init_populations(&s)) return bail(fail(SUSP_EDEVICE, "init populations"));
   if (launch_fill_i32(s.gown, (size_t)2 * s.lx * s.lz, -1, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   for (int b = 0; b < 2; ++b) {
@@ -348,24 +354,52 @@ extern "C" int susp_destroy(susp_sim *h) {
   if (!h) return SUSP_OK;
   for (int i = 0; i < 2 * h->s.prof_cap; ++i) (void)hipEventDestroy(h->s.prof_ev[i]);
   free(h->s.prof_ev);
-  if (h->s.owns_block && h->s.block) {
-    (void)hipStreamSynchronize(h->s.stream);
-    (void)hipFree(h->s.block);
-  }
+  (void)hipStreamSynchronize(h->s.stream);
+  if (h->s.gexec) (void)hipGraphExecDestroy(h->s.gexec);
+  if (h->s.clk_host) (void)hipHostFree(h->s.clk_host);
+  if (h->s.owns_block && h->s.block) (void)hipFree(h->s.block);
   delete h;
   return SUSP_OK;
 }
 
-// One lattice step (see the header for the order of the parts).
+// Protocol values of step t (shear offset and velocity at t and t+1, G', G'' weights).
+static ClockEntry clock_entry(const Sim &s, int64_t t) {
+  ClockEntry e;
+  memset(&e, 0, sizeof e);
+  protocol(s, t, &e.s, &e.ule);
+  protocol(s, t + 1, &e.s1, &e.ule1);
+  if (s.shear_kind == 2) {
+    const int64_t tI = (int64_t)s.ncyc_I * s.period, tF = tI + (int64_t)s.ncyc_F * s.period;
+    if (t >= tI && t < tF) {
+      const double om = 2.0 * 3.14159265358979323846 / (double)s.period;
+      const double ph = om * (double)(t - tI) + s.theta;
+      e.gphase = 1;
+      e.gcos = cos(ph);
+      e.gsin = sin(ph);
+    }
+  }
+  return e;
+}
+
+// Upload the protocol values of the next m <= CLK_CAP steps and rewind the device cursor.
+// The pinned staging table is reused by the next upload, hence the wait.
+static int upload_clock(Sim &s, int m) {
+  for (int k = 0; k < m; ++k) s.clk_host[k] = clock_entry(s, s.step + k);
+  HIPCHK(hipMemcpyAsync(s.clk_tab, s.clk_host, (size_t)m * sizeof(ClockEntry), hipMemcpyHostToDevice, s.stream));
+  HIPCHK(launch_clock(&s, 1));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+// One lattice step (see the header for the order of the parts).  Every kernel argument is
+// fixed except the buffer parities, which repeat every two steps; the shear offsets come
+// from the device clock.
 static int one_step(Sim &s) {
-  const int64_t t = s.step;
-  double off, ule, off1, ule1;
-  protocol(s, t, &off, &ule);
-  protocol(s, t + 1, &off1, &ule1);
-  const Box b = make_box(s, off, ule), b1 = make_box(s, off1, ule1);
+  const Box b = make_box(s, 0.0, 0.0);  // dimensions only
+  HIPCHK(launch_clock(&s, 0));
   s.hcur ^= 1;
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
-  HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1));
+  HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
@@ -388,27 +422,65 @@ static int one_step(Sim &s) {
     s.lcur ^= 1;
     HIPCHK(launch_pair_rev(&s));
     for (int k = 0; k < s.n_sub; ++k) {
-      HIPCHK(launch_substep(&s, b, k, off1, ule1));
+      HIPCHK(launch_substep(&s, b, k));
       s.pcur ^= 1;
     }
     s.hfin = (1 - s.hfin + s.n_sub) & 1;
-    HIPCHK(launch_map_update(&s, b, b1, 1));
-    HIPCHK(launch_map_update(&s, b, b1, 2));
+    HIPCHK(launch_map_update(&s, b, 1));
+    HIPCHK(launch_map_update(&s, b, 2));
   }
-  int gphase = 0;
-  double gc = 0, gsn = 0;
-  if (s.shear_kind == 2) {
-    const int64_t tI = (int64_t)s.ncyc_I * s.period, tF = tI + (int64_t)s.ncyc_F * s.period;
-    if (t >= tI && t < tF) {
-      const double om = 2.0 * 3.14159265358979323846 / (double)s.period;
-      const double ph = om * (double)(t - tI) + s.theta;
-      gphase = 1;
-      gc = cos(ph);
-      gsn = sin(ph);
+  HIPCHK(launch_stress(&s));
+  s.step += 1;
+  return SUSP_OK;
+}
+
+static int parity(const Sim &s) { return s.cur | (s.lcur << 1) | (s.hcur << 2) | (s.pcur << 3) | (s.hfin << 4); }
+
+// Record two steps on the simulation's stream as one graph.  The buffer parities repeat
+// every two steps, so the graph replays from the parity it was recorded at; recording does
+// not execute anything, so the host clock and parities are restored afterwards.
+static int record_graph(Sim &s) {
+  const int64_t step = s.step;
+  const int par = parity(s);
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
+  int rc = one_step(s);
+  if (!rc) rc = one_step(s);
+  hipError_t e = hipStreamEndCapture(s.stream, &g);
+  s.step = step;
+  if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return fail(SUSP_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  if (parity(s) != par) { (void)hipGraphDestroy(g); return fail(SUSP_ESTATE, "step parities do not repeat"); }
+  e = hipGraphInstantiate(&s.gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) { s.gexec = nullptr; return fail(SUSP_EDEVICE, "graph instantiate: %s", hipGetErrorString(e)); }
+  s.gparity = par;
+  return SUSP_OK;
+}
+
+// m steps whose clock table is on the device: pairs of steps by graph replay where possible.
+static int run_steps(Sim &s, int m) {
+  const bool graph = s.graph_on && s.stream != nullptr && !s.prof_on;
+  int k = 0;
+  if (graph && m >= 2) {
+    if (!s.gexec) {
+      int rc = record_graph(s);
+      if (rc) return rc;
+    }
+    if (parity(s) != s.gparity) {  // one plain step brings the parities back
+      int rc = one_step(s);
+      if (rc) return rc;
+      ++k;
+    }
+    for (; k + 2 <= m; k += 2) {
+      HIPCHK(hipGraphLaunch(s.gexec, s.stream));
+      s.step += 2;
     }
   }
-  HIPCHK(launch_stress(&s, gphase, gc, gsn));
-  s.step = t + 1;
+  for (; k < m; ++k) {
+    int rc = one_step(s);
+    if (rc) return rc;
+  }
   return SUSP_OK;
 }
 
@@ -416,9 +488,12 @@ extern "C" int susp_step(susp_sim *h, int64_t nsteps) {
   if (!h) return fail(SUSP_EINVAL, "NULL simulation");
   if (nsteps < 0) return fail(SUSP_EINVAL, "negative step count");
   Sim &s = h->s;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    int rc = one_step(s);
+  for (int64_t done = 0; done < nsteps;) {
+    const int m = (int)(nsteps - done < CLK_CAP ? nsteps - done : CLK_CAP);
+    int rc = upload_clock(s, m);
+    if (!rc) rc = run_steps(s, m);
     if (rc) return rc;
+    done += m;
   }
   int32_t fl = 0;
   int rc = read_flags(s, &fl);
@@ -666,7 +741,7 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     HIPCHK(hipMalloc((void **)&g, (size_t)2 * s.lx * s.lz * 4));
     hipError_t e = hipMalloc((void **)&lk, (size_t)NQ * s.nodes * 4);
     if (!e && n) e = launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr);
-    if (!e) e = n ? launch_ghosts(&s, b, g, s.gval, 0) : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
+    if (!e) e = n ? launch_ghosts(&s, b, g, s.gval, 0, nullptr) : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
     if (!e) e = launch_link_enum(&s, g, lk, b);
     std::vector<int32_t> all;
     if (!e) {
@@ -692,6 +767,12 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     if (cap < need) return fail(SUSP_EINVAL, "buffer of %zu bytes < %zu", cap, need);
     memcpy(host, out.data(), need);
   }
+  return SUSP_OK;
+}
+
+extern "C" int susp_use_graphs(susp_sim *h, int32_t enable) {
+  if (!h) return fail(SUSP_EINVAL, "NULL simulation");
+  h->s.graph_on = enable ? 1 : 0;
   return SUSP_OK;
 }
 

@@ -70,7 +70,8 @@ struct LbmArgs {
   int lx, ly, lz;
   int bxn, byn, bzn, BY, BZ;
   int nbricks, per_xcd;
-  Box b;
+  Box b;              // static dimensions; offset and velocity come from clk
+  const Clock *clk;
   double rho0, omega;
   double kax, kdg;  // -6 w_q rho0 of the axis and of the diagonal directions
   H16 h16;
@@ -304,13 +305,13 @@ __device__ inline bool same_image(const Box &b, double Dx, double Dy, double Dz)
 template <class ST>
 __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   using CT = typename Store<ST>::CT;
-  constexpr bool kPlain = std::is_same<ST, CT>::value;  // ghost rows share the storage type
   __shared__ int32_t smap[4][SPLANE];
   __shared__ int32_t skey[TSLOT];
   __shared__ double sval[2][TSLOT][HYD];
   __shared__ double spn[6][256];  // per-thread fluid stress partials
   BrickView V;
   if (!brick_view(A, V)) return;  // the whole work-group
+  const Box bx = clock_box(A.b, A.clk, 0);
   const int t = V.t, lane = V.lane;
   const int lx = A.lx, ly = A.ly, lz = A.lz;
   const size_t plane = A.plane;
@@ -365,11 +366,11 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
         const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
         double Dx, Dy, Dz;
         int k;
-        minimage(A.b, (double)x - Rx, (double)y - Ry, (double)z - Rz, Dx, Dy, Dz, k);
+        minimage(bx, (double)x - Rx, (double)y - Ry, (double)z - Rz, Dx, Dy, Dz, k);
         double v[HYD];
-        if (same_image(A.b, Dx, Dy, Dz)) {
+        if (same_image(bx, Dx, Dy, Dz)) {
           // rigid-body velocity at the node (eq. 8)
-          const double ux = U0 + k * A.b.ule + (w1 * Dz - w2 * Dy);
+          const double ux = U0 + k * bx.ule + (w1 * Dz - w2 * Dy);
           const double uy = U1 + (w2 * Dx - w0 * Dz);
           const double uz = U2 + (w0 * Dy - w1 * Dx);
           double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
@@ -409,10 +410,10 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
             if ((m >> q) & 1u) {
               double ex, ey, ez;
               int kq;
-              minimage(A.b, (double)(x - cx(q)) - Rx, (double)(y - cy(q)) - Ry, (double)(z - cz(q)) - Rz,
+              minimage(bx, (double)(x - cx(q)) - Rx, (double)(y - cy(q)) - Ry, (double)(z - cz(q)) - Rz,
                        ex, ey, ez, kq);
               const double lvx = ex + 0.5 * cx(q), lvy = ey + 0.5 * cy(q), lvz = ez + 0.5 * cz(q);
-              const double ubx = U0 + kq * A.b.ule + (w1 * lvz - w2 * lvy);
+              const double ubx = U0 + kq * bx.ule + (w1 * lvz - w2 * lvy);
               const double uby = U1 + (w2 * lvx - w0 * lvz);
               const double ubz = U2 + (w0 * lvy - w1 * lvx);
               const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ubx, uby, ubz);
@@ -544,6 +545,7 @@ static LbmArgs lbm_args(Sim *s, const Box &b) {
   A.nbricks = s->nbricks;
   A.per_xcd = (s->nbricks + 7) / 8;
   A.b = b;
+  A.clk = s->clk;
   A.rho0 = s->rho0;
   A.omega = 1.0 / s->tau;
   A.kax = -6.0 * wq(1) * s->rho0;
@@ -571,7 +573,7 @@ struct GatherArgs {
   double *hyd_fb;
   double *hyd;
   int n, lx, ly, lz, bxn, byn, BY, BZ;
-  double s;
+  const Clock *clk;  // LE offset of the step
 };
 
 // Next node coordinate (along a periodic axis of length L with bricks of B nodes) that
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(256) void k_hydro_gather(GatherArgs A) {
     if (ylo < 0) ylo = 0;
     if (yhi > A.ly - 1) yhi = A.ly - 1;
     if (ylo > yhi) continue;
-    const double cx_ = A.R[3 * p] + k * A.s;
+    const double cx_ = A.R[3 * p] + k * A.clk->cur.s;
     int xlo = (int)floor(cx_ - r), xhi = (int)ceil(cx_ + r);
     if (xhi - xlo + 1 >= A.lx) { xlo = 0; xhi = A.lx - 1; }
     for (int zz = zlo; zz <= zhi; zz = next_brick_start(zz, A.lz, A.BZ)) {
@@ -656,7 +658,8 @@ hipError_t launch_hydro_gather(Sim *s, const Box &b) {
   A.hyd = s->hyd[s->hcur];
   A.n = s->n; A.lx = s->lx; A.ly = s->ly; A.lz = s->lz;
   A.bxn = s->bxn; A.byn = s->byn; A.BY = s->BY; A.BZ = s->BZ;
-  A.s = b.s;
+  A.clk = s->clk;
+  (void)b;
   if (s->n > 0)
     hipLaunchKernelGGL(k_hydro_gather, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, A);
   return hipGetLastError();
@@ -670,7 +673,8 @@ struct GhostArgs {
   const double *R, *U, *W, *amap;
   const int32_t *cell_start, *cell_ids;
   Cells C;
-  Box b;
+  Box b;             // with clk set, offset and velocity come from the clock
+  const Clock *clk;
   int lx, ly, lz, n;
   double rho0;
   int values;
@@ -721,6 +725,7 @@ __device__ inline CT nhat(const ST *fin, size_t plane, const int32_t *own, const
 template <class ST>
 __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   using CT = typename Store<ST>::CT;
+  const Box bx = clock_box(A.b, A.clk, 0);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int npl = A.lx * A.lz;
   if (idx >= 2 * npl) return;
@@ -729,8 +734,8 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   const int z = rem / A.lx, x = rem - (rem / A.lx) * A.lx;
   const double gy = g == 0 ? -1.0 : (double)A.ly;
   // primary-box position of the ghost point, for the cell search only
-  double px = g == 0 ? (double)x + A.b.s : (double)x - A.b.s;
-  px = px - A.b.Lx * floor(px / A.b.Lx);
+  double px = g == 0 ? (double)x + bx.s : (double)x - bx.s;
+  px = px - bx.Lx * floor(px / bx.Lx);
   const double py = g == 0 ? (double)(A.ly - 1) : 0.0;
   int owner = -1, clash = 0;
   if (A.n > 0) {
@@ -743,9 +748,9 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
     for (int dy = -1; dy <= 1; ++dy) {
       int ny = ccy + dy;
       double xs = px;
-      if (ny < 0) { ny += C.ny; xs = px + A.b.s; }
-      else if (ny >= C.ny) { ny -= C.ny; xs = px - A.b.s; }
-      xs = xs - A.b.Lx * floor(xs / A.b.Lx);
+      if (ny < 0) { ny += C.ny; xs = px + bx.s; }
+      else if (ny >= C.ny) { ny -= C.ny; xs = px - bx.s; }
+      xs = xs - bx.Lx * floor(xs / bx.Lx);
       int ccx = (int)floor(xs * C.ix);
       ccx = ccx < 0 ? 0 : (ccx >= C.nx ? C.nx - 1 : ccx);
       for (int iz = 0; iz < zn; ++iz) {
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
             const int p = A.cell_ids[t];
             double dx, dy2, dz;
             int k;
-            minimage(A.b, (double)x - A.R[3 * p], gy - A.R[3 * p + 1], (double)z - A.R[3 * p + 2],
+            minimage(bx, (double)x - A.R[3 * p], gy - A.R[3 * p + 1], (double)z - A.R[3 * p + 2],
                      dx, dy2, dz, k);
             const double r2 = dx * dx + dy2 * dy2 + dz * dz;
             if (r2 < A.amap[p] * A.amap[p]) {
@@ -778,7 +783,7 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   CT *gval = (CT *)A.gval;
   const int sgn = g == 0 ? 1 : -1;
   const int yrow = g == 0 ? A.ly - 1 : 0;
-  const double xs = (double)x + sgn * A.b.s;
+  const double xs = (double)x + sgn * bx.s;
   const double x0f = floor(xs);
   const double fr = xs - x0f;
   int i0 = (int)x0f % A.lx;
@@ -786,13 +791,13 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   const int i1 = i0 + 1 == A.lx ? 0 : i0 + 1;
   for (int m = 0; m < 5; ++m) {
     const int q = gdir(g, m);
-    const CT v0 = nhat<ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, A.b, A.rho0, A.h16, q, i0, yrow, z, sgn);
-    const CT v1 = nhat<ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, A.b, A.rho0, A.h16, q, i1, yrow, z, sgn);
+    const CT v0 = nhat<ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, bx, A.rho0, A.h16, q, i0, yrow, z, sgn);
+    const CT v1 = nhat<ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, bx, A.rho0, A.h16, q, i1, yrow, z, sgn);
     gval[(size_t)((g * 5 + m) * A.lz + z) * A.lx + x] = ((CT)1 - (CT)fr) * v0 + (CT)fr * v1;
   }
 }
 
-hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values) {
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk) {
   GhostArgs A;
   A.fin = s->f[s->cur];
   A.plane = s->plane;
@@ -803,6 +808,7 @@ hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out
   A.cell_ids = s->cell_ids;
   A.C = s->cells;
   A.b = b;
+  A.clk = clk;
   A.lx = s->lx; A.ly = s->ly; A.lz = s->lz; A.n = s->n;
   A.rho0 = s->rho0;
   A.values = values;
@@ -815,6 +821,25 @@ hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out
   if (s->precision == 0) hipLaunchKernelGGL(k_ghosts<double>, grid, blk, 0, s->stream, A);
   else if (s->precision == 1) hipLaunchKernelGGL(k_ghosts<float>, grid, blk, 0, s->stream, A);
   else hipLaunchKernelGGL(k_ghosts<__half>, grid, blk, 0, s->stream, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Start of a step: the table entry of the step becomes the current clock (reset: rewind the
+// cursor after a new table upload).
+__global__ void k_clock(const ClockEntry *tab, Clock *clk, int reset) {
+  if (threadIdx.x != 0) return;
+  if (reset) {
+    clk->idx = 0;
+    return;
+  }
+  const int i = clk->idx;
+  clk->cur = tab[i < CLK_CAP ? i : CLK_CAP - 1];
+  clk->idx = i + 1;
+}
+
+hipError_t launch_clock(Sim *s, int reset) {
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s->stream, s->clk_tab, s->clk, reset);
   return hipGetLastError();
 }
 

@@ -198,7 +198,8 @@ struct PairArgs {
   const double *R, *a, *amap;
   const int32_t *cell_start, *cell_ids;
   Cells C;
-  Box b;
+  Box b;             // static dimensions; offset from clk
+  const Clock *clk;
   int n;
   double cutoff;
   int32_t *cnt, *nj;                 // new list
@@ -213,17 +214,18 @@ struct PairArgs {
 __global__ __launch_bounds__(128) void k_pairs(PairArgs A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
+  const Box bx = clock_box(A.b, A.clk, 0);
   int32_t js[NCAP];
   int c = 0, over = 0, ovl = 0;
   const double *R = A.R;
-  near_cells(A.C, A.b, R[3 * i], R[3 * i + 1], R[3 * i + 2], [&](int cell) {
+  near_cells(A.C, bx, R[3 * i], R[3 * i + 1], R[3 * i + 2], [&](int cell) {
     for (int t = A.cell_start[cell]; t < A.cell_start[cell + 1]; ++t) {
       const int j = A.cell_ids[t];
       if (j == i) continue;
       const int lo = i < j ? i : j, hi = i < j ? j : i;
       double dx, dy, dz;
       int k;
-      const double r2 = pair_geo(A.b, R, lo, hi, dx, dy, dz, k);
+      const double r2 = pair_geo(bx, R, lo, hi, dx, dy, dz, k);
       const double rc = A.a[lo] + A.a[hi] + A.cutoff;
       if (r2 < rc * rc) {
         if (c < NCAP) js[c++] = j; else over = 1;
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(128) void k_pairs(PairArgs A) {
     A.on[e] = on;
     double dx, dy, dz;
     int k;
-    const double r2 = pair_geo(A.b, R, i, j, dx, dy, dz, k);
+    const double r2 = pair_geo(bx, R, i, j, dx, dy, dz, k);
     A.hstart[e] = (sqrt(r2) - A.a[i] - A.a[j]) < 0.0 ? 1 : 0;
   }
 }
@@ -268,7 +270,7 @@ hipError_t launch_pairs(Sim *s, const Box &b) {
   PairArgs A;
   A.R = s->R[s->pcur]; A.a = s->a; A.amap = s->amap;
   A.cell_start = s->cell_start; A.cell_ids = s->cell_ids;
-  A.C = s->cells; A.b = b; A.n = s->n; A.cutoff = s->pair_cutoff;
+  A.C = s->cells; A.b = b; A.clk = s->clk; A.n = s->n; A.cutoff = s->pair_cutoff;
   const int nl = 1 - s->lcur;
   A.cnt = s->ncnt[nl]; A.nj = s->nj[nl];
   A.ocnt = s->ncnt[s->lcur]; A.onj = s->nj[s->lcur];
@@ -476,8 +478,9 @@ struct SubArgs {
   int32_t *onout;
   double *pst;
   Phys P;
-  Box b;
-  double dts, s1, ule1;
+  Box b;             // static dimensions; offsets of this and the next step from clk
+  const Clock *clk;
+  double dts;
   int n, sub, last, quasi2d;
   int32_t *flags;
 };
@@ -499,6 +502,8 @@ __device__ inline double gsum16(double v) {
 // the sphere's neighbours.  Both spheres of a pair evaluate the identical pair expression;
 // the lower id owns the spring history and the pair's stress.
 __global__ __launch_bounds__(256) void k_substep(SubArgs A) {
+  const Box bx = clock_box(A.b, A.clk, 0);
+  const double s1 = A.clk->cur.s1, ule1 = A.clk->cur.ule1;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int l = lane & 15;
@@ -515,8 +520,8 @@ __global__ __launch_bounds__(256) void k_substep(SubArgs A) {
     const size_t e = re >= 0 ? (size_t)re : own_e;
     double d[3];
     int k;
-    pair_geo(A.b, A.Ri, lo, hi, d[0], d[1], d[2], k);
-    const double Uh[3] = {A.Ui[3 * hi] + k * A.b.ule, A.Ui[3 * hi + 1], A.Ui[3 * hi + 2]};
+    pair_geo(bx, A.Ri, lo, hi, d[0], d[1], d[2], k);
+    const double Uh[3] = {A.Ui[3 * hi] + k * bx.ule, A.Ui[3 * hi + 1], A.Ui[3 * hi + 2]};
     double xi[3] = {A.xin[3 * e], A.xin[3 * e + 1], A.xin[3 * e + 2]};
     PairOut o;
     pair_forces(A.P, A.a[lo], A.a[hi], d, &A.Ui[3 * lo], Uh, &A.Wi[3 * lo], &A.Wi[3 * hi], A.dts,
@@ -558,12 +563,12 @@ __global__ __launch_bounds__(256) void k_substep(SubArgs A) {
   qw += 0.5 * A.dts * dw; qx += 0.5 * A.dts * dx; qy += 0.5 * A.dts * dy; qz += 0.5 * A.dts * dz;
   const double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   if (A.last) {  // Lees-Edwards wrap with the offset of the next step
-    if (R[1] >= A.b.Ly) { R[1] -= A.b.Ly; R[0] -= A.s1; U[0] -= A.ule1; }
-    else if (R[1] < 0.0) { R[1] += A.b.Ly; R[0] += A.s1; U[0] += A.ule1; }
-    for (int it = 0; it < 4 && R[0] >= A.b.Lx; ++it) R[0] -= A.b.Lx;
-    for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += A.b.Lx;
-    for (int it = 0; it < 4 && R[2] >= A.b.Lz; ++it) R[2] -= A.b.Lz;
-    for (int it = 0; it < 4 && R[2] < 0.0; ++it) R[2] += A.b.Lz;
+    if (R[1] >= bx.Ly) { R[1] -= bx.Ly; R[0] -= s1; U[0] -= ule1; }
+    else if (R[1] < 0.0) { R[1] += bx.Ly; R[0] += s1; U[0] += ule1; }
+    for (int it = 0; it < 4 && R[0] >= bx.Lx; ++it) R[0] -= bx.Lx;
+    for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += bx.Lx;
+    for (int it = 0; it < 4 && R[2] >= bx.Lz; ++it) R[2] -= bx.Lz;
+    for (int it = 0; it < 4 && R[2] < 0.0; ++it) R[2] += bx.Lz;
   }
   for (int c = 0; c < 3; ++c) { A.Uo[3 * i + c] = U[c]; A.Wo[3 * i + c] = W[c]; A.Ro[3 * i + c] = R[c]; }
   A.Qo[4 * i] = qw / nn; A.Qo[4 * i + 1] = qx / nn; A.Qo[4 * i + 2] = qy / nn; A.Qo[4 * i + 3] = qz / nn;
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(256) void k_substep(SubArgs A) {
   }
 }
 
-hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1) {
+hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   SubArgs A;
   const int pi = s->pcur, po = 1 - s->pcur;
   A.Ri = s->R[pi]; A.Ui = s->U[pi]; A.Wi = s->W[pi]; A.Qi = s->Q[pi];
@@ -593,7 +598,7 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1)
   A.P.eta0 = s->eta0; A.P.cutoff = s->pair_cutoff; A.P.lub_sub = s->lub_sub;
   A.b = b;
   A.dts = 1.0 / (double)s->n_sub;
-  A.s1 = s1; A.ule1 = ule1;
+  A.clk = s->clk;
   A.n = s->n; A.sub = sub; A.last = sub == s->n_sub - 1; A.quasi2d = s->quasi2d;
   A.flags = s->flags;
   if (s->n > 0)
@@ -721,7 +726,8 @@ struct MapArgs {
   int32_t *own;
   void *f;
   size_t plane;
-  Box bnew, bold;
+  Box b;             // static dimensions; offsets before and after the step from clk
+  const Clock *clk;
   double rho0;
   int quasi2d;
   double *dp;
@@ -729,16 +735,17 @@ struct MapArgs {
   H16 h16;
 };
 
-__device__ inline bool inside_new(const MapArgs &A, int v, double x, double y, double z) {
+__device__ inline bool inside_new(const MapArgs &A, const Box &bnew, int v, double x, double y, double z) {
   double d0, d1, d2;
   int k;
-  minimage(A.bnew, x - A.R[3 * v], y - A.R[3 * v + 1], z - A.R[3 * v + 2], d0, d1, d2, k);
+  minimage(bnew, x - A.R[3 * v], y - A.R[3 * v + 1], z - A.R[3 * v + 2], d0, d1, d2, k);
   return d0 * d0 + d1 * d1 + d2 * d2 < A.amap[v] * A.amap[v];
 }
 
 template <class ST, int PHASE>
 __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   using CT = typename Store<ST>::CT;
+  const Box bnew = clock_box(A.b, A.clk, 1), bold = clock_box(A.b, A.clk, 0);
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
   const double *Rn = &A.R[3 * p], *Ro = &A.R0[3 * p];
@@ -751,10 +758,10 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   const double a2 = a * a;
   double e0, e1, e2;
   int ke;
-  minimage(A.bnew, Rn[0] - Ro[0], Rn[1] - Ro[1], Rn[2] - Ro[2], e0, e1, e2, ke);
-  const double delta = sqrt(e0 * e0 + e1 * e1 + e2 * e2) + fabs(A.bnew.s - A.bold.s) + 1e-6;
+  minimage(bnew, Rn[0] - Ro[0], Rn[1] - Ro[1], Rn[2] - Ro[2], e0, e1, e2, ke);
+  const double delta = sqrt(e0 * e0 + e1 * e1 + e2 * e2) + fabs(bnew.s - bold.s) + 1e-6;
   const double ro = a + delta, ri = a - delta;
-  const Box &B = A.bnew;
+  const Box &B = bnew;
   // rows (y, z) of the shell around each image of the new position
   int zlo = (int)floor(Rn[2] - ro), zhi = (int)ceil(Rn[2] + ro);
   const bool zall = zhi - zlo + 1 >= B.lz;
@@ -815,7 +822,7 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
         const bool in_new = dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2] < a2;
         double dd0, dd1, dd2;
         int ko;
-        minimage(A.bold, (double)x - Ro[0], (double)y - Ro[1], (double)z - Ro[2], dd0, dd1, dd2, ko);
+        minimage(bold, (double)x - Ro[0], (double)y - Ro[1], (double)z - Ro[2], dd0, dd1, dd2, ko);
         const bool in_old = dd0 * dd0 + dd1 * dd1 + dd2 * dd2 < a2;
         const int64_t node = x + (int64_t)B.lx * (y + (int64_t)B.ly * z);
         if (PHASE == 1 && in_new && !in_old) {
@@ -836,7 +843,7 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
             acc[5] += dn[0] * j1 - dn[1] * j0;
             acc[6] += rho;
           } else if (v != p) {
-            if (inside_new(A, v, x, y, z)) {  // both spheres hold the node: overlap
+            if (inside_new(A, bnew, v, x, y, z)) {  // both spheres hold the node: overlap
               atomicMin(&A.own[node], p);
               atomicOr(A.flags, 1);
             } else if (atomicCAS(&A.own[node], v, p) != v) {  // v left it; a third claim is an overlap
@@ -888,14 +895,14 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   for (int c = 0; c < 3; ++c) { A.Uw[3 * p + c] = U[c]; A.Ww[3 * p + c] = W[c]; }
 }
 
-hipError_t launch_map_update(Sim *s, const Box &bold, const Box &bnew, int phase) {
+hipError_t launch_map_update(Sim *s, const Box &box, int phase) {
   MapArgs A;
   A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
   A.R0 = s->R0; A.amap = s->amap; A.m = s->m; A.I = s->I;
   A.Uw = s->U[s->pcur]; A.Ww = s->W[s->pcur];
   A.own = s->own;
   A.f = s->f[s->cur]; A.plane = s->plane;
-  A.bnew = bnew; A.bold = bold;
+  A.b = box; A.clk = s->clk;
   A.rho0 = s->rho0; A.quasi2d = s->quasi2d;
   A.dp = s->dp; A.flags = s->flags;
   A.h16 = s->h16;
@@ -943,7 +950,7 @@ __global__ __launch_bounds__(256) void k_reduce1(const double *pineq, int nblk, 
 // acc layout: [0,30) sig_last, [30,60) sig_sum, 60 count, 61 gp_cos, 62 gp_sin, 63 gp_count,
 // 64 ledger
 __global__ void k_reduce2(const double *part, double *acc, double cf, double invV, double invns,
-                          int gphase, double gcos, double gsin, int has_particles) {
+                          const Clock *clk, int has_particles) {
   __shared__ double v[32];
   const int c = threadIdx.x;
   if (c < 31) {
@@ -965,18 +972,19 @@ __global__ void k_reduce2(const double *part, double *acc, double cf, double inv
   for (int k = 0; k < 5; ++k) sxy += sig[6 * k + 3];
   for (int k = 0; k < 30; ++k) { acc[k] = sig[k]; acc[30 + k] += sig[k]; }
   acc[60] += 1.0;
-  if (gphase) { acc[61] += sxy * gcos; acc[62] += sxy * gsin; acc[63] += 1.0; }
+  const ClockEntry &ce = clk->cur;
+  if (ce.gphase) { acc[61] += sxy * ce.gcos; acc[62] += sxy * ce.gsin; acc[63] += 1.0; }
   acc[64] += v[30];
 }
 
-hipError_t launch_stress(Sim *s, int gphase, double gcos, double gsin) {
+hipError_t launch_stress(Sim *s) {
   double *part = s->acc + 128;
   hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, s->stream, s->pineq,
                      s->lbm_blocks, s->hyd[s->hcur], s->pst, s->dp, s->n, part);
   const double V = (double)s->lx * s->ly * s->lz;
   const double cf = -(1.0 - 0.5 / s->tau) / V;
   hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, 1.0 / V,
-                     1.0 / (double)s->n_sub, gphase, gcos, gsin, s->n > 0 ? 1 : 0);
+                     1.0 / (double)s->n_sub, s->clk, s->n > 0 ? 1 : 0);
   return hipGetLastError();
 }
 

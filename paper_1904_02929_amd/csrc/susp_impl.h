@@ -98,6 +98,31 @@ template <> struct Store<__half> {
   }
 };
 
+// Shear-protocol values of one lattice step t (eq. 16 or simple shear): LE offset and
+// velocity at t and t+1, and the G', G'' quadrature weights of the step.  The host writes a
+// table of them ahead of a run of steps; k_clock copies entry idx to cur at the start of
+// each step, so that a recorded sequence of steps (a HIP graph) replays with fixed
+// kernel arguments.
+struct ClockEntry {
+  double s, ule, s1, ule1, gcos, gsin;
+  int32_t gphase, pad;
+};
+struct Clock {
+  ClockEntry cur;
+  int32_t idx, pad;
+};
+constexpr int CLK_CAP = 4096;  // steps per table upload
+
+// Box of the current step (next = 0: offset s, velocity ule) or of the next one (s1, ule1)
+// from the device clock; without a clock the box is used as given.
+__device__ inline Box clock_box(Box b, const Clock *c, int next) {
+  if (c) {
+    b.s = next ? c->cur.s1 : c->cur.s;
+    b.ule = next ? c->cur.ule1 : c->cur.ule;
+  }
+  return b;
+}
+
 // Cell grid for the neighbour search.
 struct Cells {
   int nx, ny, nz;
@@ -108,7 +133,7 @@ struct Sim;
 
 // ---- launchers (fluid.hip) ----
 hipError_t launch_init_populations(Sim *s);
-hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values);
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk);
 hipError_t launch_lbm(Sim *s, const Box &b);
 hipError_t launch_hydro_gather(Sim *s, const Box &b);
 hipError_t launch_pop_convert(Sim *s, double *dev64, int to_storage);
@@ -117,11 +142,12 @@ hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[19][nod
 hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch);
 hipError_t launch_pairs(Sim *s, const Box &b);
 hipError_t launch_pair_rev(Sim *s);
-hipError_t launch_substep(Sim *s, const Box &b, int sub, double s1, double ule1);
+hipError_t launch_substep(Sim *s, const Box &b, int sub);
 hipError_t launch_map_full(Sim *s, const Box &b);
-hipError_t launch_map_update(Sim *s, const Box &bold, const Box &bnew, int phase);
-hipError_t launch_stress(Sim *s, int gphase, double gcos, double gsin);
+hipError_t launch_map_update(Sim *s, const Box &b, int phase);
+hipError_t launch_stress(Sim *s);
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
+hipError_t launch_clock(Sim *s, int reset);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 
 struct Sim {
@@ -181,6 +207,13 @@ struct Sim {
   int32_t *flags;
   // clock
   int64_t step;
+  ClockEntry *clk_tab;   // device table of the next steps' protocol values
+  Clock *clk;            // device: current entry and table cursor
+  ClockEntry *clk_host;  // pinned host staging of the table
+  // two recorded steps replayed as one HIP graph (streams other than the null stream)
+  int graph_on;            // use the graph when possible
+  hipGraphExec_t gexec;    // null until recorded
+  int gparity;             // cur ^ 2 lcur ^ 4 hcur ^ 8 pcur ^ 16 hfin at recording
   // optional timing of the lattice kernel with HIP events on the simulation's stream
   int prof_on;
   int prof_used, prof_cap;

@@ -73,6 +73,7 @@ def lib():
         L.susp_get_hydro.argtypes = [vp, _PD, _PD, _PD, _PI]
         L.susp_get_lists.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_size_t)]
         L.susp_get_derived.argtypes = [vp, _PD]
+        L.susp_use_graphs.argtypes = [vp, C.c_int32]
         L.susp_profile.argtypes = [vp, C.c_int32]
         L.susp_profile_read.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
         L.susp_last_error.restype = C.c_char_p
@@ -172,6 +173,9 @@ class Simulation:
         if check:
             _chk(rc)
         return rc
+
+    def use_graphs(self, enable=True):
+        _chk(lib().susp_use_graphs(self.h, 1 if enable else 0))
 
     def profile(self, enable=True):
         _chk(lib().susp_profile(self.h, 1 if enable else 0))
