@@ -46,9 +46,11 @@ template <class T> __device__ inline T wave_sum(T v) {
 // (exactly the link sums of eqs. 6, 9, 10 regrouped).  A sphere is convex, so of two
 // opposite directions at most one links the node to the same sphere; the sums are formed
 // per opposite pair, in FP64 (torque and stresslet cancel strongly over a surface).
-// Per-sphere sums of the brick are accumulated in an LDS hash table (two copies to halve
-// atomic contention) and written once per brick; k_hydro_gather adds a sphere's brick
-// entries in a fixed order.
+// Per-sphere sums of the brick are accumulated in an LDS hash table with one copy per wave
+// (a wave adds its lanes in a fixed order; the copies are summed in wave order) and written
+// once per brick; k_hydro_gather adds a sphere's brick entries in a fixed order.  The sums
+// are therefore bitwise reproducible (unless a brick touches more than TSLOT spheres, whose
+// overflow goes through global atomics).
 constexpr int TX = 64, TY = 4;
 constexpr int TSLOT = 128;
 constexpr int SROW = TX + 2, SPLANE = (TY + 2) * SROW;  // staged owner plane: 6 rows of 66
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   using CT = typename Store<ST>::CT;
   __shared__ int32_t smap[4][SPLANE];
   __shared__ int32_t skey[TSLOT];
-  __shared__ double sval[2][TSLOT][HYD];
+  __shared__ double sval[4][TSLOT][HYD];  // one copy per wave: a fixed summation order
   __shared__ double spn[6][256];  // per-thread fluid stress partials
   BrickView V;
   if (!brick_view(A, V)) return;  // the whole work-group
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   const int lx = A.lx, ly = A.ly, lz = A.lz;
   const size_t plane = A.plane;
   for (int i = t; i < TSLOT; i += 256) skey[i] = -1;
-  for (int i = t; i < 2 * TSLOT * HYD; i += 256) (&sval[0][0][0])[i] = 0.0;
+  for (int i = t; i < 4 * TSLOT * HYD; i += 256) (&sval[0][0][0])[i] = 0.0;
 #pragma unroll
   for (int c = 0; c < 6; ++c) spn[c][t] = 0.0;
   const CT om = (CT)A.omega;
@@ -435,7 +437,7 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
         }
         v[12] = (double)__builtin_popcount(m);
         const int slot = table_slot(skey, p);
-        double *dst = slot >= 0 ? &sval[t & 1][slot][0] : &A.hyd_fb[(size_t)p * HYD];
+        double *dst = slot >= 0 ? &sval[V.wv][slot][0] : &A.hyd_fb[(size_t)p * HYD];
 #pragma unroll
         for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&dst[c], v[c]);
       });
@@ -505,7 +507,7 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
     A.bt_key[(size_t)V.brick * TSLOT + i] = key;
     if (key >= 0)
       for (int c = 0; c < HYD; ++c)
-        A.bt_val[((size_t)V.brick * TSLOT + i) * HYD + c] = sval[0][i][c] + sval[1][i][c];
+        A.bt_val[((size_t)V.brick * TSLOT + i) * HYD + c] = ((sval[0][i][c] + sval[1][i][c]) + sval[2][i][c]) + sval[3][i][c];
   }
   // ---- brick partial of the non-equilibrium momentum flux (fluid stress): the 256
   //      per-thread partials of each component summed by one wave in a fixed order ----
