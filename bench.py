@@ -7,8 +7,9 @@ shear at 1e-4, bidisperse spheres of radii 4.5/6.3 (1:1) at volume fraction 0.55
 
 Prints one JSON line: whole-step throughput in MLUPS (all lattice nodes per second), the
 roofline of the dominant kernel (the fused stream/bounce-back/collide kernel, timed with HIP
-events on the simulation's stream), and the FP64 CPU oracle timed on a bounded sample of the
-same workload.
+events on the simulation's stream), the FP64 CPU oracle timed on a bounded sample of the
+same workload, and the serving comparison: the same mixed requests served one at a time by
+the plain loop and by the batched server (jobs per hour, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -21,6 +22,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the batched server runs one stream per job; give them their own hardware queues (read by
+# the HIP runtime when it starts, so set before torch is imported)
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "MLUPS & % HBM roofline; batched jobs/hr + p99 latency vs plain loop"
 HBM_PEAK_GBS = 8000.0
@@ -93,6 +97,9 @@ def main():
     ap.add_argument("--workload", default="large3d", choices=["large3d", "bulk96", "empty256"])
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=24,
+                    help="requests in the serving comparison (0: skip it)")
+    ap.add_argument("--serve-steps", type=int, default=1000, help="lattice steps per request")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "reference kernel for scaling the HBM byte counters)")
@@ -155,10 +162,21 @@ def main():
     with open(os.path.join(ROOT, "paper_1904_02929_amd", "csrc", "fluid.hip"), "rb") as fh:
         src_hash = hashlib.sha256(fh.read()).hexdigest()
     kernel_key = "k_lbm_%s_%s" % (wname, args.precision)
+    sim.close()
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on %d steps" % args.cpu_steps)
         cpu = cpu_baseline(w, args.cpu_steps)
+    serving = None
+    if args.serve_jobs > 0:
+        from paper_1904_02929_amd import serve
+        log("serving %d requests of %d steps: plain loop, then the batched server"
+            % (args.serve_jobs, args.serve_steps))
+        serving = serve.serve_benchmark(n_jobs=args.serve_jobs, steps=args.serve_steps, log=log)
+        serving["workload"] = ("mixed requests: half quasi-2D monolayers L x L x 10 (L 128-384, "
+                               "area fraction 0.70-0.80, oscillatory), half 3D bulk L^3 "
+                               "(L 64-128, phi 0.50-0.56, simple shear); Poisson arrivals at "
+                               "jobs / (0.25 x plain-loop time); FP32")
 
     out = {
         "metric": METRIC,
@@ -199,9 +217,9 @@ def main():
             "fluid_nodes": n_fluid,
         },
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
-    sim.close()
 
 
 if __name__ == "__main__":

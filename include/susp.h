@@ -91,6 +91,8 @@ typedef struct {
   double theta;              /* initial phase Theta                                      */
   int32_t ncyc_I, ncyc_F;    /* initial and observation cycles                           */
   int32_t fp16_exp;          /* k of the FP16 storage scale 2^k (SUSP_FP16STORE only)    */
+  int32_t brick_y, brick_z;  /* lattice-kernel brick of 64 x brick_y x brick_z nodes;
+                                0 = chosen from the lattice size (brick_y a multiple of 4) */
 } susp_params;
 
 /* Fill *p with the paper's defaults (tau 1, rho0 1, map_ratio 0.95, rho_p 1, kt 0.5 kn,
@@ -176,13 +178,13 @@ int susp_get_lists(susp_sim *s, int32_t kind, void *host, size_t *bytes);
 /* Resolved constants: {m0, kn, kt, eta_n, lub_delta, F0, debye_lambda, eta0, a_min, a_max}. */
 int susp_get_derived(susp_sim *s, double out[10]);
 
-/* Graph replay of steps (default on).  On a stream other than the null stream, susp_step
- * records two consecutive steps once as a HIP graph and replays it for pairs of steps
- * (the buffer parities repeat every two steps; the shear protocol is read from a device
- * table that susp_step uploads ahead of the steps).  Results are bit-identical to plain
- * launches.  Off, or on the null stream, or while profiling, every kernel is launched
- * one by one.                                                                              */
-int susp_use_graphs(susp_sim *s, int32_t enable);
+/* Graph replay of steps.  On a stream other than the null stream, susp_step records
+ * 2 x pairs consecutive steps once as a HIP graph and replays it for every run of that
+ * many steps (the buffer parities repeat every two steps; the shear protocol is read from
+ * a device table that susp_step uploads ahead of the steps); left-over steps are launched
+ * one by one.  Results are bit-identical to plain launches.  pairs in [0, 64], default 5;
+ * 0, the null stream or profiling: every kernel is launched one by one.                   */
+int susp_use_graphs(susp_sim *s, int32_t pairs);
 
 /* Timing of the lattice kernel (fused stream/bounce-back/collide): while enabled, every
  * step records a pair of HIP events around that kernel on the simulation's stream.
@@ -190,6 +192,58 @@ int susp_use_graphs(susp_sim *s, int32_t enable);
  * number of timed launches since the previous read, and resets both.                     */
 int susp_profile(susp_sim *s, int32_t enable);
 int susp_profile_read(susp_sim *s, double *ms_total, int64_t *launches);
+
+/* ---- Batches: many independent simulations sharing one GPU --------------------------
+ * A batch holds up to max_jobs simulations of any box size and parameters, each with its
+ * own device block and its own HIP stream (created by the batch, default priority), and
+ * admits a new one only while the sum of their susp_footprint_bytes stays within
+ * hbm_budget.  susp_batch_step queues the steps of every job on its stream (pairs of steps
+ * replayed from one recorded HIP graph per job, see susp_use_graphs), so that small jobs
+ * fill the GPU together, then waits for all of them.  A job stepped in a batch gives the
+ * same results, bit for bit, as the same job stepped alone.
+ * Brick shapes: with autotune set, a job whose brick_y/brick_z are 0 gets the shape that
+ * ran its lattice kernel fastest among a few candidates, timed on a scratch copy of the job
+ * the first time its (lx, ly, lz, precision, with/without spheres) is seen; the choice is
+ * kept for the batch's lifetime.                                                            */
+typedef struct susp_batch susp_batch;
+
+/* max_jobs >= 1; hbm_budget in bytes (> 0). */
+int susp_batch_create(int32_t max_jobs, size_t hbm_budget, int32_t autotune, susp_batch **out);
+
+/* Admit a job.  On success *slot receives its index (0 <= slot < max_jobs).  SUSP_ENOMEM
+ * with nothing changed if its footprint does not fit in the remaining budget, SUSP_ESTATE
+ * if every slot is taken; otherwise the errors of susp_create.                              */
+int susp_batch_add(susp_batch *b, const susp_params *p, int32_t *slot);
+
+/* Release a job and its device memory (its slot becomes free). */
+int susp_batch_remove(susp_batch *b, int32_t slot);
+
+/* Advance every admitted job by nsteps (>= 0).  SUSP_EUNSTABLE if any job reported an
+ * instability (the message names the slots; all jobs have still been advanced).           */
+int susp_batch_step(susp_batch *b, int64_t nsteps);
+
+/* Queue nsteps steps of one job on its stream and return at once (continuous batching:
+ * every job runs as soon as it is queued, none waits for another).  susp_batch_poll sets
+ * *done to 1 once the job's queued steps have completed, and then returns its status
+ * (SUSP_EUNSTABLE if they raised an instability), else *done = 0 and SUSP_OK.             */
+int susp_batch_launch(susp_batch *b, int32_t slot, int64_t nsteps);
+int susp_batch_poll(susp_batch *b, int32_t slot, int32_t *done);
+
+/* susp_stress of one job. */
+int susp_batch_stress(susp_batch *b, int32_t slot, double out[5][6], double gg[2]);
+
+/* The job's simulation handle, for the state getters (NULL if the slot is free).  It stays
+ * owned by the batch: do not destroy it.                                                   */
+susp_sim *susp_batch_sim(susp_batch *b, int32_t slot);
+
+/* Sum of the admitted jobs' footprints, in bytes. */
+size_t susp_batch_bytes(const susp_batch *b);
+
+/* The brick shape autotuning gives (or has given) jobs of these parameters. */
+int susp_batch_tune(susp_batch *b, const susp_params *p, int32_t *brick_y, int32_t *brick_z);
+
+/* Release every job, the streams and the batch. */
+int susp_batch_destroy(susp_batch *b);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *susp_last_error(void);

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsusp.so")
-SOURCES = ["api.hip", "fluid.hip", "particles.hip"]
+SOURCES = ["api.hip", "batch.hip", "fluid.hip", "particles.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -183,12 +183,18 @@ static int resolve(const susp_params *p, Sim &s) {
   // bricks of 64 x BY x BZ nodes for the lattice kernel: as large as possible while
   // leaving about 2048 of them to spread over the 256 compute units
   s.bxn = (p->lx + 63) / 64;
-  s.BY = 16; s.BZ = 16;
   auto nbr = [&]() { return s.bxn * ((p->ly + s.BY - 1) / s.BY) * ((p->lz + s.BZ - 1) / s.BZ); };
-  while (nbr() < 2048 && (s.BY > 4 || s.BZ > 1)) {
-    if (s.BZ >= s.BY && s.BZ > 1) s.BZ /= 2;
-    else if (s.BY > 4) s.BY /= 2;
-    else s.BZ /= 2;
+  if (p->brick_y || p->brick_z) {
+    if (p->brick_y < 4 || p->brick_y % 4 || p->brick_y > 1024 || p->brick_z < 1 || p->brick_z > 1024)
+      return fail(SUSP_EINVAL, "brick_y must be a positive multiple of 4 and brick_z positive (<= 1024)");
+    s.BY = p->brick_y; s.BZ = p->brick_z;
+  } else {
+    s.BY = 16; s.BZ = 16;
+    while (nbr() < 2048 && (s.BY > 4 || s.BZ > 1)) {
+      if (s.BZ >= s.BY && s.BZ > 1) s.BZ /= 2;
+      else if (s.BY > 4) s.BY /= 2;
+      else s.BZ /= 2;
+    }
   }
   s.byn = (p->ly + s.BY - 1) / s.BY;
   s.bzn = (p->lz + s.BZ - 1) / s.BZ;
@@ -297,8 +303,8 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
   s.block = base;
   carve(s, base);
   auto bail = [&](int code) { susp_destroy(h); return code; };
-  if (hipHostMalloc((void **)&s.clk_host, (size_t)CLK_CAP * sizeof(ClockEntry), hipHostMallocDefault))
-    return bail(fail(SUSP_ENOMEM, "pinned clock table"));
+  s.clk_host = (ClockEntry *)malloc((size_t)CLK_CAP * sizeof(ClockEntry));
+  if (!s.clk_host) return bail(fail(SUSP_ENOMEM, "clock table"));
   if (launch_fill_i32((int32_t *)s.clk, sizeof(Clock) / 4, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   const size_t n = (size_t)s.n;
   if (n) {
@@ -319,12 +325,15 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       if (hipMemcpyAsync(s.Q[b], v.data(), n * 32, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
       if (hipStreamSynchronize(s.stream)) return bail(fail(SUSP_EDEVICE, "sync"));
     }
-    if (hipMemcpy(s.a, a.data(), n * 8, hipMemcpyHostToDevice) || hipMemcpy(s.m, m.data(), n * 8, hipMemcpyHostToDevice) ||
-        hipMemcpy(s.I, I.data(), n * 8, hipMemcpyHostToDevice) || hipMemcpy(s.amap, am.data(), n * 8, hipMemcpyHostToDevice))
+    if (hipMemcpyAsync(s.a, a.data(), n * 8, hipMemcpyHostToDevice, s.stream) ||
+        hipMemcpyAsync(s.m, m.data(), n * 8, hipMemcpyHostToDevice, s.stream) ||
+        hipMemcpyAsync(s.I, I.data(), n * 8, hipMemcpyHostToDevice, s.stream) ||
+        hipMemcpyAsync(s.amap, am.data(), n * 8, hipMemcpyHostToDevice, s.stream) ||
+        hipStreamSynchronize(s.stream))
       return bail(fail(SUSP_EDEVICE, "upload of radii"));
   }
   s.cur = 0; s.pcur = 0; s.hcur = 0; s.lcur = 0; s.hfin = 0; s.step = 0;
-  s.graph_on = 1;
+  s.graph_on = 5;
   if (launch_init_populations(&s)) return bail(fail(SUSP_EDEVICE, "init populations"));
   if (launch_fill_i32(s.gown, (size_t)2 * s.lx * s.lz, -1, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   for (int b = 0; b < 2; ++b) {
@@ -356,7 +365,7 @@ extern "C" int susp_destroy(susp_sim *h) {
   free(h->s.prof_ev);
   (void)hipStreamSynchronize(h->s.stream);
   if (h->s.gexec) (void)hipGraphExecDestroy(h->s.gexec);
-  if (h->s.clk_host) (void)hipHostFree(h->s.clk_host);
+  free(h->s.clk_host);
   if (h->s.owns_block && h->s.block) (void)hipFree(h->s.block);
   delete h;
   return SUSP_OK;
@@ -382,7 +391,7 @@ static ClockEntry clock_entry(const Sim &s, int64_t t) {
 }
 
 // Upload the protocol values of the next m <= CLK_CAP steps and rewind the device cursor.
-// The pinned staging table is reused by the next upload, hence the wait.
+// The staging table is reused by the next upload, hence the wait (for this stream only).
 static int upload_clock(Sim &s, int m) {
   for (int k = 0; k < m; ++k) s.clk_host[k] = clock_entry(s, s.step + k);
   HIPCHK(hipMemcpyAsync(s.clk_tab, s.clk_host, (size_t)m * sizeof(ClockEntry), hipMemcpyHostToDevice, s.stream));
@@ -436,16 +445,16 @@ static int one_step(Sim &s) {
 
 static int parity(const Sim &s) { return s.cur | (s.lcur << 1) | (s.hcur << 2) | (s.pcur << 3) | (s.hfin << 4); }
 
-// Record two steps on the simulation's stream as one graph.  The buffer parities repeat
-// every two steps, so the graph replays from the parity it was recorded at; recording does
-// not execute anything, so the host clock and parities are restored afterwards.
+// Record 2 x graph_on steps on the simulation's stream as one graph.  The buffer parities
+// repeat every two steps, so the graph replays from the parity it was recorded at;
+// recording does not execute anything, so the host clock is restored afterwards.
 static int record_graph(Sim &s) {
   const int64_t step = s.step;
   const int par = parity(s);
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-  int rc = one_step(s);
-  if (!rc) rc = one_step(s);
+  int rc = SUSP_OK;
+  for (int k = 0; k < 2 * s.graph_on && !rc; ++k) rc = one_step(s);
   hipError_t e = hipStreamEndCapture(s.stream, &g);
   s.step = step;
   if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -458,11 +467,13 @@ static int record_graph(Sim &s) {
   return SUSP_OK;
 }
 
-// m steps whose clock table is on the device: pairs of steps by graph replay where possible.
+// m steps whose clock table is on the device: runs of 2 x graph_on steps by graph replay
+// where possible.
 static int run_steps(Sim &s, int m) {
-  const bool graph = s.graph_on && s.stream != nullptr && !s.prof_on;
+  const bool graph = s.graph_on > 0 && s.stream != nullptr && !s.prof_on;
+  const int gs = 2 * s.graph_on;
   int k = 0;
-  if (graph && m >= 2) {
+  if (graph && m >= gs) {
     if (!s.gexec) {
       int rc = record_graph(s);
       if (rc) return rc;
@@ -472,9 +483,9 @@ static int run_steps(Sim &s, int m) {
       if (rc) return rc;
       ++k;
     }
-    for (; k + 2 <= m; k += 2) {
+    for (; k + gs <= m; k += gs) {
       HIPCHK(hipGraphLaunch(s.gexec, s.stream));
-      s.step += 2;
+      s.step += gs;
     }
   }
   for (; k < m; ++k) {
@@ -484,7 +495,10 @@ static int run_steps(Sim &s, int m) {
   return SUSP_OK;
 }
 
-extern "C" int susp_step(susp_sim *h, int64_t nsteps) {
+namespace susp {
+
+// Queue nsteps steps on the simulation's stream (clock uploads wait only for their own copy).
+int launch_steps(susp_sim *h, int64_t nsteps) {
   if (!h) return fail(SUSP_EINVAL, "NULL simulation");
   if (nsteps < 0) return fail(SUSP_EINVAL, "negative step count");
   Sim &s = h->s;
@@ -495,14 +509,28 @@ extern "C" int susp_step(susp_sim *h, int64_t nsteps) {
     if (rc) return rc;
     done += m;
   }
+  return SUSP_OK;
+}
+
+// Wait for the simulation's stream and turn its instability flags into a status.
+int check_flags(susp_sim *h) {
   int32_t fl = 0;
-  int rc = read_flags(s, &fl);
+  int rc = read_flags(h->s, &fl);
   if (rc) return rc;
   if (fl) {
     return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite, 4 neighbour "
                 "overflow, 8 node touching more than six spheres)", fl);
   }
   return SUSP_OK;
+}
+
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+}  // namespace susp
+
+extern "C" int susp_step(susp_sim *h, int64_t nsteps) {
+  int rc = launch_steps(h, nsteps);
+  return rc ? rc : check_flags(h);
 }
 
 extern "C" int susp_stress(susp_sim *h, double out[5][6], double gg[2]) {
@@ -770,9 +798,15 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
   return SUSP_OK;
 }
 
-extern "C" int susp_use_graphs(susp_sim *h, int32_t enable) {
+extern "C" int susp_use_graphs(susp_sim *h, int32_t pairs) {
   if (!h) return fail(SUSP_EINVAL, "NULL simulation");
-  h->s.graph_on = enable ? 1 : 0;
+  if (pairs < 0 || pairs > 64) return fail(SUSP_EINVAL, "pairs must be in [0, 64]");
+  if (pairs != h->s.graph_on && h->s.gexec) {
+    HIPCHK(hipStreamSynchronize(h->s.stream));
+    (void)hipGraphExecDestroy(h->s.gexec);
+    h->s.gexec = nullptr;
+  }
+  h->s.graph_on = pairs;
   return SUSP_OK;
 }
 

@@ -13,6 +13,7 @@
 //                 accumulators, global stress/G' accumulators, flags
 #pragma once
 #include <hip/hip_runtime.h>
+#include "../../include/susp.h"
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 #include <stddef.h>
@@ -209,9 +210,9 @@ struct Sim {
   int64_t step;
   ClockEntry *clk_tab;   // device table of the next steps' protocol values
   Clock *clk;            // device: current entry and table cursor
-  ClockEntry *clk_host;  // pinned host staging of the table
-  // two recorded steps replayed as one HIP graph (streams other than the null stream)
-  int graph_on;            // use the graph when possible
+  ClockEntry *clk_host;  // host staging of the table
+  // recorded steps replayed as one HIP graph (streams other than the null stream)
+  int graph_on;            // pairs of steps per graph (0: no graphs)
   hipGraphExec_t gexec;    // null until recorded
   int gparity;             // cur ^ 2 lcur ^ 4 hcur ^ 8 pcur ^ 16 hfin at recording
   // optional timing of the lattice kernel with HIP events on the simulation's stream
@@ -219,5 +220,10 @@ struct Sim {
   int prof_used, prof_cap;
   hipEvent_t *prof_ev;  // [2 * prof_cap]: start, end of each timed launch
 };
+
+// ---- stepping helpers shared by the single-simulation and batch entry points (api.hip) ----
+int launch_steps(susp_sim *h, int64_t nsteps);
+int check_flags(susp_sim *h);
+int set_error(int code, const char *msg);
 
 }  // namespace susp

@@ -35,6 +35,7 @@ class Params(C.Structure):
         ("shear_kind", C.c_int32), ("gamma_dot", C.c_double), ("g0_I", C.c_double),
         ("g0_F", C.c_double), ("period", C.c_int32), ("theta", C.c_double),
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32), ("fp16_exp", C.c_int32),
+        ("brick_y", C.c_int32), ("brick_z", C.c_int32),
     ]
 
 
@@ -77,6 +78,19 @@ def lib():
         L.susp_profile.argtypes = [vp, C.c_int32]
         L.susp_profile_read.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
         L.susp_last_error.restype = C.c_char_p
+        L.susp_batch_create.argtypes = [C.c_int32, C.c_size_t, C.c_int32, C.POINTER(vp)]
+        L.susp_batch_add.argtypes = [vp, C.POINTER(Params), C.POINTER(C.c_int32)]
+        L.susp_batch_remove.argtypes = [vp, C.c_int32]
+        L.susp_batch_step.argtypes = [vp, C.c_int64]
+        L.susp_batch_stress.argtypes = [vp, C.c_int32, _PD, _PD]
+        L.susp_batch_launch.argtypes = [vp, C.c_int32, C.c_int64]
+        L.susp_batch_poll.argtypes = [vp, C.c_int32, _PI]
+        L.susp_batch_sim.argtypes = [vp, C.c_int32]
+        L.susp_batch_sim.restype = vp
+        L.susp_batch_bytes.argtypes = [vp]
+        L.susp_batch_bytes.restype = C.c_size_t
+        L.susp_batch_tune.argtypes = [vp, C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.susp_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -174,8 +188,9 @@ class Simulation:
             _chk(rc)
         return rc
 
-    def use_graphs(self, enable=True):
-        _chk(lib().susp_use_graphs(self.h, 1 if enable else 0))
+    def use_graphs(self, pairs=5):
+        """Steps per replayed graph = 2 * pairs (0 or False: plain launches)."""
+        _chk(lib().susp_use_graphs(self.h, int(pairs)))
 
     def profile(self, enable=True):
         _chk(lib().susp_profile(self.h, 1 if enable else 0))
@@ -263,3 +278,93 @@ class Simulation:
         if kind == LIST_LINKS:
             return buf.reshape(-1, 3)
         return buf
+
+
+class _JobView(Simulation):
+    """State getters of a job owned by a Batch (never destroys it)."""
+
+    def __init__(self, handle, p: Params):
+        self.h = C.c_void_p(handle)
+        self.params = p
+        self.n = p.n
+        self.shape = (p.lz, p.ly, p.lx)
+        self.stream = None
+        self.ws = None
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Many independent simulations on the current HIP device (one stream each).
+
+    add() returns a slot, or None when the job's footprint does not fit in the remaining
+    budget (admission refused; nothing changed)."""
+
+    def __init__(self, max_jobs, hbm_budget, autotune=True):
+        h = C.c_void_p()
+        _chk(lib().susp_batch_create(int(max_jobs), int(hbm_budget), 1 if autotune else 0, C.byref(h)))
+        self.h = h
+        self.max_jobs = int(max_jobs)
+        self._params = {}
+
+    def add(self, p: Params):
+        slot = C.c_int32(-1)
+        rc = lib().susp_batch_add(self.h, C.byref(p), C.byref(slot))
+        if rc == ENOMEM:
+            return None
+        _chk(rc)
+        self._params[slot.value] = p
+        return slot.value
+
+    def remove(self, slot):
+        _chk(lib().susp_batch_remove(self.h, int(slot)))
+        self._params.pop(slot, None)
+
+    def step(self, n, check=True):
+        rc = lib().susp_batch_step(self.h, int(n))
+        if check:
+            _chk(rc)
+        return rc
+
+    def launch(self, slot, n):
+        """Queue n steps of one job and return at once."""
+        _chk(lib().susp_batch_launch(self.h, int(slot), int(n)))
+
+    def poll(self, slot):
+        """(done, status): done once the job's queued steps have completed."""
+        d = C.c_int32(0)
+        rc = lib().susp_batch_poll(self.h, int(slot), C.byref(d))
+        if rc not in (OK, EUNSTABLE):
+            _chk(rc)
+        return bool(d.value), rc
+
+    def stress(self, slot):
+        out = np.zeros((5, 6)); gg = np.zeros(2)
+        _chk(lib().susp_batch_stress(self.h, int(slot), _pd(out), _pd(gg)))
+        return out, gg
+
+    def job(self, slot):
+        h = lib().susp_batch_sim(self.h, int(slot))
+        if not h:
+            raise SuspError(EINVAL, "slot %d is free" % slot)
+        return _JobView(h, self._params[slot])
+
+    def bytes_in_use(self):
+        return int(lib().susp_batch_bytes(self.h))
+
+    def tune(self, p: Params):
+        by = C.c_int32(); bz = C.c_int32()
+        _chk(lib().susp_batch_tune(self.h, C.byref(p), C.byref(by), C.byref(bz)))
+        return by.value, bz.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().susp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

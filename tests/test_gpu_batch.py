@@ -1,0 +1,142 @@
+"""Batches through the C ABI: jobs stepped together give the results of the same jobs
+stepped alone, bit for bit; admission by footprint; slot reuse; autotuned brick shapes."""
+import sys
+
+import numpy as np
+import pytest
+
+import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def susp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_02929_amd import susp as S
+    S.lib()
+    return S
+
+
+def _jobs(S):
+    out = []
+    for box, phi, seed, gd in (((64, 48, 40), 0.30, 5, 1e-3), ((41, 48, 37), 0.40, 6, 5e-4),
+                               ((70, 44, 33), 0.25, 8, 8e-4)):
+        b, pos, vel, om, rad, kw = PU.dense_workload(box, phi, seed, gd)
+        out.append((b, pos, vel, om, rad, kw))
+    # an oscillatory one
+    b, pos, vel, om, rad, _ = PU.dense_workload((48, 41, 36), 0.30, 9, 0.0)
+    out.append((b, pos, vel, om, rad, dict(shear_kind=2, g0_I=0.004, g0_F=0.002, period=20,
+                                          ncyc_I=1, ncyc_F=1, theta=0.5)))
+    return out
+
+
+def _params(S, job, brick=None):
+    b, pos, vel, om, rad, kw = job
+    kw = dict(kw)
+    if brick is not None:
+        kw["brick_y"], kw["brick_z"] = brick
+    return S.make_params(b, radius=rad, pos=pos, vel=vel, omega=om, precision=S.FP32, **kw)
+
+
+def _state(sim):
+    R, U, W, Q = sim.get_particles()
+    F, T, S, nl = sim.hydro()
+    return [sim.get_populations(), R, U, W, Q, F, T, S, nl]
+
+
+def test_batched_equals_alone(susp):
+    S = susp
+    jobs = _jobs(S)
+    print("\n[batch] %d jobs: %s" % (len(jobs), [j[0] for j in jobs]), flush=True)
+    sys.stdout.flush()
+    batch = S.Batch(8, 1 << 34, autotune=True)
+    slots, bricks = [], []
+    for j in jobs:
+        p = _params(S, j)
+        bricks.append(batch.tune(p))
+        slots.append(batch.add(p))
+    assert None not in slots and len(set(slots)) == len(slots)
+    for by, bz in bricks:
+        assert (by, bz) == (0, 0) or (by % 4 == 0 and by >= 4 and bz >= 1)
+    for n in (9, 4, 1):
+        batch.step(n)
+    got = [(_state(batch.job(s)), batch.stress(s)) for s in slots]
+    for j, br, (st, (sig, gg)) in zip(jobs, bricks, got):
+        alone = S.Simulation(_params(S, j, br))
+        alone.step(14)
+        ref = _state(alone)
+        for k, (x, y) in enumerate(zip(st, ref)):
+            assert np.array_equal(x, y), "box %s field %d differs" % (j[0], k)
+        sig_a, gg_a = alone.stress()
+        assert np.array_equal(sig, sig_a) and np.array_equal(gg, gg_a)
+        alone.close()
+    batch.close()
+
+
+def test_admission_and_slot_reuse(susp):
+    S = susp
+    jobs = _jobs(S)[:3]
+    # the largest job first: once it leaves, its block can hold the third
+    jobs.sort(key=lambda j: -S.footprint_bytes(_params(S, j)))
+    fp = [S.footprint_bytes(_params(S, j)) for j in jobs]
+    budget = fp[0] + fp[1]  # room for job 2 only once job 0 has left
+    batch = S.Batch(3, budget, autotune=False)
+    a = batch.add(_params(S, jobs[0]))
+    b = batch.add(_params(S, jobs[1]))
+    assert a is not None and b is not None
+    assert batch.bytes_in_use() == fp[0] + fp[1]
+    assert batch.add(_params(S, jobs[2])) is None  # over budget: refused, nothing changed
+    assert batch.bytes_in_use() == fp[0] + fp[1]
+    batch.step(3)
+    batch.remove(a)
+    assert batch.bytes_in_use() == fp[1]
+    c = batch.add(_params(S, jobs[2]))
+    assert c == a  # the freed slot is reused
+    batch.step(2)
+    batch.remove(b)
+    batch.remove(c)
+    assert batch.bytes_in_use() == 0
+    batch.step(1)  # no jobs: nothing to do
+    batch.close()
+
+
+def test_batch_full(susp):
+    S = susp
+    jobs = _jobs(S)
+    batch = S.Batch(1, 1 << 34, autotune=False)
+    assert batch.add(_params(S, jobs[0])) == 0
+    with pytest.raises(S.SuspError) as e:
+        batch.add(_params(S, jobs[1]))
+    assert e.value.code == S.ESTATE
+    batch.close()
+
+
+def test_launch_and_poll_equal_alone(susp):
+    import time
+    S = susp
+    jobs = _jobs(S)[:3]
+    batch = S.Batch(4, 1 << 34, autotune=False)
+    steps = (23, 8, 15)
+    slots = [batch.add(_params(S, j)) for j in jobs]
+    for s, n in zip(slots, steps):
+        batch.launch(s, n)
+    t0 = time.time()
+    left = set(slots)
+    while left:
+        for s in list(left):
+            done, rc = batch.poll(s)
+            if done:
+                assert rc == S.OK
+                left.discard(s)
+        assert time.time() - t0 < 60.0, "jobs did not finish"
+        time.sleep(0.001)
+    for j, s, n in zip(jobs, slots, steps):
+        alone = S.Simulation(_params(S, j))
+        alone.step(n)
+        for k, (x, y) in enumerate(zip(_state(batch.job(s)), _state(alone))):
+            assert np.array_equal(x, y), "box %s field %d differs" % (j[0], k)
+        alone.close()
+    batch.close()

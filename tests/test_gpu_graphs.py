@@ -1,7 +1,8 @@
 """Graph replay of steps against plain launches (both through the C ABI).
 
 Two simulations of the same suspension: one on the null stream (every kernel launched one
-by one), one on its own stream (pairs of steps replayed from one recorded HIP graph).  After
+by one), one on its own stream (runs of 2, 4, 6 or 10 steps replayed from one recorded HIP
+graph, the rest launched one by one).  After
 every run of steps, with eager work and synchronisation in between, the populations,
 particle state and hydrodynamic sums must be bit-identical: the graph holds the same kernels
 with the same arguments, the shear protocol comes from the device clock table, and every
@@ -48,8 +49,8 @@ def test_graph_replay_is_bit_identical(torch_mod, kind):
     side = torch.cuda.Stream()
     graph = susp.Simulation(p_b, stream=side)
     assert graph.stream.cuda_stream != 0
-    for chunk, use in ((7, True), (5, True), (3, False), (10, True), (1, True), (40, True)):
-        graph.use_graphs(use)
+    for chunk, pairs in ((7, 1), (5, 1), (3, 0), (10, 5), (1, 5), (40, 5), (13, 2), (24, 3)):
+        graph.use_graphs(pairs)
         plain.step(chunk)
         graph.step(chunk)
         torch.cuda.synchronize()
