@@ -49,8 +49,9 @@ typedef enum {
   SUSP_EINVAL = -1,     /* a parameter or argument is out of range                      */
   SUSP_ENOMEM = -2,     /* device allocation failed or workspace too small             */
   SUSP_EDEVICE = -3,    /* a HIP call failed                                            */
-  SUSP_EUNSTABLE = -4,  /* mapped spheres overlap, non-finite particle state, or a
-                           particle exceeded the neighbour capacity                     */
+  SUSP_EUNSTABLE = -4,  /* mapped spheres overlap, non-finite particle state, a particle
+                           exceeded the neighbour capacity, a node touches more than six
+                           spheres, or a sphere moved more than one node in one step     */
   SUSP_ESTATE = -5      /* a state buffer does not match the simulation                */
 } susp_status;
 
@@ -114,8 +115,10 @@ int susp_create(const susp_params *p, void *stream, void *workspace, size_t ws_b
                 susp_sim **out);
 
 /* Advance nsteps lattice steps (nsteps >= 0).  Returns SUSP_EUNSTABLE if any of those
- * steps found overlapping mapped spheres, a non-finite particle state or a neighbour-list
- * overflow (the state has still been advanced).                                            */
+ * steps found overlapping mapped spheres, a non-finite particle state, a neighbour-list
+ * overflow, a node linked to more than six spheres or a sphere displaced by more than one
+ * node in one step (the state has still been advanced; after a displacement that large the
+ * solid map is no longer updated and the state is meaningless).                            */
 int susp_step(susp_sim *s, int64_t nsteps);
 
 /* Stress averaged over the steps since the previous call (or creation), then reset:

@@ -228,6 +228,7 @@ static size_t carve(Sim &s, char *base) {
   }
   s.R0 = (double *)take(n * 3 * 8);
   s.bt_key = (int32_t *)take((size_t)s.nbricks * 128 * 4);
+  s.bt_cnt = (int32_t *)take((size_t)s.nbricks * 4);
   s.bt_val = (double *)take((size_t)s.nbricks * 128 * HYD * 8);
   s.hyd_fb = (double *)take(n * HYD * 8);
   s.a = (double *)take(n * 8);
@@ -409,6 +410,7 @@ static int one_step(Sim &s) {
   s.hcur ^= 1;
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
   HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk));
+  HIPCHK(launch_brick_lists(&s));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
@@ -519,7 +521,8 @@ int check_flags(susp_sim *h) {
   if (rc) return rc;
   if (fl) {
     return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite, 4 neighbour "
-                "overflow, 8 node touching more than six spheres)", fl);
+                "overflow, 8 node touching more than six spheres, 16 sphere moved more than a node in "
+                "a step)", fl);
   }
   return SUSP_OK;
 }

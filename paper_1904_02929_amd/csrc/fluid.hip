@@ -8,6 +8,8 @@
 //  helpers    equilibrium fill, FP64 <-> storage conversion, link enumeration.
 #include "susp_impl.h"
 
+#include <type_traits>
+
 namespace susp {
 
 // ---------------------------------------------------------------------------------------
@@ -53,6 +55,7 @@ template <class T> __device__ inline T wave_sum(T v) {
 // overflow goes through global atomics).
 constexpr int TX = 64, TY = 4;
 constexpr int TSLOT = 128;
+constexpr int SDAT = 10;  // doubles per LDS sphere state (R, U, W; padded to 16 bytes)
 constexpr int SROW = TX + 2, SPLANE = (TY + 2) * SROW;  // staged owner plane: 6 rows of 66
 
 struct LbmArgs {
@@ -64,7 +67,8 @@ struct LbmArgs {
   const int32_t *gown;
   const void *gval;
   const double *R, *U, *W;
-  int32_t *bt_key;
+  int32_t *bt_key;        // in: the spheres listed for each brick; out: its table's keys
+  const int32_t *bt_cnt;  // number of spheres listed for each brick
   double *bt_val;
   double *hyd_fb;
   double *pineq;
@@ -86,6 +90,18 @@ __device__ inline int table_slot(int32_t *skey, int p) {
     int key = skey[h];
     if (key == -1) key = atomicCAS(&skey[h], -1, p);
     if (key == -1 || key == p) return h;
+    h = (h + 1) & (TSLOT - 1);
+  }
+  return -1;
+}
+
+// Slot of sphere p in a brick's LDS table, or -1 if it is not there.
+__device__ inline int table_find(const int32_t *skey, int p) {
+  int h = p & (TSLOT - 1);
+  for (int probe = 0; probe < TSLOT; ++probe) {
+    const int key = skey[h];
+    if (key == p) return h;
+    if (key == -1) return -1;
     h = (h + 1) & (TSLOT - 1);
   }
   return -1;
@@ -144,6 +160,11 @@ template <> struct RowIO<__half> {
   }
 };
 
+// Wait here for every outstanding vector-memory access (s_waitcnt vmcnt(0); expcnt and
+// lgkmcnt left free), so that a rare branch that loads settles inside the branch instead
+// of leaving the wait to the code after it, where it would hold up the common path.
+__device__ inline void vm_settle() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Work-group barrier that orders LDS only: the lattice kernel's global stores are never
 // read back within the kernel, so waiting for them at every z step would only add latency.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
@@ -164,9 +185,10 @@ template <class T> __device__ inline T *opaque_uniform(T *p) {
 }
 
 // One thread's view of its brick: the lane's column, the staged entries of the owner ring.
+// A lane past the box end (xin false) computes a copy of the box's last column.
 struct BrickView {
   int brick, t, lane, wv;
-  int x, z_lo, z_hi, y_lo, y_hi;
+  int x0, z_lo, z_hi, y_lo, y_hi;
   bool xin;
   uint32_t xc, xm, xp;  // x of the node and of the pull sources c_x = +1, -1 (periodic)
 };
@@ -183,10 +205,9 @@ __device__ inline bool brick_view(const LbmArgs &A, BrickView &V) {
   V.t = threadIdx.x;
   V.lane = V.t & 63;
   V.wv = __builtin_amdgcn_readfirstlane(V.t >> 6);
-  V.x = bxi * TX + V.lane;
-  V.xin = V.x < A.lx;
-  // lanes past the box end use the last column for loads (their results are not stored)
-  V.xc = V.xin ? V.x : A.lx - 1;
+  V.x0 = bxi * TX;
+  V.xin = V.x0 + V.lane < A.lx;
+  V.xc = V.xin ? V.x0 + V.lane : A.lx - 1;
   V.xm = V.xc == 0 ? A.lx - 1 : V.xc - 1;
   V.xp = V.xc == (uint32_t)(A.lx - 1) ? 0 : V.xc + 1;
   V.z_lo = bzi * A.BZ;
@@ -196,22 +217,32 @@ __device__ inline bool brick_view(const LbmArgs &A, BrickView &V) {
   return true;
 }
 
-// Walk the brick: for every z step and row band call node(y, z, sm, s0, sp, cen) in every
-// wave, with the staged owner planes z-1, z, z+1 and the lane's centre entry (y may be
-// >= ly in the last band of a box whose ly is not a multiple of TY).
-template <class Fn>
-__device__ inline void walk_brick(const LbmArgs &A, const BrickView &V, int32_t (*smap)[SPLANE], Fn &&node) {
+// Walk the brick.  For every row band: band(y, z_lo, sm, s0, sp, cen) once, with the staged
+// owner planes z_lo-1, z_lo, z_lo+1; then for every z step node(par, y, live, z, sm, s0, sp,
+// spp, cen, last, put) in every wave, with the staged planes z-1 .. z+2, the lane's centre
+// entry and whether z is the band's last step; put() stores the plane fetched in this step
+// into the ring (any time in the step: the slot it overwrites is no longer read).  par is
+// Parity<0> on the band's even steps and Parity<1> on the odd ones.  A wave whose row lies
+// past the box (the last band of a box whose ly is not a multiple of TY) walks a copy of
+// row ly - 1, and a lane past the box end a copy of column lx - 1: live is false for them.
+// The planes sit in a ring of NRING slots; each step fetches plane z+3.
+constexpr int NRING = 5;
+template <int P> struct Parity { static constexpr int v = P; };
+template <class Band, class Fn>
+__device__ inline void walk_brick(const LbmArgs &A, const BrickView &V, int32_t (*smap)[SPLANE],
+                                  Band &&band, Fn &&node) {
   const int lx = A.lx, ly = A.ly, lz = A.lz, t = V.t;
   // the staged entries (row, column of a staged plane) of this thread: t and t + 256
   const bool two = t + 256 < SPLANE;
   const int e1 = two ? t + 256 : t;
-  const int x0 = V.x - V.lane;
+  const int x0 = V.x0;
   int gx0 = (x0 - 1 + t % SROW) % lx, gx1 = (x0 - 1 + e1 % SROW) % lx;
   gx0 += gx0 < 0 ? lx : 0;
   gx1 += gx1 < 0 ? lx : 0;
+  const int col = (int)V.xc - x0 + 1;  // the lane's column in a staged row
   for (int y0 = V.y_lo; y0 < V.y_hi; y0 += TY) {
     // source of each staged entry: a row of the owner map, or a ghost owner plane beyond
-    // y = -1 and y = ly (rows past ly only feed lanes that do nothing)
+    // y = -1 and y = ly (rows past ly only feed copies)
     const int gy0 = y0 - 1 + t / SROW, gy1 = y0 - 1 + e1 / SROW;
     const int32_t *ep0 = gy0 < 0 ? A.gown + gx0
                        : gy0 >= ly ? A.gown + (size_t)lz * lx + gx0
@@ -222,29 +253,49 @@ __device__ inline void walk_brick(const LbmArgs &A, const BrickView &V, int32_t 
     const int es0 = (gy0 < 0 || gy0 >= ly) ? lx : lx * ly;
     const int es1 = (gy1 < 0 || gy1 >= ly) ? lx : lx * ly;
     auto fetch = [&](int zz, int32_t &v0, int32_t &v1) {
-      zz = zz < 0 ? zz + lz : (zz >= lz ? zz - lz : zz);
+      zz = zz < 0 ? zz + lz : (zz >= lz ? zz - lz : zz);  // zz in [-1, lz + 2], lz >= 8
       v0 = ep0[zz * es0];
       v1 = ep1[zz * es1];
     };
     {
-      int32_t a0, a1, b0, b1, c0, c1;
+      int32_t a0, a1, b0, b1, c0, c1, d0, d1;
       fetch(V.z_lo - 1, a0, a1);
       fetch(V.z_lo, b0, b1);
       fetch(V.z_lo + 1, c0, c1);
+      fetch(V.z_lo + 2, d0, d1);
       __syncthreads();  // the previous row band is done with the ring
-      smap[0][t] = a0; smap[1][t] = b0; smap[2][t] = c0;
-      if (two) { smap[0][e1] = a1; smap[1][e1] = b1; smap[2][e1] = c1; }
+      smap[0][t] = a0; smap[1][t] = b0; smap[2][t] = c0; smap[3][t] = d0;
+      if (two) { smap[0][e1] = a1; smap[1][e1] = b1; smap[2][e1] = c1; smap[3][e1] = d1; }
     }
-    const int yb = y0 + V.wv;  // this wave's row (uniform)
-    for (int zb = V.z_lo; zb < V.z_hi; ++zb) {
-      lds_barrier();  // plane z+1 is staged; plane z-2's slot is free
-      const int r = zb - V.z_lo + 1;  // ring index of plane zb
-      // plane z+2 for the next step (past the brick's last plane it is fetched but unused)
+    const bool rowlive = y0 + V.wv < ly;                 // uniform
+    const int yb = rowlive ? y0 + V.wv : ly - 1;         // this wave's row (uniform)
+    const bool live = rowlive && V.xin;
+    const int cen = (yb - y0 + 1) * SROW + col;
+    lds_barrier();  // the band's first planes are staged
+    band(yb, V.z_lo, smap[0], smap[1], smap[2], cen);
+    int r = 1;  // ring slot of plane zb
+    auto step = [&](auto par, int zb) __attribute__((always_inline)) {
+      lds_barrier();  // plane z+2 is staged; the slot of plane z-2 is free
+      const int rm = r == 0 ? NRING - 1 : r - 1;
+      const int rp = r == NRING - 1 ? 0 : r + 1;
+      const int rpp = rp == NRING - 1 ? 0 : rp + 1;
+      const int rw = rpp == NRING - 1 ? 0 : rpp + 1;  // = slot of plane z-2
+      // plane z+3 for the step after next (past the brick's end it is fetched but unused)
       int32_t f0, f1;
-      fetch(zb + 2, f0, f1);
-      node(yb, zb, smap[(r - 1) & 3], smap[r & 3], smap[(r + 1) & 3], (V.wv + 1) * SROW + V.lane + 1);
-      smap[(r + 2) & 3][t] = f0;
-      if (two) smap[(r + 2) & 3][e1] = f1;
+      fetch(zb + 3, f0, f1);
+      auto put = [&]() __attribute__((always_inline)) {
+        smap[rw][t] = f0;
+        if (two) smap[rw][e1] = f1;
+      };
+      node(par, yb, live, zb, smap[rm], smap[r], smap[rp], smap[rpp], cen, zb + 1 == V.z_hi, put);
+      r = rp;
+    };
+    // two steps per trip (even and odd parity), so that a node can keep two register
+    // sets without copying one into the other
+    for (int zb = V.z_lo; zb < V.z_hi; zb += 2) {
+      step(Parity<0>(), zb);
+      if (zb + 1 < V.z_hi) step(Parity<1>(), zb + 1);
+      else vm_settle();  // (an odd band length: keep the pending history of the loop)
     }
   }
 }
@@ -293,34 +344,83 @@ __device__ inline bool for_each_sphere(const int32_t *sm, const int32_t *s0, con
   return rem == 0;
 }
 
-// Every link source X - c_q lies in the image of X itself unless X is within one node of
-// half a period from the centre (boxes thin compared with the sphere); then each link
-// finds its own image.
-__device__ inline bool same_image(const Box &b, double Dx, double Dy, double Dz) {
-  return fabs(Dx) <= 0.5 * b.Lx - 1.000001 && fabs(Dy) <= 0.5 * b.Ly - 1.000001 &&
-         fabs(Dz) <= 0.5 * b.Lz - 1.000001;
+// Directions q whose component k (0 x, 1 y, 2 z) of c_q equals sgn, as a bit mask.
+__host__ __device__ constexpr uint32_t dir_mask(int k, int sgn) {
+  uint32_t m = 0;
+  for (int q = 1; q < NQ; ++q)
+    if ((k == 0 ? cx(q) : k == 1 ? cy(q) : cz(q)) == sgn) m |= 1u << q;
+  return m;
+}
+
+// The solid end X - c_q of every link in m lies in the image of the sphere nearest to X
+// (D = X - R in that image) when each component of D - c_q stays inside the half period
+// (with a small margin, so that no rounding can tip the choice); then the lever of each
+// link is D - c_q / 2 and one minimum image serves all of them.  Fails only for nodes
+// about half a period from the centre whose links point across it (thin boxes).
+__device__ inline bool same_image(const Box &b, double Dx, double Dy, double Dz, uint32_t m) {
+  constexpr double e = 1e-6;
+  const double hx = 0.5 * b.Lx - e, hy = 0.5 * b.Ly - e, hz = 0.5 * b.Lz - e;
+  bool ok = true;
+  if (m & dir_mask(0, 1)) ok = ok && Dx - 1.0 >= -hx;
+  if (m & dir_mask(0, -1)) ok = ok && Dx + 1.0 <= hx;
+  if (m & dir_mask(1, 1)) ok = ok && Dy - 1.0 >= -hy;
+  if (m & dir_mask(1, -1)) ok = ok && Dy + 1.0 <= hy;
+  if (m & dir_mask(2, 1)) ok = ok && Dz - 1.0 >= -hz;
+  if (m & dir_mask(2, -1)) ok = ok && Dz + 1.0 <= hz;
+  return ok && fabs(Dx) <= hx && fabs(Dy) <= hy && fabs(Dz) <= hz;
 }
 
 // ---- k_lbm: pull (eq. 3), bounce-back on moving spheres (eq. 7) with the link sums
 //      (eqs. 6, 9, 10), BGK collision (eq. 4) on the deviations, non-equilibrium momentum
 //      flux per brick ----
+//
+// Memory pipeline.  Vector-memory waits count in issue order, so a wait for one load also
+// waits for every load and store issued before it, and a load or store skipped by a branch
+// leaves the compiler unsure of the count (it then waits for more).  Hence the hot path has
+// no branch around a global access: lanes past the box end and waves past the last row
+// compute a copy of the last column or row and store the same values to the same places,
+// and each step issues, in this order, the owner plane z+3, the populations of the next
+// node (link directions load the node's own opposite population instead of the pull), and
+// this node's stores.  The spheres' states come from LDS.  A node therefore waits only for
+// loads issued one step earlier.
 template <class ST>
 __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   using CT = typename Store<ST>::CT;
-  __shared__ int32_t smap[4][SPLANE];
+  __shared__ int32_t smap[NRING][SPLANE];
   __shared__ int32_t skey[TSLOT];
+  // 4-byte arithmetic: sphere states in LDS, FP32 stress partials; FP64: states read from
+  // memory, FP64 partials (the LDS budget of two work-groups per compute unit)
+  constexpr bool PF = sizeof(CT) == 4;
+  using PT = typename std::conditional<PF, float, double>::type;
+  __shared__ double sdat[PF ? TSLOT : 1][SDAT];  // R, U, W of each table entry
   __shared__ double sval[4][TSLOT][HYD];  // one copy per wave: a fixed summation order
-  __shared__ double spn[6][256];  // per-thread fluid stress partials
+  __shared__ PT spn[6][256];                // per-thread fluid stress partials
   BrickView V;
   if (!brick_view(A, V)) return;  // the whole work-group
   const Box bx = clock_box(A.b, A.clk, 0);
   const int t = V.t, lane = V.lane;
   const int lx = A.lx, ly = A.ly, lz = A.lz;
   const size_t plane = A.plane;
+  // ---- the brick's table: the spheres listed for it, with their states ----
   for (int i = t; i < TSLOT; i += 256) skey[i] = -1;
   for (int i = t; i < 4 * TSLOT * HYD; i += 256) (&sval[0][0][0])[i] = 0.0;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) spn[c][t] = 0.0;
+  for (int c = 0; c < 6; ++c) spn[c][t] = (PT)0;
+  __syncthreads();
+  {
+    const int cnt = min(A.bt_cnt[V.brick], TSLOT);  // past TSLOT: the global fallback
+    for (int i = t; i < cnt; i += 256) table_slot(skey, A.bt_key[(size_t)V.brick * TSLOT + i]);
+  }
+  __syncthreads();
+  for (int i = t; PF && i < TSLOT * 9; i += 256) {
+    const int slot = i / 9, c = i - 9 * (i / 9);
+    const int key = skey[slot];
+    if (key >= 0) {
+      const double *src = c < 3 ? A.R : (c < 6 ? A.U : A.W);
+      sdat[slot][c] = src[3 * key + c % 3];
+    }
+  }
+  // (the first row band's barrier orders these writes before any use)
   const CT om = (CT)A.omega;
   const CT rho0 = (CT)A.rho0;
   constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
@@ -329,48 +429,115 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   // byte offsets of the lane's column and of its pull sources c_x = +1, -1
   const uint32_t xcb = V.xc * es, xmb = V.xm * es, xpb = V.xp * es;
   const uint32_t xcg = V.xc * ges, xmg = V.xm * ges, xpg = V.xp * ges;
-  walk_brick(A, V, smap, [&](int yb, int zb, const int32_t *sm, const int32_t *s0, const int32_t *sp, int cen) {
-    if (yb >= ly) return;
+  // The populations a node needs: for a link direction q (bit q of lk: X - c_q is solid)
+  // the node's own opposite population n*_qbar(X), which bounce-back sends back (eq. 7),
+  // else the pull source n*_q(X - c_q) (eq. 3).  Every lane loads (a solid node's values
+  // are replaced by the rest state).
+  auto load_node = [&](int yb, int zb, uint32_t lk, CT *dst) __attribute__((always_inline)) {
     const int y = opaque_uniform(yb), z = opaque_uniform(zb);
     const uint32_t pb = (uint32_t)opaque_uniform((int)(plane * es));  // plane stride, bytes
     const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
     const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
-    CT n[NQ];  // populations in, post-collision populations out (0 = rest state if solid)
-    uint32_t all = 0;  // link directions of a fluid node (bit q: X - c_q is solid)
-    int ph = -1;       // the largest sphere id among them
-    if (V.xin && s0[cen] == -1) {
-      n[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
-      // ---- pull ----
+    dst[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
+    // one load per direction, no branch (a pull across a sliding plane reads some row of
+    // the array, or nothing, and is replaced below)
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      const bool lq = (lk >> q) & 1u;
+      const uint32_t own_off = opp(q) * pb + rowc + xcb;  // w_qbar = w_q: same FP16 scale
+      const int ys = y - cy(q);
+      const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
+      const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
+      const uint32_t pull_off = q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb;
+      dst[q] = RowIO<ST>::ld(rin, lq ? own_off : pull_off, q, A.h16);
+    }
+    if (y == 0 || y == ly - 1) {  // uniform: directions across the sliding plane read the
+                                  // Lees-Edwards ghost row (these rows do not overlap)
+      const int side = y == 0 ? 0 : 1;
+      CT g[5];
 #pragma unroll
       for (int q = 1; q < NQ; ++q) {
-        const int ys = y - cy(q);
-        const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
-        const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
-        const bool gh = cy(q) != 0 && (ys < 0 || ys >= ly);
-        if (gh) {  // uniform: a Lees-Edwards ghost row
+        if (cy(q) == (side == 0 ? 1 : -1)) {
+          const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
           const uint32_t xsg = cx(q) == 1 ? xmg : (cx(q) == -1 ? xpg : xcg);
-          n[q] = RowIO<CT>::ld(rgh, (uint32_t)((((ys < 0 ? 0 : 1) * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
-        } else {
-          n[q] = RowIO<ST>::ld(rin, q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb, q, A.h16);
+          g[gslot(q)] = RowIO<CT>::ld(rgh, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
         }
       }
-      // ---- links: the node's own opposite population, bounced back ----
-      all = link_bits(sm, s0, sp, cen, &ph);
+      vm_settle();
 #pragma unroll
-      for (int q = 1; q < NQ; ++q)
-        if ((all >> q) & 1u)
-          n[q] = RowIO<ST>::ld(rin, opp(q) * pb + rowc + xcb, opp(q), A.h16);
-      const int x = V.x;
+      for (int q = 1; q < NQ; ++q) {
+        if (cy(q) == (side == 0 ? 1 : -1)) {
+          const bool lq = (lk >> q) & 1u;
+          dst[q] = lq ? dst[q] : g[gslot(q)];
+        }
+      }
+    }
+  };
+  // With 4-byte arithmetic a step loads the next node while it computes (two register sets:
+  // even steps work on ra and load into rb, odd steps the other way round); in FP64 each
+  // node loads its own (register budget).
+  CT ra[NQ], rb[NQ];
+  bool nfl = false;      // the next node is a fluid node
+  uint32_t nall = 0;     // its link directions
+  int nph = -1;          // the largest sphere id among them
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) { ra[q] = 0; rb[q] = 0; }
+  // n: this node's populations in, post-collision populations out (0 = rest state if
+  // solid); pn: the next node's loads.  live: the lane's node is its own (not a copy).
+  auto node = [&](CT (&n)[NQ], CT (&pn)[NQ], int yb, bool live, int zb, const int32_t *sm,
+                  const int32_t *s0, const int32_t *sp, const int32_t *spp, int cen, bool last,
+                  auto &&put) __attribute__((always_inline)) {
+    const int y = opaque_uniform(yb), z = opaque_uniform(zb);
+    const uint32_t pb = (uint32_t)opaque_uniform((int)(plane * es));  // plane stride, bytes
+    const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
+    bool fl;           // fluid node
+    uint32_t all = 0;  // its link directions (bit q: X - c_q is solid)
+    int ph = -1;       // the largest sphere id among them
+    if (PF) {
+      fl = nfl; all = nall; ph = nph;
+    } else {
+      fl = s0[cen] == -1;
+      if (fl) all = link_bits(sm, s0, sp, cen, &ph);
+      load_node(yb, zb, all, n);
+    }
+    if (PF && !last) {
+      nfl = sp[cen] == -1;
+      nall = 0;
+      nph = -1;
+      if (nfl) nall = link_bits(s0, sp, spp, cen, &nph);
+      load_node(yb, zb + 1, nall, pn);
+    } else if (PF) {
+      vm_settle();  // a band's last step: nothing to overlap
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) pn[q] = 0;  // (the old values are dead on every path)
+    }
+    if (fl) {
+      const int x = V.xc;
       const bool done = for_each_sphere(sm, s0, sp, cen, all, ph, [&](int p, uint32_t m) {
-        // the sphere's state, all loads issued together
-        const double Rx = A.R[3 * p], Ry = A.R[3 * p + 1], Rz = A.R[3 * p + 2];
-        const double U0 = A.U[3 * p], U1 = A.U[3 * p + 1], U2 = A.U[3 * p + 2];
-        const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
+        // the sphere's state: from the brick's table, else (not listed) from memory
+        const int slot = table_find(skey, p);
+        double Rx, Ry, Rz, U0, U1, U2, w0, w1, w2;
+        if (PF) {
+          const int sl = slot >= 0 ? slot : 0;
+          Rx = sdat[sl][0]; Ry = sdat[sl][1]; Rz = sdat[sl][2];
+          U0 = sdat[sl][3]; U1 = sdat[sl][4]; U2 = sdat[sl][5];
+          w0 = sdat[sl][6]; w1 = sdat[sl][7]; w2 = sdat[sl][8];
+          if (slot < 0) {  // rare: not listed (full table)
+            Rx = A.R[3 * p]; Ry = A.R[3 * p + 1]; Rz = A.R[3 * p + 2];
+            U0 = A.U[3 * p]; U1 = A.U[3 * p + 1]; U2 = A.U[3 * p + 2];
+            w0 = A.W[3 * p]; w1 = A.W[3 * p + 1]; w2 = A.W[3 * p + 2];
+            vm_settle();
+          }
+        } else {
+          Rx = A.R[3 * p]; Ry = A.R[3 * p + 1]; Rz = A.R[3 * p + 2];
+          U0 = A.U[3 * p]; U1 = A.U[3 * p + 1]; U2 = A.U[3 * p + 2];
+          w0 = A.W[3 * p]; w1 = A.W[3 * p + 1]; w2 = A.W[3 * p + 2];
+        }
         double Dx, Dy, Dz;
         int k;
         minimage(bx, (double)x - Rx, (double)y - Ry, (double)z - Rz, Dx, Dy, Dz, k);
         double v[HYD];
-        if (same_image(bx, Dx, Dy, Dz)) {
+        if (same_image(bx, Dx, Dy, Dz, m)) {
           // rigid-body velocity at the node (eq. 8)
           const double ux = U0 + k * bx.ule + (w1 * Dz - w2 * Dy);
           const double uy = U1 + (w2 * Dx - w0 * Dz);
@@ -436,12 +603,17 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
           }
         }
         v[12] = (double)__builtin_popcount(m);
-        const int slot = table_slot(skey, p);
-        double *dst = slot >= 0 ? &sval[V.wv][slot][0] : &A.hyd_fb[(size_t)p * HYD];
+        if (live) {
+          if (slot >= 0) {  // LDS atomics (the two address spaces kept apart: no flat atomics)
 #pragma unroll
-        for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&dst[c], v[c]);
+            for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&sval[V.wv][slot][c], v[c]);
+          } else {
+#pragma unroll
+            for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&A.hyd_fb[(size_t)p * HYD + c], v[c]);
+          }
+        }
       });
-      if (!done) atomicOr(A.flags, 8);
+      if (!done && live) atomicOr(A.flags, 8);
       // ---- moments and BGK collision on the deviations d_q = n_q - w_q rho0, opposite
       //      directions paired: feq_q,qbar = w (a + 4.5 rho cu^2) +- 3 w rho cu ----
       CT rd = n[0], jx = 0, jy = 0, jz = 0;
@@ -486,19 +658,35 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
         addc(s[4], cx(q) * cz(q), ps[pi]);
         addc(s[5], cy(q) * cz(q), ps[pi]);
       }
+      if (live) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) spn[c][t] += (double)s[c];
+        for (int c = 0; c < 6; ++c) spn[c][t] += (PT)s[c];
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) n[q] = 0;
     }
+    put();  // the owner plane fetched this step, into the ring
     // every node of the row is stored, so that the wave writes whole cache lines (HBM3E
-    // has no write mask: a partly written line costs a read-modify-write)
-    if (V.xin) {  // (lanes past the box end would alias the last column through xc)
+    // has no write mask: a partly written line costs a read-modify-write); copies store
+    // what the node's own lane or wave stores
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        RowIO<ST>::st(rout, q * pb + rowc + xcb, n[q], q, A.h16);
-    }
+    for (int q = 0; q < NQ; ++q)
+      RowIO<ST>::st(rout, q * pb + rowc + xcb, n[q], q, A.h16);
+  };
+  walk_brick(A, V, smap,
+             [&](int yb, int z_lo, const int32_t *sm, const int32_t *s0, const int32_t *sp, int cen) {
+    if (!PF) return;
+    nfl = s0[cen] == -1;
+    nall = 0;
+    nph = -1;
+    if (nfl) nall = link_bits(sm, s0, sp, cen, &nph);
+    load_node(yb, z_lo, nall, ra);
+    vm_settle();  // once per band: the steps then see one history of pending accesses
+  }, [&](auto par, int yb, bool live, int zb, const int32_t *sm, const int32_t *s0, const int32_t *sp,
+         const int32_t *spp, int cen, bool last, auto &&put) {
+    if constexpr (decltype(par)::v == 0) node(ra, rb, yb, live, zb, sm, s0, sp, spp, cen, last, put);
+    else node(rb, ra, yb, live, zb, sm, s0, sp, spp, cen, last, put);
   });
   __syncthreads();
   // ---- brick table out ----
@@ -514,7 +702,8 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   if (V.wv == 0) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      const double v = wave_sum(spn[c][lane] + spn[c][lane + 64] + spn[c][lane + 128] + spn[c][lane + 192]);
+      const double v = wave_sum(((double)spn[c][lane] + (double)spn[c][lane + 64]) +
+                                ((double)spn[c][lane + 128] + (double)spn[c][lane + 192]));
       if (lane == 0) A.pineq[(size_t)V.brick * 6 + c] = v;
     }
   }
@@ -538,6 +727,7 @@ static LbmArgs lbm_args(Sim *s, const Box &b) {
   A.U = s->U[s->pcur];
   A.W = s->W[s->pcur];
   A.bt_key = s->bt_key;
+  A.bt_cnt = s->bt_cnt;
   A.bt_val = s->bt_val;
   A.hyd_fb = s->hyd_fb;
   A.pineq = s->pineq;
@@ -565,25 +755,23 @@ hipError_t launch_lbm(Sim *s, const Box &b) {
   return hipGetLastError();
 }
 
-// Per-sphere hydrodynamic sums: the entries of every brick the sphere's links can reach
-// (nodes within a_map + 2 of any of its Lees-Edwards images), added in brick order, plus
-// the overflow accumulator (which is cleared for the next step).  One wave per sphere.
-struct GatherArgs {
-  const double *R, *amap;
-  const int32_t *bt_key;
-  const double *bt_val;
-  double *hyd_fb;
-  double *hyd;
-  int n, lx, ly, lz, bxn, byn, BY, BZ;
-  const Clock *clk;  // LE offset of the step
+// Bricks near a sphere.  The lattice kernel's table for a brick must hold every sphere
+// whose owner entries its staged region (the brick and a one-node halo, with the ghost
+// rows beyond y = -1 and y = ly) can hold: nodes within a_map of one of the sphere's
+// Lees-Edwards images (at R + k (s, Ly, 0)), hence every brick with a node within a_map + 2
+// of an image.  The same enumeration lists the spheres for each brick (k_brick_lists) and
+// gathers a sphere's sums (k_hydro_gather).
+struct BrickGeo {
+  int lx, ly, lz, bxn, byn, BY, BZ;
 };
 
-// Next node coordinate (along a periodic axis of length L with bricks of B nodes) that
-// starts a new brick after coordinate xx.
+// Next node coordinate (along a periodic axis of length L with bricks of B nodes, the last
+// one shorter when B does not divide L) that starts a new brick after coordinate xx.
 __device__ inline int next_brick_start(int xx, int L, int B) {
   int w = xx % L;
   w = w < 0 ? w + L : w;
-  return xx + (B - (w % B));
+  const int nxt = (w / B + 1) * B;  // start of the following brick, or past the axis end
+  return xx + ((nxt < L ? nxt : L) - w);
 }
 __device__ inline int brick_of(int xx, int L, int B) {
   int w = xx % L;
@@ -591,59 +779,130 @@ __device__ inline int brick_of(int xx, int L, int B) {
   return w / B;
 }
 
+// fn(brick) for every brick with a node within r of an image of the sphere at Rp (LE offset
+// s), each once, in a fixed order; run by a whole wave, fn in every lane.  vis: the wave's
+// list of visited bricks (a wrapped range can reach a brick twice; past 256 entries a
+// brick may be visited again).
+template <class F>
+__device__ inline void sphere_bricks(const BrickGeo &G, const double *Rp, double r, double s,
+                                     int *vis, int lane, F &&fn) {
+  int nvis = 0;
+  int zlo = (int)floor(Rp[2] - r), zhi = (int)ceil(Rp[2] + r);
+  if (zhi - zlo + 1 >= G.lz) { zlo = 0; zhi = G.lz - 1; }
+  for (int k = -1; k <= 1; ++k) {
+    const double cy_ = Rp[1] + k * (double)G.ly;
+    int ylo = (int)floor(cy_ - r), yhi = (int)ceil(cy_ + r);
+    if (ylo < 0) ylo = 0;
+    if (yhi > G.ly - 1) yhi = G.ly - 1;
+    if (ylo > yhi) continue;
+    const double cx_ = Rp[0] + k * s;
+    int xlo = (int)floor(cx_ - r), xhi = (int)ceil(cx_ + r);
+    if (xhi - xlo + 1 >= G.lx) { xlo = 0; xhi = G.lx - 1; }
+    for (int zz = zlo; zz <= zhi; zz = next_brick_start(zz, G.lz, G.BZ)) {
+      const int bz = brick_of(zz, G.lz, G.BZ);
+      for (int by = ylo / G.BY; by <= yhi / G.BY; ++by) {
+        for (int xx = xlo; xx <= xhi; xx = next_brick_start(xx, G.lx, TX)) {
+          const int brick = brick_of(xx, G.lx, TX) + G.bxn * (by + G.byn * bz);
+          bool dup = false;
+          for (int base = 0; base < nvis; base += 64) {
+            const int v = base + lane < nvis ? vis[base + lane] : -1;
+            if (__ballot(v == brick)) { dup = true; break; }
+          }
+          if (dup) continue;
+          if (nvis < 256) {
+            if (lane == 0) vis[nvis] = brick;
+            ++nvis;
+            __builtin_amdgcn_wave_barrier();
+          }
+          fn(brick);
+        }
+      }
+    }
+  }
+}
+
+// ---- k_brick_lists: each sphere appends its id to the list of every brick near it (one
+//      wave per sphere; the list order is immaterial: the brick's sums are kept per sphere)
+struct ListArgs {
+  const double *R, *amap;
+  int32_t *bt_key, *bt_cnt;
+  int n;
+  BrickGeo G;
+  const Clock *clk;
+};
+
+__global__ __launch_bounds__(256) void k_brick_lists(ListArgs A) {
+  __shared__ int vis[4][256];
+  const int wv = threadIdx.x >> 6;
+  const int p = blockIdx.x * 4 + wv;
+  const int lane = threadIdx.x & 63;
+  if (p >= A.n) return;  // uniform per wave
+  if (!(isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2]))) return;
+  sphere_bricks(A.G, &A.R[3 * p], A.amap[p] + 2.0, A.clk->cur.s, vis[wv], lane, [&](int brick) {
+    if (lane == 0) {
+      const int c = atomicAdd(&A.bt_cnt[brick], 1);
+      if (c < TSLOT) A.bt_key[(size_t)brick * TSLOT + c] = p;
+    }
+  });
+}
+
+static BrickGeo brick_geo(const Sim *s) {
+  BrickGeo G;
+  G.lx = s->lx; G.ly = s->ly; G.lz = s->lz;
+  G.bxn = s->bxn; G.byn = s->byn; G.BY = s->BY; G.BZ = s->BZ;
+  return G;
+}
+
+hipError_t launch_brick_lists(Sim *s) {
+  hipError_t e = launch_fill_i32(s->bt_cnt, (size_t)s->nbricks, 0, s->stream);
+  if (e != hipSuccess || s->n == 0) return e;
+  ListArgs A;
+  A.R = s->R[s->pcur]; A.amap = s->amap;
+  A.bt_key = s->bt_key; A.bt_cnt = s->bt_cnt;
+  A.n = s->n;
+  A.G = brick_geo(s);
+  A.clk = s->clk;
+  hipLaunchKernelGGL(k_brick_lists, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, A);
+  return hipGetLastError();
+}
+
+// Per-sphere hydrodynamic sums: the entries of every brick near the sphere, added in brick
+// order, plus the overflow accumulator (which is cleared for the next step).  One wave per
+// sphere.
+struct GatherArgs {
+  const double *R, *amap;
+  const int32_t *bt_key;
+  const double *bt_val;
+  double *hyd_fb;
+  double *hyd;
+  int n;
+  BrickGeo G;
+  const Clock *clk;  // LE offset of the step
+};
+
 __global__ __launch_bounds__(256) void k_hydro_gather(GatherArgs A) {
   __shared__ int vis[4][256];
   const int wv = threadIdx.x >> 6;
   const int p = blockIdx.x * 4 + wv;
   const int lane = threadIdx.x & 63;
   if (p >= A.n) return;  // uniform per wave
-  const double r = A.amap[p] + 2.0;
   double acc[HYD];
 #pragma unroll
   for (int c = 0; c < HYD; ++c) acc[c] = 0.0;
-  int nvis = 0;
-  int zlo = (int)floor(A.R[3 * p + 2] - r), zhi = (int)ceil(A.R[3 * p + 2] + r);
-  if (zhi - zlo + 1 >= A.lz) { zlo = 0; zhi = A.lz - 1; }
-  for (int k = -1; k <= 1; ++k) {
-    const double cy_ = A.R[3 * p + 1] + k * (double)A.ly;
-    int ylo = (int)floor(cy_ - r), yhi = (int)ceil(cy_ + r);
-    if (ylo < 0) ylo = 0;
-    if (yhi > A.ly - 1) yhi = A.ly - 1;
-    if (ylo > yhi) continue;
-    const double cx_ = A.R[3 * p] + k * A.clk->cur.s;
-    int xlo = (int)floor(cx_ - r), xhi = (int)ceil(cx_ + r);
-    if (xhi - xlo + 1 >= A.lx) { xlo = 0; xhi = A.lx - 1; }
-    for (int zz = zlo; zz <= zhi; zz = next_brick_start(zz, A.lz, A.BZ)) {
-      const int bz = brick_of(zz, A.lz, A.BZ);
-      for (int by = ylo / A.BY; by <= yhi / A.BY; ++by) {
-        for (int xx = xlo; xx <= xhi; xx = next_brick_start(xx, A.lx, TX)) {
-          const int brick = brick_of(xx, A.lx, TX) + A.bxn * (by + A.byn * bz);
-          // skip bricks already visited (a wrapped range can reach a brick twice)
-          bool dup = false;
-          for (int base = 0; base < nvis; base += 64) {
-            const int v = base + lane < nvis ? vis[wv][base + lane] : -1;
-            if (__ballot(v == brick)) { dup = true; break; }
-          }
-          if (dup) continue;
-          if (nvis < 256) {
-            if (lane == 0) vis[wv][nvis] = brick;
-            ++nvis;
-            __builtin_amdgcn_wave_barrier();
-          }
-          // find p among the brick's keys (at most one slot holds it)
-          int hit = -1;
-          for (int s0 = 0; s0 < TSLOT; s0 += 64) {
-            const int key = A.bt_key[(size_t)brick * TSLOT + s0 + lane];
-            const uint64_t m = __ballot(key == p);
-            if (m) { hit = s0 + __ffsll((unsigned long long)m) - 1; break; }
-          }
-          if (hit >= 0) {
-#pragma unroll
-            for (int c = 0; c < HYD; ++c) acc[c] += A.bt_val[((size_t)brick * TSLOT + hit) * HYD + c];
-          }
-        }
+  if (isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2])) {
+    sphere_bricks(A.G, &A.R[3 * p], A.amap[p] + 2.0, A.clk->cur.s, vis[wv], lane, [&](int brick) {
+      // find p among the brick's keys (at most one slot holds it)
+      int hit = -1;
+      for (int s0 = 0; s0 < TSLOT; s0 += 64) {
+        const int key = A.bt_key[(size_t)brick * TSLOT + s0 + lane];
+        const uint64_t m = __ballot(key == p);
+        if (m) { hit = s0 + __ffsll((unsigned long long)m) - 1; break; }
       }
-    }
+      if (hit >= 0) {
+#pragma unroll
+        for (int c = 0; c < HYD; ++c) acc[c] += A.bt_val[((size_t)brick * TSLOT + hit) * HYD + c];
+      }
+    });
   }
   if (lane == 0) {
     for (int c = 0; c < HYD; ++c) {
@@ -658,8 +917,8 @@ hipError_t launch_hydro_gather(Sim *s, const Box &b) {
   A.R = s->R[s->pcur]; A.amap = s->amap;
   A.bt_key = s->bt_key; A.bt_val = s->bt_val; A.hyd_fb = s->hyd_fb;
   A.hyd = s->hyd[s->hcur];
-  A.n = s->n; A.lx = s->lx; A.ly = s->ly; A.lz = s->lz;
-  A.bxn = s->bxn; A.byn = s->byn; A.BY = s->BY; A.BZ = s->BZ;
+  A.n = s->n;
+  A.G = brick_geo(s);
   A.clk = s->clk;
   (void)b;
   if (s->n > 0)

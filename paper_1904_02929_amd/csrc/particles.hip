@@ -759,7 +759,15 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   double e0, e1, e2;
   int ke;
   minimage(bnew, Rn[0] - Ro[0], Rn[1] - Ro[1], Rn[2] - Ro[2], e0, e1, e2, ke);
-  const double delta = sqrt(e0 * e0 + e1 * e1 + e2 * e2) + fabs(bnew.s - bold.s) + 1e-6;
+  const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+  if (!(disp <= 1.0)) {  // a blown-up run: more than a node per step (the shell would be huge)
+    if (lane == 0) atomicOr(A.flags, 16);
+    return;
+  }
+  // change of the Lees-Edwards offset, taken modulo the period (the offset wraps at Lx)
+  double ds = bnew.s - bold.s;
+  ds -= bnew.Lx * rint(ds / bnew.Lx);
+  const double delta = disp + fabs(ds) + 1e-6;
   const double ro = a + delta, ri = a - delta;
   const Box &B = bnew;
   // rows (y, z) of the shell around each image of the new position

@@ -137,6 +137,7 @@ hipError_t launch_init_populations(Sim *s);
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk);
 hipError_t launch_lbm(Sim *s, const Box &b);
 hipError_t launch_hydro_gather(Sim *s, const Box &b);
+hipError_t launch_brick_lists(Sim *s);
 hipError_t launch_pop_convert(Sim *s, double *dev64, int to_storage);
 hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[19][nodes]*/, const Box &b);
 // ---- launchers (particles.hip) ----
@@ -188,7 +189,9 @@ struct Sim {
   double *a, *m, *I, *amap;
   double *hyd[2];
   int hcur;
-  int32_t *bt_key;  // [nbricks][128] sphere ids of each brick's link table (-1 empty)
+  int32_t *bt_key;  // [nbricks][128] spheres listed for each brick (k_brick_lists), then
+                    // the keys of its link table (k_lbm; -1 empty)
+  int32_t *bt_cnt;  // [nbricks] number of spheres listed for each brick
   double *bt_val;   // [nbricks][128][HYD]
   double *hyd_fb;   // [n][HYD] overflow of full brick tables
   double *pst;   // [n][PST]

@@ -41,7 +41,7 @@ def oracle_for(box, kw, pos, vel, omega, radius):
 
 def gpu_for(box, kw, pos, vel, omega, radius, precision):
     from paper_1904_02929_amd import susp
-    gk = {k: v for k, v in kw.items() if k in ORACLE_KEYS or k == "fp16_exp"}
+    gk = {k: v for k, v in kw.items() if k in ORACLE_KEYS or k in ("fp16_exp", "brick_y", "brick_z")}
     p = susp.make_params(box, radius=radius, pos=pos, vel=vel, omega=omega, precision=precision, **gk)
     return susp.Simulation(p)
 

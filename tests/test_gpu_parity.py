@@ -115,6 +115,17 @@ def test_dense_one_step(precision):
     assert o.s.nhist > 0  # contacts are active in the compared step
 
 
+@pytest.mark.parametrize("brick", [(8, 4), (16, 8)])
+def test_dense_partial_bricks_fp32(brick):
+    # bricks that divide none of 41 x 48 x 37 (x: one brick of 64 over 41 columns; the last
+    # z brick is short), so that brick enumeration wraps through a short brick
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=5)
+    kw = dict(kw, brick_y=brick[0], brick_z=brick[1])
+    o, g = _one_step_parity(box, pos, vel, om, rad, kw, 1, presteps=12)
+    F, T, S, nl = g.hydro()
+    assert np.array_equal(nl, o.nlinks)
+
+
 def test_dense_straddling_le_plane_fp32():
     # spheres placed across the sliding plane and across the x and z faces
     box, pos, vel, om, rad, kw = PU.dense_workload(seed=3)
@@ -144,6 +155,17 @@ def test_monolayer_oscillatory_fp32():
 def test_pure_fluid_le_fp32():
     kw = dict(shear_kind=1, gamma_dot=2e-3)
     _one_step_parity((24, 40, 17), np.zeros((0, 3)), None, None, np.zeros(0), kw, 1, presteps=25)
+
+
+def test_le_offset_wraps_fp64():
+    # u = gamma_dot * ly = 0.08: the Lees-Edwards offset passes lx = 16 between steps 199
+    # and 200, so the compared step moves the solid map across the wrap of the offset
+    from paper_1904_02929_amd import synth
+    box = (16, 40, 17)
+    pos = np.array([[8.0, 10.0, 8.0], [8.0, 29.0, 8.5], [3.0, 39.6, 9.0]])
+    rad = np.array([4.5, 4.5, 4.5])
+    vel, om = synth.affine_start(pos, rad, 2e-3, box[1])
+    _one_step_parity(box, pos, vel, om, rad, dict(shear_kind=1, gamma_dot=2e-3), 0, presteps=199)
 
 
 def test_multistep_fp64_from_create():
