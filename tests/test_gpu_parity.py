@@ -168,6 +168,14 @@ def test_le_offset_wraps_fp64():
     _one_step_parity(box, pos, vel, om, rad, dict(shear_kind=1, gamma_dot=2e-3), 0, presteps=199)
 
 
+def test_full_size_one_step_fp32():
+    # the benchmark workload at its full size (256^3, 12,914 spheres) in the launch
+    # configuration bench.py times (heuristic bricks, FP32): one step from the oracle's start
+    from paper_1904_02929_amd import synth
+    w = synth.bulk3d(256, 0.55, 1e-4, seed=1)
+    _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params), 1, presteps=0)
+
+
 def test_multistep_fp64_from_create():
     # both sides start from their own initial state and run 25 steps
     box, pos, vel, om, rad, kw = PU.dense_workload(seed=11)
