@@ -33,12 +33,13 @@ template <class T> __device__ inline T wave_sum(T v) {
 // Lattice kernel k_lbm: pull-stream, moving bounce-back, link sums, BGK collision and the
 // fluid stress partials in one pass.  The lattice is walked in bricks of TX x BY x BZ
 // nodes, one work-group per brick: its four waves take four consecutive rows (one 64-node
-// x segment each) and walk the brick's z range together.  The owner map of planes z-1, z,
-// z+1 (rows y-1 .. y+4 with a one-node x halo; rows beyond the box edges come from the
-// Lees-Edwards ghost owner planes) sits in a ring of four LDS planes; each z step fetches
-// one new plane, one step ahead.  Row and plane of every pull source are uniform over a
-// wave, so a population load is a uniform row pointer plus the lane's (periodically
-// wrapped) x.
+// x segment each) and walk the brick's z range together.  The owner map of planes z-1 ..
+// z+2 (rows y-1 .. y+4 with a one-node x halo; rows beyond the box edges come from the
+// Lees-Edwards ghost owner planes) sits in a ring of five LDS planes; each z step fetches
+// plane z+3.  Row and plane of every pull source are uniform over a wave, so a population
+// load is a uniform row offset plus the lane's (periodically wrapped) x.  The spheres that
+// can own a node of the brick's staged region are listed per brick beforehand
+// (k_brick_lists); their states sit in LDS beside the brick's link table.
 //
 // Links: with lever r_b - R = D - c_q/2 (D = node minus sphere centre, minimum image) the
 // surface velocity along the link is u_b.c_q = u(X).c_q, because (W x c).c = 0; hence one
@@ -51,8 +52,8 @@ template <class T> __device__ inline T wave_sum(T v) {
 // Per-sphere sums of the brick are accumulated in an LDS hash table with one copy per wave
 // (a wave adds its lanes in a fixed order; the copies are summed in wave order) and written
 // once per brick; k_hydro_gather adds a sphere's brick entries in a fixed order.  The sums
-// are therefore bitwise reproducible (unless a brick touches more than TSLOT spheres, whose
-// overflow goes through global atomics).
+// are therefore bitwise reproducible (unless more than TSLOT spheres are listed for a
+// brick: the rest go through global atomics).
 constexpr int TX = 64, TY = 4;
 constexpr int TSLOT = 128;
 constexpr int SDAT = 10;  // doubles per LDS sphere state (R, U, W; padded to 16 bytes)
