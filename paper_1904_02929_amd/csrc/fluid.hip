@@ -787,6 +787,11 @@ __device__ inline int brick_of(int xx, int L, int B) {
 template <class F>
 __device__ inline void sphere_bricks(const BrickGeo &G, const double *Rp, double r, double s,
                                      int *vis, int lane, F &&fn) {
+  // a runaway (or non-finite) position of a failed run: no bricks, and no loop whose bounds
+  // come from a coordinate far outside the box
+  if (!(Rp[0] > -2.0 * G.lx && Rp[0] < 3.0 * G.lx && Rp[1] > -2.0 * G.ly && Rp[1] < 3.0 * G.ly &&
+        Rp[2] > -2.0 * G.lz && Rp[2] < 3.0 * G.lz && r < 0.5 * G.lx + 0.5 * G.ly + 0.5 * G.lz))
+    return;
   int nvis = 0;
   int zlo = (int)floor(Rp[2] - r), zhi = (int)ceil(Rp[2] + r);
   if (zhi - zlo + 1 >= G.lz) { zlo = 0; zhi = G.lz - 1; }

@@ -572,9 +572,11 @@ __global__ __launch_bounds__(256) void k_substep(SubArgs A) {
   }
   for (int c = 0; c < 3; ++c) { A.Uo[3 * i + c] = U[c]; A.Wo[3 * i + c] = W[c]; A.Ro[3 * i + c] = R[c]; }
   A.Qo[4 * i] = qw / nn; A.Qo[4 * i + 1] = qx / nn; A.Qo[4 * i + 2] = qy / nn; A.Qo[4 * i + 3] = qz / nn;
-  if (A.last) {
+  if (A.last) {  // non-finite, or a runaway the bounded wraps could not bring back
     bool ok = true;
     for (int c = 0; c < 3; ++c) ok = ok && isfinite(R[c]) && isfinite(U[c]) && isfinite(W[c]);
+    ok = ok && R[0] > -bx.Lx && R[0] < 2.0 * bx.Lx && R[1] > -bx.Ly && R[1] < 2.0 * bx.Ly &&
+         R[2] > -bx.Lz && R[2] < 2.0 * bx.Lz;
     if (!ok) atomicOr(A.flags, 2);
   }
 }

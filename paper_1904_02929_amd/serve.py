@@ -150,6 +150,7 @@ class Server:
     sleep: object = time.sleep
     log: list = field(default_factory=list)
     host_s: float = 0.0   # time spent admitting jobs and queueing their steps
+    progress: object = None  # progress(finished, total), called as jobs finish
 
     def run(self, jobs):
         ex = self.executor
@@ -199,6 +200,8 @@ class Server:
                 res = ex.result(slot)
                 ex.remove(slot)
                 done.append(Done(v[0].jid, v[0].arrival, v[1], now(), res, v[3]))
+                if self.progress is not None:
+                    self.progress(len(done), len(jobs))
             self.log.append((now(), len(active)))
             if not progressed:
                 wait = self.poll_s
@@ -297,8 +300,10 @@ def serve_benchmark(n_jobs=64, steps=3000, budget=8 << 30, seed=1904, workers=8,
     log("serving: %d jobs packed in %.1f s" % (n_jobs, time.perf_counter() - t))
     # plain loop: service time of every job alone
     service = np.zeros(n_jobs)
-    for s in specs:
+    for k, s in enumerate(specs):
         service[s.jid], _ = run_alone(s, ws[s.jid])
+        if (k + 1) % 8 == 0:
+            log("serving: plain loop %d/%d jobs, %.1f s" % (k + 1, n_jobs, float(service.sum())))
     t_plain = float(service.sum())
     log("serving: plain loop %.1f s for %d jobs" % (t_plain, n_jobs))
     rate = n_jobs / (0.25 * t_plain)
@@ -313,13 +318,14 @@ def serve_benchmark(n_jobs=64, steps=3000, budget=8 << 30, seed=1904, workers=8,
     ex.tune(specs)
     t_tune = time.perf_counter() - t
     log("serving: autotuned %d lattice kinds in %.1f s" % (len(set((s.kind, s.L) for s in specs)), t_tune))
-    srv = Server(ex, budget)
+    every = lambda k, n: k % 8 == 0 and log("serving: batched %d/%d jobs done" % (k, n))
+    srv = Server(ex, budget, progress=every)
     done = srv.run(specs)
     torch.cuda.synchronize()
     # capacity: the same requests all present at the start (the server never idles)
     sat = [JobSpec(**{**s.__dict__, "arrival": 0.0}) for s in specs]
     t = time.perf_counter()
-    Server(ex, budget).run(sat)
+    Server(ex, budget, progress=every).run(sat)
     torch.cuda.synchronize()
     t_sat = time.perf_counter() - t
     ex.close()
