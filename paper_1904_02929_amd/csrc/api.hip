@@ -229,6 +229,8 @@ static size_t carve(Sim &s, char *base) {
   s.R0 = (double *)take(n * 3 * 8);
   s.bt_key = (int32_t *)take((size_t)s.nbricks * 128 * 4);
   s.bt_cnt = (int32_t *)take((size_t)s.nbricks * 4);
+  s.sp_cnt = (int32_t *)take(n * 4);
+  s.sp_ent = (int32_t *)take(n * 64 * 4);
   s.bt_val = (double *)take((size_t)s.nbricks * 128 * HYD * 8);
   s.hyd_fb = (double *)take(n * HYD * 8);
   s.a = (double *)take(n * 8);
@@ -349,6 +351,7 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       return bail(fail(SUSP_EDEVICE, "fill"));
   }
   if (n && launch_fill_f64(s.hyd_fb, n * HYD, 0.0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  if (n && launch_fill_i32(s.sp_cnt, n, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   if (n && (launch_fill_f64(s.pst, n * PST, 0.0, s.stream) || launch_fill_f64(s.dp, n * 8, 0.0, s.stream) ||
             launch_fill_i32(s.hstart, n * NCAP, 0, s.stream)))
     return bail(fail(SUSP_EDEVICE, "fill"));
@@ -432,8 +435,8 @@ static int one_step(Sim &s) {
     HIPCHK(e);
     HIPCHK(hipEventRecord(s.join_ev, s.aux));
   }
-  HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk));
   HIPCHK(launch_brick_lists(&s));
+  HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
@@ -799,7 +802,7 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     HIPCHK(hipMalloc((void **)&g, (size_t)2 * s.lx * s.lz * 4));
     hipError_t e = hipMalloc((void **)&lk, (size_t)NQ * s.nodes * 4);
     if (!e && n) e = launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr);
-    if (!e) e = n ? launch_ghosts(&s, b, g, s.gval, 0, nullptr) : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
+    if (!e) e = n ? launch_ghosts(&s, b, g, s.gval, 0, nullptr, 0) : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
     if (!e) e = launch_link_enum(&s, g, lk, b);
     std::vector<int32_t> all;
     if (!e) {

@@ -57,6 +57,7 @@ template <class T> __device__ inline T wave_sum(T v) {
 constexpr int TX = 64, TY = 4;
 constexpr int TSLOT = 128;
 constexpr int SDAT = 10;  // doubles per LDS sphere state (R, U, W; padded to 16 bytes)
+constexpr int SPCAP = 64;  // table entries with links kept per sphere (past it: enumeration)
 constexpr int SROW = TX + 2, SPLANE = (TY + 2) * SROW;  // staged owner plane: 6 rows of 66
 
 struct LbmArgs {
@@ -71,6 +72,7 @@ struct LbmArgs {
   int32_t *bt_key;        // in: the spheres listed for each brick; out: its table's keys
   const int32_t *bt_cnt;  // number of spheres listed for each brick
   double *bt_val;
+  int32_t *sp_cnt, *sp_ent;  // per sphere: its table entries with links (brick*TSLOT+slot)
   double *hyd_fb;
   double *pineq;
   int32_t *flags;
@@ -694,9 +696,16 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   for (int i = t; i < TSLOT; i += 256) {
     const int key = skey[i];
     A.bt_key[(size_t)V.brick * TSLOT + i] = key;
-    if (key >= 0)
+    if (key >= 0) {
       for (int c = 0; c < HYD; ++c)
         A.bt_val[((size_t)V.brick * TSLOT + i) * HYD + c] = ((sval[0][i][c] + sval[1][i][c]) + sval[2][i][c]) + sval[3][i][c];
+      // entries with links go on the sphere's list (k_hydro_gather orders them by index)
+      const double nl = ((sval[0][i][HYD - 1] + sval[1][i][HYD - 1]) + sval[2][i][HYD - 1]) + sval[3][i][HYD - 1];
+      if (nl > 0.0) {
+        const int c = atomicAdd(&A.sp_cnt[key], 1);
+        if (c < SPCAP) A.sp_ent[(size_t)key * SPCAP + c] = V.brick * TSLOT + i;
+      }
+    }
   }
   // ---- brick partial of the non-equilibrium momentum flux (fluid stress): the 256
   //      per-thread partials of each component summed by one wave in a fixed order ----
@@ -730,6 +739,8 @@ static LbmArgs lbm_args(Sim *s, const Box &b) {
   A.bt_key = s->bt_key;
   A.bt_cnt = s->bt_cnt;
   A.bt_val = s->bt_val;
+  A.sp_cnt = s->sp_cnt;
+  A.sp_ent = s->sp_ent;
   A.hyd_fb = s->hyd_fb;
   A.pineq = s->pineq;
   A.flags = s->flags;
@@ -872,13 +883,18 @@ hipError_t launch_brick_lists(Sim *s) {
   return hipGetLastError();
 }
 
-// Per-sphere hydrodynamic sums: the entries of every brick near the sphere, added in brick
-// order, plus the overflow accumulator (which is cleared for the next step).  One wave per
-// sphere.
+// Per-sphere hydrodynamic sums, one wave per sphere.  k_lbm lists each sphere's table
+// entries with links (at most SPCAP); the wave sorts them by index (brick, then slot) so that
+// the order does not depend on how the flushes interleaved, and adds them by a fixed lane
+// butterfly.  A sphere with more entries (tiny bricks) visits every brick near it instead,
+// in enumeration order.  Either way the overflow accumulator is added and cleared, and so is
+// the entry count, for the next step.
 struct GatherArgs {
   const double *R, *amap;
   const int32_t *bt_key;
   const double *bt_val;
+  int32_t *sp_cnt;
+  const int32_t *sp_ent;
   double *hyd_fb;
   double *hyd;
   int n;
@@ -895,7 +911,25 @@ __global__ __launch_bounds__(256) void k_hydro_gather(GatherArgs A) {
   double acc[HYD];
 #pragma unroll
   for (int c = 0; c < HYD; ++c) acc[c] = 0.0;
-  if (isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2])) {
+  const int cnt = A.sp_cnt[p];
+  if (cnt <= SPCAP) {
+    // the entries, sorted ascending across the wave (bitonic; empty lanes sort last)
+    int e = lane < cnt ? A.sp_ent[(size_t)p * SPCAP + lane] : 0x7fffffff;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int o = __shfl_xor(e, j, 64);
+        const bool up = (lane & k) == 0, low = (lane & j) == 0;
+        e = (low == up) ? min(e, o) : max(e, o);
+      }
+    }
+    double v[HYD];
+#pragma unroll
+    for (int c = 0; c < HYD; ++c) v[c] = lane < cnt ? A.bt_val[(size_t)e * HYD + c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < HYD; ++c) acc[c] = wave_sum(v[c]);
+  } else if (isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2])) {
     sphere_bricks(A.G, &A.R[3 * p], A.amap[p] + 2.0, A.clk->cur.s, vis[wv], lane, [&](int brick) {
       // find p among the brick's keys (at most one slot holds it)
       int hit = -1;
@@ -915,6 +949,7 @@ __global__ __launch_bounds__(256) void k_hydro_gather(GatherArgs A) {
       A.hyd[(size_t)p * HYD + c] = acc[c] + A.hyd_fb[(size_t)p * HYD + c];
       A.hyd_fb[(size_t)p * HYD + c] = 0.0;
     }
+    A.sp_cnt[p] = 0;
   }
 }
 
@@ -922,6 +957,7 @@ hipError_t launch_hydro_gather(Sim *s, const Box &b) {
   GatherArgs A;
   A.R = s->R[s->pcur]; A.amap = s->amap;
   A.bt_key = s->bt_key; A.bt_val = s->bt_val; A.hyd_fb = s->hyd_fb;
+  A.sp_cnt = s->sp_cnt; A.sp_ent = s->sp_ent;
   A.hyd = s->hyd[s->hcur];
   A.n = s->n;
   A.G = brick_geo(s);
@@ -949,6 +985,10 @@ struct GhostArgs {
   void *gval;
   int32_t *flags;
   H16 h16;
+  // with lists set: the spheres listed for each brick (k_brick_lists of this step), which
+  // hold every sphere that can own a ghost point of the brick's first or last row band
+  const int32_t *bt_key, *bt_cnt;
+  int lists, bxn, byn, BZ;
 };
 
 // Galilean-corrected post-collision deviation of direction q at node (x,yrow,z) seen from
@@ -1005,7 +1045,28 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   px = px - bx.Lx * floor(px / bx.Lx);
   const double py = g == 0 ? (double)(A.ly - 1) : 0.0;
   int owner = -1, clash = 0;
-  if (A.n > 0) {
+  auto test = [&](int p) {
+    double dx, dy2, dz;
+    int k;
+    minimage(bx, (double)x - A.R[3 * p], gy - A.R[3 * p + 1], (double)z - A.R[3 * p + 2], dx, dy2, dz, k);
+    const double r2 = dx * dx + dy2 * dy2 + dz * dz;
+    if (r2 < A.amap[p] * A.amap[p]) {
+      if (owner >= 0 && owner != p) clash = 1;
+      if (owner < 0 || p < owner) owner = p;
+    }
+  };
+  bool listed = false;
+  if (A.n > 0 && A.lists) {
+    const int brick = x / TX + A.bxn * ((g == 0 ? 0 : A.byn - 1) + A.byn * (z / A.BZ));
+    const int cnt = A.bt_cnt[brick];
+    if (cnt <= TSLOT) {
+      const int32_t *key = A.bt_key + (size_t)brick * TSLOT;
+#pragma unroll 4
+      for (int i = 0; i < cnt; ++i) test(key[i]);
+      listed = true;
+    }
+  }
+  if (A.n > 0 && !listed) {
     const Cells &C = A.C;
     int ccy = (int)floor(py * C.iy);
     ccy = ccy < 0 ? 0 : (ccy >= C.ny ? C.ny - 1 : ccy);
@@ -1027,18 +1088,7 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
           int nx = C.nx >= 3 ? ccx + ix - 1 : ix;
           nx = nx < 0 ? nx + C.nx : (nx >= C.nx ? nx - C.nx : nx);
           const int c = nx + C.nx * (ny + C.ny * nz);
-          for (int t = A.cell_start[c]; t < A.cell_start[c + 1]; ++t) {
-            const int p = A.cell_ids[t];
-            double dx, dy2, dz;
-            int k;
-            minimage(bx, (double)x - A.R[3 * p], gy - A.R[3 * p + 1], (double)z - A.R[3 * p + 2],
-                     dx, dy2, dz, k);
-            const double r2 = dx * dx + dy2 * dy2 + dz * dz;
-            if (r2 < A.amap[p] * A.amap[p]) {
-              if (owner >= 0 && owner != p) clash = 1;
-              if (owner < 0 || p < owner) owner = p;
-            }
-          }
+          for (int t = A.cell_start[c]; t < A.cell_start[c + 1]; ++t) test(A.cell_ids[t]);
         }
       }
     }
@@ -1064,8 +1114,12 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   }
 }
 
-hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk) {
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,
+                         int lists) {
   GhostArgs A;
+  A.bt_key = s->bt_key; A.bt_cnt = s->bt_cnt;
+  A.lists = lists && s->n > 0;
+  A.bxn = s->bxn; A.byn = s->byn; A.BZ = s->BZ;
   A.fin = s->f[s->cur];
   A.plane = s->plane;
   A.own = s->own;

@@ -135,7 +135,8 @@ struct Sim;
 
 // ---- launchers (fluid.hip) ----
 hipError_t launch_init_populations(Sim *s);
-hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk);
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,
+                         int lists);
 hipError_t launch_lbm(Sim *s, const Box &b);
 hipError_t launch_hydro_gather(Sim *s, const Box &b);
 hipError_t launch_brick_lists(Sim *s);
@@ -197,6 +198,8 @@ struct Sim {
   int32_t *bt_key;  // [nbricks][128] spheres listed for each brick (k_brick_lists), then
                     // the keys of its link table (k_lbm; -1 empty)
   int32_t *bt_cnt;  // [nbricks] number of spheres listed for each brick
+  int32_t *sp_cnt;  // [n] table entries with links per sphere (k_lbm appends, gather clears)
+  int32_t *sp_ent;  // [n][64] those entries, brick * 128 + slot
   double *bt_val;   // [nbricks][128][HYD]
   double *hyd_fb;   // [n][HYD] overflow of full brick tables
   double *pst;   // [n][PST]
