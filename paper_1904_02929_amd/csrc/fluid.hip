@@ -124,6 +124,26 @@ template <class T> __device__ inline void addc(T &acc, int c, T v) {
   if (c > 0) acc += v;
   else if (c < 0) acc -= v;
 }
+
+// Link sums over the 9 opposite pairs: coefficient kind sel (0 c_x, 1 c_y, 2 c_z, 3 c_x c_y,
+// 4 c_x c_z, 5 c_y c_z) of direction q, and the first pair where it is nonzero.
+__host__ __device__ constexpr int pair_coef(int sel, int q) {
+  return sel == 0 ? cx(q) : sel == 1 ? cy(q) : sel == 2 ? cz(q)
+       : sel == 3 ? cx(q) * cy(q) : sel == 4 ? cx(q) * cz(q) : cy(q) * cz(q);
+}
+__host__ __device__ constexpr int first_pair(int sel) {
+  int f = 9;
+  for (int pi = 8; pi >= 0; --pi)
+    if (pair_coef(sel, 2 * pi + 1) != 0) f = pi;
+  return f;
+}
+// acc += c * v (c in {-1, 0, 1}, compile time) for pair pi, or acc = c * v at the first pair
+// of its kind
+__device__ inline void acc_pair(double &acc, int pi, int sel, int c, double v) {
+  const bool first = pi == first_pair(sel);
+  if (c > 0) acc = first ? v : acc + v;
+  else if (c < 0) acc = first ? -v : acc - v;
+}
 __device__ inline float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fmaT(double a, double b, double c) { return fma(a, b, c); }
 
@@ -555,13 +575,16 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
             const double mq = lq ? fma(2.0, fq, -corr) : 0.0;
             const double mb = lb ? fma(2.0, fb, corr) : 0.0;
             const double sm2 = mq + mb, df = mq - mb;
-            addc(g0, cx(q), df); addc(g1, cy(q), df); addc(g2, cz(q), df);
-            if (cx(q) != 0) mxx += sm2;
-            if (cy(q) != 0) myy += sm2;
-            if (cz(q) != 0) mzz += sm2;
-            addc(mxy, cx(q) * cy(q), sm2); addc(mxz, cx(q) * cz(q), sm2); addc(myz, cy(q) * cz(q), sm2);
-            if (lq) n[q] = (CT)(fq - corr);
-            if (lb) n[b] = (CT)(fb + corr);
+            // each sum starts at its first contributing pair (no addition to zero)
+            acc_pair(g0, pi, 0, cx(q), df); acc_pair(g1, pi, 1, cy(q), df); acc_pair(g2, pi, 2, cz(q), df);
+            acc_pair(mxx, pi, 0, cx(q) * cx(q), sm2);
+            acc_pair(myy, pi, 1, cy(q) * cy(q), sm2);
+            acc_pair(mzz, pi, 2, cz(q) * cz(q), sm2);
+            acc_pair(mxy, pi, 3, cx(q) * cy(q), sm2); acc_pair(mxz, pi, 4, cx(q) * cz(q), sm2);
+            acc_pair(myz, pi, 5, cy(q) * cz(q), sm2);
+            const CT cr = (CT)corr;
+            if (lq) n[q] = n[q] - cr;
+            if (lb) n[b] = n[b] + cr;
           }
           v[0] = -g0; v[1] = -g1; v[2] = -g2;
           v[3] = Dy * v[2] - Dz * v[1];
