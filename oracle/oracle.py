@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32),
         ("wall_y", C.c_int32), ("wall_u_bot", C.c_double), ("wall_u_top", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
+        ("contact_bins", C.c_int32),
     ]
 
 
@@ -71,6 +72,7 @@ class Sim(C.Structure):
         ("sig_count", C.c_int64), ("gp_cos", C.c_double), ("gp_sin", C.c_double),
         ("gp_count", C.c_int64), ("ledger", C.c_double), ("flags", C.c_int32),
         ("nthreads", C.c_int32),
+        ("cst", _PD), ("ctot", C.c_double * 6), ("csig", C.c_double * 6), ("csamples", C.c_int64),
     ]
 
 
@@ -102,6 +104,9 @@ def lib():
         L.orc_dlvo.argtypes = [C.POINTER(Params), C.POINTER(Derived), C.c_double, C.c_double,
                                _PD, _PD]
         L.orc_lattice.argtypes = [_PI, _PI, _PI, _PD, _PI]
+        L.orc_contact_stats.argtypes = [C.POINTER(Sim), C.c_int32, _PD, _PD]
+        L.orc_contact_stats.restype = C.c_int
+        L.orc_sym3_eigen.argtypes = [_PD, _PD]
         _lib = L
     return _lib
 
@@ -119,6 +124,7 @@ DEFAULTS = dict(
     lub_delta=-1.0, lub_hc=0.5, lub_subtract_hc=1, F0=-1.0, debye_lambda=-1.0, pair_cutoff=1.0,
     n_sub=8, quasi2d=0, shear_kind=0, gamma_dot=0.0, g0_I=0.0, g0_F=0.0, period=1, theta=0.0,
     ncyc_I=0, ncyc_F=0, wall_y=0, wall_u_bot=0.0, wall_u_top=0.0, gx=0.0, gy=0.0, gz=0.0,
+    contact_bins=0,
 )
 
 
@@ -193,6 +199,14 @@ def dlvo(params, derived, ai, aj, d):
     Fi = np.zeros(3)
     lib().orc_dlvo(C.byref(params), C.byref(derived), float(ai), float(aj), _pd(_v3(d)), _pd(Fi))
     return Fi
+
+
+def sym3_eigen(a6):
+    """Eigenvalues (descending) of the symmetric 3x3 matrix xx yy zz xy xz yz."""
+    a = np.ascontiguousarray(a6, np.float64).reshape(6)
+    ev = np.zeros(3)
+    lib().orc_sym3_eigen(_pd(a), _pd(ev))
+    return ev
 
 
 class Oracle:
@@ -278,6 +292,15 @@ class Oracle:
         out = np.zeros((5, 6)); gg = np.zeros(2)
         lib().orc_stress(self.ptr, _pd(out), _pd(gg))
         return out, gg
+
+    def contact_stats(self, nbins):
+        """(hist[5][nbins] = rho, xi_N, xi_T, zeta_N, zeta_T; summary[12]) since the last
+        call, then reset (see orc_contact_stats)."""
+        hist = np.zeros((5, nbins)); summ = np.zeros(12)
+        rc = lib().orc_contact_stats(self.ptr, int(nbins), _pd(hist), _pd(summ))
+        if rc:
+            raise ValueError("nbins must equal the simulation's contact_bins")
+        return hist, summ
 
     def sig_last(self):
         return np.array([[self.s.sig_last[k][c] for c in range(6)] for k in range(5)])

@@ -9,6 +9,7 @@
  *   DLVO repulsion                   eq. (13)
  *   total stress                     eq. (15)
  *   oscillatory strain, G', G''      eqs. (16)-(18)
+ *   contact statistics               eqs. (19)-(23), (26)-(27), App. C; Delta lambda / P
  *   LB update, moments, collision    App. A eqs. (3)-(5) (collision taken as single-time BGK)
  *   moving bounce-back, link force   App. A eqs. (6)-(8); force and torque sums eqs. (9)-(10)
  *   mapped radius, lubrication       App. A (mapped radius 0.95 a; grand-resistance matrix
@@ -408,6 +409,7 @@ orc_sim *orc_create(const orc_params *p, int32_t np, const double *pos, const do
   S->Frest = (double *)xcalloc(3 * (size_t)np, sizeof(double));
   S->Trest = (double *)xcalloc(3 * (size_t)np, sizeof(double));
   S->gown = (int32_t *)xcalloc(2 * (size_t)p->lx * p->lz, sizeof(int32_t));
+  S->cst = (double *)xcalloc(3 * (size_t)(p->contact_bins > 0 ? p->contact_bins : 1), sizeof(double));
   for (int i = 0; i < np; ++i) {
     for (int c = 0; c < 3; ++c) {
       S->R[3 * i + c] = pos[3 * i + c];
@@ -449,7 +451,7 @@ void orc_destroy(orc_sim *S) {
   free(S->f); free(S->fn); free(S->own); free(S->R); free(S->U); free(S->W); free(S->Q);
   free(S->a); free(S->m); free(S->I); free(S->amap); free(S->Fh); free(S->Th); free(S->Sh);
   free(S->nlinks); free(S->Frest); free(S->Trest); free(S->pi); free(S->pj); free(S->hi); free(S->hj); free(S->hxi);
-  free(S->gown);
+  free(S->gown); free(S->cst);
   free(S);
 }
 
@@ -782,6 +784,41 @@ static void uncover_fn(orc_sim *S, int p, int64_t node, int x, int y, int z, voi
 static int finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 
 /* ---------------- the full step ---------------- */
+/* ---------------- contact statistics (Sec. 4.2, eqs. 19-23) ----------------
+ * A contact is a pair whose surfaces overlap at the last DEM substep of a step; dv = R_i - R_j
+ * (minimum image), Fn and Fc the normal and the total contact force on i at that substep.
+ * Orientation: theta = atan(r_y / r_x) of the in-plane part of dv, in [0, pi) (the contact
+ * seen from either sphere is one orientation); a contact with no in-plane part counts at 0.
+ * F_nor: the normal force, positive when it pushes the spheres apart.  F_tan: the component
+ * along t_theta = (-sin theta, cos theta) of the tangential force on the sphere at the tail
+ * of n_theta, positive when it turns that sphere counterclockwise.  Seen from the other
+ * sphere n_theta, t_theta and the force all reverse, so both values are the same.          */
+static void contact_sample(orc_sim *S, const double dv[3], const double Fn[3], const double Fc[3]) {
+  const int nb = S->p.contact_bins;
+  double r = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  double rxy = sqrt(dv[0] * dv[0] + dv[1] * dv[1]);
+  double nx = 1.0, ny = 0.0;
+  if (rxy > 0.0) { nx = dv[0] / rxy; ny = dv[1] / rxy; }
+  double fnor = (Fn[0] * dv[0] + Fn[1] * dv[1] + Fn[2] * dv[2]) / r;
+  double ft[3] = {Fc[0] - Fn[0], Fc[1] - Fn[1], Fc[2] - Fn[2]};
+  /* n_theta = dv / |dv| points from j to i, so the sphere at its tail is j, which feels -ft */
+  double ftan = -(ft[0] * (-ny) + ft[1] * nx);
+  double ox = nx, oy = ny;
+  if (oy < 0.0 || (oy == 0.0 && ox < 0.0)) { ox = -ox; oy = -oy; }
+  double th = atan2(oy, ox);
+  int b = (int)(th * (double)nb / PI);
+  if (b < 0) b = 0;
+  if (b > nb - 1) b = nb - 1;
+  S->cst[3 * b] += 1.0;
+  S->cst[3 * b + 1] += fnor;
+  S->cst[3 * b + 2] += ftan;
+  S->ctot[0] += 1.0;
+  S->ctot[1] += fnor;
+  /* integrand of eqs. 26-27: [F_nor n - F_tan t] (x) n with n = (nx, ny), t = (-ny, nx) */
+  double vx = fnor * nx - ftan * (-ny), vy = fnor * ny - ftan * nx;
+  S->ctot[2] += vx * nx; S->ctot[3] += vx * ny; S->ctot[4] += vy * nx; S->ctot[5] += vy * ny;
+}
+
 static void one_step(orc_sim *S) {
   orc_params *P = &S->p;
   const int np = S->np;
@@ -834,6 +871,7 @@ static void one_step(orc_sim *S) {
       double Fc[3], Tci[3], Tcj[3], Fn[3], Fr[3], Fl[3], Tli[3], Tlj[3], Si[6], Sj[6];
       pon[k] = orc_contact(P, &S->d, S->a[i], S->a[j], d, Ui, Uj, Wi, Wj, dts, &pxi[3 * k],
                            Fc, Tci, Tcj, Fn);
+      if (P->contact_bins > 0 && sub == ns - 1 && pon[k]) contact_sample(S, d, Fn, Fc);
       orc_dlvo(P, &S->d, S->a[i], S->a[j], d, Fr);
       orc_lubrication(P, &S->d, S->a[i], S->a[j], d, Ui, Uj, Wi, Wj, Fl, Tli, Tlj, Si, Sj);
       for (int c = 0; c < 3; ++c) {
@@ -934,6 +972,10 @@ static void one_step(orc_sim *S) {
   for (int k = 0; k < 5; ++k)
     for (int c = 0; c < 6; ++c) { S->sig_last[k][c] = sig[k][c]; S->sig_sum[k][c] += sig[k][c]; }
   S->sig_count += 1;
+  if (P->contact_bins > 0) {
+    for (int c = 0; c < 6; ++c) S->csig[c] += sig[0][c] + sig[1][c] + sig[2][c] + sig[3][c] + sig[4][c];
+    S->csamples += 1;
+  }
   /* G', G'' (eqs. 17-18, rectangle rule over the observation periods) */
   if (P->shear_kind == 2) {
     int64_t tI = (int64_t)P->ncyc_I * P->period, tF = tI + (int64_t)P->ncyc_F * P->period;
@@ -970,4 +1012,114 @@ void orc_stress(orc_sim *S, double out[5][6], double gg[2]) {
   } else {
     gg[0] = 0.0; gg[1] = 0.0;
   }
+}
+
+/* Eigenvalues of a symmetric 3x3 matrix by cyclic Jacobi rotations, sorted descending. */
+void orc_sym3_eigen(const double a6[6], double ev[3]) {
+  double A[3][3] = {{a6[0], a6[3], a6[4]}, {a6[3], a6[1], a6[5]}, {a6[4], a6[5], a6[2]}};
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    if (off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        /* rotation in the (p, q) plane that zeroes A[p][q] */
+        double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) {  /* columns p, q */
+          double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  /* rows p, q */
+          double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  ev[0] = A[0][0]; ev[1] = A[1][1]; ev[2] = A[2][2];
+  for (int i = 0; i < 3; ++i)
+    for (int k = i + 1; k < 3; ++k)
+      if (ev[k] > ev[i]) { double x = ev[i]; ev[i] = ev[k]; ev[k] = x; }
+}
+
+/* Distributions of eqs. 19-23 per bin, the stress of eq. 27 (3D) or eq. 26 (monolayer) and
+ * the anisotropy Delta lambda / P of the mean total stress, over the steps since the last call.
+ * The integral of eqs. 26-27 is taken over the contacts themselves, i.e. <F_nor> times the
+ * integral of [zeta_N n - zeta_T t] n equals the mean of [F_nor n - F_tan t] n over contacts.
+ * Prefactor: the one for which the formula equals the contact virial of eq. 12 when every
+ * contact is between spheres of radius a at distance 2a: 3 phi3 Z / (4 pi a^2) in 3D (App. C)
+ * and phi Z / (pi a) per unit area in a monolayer (eq. 26), divided by lz to give a stress per
+ * unit volume like eq. 15.  a is the mean radius, Z = 2 contacts / spheres.              */
+int orc_contact_stats(orc_sim *S, int32_t nbins, double *hist, double summary[12]) {
+  const orc_params *P = &S->p;
+  if (nbins <= 0 || nbins != P->contact_bins) return -1;
+  const double dth = PI / (double)nbins;
+  const double nc = S->ctot[0];
+  const double fmean = nc > 0.0 ? S->ctot[1] / nc : 0.0;  /* <F_nor> */
+  for (int b = 0; b < nbins; ++b) {
+    double c = S->cst[3 * b];
+    double rho = nc > 0.0 ? c / (nc * dth) : 0.0;                 /* eq. 23 normalisation */
+    double fnor = c > 0.0 ? S->cst[3 * b + 1] / c : 0.0;         /* F_nor(theta)          */
+    double ftan = c > 0.0 ? S->cst[3 * b + 2] / c : 0.0;         /* F_tan(theta)          */
+    double xn = fmean != 0.0 ? fnor / fmean : 0.0;               /* eq. 21                */
+    double xt = fmean != 0.0 ? ftan / fmean : 0.0;               /* eq. 22                */
+    hist[b] = rho;
+    hist[nbins + b] = xn;
+    hist[2 * nbins + b] = xt;
+    hist[3 * nbins + b] = rho * xn;                               /* eq. 19                */
+    hist[4 * nbins + b] = rho * xt;                               /* eq. 20                */
+  }
+  const double samples = (double)S->csamples;
+  const int np = S->np;
+  double Z = (np > 0 && samples > 0.0) ? 2.0 * nc / ((double)np * samples) : 0.0;
+  double asum = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int i = 0; i < np; ++i) {
+    asum += S->a[i];
+    a2 += PI * S->a[i] * S->a[i];
+    a3 += (4.0 / 3.0) * PI * S->a[i] * S->a[i] * S->a[i];
+  }
+  double am = np > 0 ? asum / (double)np : 0.0;
+  double frac, C;
+  if (P->quasi2d) {
+    frac = a2 / ((double)P->lx * (double)P->ly);
+    C = am > 0.0 ? frac * Z / (PI * am) / (double)P->lz : 0.0;
+  } else {
+    frac = a3 / ((double)P->lx * (double)P->ly * (double)P->lz);
+    C = am > 0.0 ? 3.0 * frac * Z / (4.0 * PI * am * am) : 0.0;
+  }
+  double sh[4];
+  for (int k = 0; k < 4; ++k) sh[k] = nc > 0.0 ? C * (S->ctot[2 + k] / nc) : 0.0;
+  /* stress anisotropy of the mean total stress: Delta lambda = largest - smallest eigenvalue,
+   * P = minus the mean eigenvalue (3D); the x-y block in a monolayer */
+  double M[6];
+  for (int c = 0; c < 6; ++c) M[c] = samples > 0.0 ? S->csig[c] / samples : 0.0;
+  double dl, pr;
+  if (P->quasi2d) {
+    double mid = 0.5 * (M[0] + M[1]);
+    double rad = sqrt(0.25 * (M[0] - M[1]) * (M[0] - M[1]) + M[3] * M[3]);
+    dl = 2.0 * rad;
+    pr = -mid;
+  } else {
+    double ev[3];
+    orc_sym3_eigen(M, ev);
+    dl = ev[0] - ev[2];
+    pr = -(ev[0] + ev[1] + ev[2]) / 3.0;
+  }
+  summary[0] = samples;
+  summary[1] = samples > 0.0 ? nc / samples : 0.0;
+  summary[2] = Z;
+  summary[3] = fmean;
+  summary[4] = sh[0]; summary[5] = sh[1]; summary[6] = sh[2]; summary[7] = sh[3];
+  summary[8] = dl;
+  summary[9] = pr;
+  summary[10] = pr != 0.0 ? dl / pr : 0.0;
+  summary[11] = frac;
+  memset(S->cst, 0, 3 * sizeof(double) * (size_t)nbins);
+  memset(S->ctot, 0, sizeof S->ctot);
+  memset(S->csig, 0, sizeof S->csig);
+  S->csamples = 0;
+  return 0;
 }

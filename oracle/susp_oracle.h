@@ -44,6 +44,8 @@ typedef struct {
   int32_t wall_y;              /* 1: rows y=0 and y=ly-1 are static/moving walls      */
   double wall_u_bot, wall_u_top;
   double gx, gy, gz;           /* uniform body force per node                         */
+  int32_t contact_bins;        /* > 0: contact statistics (Sec. 4.2) in this many angular
+                                  bins over [0, pi), sampled once per step              */
 } orc_params;
 
 /* Fully resolved constants after defaults are applied. */
@@ -87,6 +89,12 @@ typedef struct {
   double ledger;             /* fluid mass removed by covering minus mass restored    */
   int32_t flags;             /* 1 mapped-sphere overlap, 2 non-finite particle state  */
   int32_t nthreads;
+  /* contact statistics since the last orc_contact_stats call */
+  double *cst;               /* [contact_bins][3] contacts, sum F_nor, sum F_tan per bin */
+  double ctot[6];            /* contacts, sum F_nor, sum of [F_nor n - F_tan t] (x) n
+                                (xx, xy, yx, yy) over all contacts                     */
+  double csig[6];            /* sum over sampled steps of the total stress (eq. 15)    */
+  int64_t csamples;          /* sampled steps                                          */
 } orc_sim;
 
 /* D3Q19 lattice as used by the oracle (index q: velocity, weight, opposite). */
@@ -104,6 +112,14 @@ int orc_remap(orc_sim *s);
 int orc_set_history(orc_sim *s, int32_t n, const int32_t *i, const int32_t *j, const double *xi);
 /* Averages since the previous call; gg = {G', G''} over completed observation steps. */
 void orc_stress(orc_sim *s, double out[5][6], double gg[2]);
+/* Contact statistics (Sec. 4.2, eqs. 19-23, 26-27; App. C) over the steps since the previous
+ * call, then reset.  hist[5][nbins] = rho, xi_N, xi_T, zeta_N, zeta_T at the bin centres
+ * (nbins must equal contact_bins); summary[12] = samples, contacts per sample, Z, <F_nor>,
+ * sigma_hat xx, xy, yx, yy, Delta lambda, P, Delta lambda / P, volume (area) fraction.
+ * Returns -1 if nbins does not match, else 0.                                            */
+int orc_contact_stats(orc_sim *s, int32_t nbins, double *hist, double summary[12]);
+/* Eigenvalues of a symmetric 3x3 matrix (xx yy zz xy xz yz), descending (Jacobi). */
+void orc_sym3_eigen(const double a[6], double ev[3]);
 /* LE protocol at step t: offset s (wrapped to [0,lx)) and sliding velocity. */
 void orc_protocol(const orc_params *p, int64_t t, double *s, double *ule);
 
