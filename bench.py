@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
     ap.add_argument("--workload", default="large3d", choices=["large3d", "bulk96", "empty256"])
+    ap.add_argument("--contact-bins", type=int, default=0,
+                    help="also sample the contact statistics every step in this many bins")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=24,
@@ -130,7 +132,7 @@ def main():
     w, wname = workload(args.workload)
     log("workload %s: box %s, %d spheres (%.1f s to generate)" % (wname, w.box, w.n, time.perf_counter() - t))
     p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
-                         precision=PREC[args.precision], **w.params)
+                         precision=PREC[args.precision], contact_bins=args.contact_bins, **w.params)
     sim = susp.Simulation(p)
     stream = sim.stream
     sim.step(args.warmup)
@@ -200,6 +202,7 @@ def main():
             "shear_rate": w.params.get("gamma_dot"),
             "precision": args.precision,
             "n_sub": int(p.n_sub),
+            "contact_bins": int(args.contact_bins),
             "status": int(rc),
         },
         "fluid_mlups": round(n_fluid * args.steps / (ms / 1e3) / 1e6, 2),

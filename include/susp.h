@@ -94,6 +94,8 @@ typedef struct {
   int32_t fp16_exp;          /* k of the FP16 storage scale 2^k (SUSP_FP16STORE only)    */
   int32_t brick_y, brick_z;  /* lattice-kernel brick of 64 x brick_y x brick_z nodes;
                                 0 = chosen from the lattice size (brick_y a multiple of 4) */
+  int32_t contact_bins;      /* 0: off; 1..360: contact statistics (susp_contact_stats)
+                                sampled every step in this many orientation bins          */
 } susp_params;
 
 /* Fill *p with the paper's defaults (tau 1, rho0 1, map_ratio 0.95, rho_p 1, kt 0.5 kn,
@@ -126,6 +128,30 @@ int susp_step(susp_sim *s, int64_t nsteps);
  * yz, each divided by the box volume (eqs. 12, 14, 15).  gg = {G', G''} from eqs. (17)-(18)
  * over the observation steps completed so far (0 if none).  Synchronises.                */
 int susp_stress(susp_sim *s, double out[5][6], double gg[2]);
+
+/* Contact-force statistics of Sec. 4.2 (eqs. 19-23) and the stress built from them (eq. 27
+ * for 3D suspensions, eq. 26 for monolayers; App. C), over the steps since the previous call
+ * (or creation), then reset.  Needs contact_bins > 0; nbins must equal it (else SUSP_EINVAL).
+ * A contact is a pair whose surfaces overlap at the last DEM substep of a step.  Its
+ * orientation theta in [0, pi) is that of the in-plane part (x, y) of the centre-to-centre
+ * vector (both senses are one orientation; no in-plane part counts as 0), binned in nbins
+ * equal bins.  F_nor: normal contact force, positive when it pushes the spheres apart;
+ * F_tan: component along t = (-sin theta, cos theta) of the tangential contact force on the
+ * sphere from which n = (cos theta, sin theta) points to the other, positive when it turns
+ * that sphere counterclockwise.
+ *   hist[5][nbins] (host, caller-owned): per bin centre, rho(theta) normalised as in eq. 23,
+ *     xi_N = F_nor(theta) / <F_nor> (eq. 21), xi_T = F_tan(theta) / <F_nor> (eq. 22),
+ *     zeta_N = rho xi_N (eq. 19), zeta_T = rho xi_T (eq. 20); F_nor(theta) and F_tan(theta)
+ *     are the mean forces of the bin's contacts, <F_nor> the mean over all contacts.
+ *   summary[12] (host): samples (steps), contacts per step, Z = 2 contacts / spheres,
+ *     <F_nor>, sigma_hat xx, xy, yx, yy (eq. 27 in 3D, eq. 26 per unit volume in a monolayer,
+ *     with the integral over the contacts themselves and the prefactor that makes it the
+ *     contact virial for equal spheres at distance 2a: 3 phi Z / (4 pi a^2), phi Z / (pi a lz);
+ *     compression counts positive), Delta lambda, P, Delta lambda / P of the mean total
+ *     stress over the same steps (3D: largest minus smallest eigenvalue and minus the mean
+ *     eigenvalue; monolayer: the x-y block), and phi (volume, or area, fraction).
+ * Synchronises.                                                                            */
+int susp_contact_stats(susp_sim *s, int32_t nbins, double *hist, double summary[12]);
 
 /* Release the simulation (and its device block unless it came from a workspace). */
 int susp_destroy(susp_sim *s);

@@ -157,6 +157,21 @@ static int resolve(const susp_params *p, Sim &s) {
   s.gamma_dot = p->gamma_dot; s.g0_I = p->g0_I; s.g0_F = p->g0_F; s.theta = p->theta;
   s.period = p->period; s.ncyc_I = p->ncyc_I; s.ncyc_F = p->ncyc_F;
   s.fp16_exp = p->fp16_exp;
+  if (p->contact_bins < 0 || p->contact_bins > 360) return fail(SUSP_EINVAL, "contact_bins must be in [0, 360]");
+  s.cbins = p->contact_bins;
+  s.cchunks = p->n > 0 ? (p->n + 255) / 256 : 1;
+  {
+    // eqs. 26-27: mean radius and the volume (monolayer: area) fraction of the spheres
+    double as = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int i = 0; i < p->n; ++i) {
+      const double a = p->radius[i];
+      as += a;
+      a2 += PI * a * a;
+      a3 += (4.0 / 3.0) * PI * a * a * a;
+    }
+    s.cgeo[0] = p->n > 0 ? as / p->n : 0.0;
+    s.cgeo[1] = p->quasi2d ? a2 / ((double)p->lx * p->ly) : a3 / ((double)p->lx * p->ly * p->lz);
+  }
   if (p->precision == 2 && (p->fp16_exp < -20 || p->fp16_exp > 20))
     return fail(SUSP_EINVAL, "fp16_exp out of [-20, 20]");
   s.h16.up = (float)ldexp(1.0, p->fp16_exp);  // deviation -> storage: d / w_q * 2^k
@@ -250,6 +265,13 @@ static size_t carve(Sim &s, char *base) {
   }
   s.hstart = (int32_t *)take(n * NCAP * 4);
   s.rev = (int32_t *)take(n * NCAP * 4);
+  if (s.cbins > 0) {
+    s.crec = (double *)take(n * NCAP * 4 * 8);
+    s.cflag = (int32_t *)take(n * NCAP * 4);
+    s.cpart = (double *)take((size_t)(s.cbins + 1) * s.cchunks * 6 * 8);
+    s.cacc = (double *)take((size_t)((s.cbins + 1) * 6 + 8) * 8);
+    s.cout = (double *)take((size_t)(5 * s.cbins + 12) * 8);
+  }
   s.pineq = (double *)take((size_t)s.lbm_blocks * 6 * 8);
   s.acc = (double *)take((size_t)(128 + 128 * 32) * 8);
   s.flags = (int32_t *)take(256);
@@ -359,6 +381,9 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       launch_fill_f64(s.pineq, (size_t)s.lbm_blocks * 6, 0.0, s.stream))
     return bail(fail(SUSP_EDEVICE, "fill"));
   if (launch_fill_i32(s.cell_start, (size_t)s.ncell + 1, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  if (s.cbins > 0 && (launch_fill_f64(s.cacc, (size_t)(s.cbins + 1) * 6 + 8, 0.0, s.stream) ||
+                      (n && launch_fill_i32(s.cflag, n * NCAP, 0, s.stream))))
+    return bail(fail(SUSP_EDEVICE, "fill"));
   rc = remap(s);
   if (rc) return bail(rc);
   int32_t fl = 0;
@@ -471,6 +496,7 @@ static int one_step(Sim &s) {
     HIPCHK(launch_map_update(&s, b, 2));
   }
   HIPCHK(launch_stress(&s));
+  HIPCHK(launch_contact_sample(&s));
   s.step += 1;
   return SUSP_OK;
 }
@@ -584,6 +610,18 @@ extern "C" int susp_stress(susp_sim *h, double out[5][6], double gg[2]) {
     gg[1] = 0.0;
   }
   HIPCHK(launch_fill_f64(s.acc + 30, 31, 0.0, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+extern "C" int susp_contact_stats(susp_sim *h, int32_t nbins, double *hist, double summary[12]) {
+  if (!h || !hist || !summary) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  if (s.cbins <= 0) return fail(SUSP_EINVAL, "contact statistics are off (contact_bins = 0)");
+  if (nbins != s.cbins) return fail(SUSP_EINVAL, "nbins %d differs from contact_bins %d", nbins, s.cbins);
+  HIPCHK(launch_contact_final(&s));
+  HIPCHK(hipMemcpyAsync(hist, s.cout, (size_t)5 * nbins * 8, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipMemcpyAsync(summary, s.cout + (size_t)5 * nbins, 12 * 8, hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
   return SUSP_OK;
 }

@@ -321,6 +321,7 @@ __device__ inline LubF lubf(double a, double b, double inv, double lg) {
 struct PairOut {
   double F[3], Tl[3], Th[3];
   double vc[6], vr[6], sl[6];  // contact virial, DLVO virial (x -1/2 sym), stresslet sum
+  double fnor, ft[3];          // contact: signed normal magnitude (+ apart), tangential force
   int on;
 };
 
@@ -336,8 +337,9 @@ __device__ inline void sym_add(double *o, const double *a, const double *b, doub
 __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[3],
                             const double *Ui, const double Uj[3], const double *Wi,
                             const double *Wj, double dt, double xi[3], int on_in, PairOut &o) {
-  for (int c = 0; c < 3; ++c) { o.F[c] = 0; o.Tl[c] = 0; o.Th[c] = 0; }
+  for (int c = 0; c < 3; ++c) { o.F[c] = 0; o.Tl[c] = 0; o.Th[c] = 0; o.ft[c] = 0; }
   for (int c = 0; c < 6; ++c) { o.vc[c] = 0; o.vr[c] = 0; o.sl[c] = 0; }
+  o.fnor = 0;
   (void)on_in;
   const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
   const double r = sqrt(r2);
@@ -378,6 +380,8 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
     for (int c = 0; c < 3; ++c) Fc[c] = Fn[c] + Ft[c];
     crs(-ai * n[0], -ai * n[1], -ai * n[2], Ft[0], Ft[1], Ft[2], o.Tl[0], o.Tl[1], o.Tl[2]);
     crs(-aj * n[0], -aj * n[1], -aj * n[2], Ft[0], Ft[1], Ft[2], o.Th[0], o.Th[1], o.Th[2]);
+    o.fnor = fnm;
+    for (int c = 0; c < 3; ++c) o.ft[c] = Ft[c];
     o.on = 1;
   } else {
     xi[0] = xi[1] = xi[2] = 0.0;
@@ -477,6 +481,8 @@ struct SubArgs {
   double *xout;
   int32_t *onout;
   double *pst;
+  double *crec;     // contact records of the last substep (null: statistics off)
+  int32_t *cflag;
   Phys P;
   Box b;             // static dimensions; offsets of this and the next step from clk
   const Clock *clk;
@@ -498,10 +504,31 @@ __device__ inline double gsum16(double v) {
   return v;
 }
 
+// Contact statistics (Sec. 4.2, eqs. 19-23): record of a pair in contact at the last substep,
+// kept in the lower id's entry: the in-plane unit direction n of d = R_lo - R_hi ((1, 0) if d
+// has no in-plane part), F_nor and F_tan, the component along t = (-n_y, n_x) of the
+// tangential force on the sphere at the tail of n (hi, which feels -ft): positive when it
+// turns that sphere counterclockwise; it is the same seen from lo.  Flag 1 marks a record.
+__device__ inline void record_contact(const SubArgs &A, size_t e, bool keep, const double d[3],
+                                      const PairOut &o) {
+  if (keep) {
+    const double rxy = sqrt(d[0] * d[0] + d[1] * d[1]);
+    double nx = 1.0, ny = 0.0;
+    if (rxy > 0.0) { nx = d[0] / rxy; ny = d[1] / rxy; }
+    A.crec[4 * e] = nx;
+    A.crec[4 * e + 1] = ny;
+    A.crec[4 * e + 2] = o.fnor;
+    A.crec[4 * e + 3] = -(o.ft[0] * (-ny) + o.ft[1] * nx);
+  }
+  A.cflag[e] = keep ? 1 : 0;
+}
+
 // One DEM substep; 16 lanes per sphere (four spheres per wave), the lanes striding over
 // the sphere's neighbours.  Both spheres of a pair evaluate the identical pair expression;
 // the lower id owns the spring history and the pair's stress.
-__global__ __launch_bounds__(256) void k_substep(SubArgs A) {
+// REC: the last substep of a step with contact statistics on (records each contact).
+template <bool REC>
+__global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   const Box bx = clock_box(A.b, A.clk, 0);
   const double s1 = A.clk->cur.s1, ule1 = A.clk->cur.ule1;
   const int lane = threadIdx.x & 63;
@@ -534,6 +561,7 @@ __global__ __launch_bounds__(256) void k_substep(SubArgs A) {
     } else {
       for (int c = 0; c < 3; ++c) { F[c] -= o.F[c]; T[c] += o.Th[c]; }
     }
+    if (REC) record_contact(A, own_e, i == lo && o.on, d, o);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) { F[c] = gsum16(F[c]); T[c] = gsum16(T[c]); }
@@ -595,6 +623,8 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   A.xin = s->hxi[hin]; A.onin = s->hon[hin];
   A.xout = s->hxi[1 - hin]; A.onout = s->hon[1 - hin];
   A.pst = s->pst;
+  A.crec = s->cbins > 0 ? s->crec : nullptr;
+  A.cflag = s->cflag;
   A.P.kn = s->kn; A.P.kt = s->kt; A.P.eta_n = s->eta_n; A.P.mu = s->mu;
   A.P.delta = s->lub_delta; A.P.hc = s->lub_hc; A.P.F0 = s->F0; A.P.lambda = s->lambda;
   A.P.eta0 = s->eta0; A.P.cutoff = s->pair_cutoff; A.P.lub_sub = s->lub_sub;
@@ -603,8 +633,12 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   A.clk = s->clk;
   A.n = s->n; A.sub = sub; A.last = sub == s->n_sub - 1; A.quasi2d = s->quasi2d;
   A.flags = s->flags;
-  if (s->n > 0)
-    hipLaunchKernelGGL(k_substep, dim3((s->n + 15) / 16), dim3(256), 0, s->stream, A);
+  if (s->n > 0) {
+    if (A.crec && A.last)
+      hipLaunchKernelGGL(k_substep<true>, dim3((s->n + 15) / 16), dim3(256), 0, s->stream, A);
+    else
+      hipLaunchKernelGGL(k_substep<false>, dim3((s->n + 15) / 16), dim3(256), 0, s->stream, A);
+  }
   return hipGetLastError();
 }
 
@@ -995,6 +1029,190 @@ hipError_t launch_stress(Sim *s) {
   const double cf = -(1.0 - 0.5 / s->tau) / V;
   hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, 1.0 / V,
                      1.0 / (double)s->n_sub, s->clk, s->n > 0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Contact statistics.  Per step: k_cstat_part sums the recorded contacts of 256 spheres per
+// work-group, for one orientation bin (count, sum F_nor, sum F_tan) or, in the last bin
+// index, over all contacts (count, sum F_nor, and the four in-plane components of
+// [F_nor n - F_tan t] (x) n, the integrand of eqs. 26-27); k_cstat_acc adds the chunks in
+// order to the running sums together with the step's total stress.  Fixed orders
+// throughout, so the statistics are bitwise reproducible.
+struct CstatArgs {
+  const int32_t *cnt, *cflag;
+  const double *rec;
+  double *part;
+  int n, nb, chunks;
+};
+
+// Orientation bin of the in-plane direction (nx, ny): the angle folded into [0, pi) (both
+// senses are one orientation), in FP64, nb equal bins.
+__device__ inline int orient_bin(double nx, double ny, int nb) {
+  const double PI = 3.14159265358979323846;
+  double ox = nx, oy = ny;
+  if (oy < 0.0 || (oy == 0.0 && ox < 0.0)) { ox = -ox; oy = -oy; }
+  const double th = atan2(oy, ox);
+  const int bin = (int)(th * (double)nb / PI);
+  return bin < 0 ? 0 : (bin > nb - 1 ? nb - 1 : bin);
+}
+
+__global__ __launch_bounds__(256) void k_cstat_part(CstatArgs A) {
+  __shared__ double red[6][256];
+  const int b = blockIdx.x / A.chunks, k = blockIdx.x % A.chunks;
+  const int t = threadIdx.x, i = k * 256 + t;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  if (i < A.n) {
+    const int c = A.cnt[i];
+    for (int u = 0; u < c; ++u) {
+      const size_t e = (size_t)i * NCAP + u;
+      if (A.cflag[e] == 0) continue;
+      const double nx = A.rec[4 * e], ny = A.rec[4 * e + 1];
+      if (b < A.nb && orient_bin(nx, ny, A.nb) != b) continue;
+      const double fn = A.rec[4 * e + 2], ft = A.rec[4 * e + 3];
+      v[0] += 1.0;
+      v[1] += fn;
+      if (b < A.nb) {
+        v[2] += ft;
+      } else {
+        const double vx = fn * nx - ft * (-ny), vy = fn * ny - ft * nx;
+        v[2] += vx * nx; v[3] += vx * ny; v[4] += vy * nx; v[5] += vy * ny;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) red[c][t] = v[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t < 6) A.part[(size_t)blockIdx.x * 6 + t] = red[t][0];
+}
+
+// one wave per bin (and the totals): lane l adds chunks l, l + 64, ... in order, then a fixed
+// butterfly over the lanes; acc[0..29] holds this step's stress parts
+__global__ __launch_bounds__(64) void k_cstat_acc(const double *part, double *cacc, const double *acc, int nb,
+                                                  int chunks) {
+  const int b = blockIdx.x, l = threadIdx.x;
+  for (int c = 0; c < 6; ++c) {
+    double x = 0.0;
+    for (int k = l; k < chunks; k += 64) x += part[((size_t)b * chunks + k) * 6 + c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (l == 0) cacc[b * 6 + c] += x;
+  }
+  if (b == nb && l == 0) {
+    double *sg = cacc + (nb + 1) * 6;
+    for (int c = 0; c < 6; ++c) sg[c] += acc[c] + acc[6 + c] + acc[12 + c] + acc[18 + c] + acc[24 + c];
+    sg[6] += 1.0;
+  }
+}
+
+hipError_t launch_contact_sample(Sim *s) {
+  if (s->cbins <= 0) return hipSuccess;
+  if (s->n > 0) {
+    CstatArgs A;
+    A.cnt = s->ncnt[s->lcur]; A.cflag = s->cflag; A.rec = s->crec; A.part = s->cpart;
+    A.n = s->n; A.nb = s->cbins; A.chunks = s->cchunks;
+    hipLaunchKernelGGL(k_cstat_part, dim3((s->cbins + 1) * s->cchunks), dim3(256), 0, s->stream, A);
+  } else {
+    hipError_t e = launch_fill_f64(s->cpart, (size_t)(s->cbins + 1) * s->cchunks * 6, 0.0, s->stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_cstat_acc, dim3(s->cbins + 1), dim3(64), 0, s->stream, s->cpart, s->cacc, s->acc,
+                     s->cbins, s->cchunks);
+  return hipGetLastError();
+}
+
+// Eigenvalues of a symmetric 3x3 matrix (xx yy zz xy xz yz), descending: the trigonometric
+// solution of the characteristic cubic (Smith, Commun. ACM 4, 168 (1961)).
+__device__ inline void sym3_eig(const double m[6], double ev[3]) {
+  const double PI = 3.14159265358979323846;
+  const double p1 = m[3] * m[3] + m[4] * m[4] + m[5] * m[5];
+  const double q = (m[0] + m[1] + m[2]) / 3.0;
+  if (p1 == 0.0) {
+    ev[0] = m[0]; ev[1] = m[1]; ev[2] = m[2];
+  } else {
+    const double a = m[0] - q, b = m[1] - q, c = m[2] - q;
+    const double p = sqrt((a * a + b * b + c * c + 2.0 * p1) / 6.0);
+    const double ip = 1.0 / p;
+    const double B0 = a * ip, B1 = b * ip, B2 = c * ip, B3 = m[3] * ip, B4 = m[4] * ip, B5 = m[5] * ip;
+    // det(B) / 2 with B = (A - q I) / p
+    double r = 0.5 * (B0 * (B1 * B2 - B5 * B5) - B3 * (B3 * B2 - B5 * B4) + B4 * (B3 * B5 - B1 * B4));
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    const double phi = acos(r) / 3.0;
+    ev[0] = q + 2.0 * p * cos(phi);
+    ev[2] = q + 2.0 * p * cos(phi + 2.0 * PI / 3.0);
+    ev[1] = 3.0 * q - ev[0] - ev[2];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int k = i + 1; k < 3; ++k)
+      if (ev[k] > ev[i]) { const double x = ev[i]; ev[i] = ev[k]; ev[k] = x; }
+}
+
+// Read-out: the distributions of eqs. 19-23 per bin, <F_nor>, Z, the stress of eq. 27 (3D) or
+// eq. 26 (monolayer, per unit volume), Delta lambda / P of the mean total stress; then the
+// running sums are cleared.  One work-group of 256 threads.
+__global__ __launch_bounds__(256) void k_cstat_final(double *cacc, double *out, int nb, int n, double amean,
+                                                     double frac, int quasi2d, double lz) {
+  const double PI = 3.14159265358979323846;
+  const double *tot = cacc + nb * 6;
+  const double *sg = cacc + (nb + 1) * 6;
+  const double nc = tot[0];
+  const double fmean = nc > 0.0 ? tot[1] / nc : 0.0;
+  const double dth = PI / (double)nb;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double c = cacc[b * 6];
+    const double rho = nc > 0.0 ? c / (nc * dth) : 0.0;
+    const double fnor = c > 0.0 ? cacc[b * 6 + 1] / c : 0.0;
+    const double ftan = c > 0.0 ? cacc[b * 6 + 2] / c : 0.0;
+    const double xn = fmean != 0.0 ? fnor / fmean : 0.0;
+    const double xt = fmean != 0.0 ? ftan / fmean : 0.0;
+    out[b] = rho;
+    out[nb + b] = xn;
+    out[2 * nb + b] = xt;
+    out[3 * nb + b] = rho * xn;
+    out[4 * nb + b] = rho * xt;
+  }
+  if (threadIdx.x == 0) {
+    double *sm = out + 5 * nb;
+    const double samples = sg[6];
+    const double Z = (n > 0 && samples > 0.0) ? 2.0 * nc / ((double)n * samples) : 0.0;
+    double C = 0.0;
+    if (amean > 0.0)
+      C = quasi2d ? frac * Z / (PI * amean) / lz : 3.0 * frac * Z / (4.0 * PI * amean * amean);
+    double M[6];
+    for (int c = 0; c < 6; ++c) M[c] = samples > 0.0 ? sg[c] / samples : 0.0;
+    double dl, pr;
+    if (quasi2d) {
+      const double mid = 0.5 * (M[0] + M[1]);
+      dl = 2.0 * sqrt(0.25 * (M[0] - M[1]) * (M[0] - M[1]) + M[3] * M[3]);
+      pr = -mid;
+    } else {
+      double ev[3];
+      sym3_eig(M, ev);
+      dl = ev[0] - ev[2];
+      pr = -(ev[0] + ev[1] + ev[2]) / 3.0;
+    }
+    sm[0] = samples;
+    sm[1] = samples > 0.0 ? nc / samples : 0.0;
+    sm[2] = Z;
+    sm[3] = fmean;
+    for (int k = 0; k < 4; ++k) sm[4 + k] = nc > 0.0 ? C * (tot[2 + k] / nc) : 0.0;
+    sm[8] = dl;
+    sm[9] = pr;
+    sm[10] = pr != 0.0 ? dl / pr : 0.0;
+    sm[11] = frac;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < (nb + 1) * 6 + 8; k += blockDim.x) cacc[k] = 0.0;
+}
+
+hipError_t launch_contact_final(Sim *s) {
+  hipLaunchKernelGGL(k_cstat_final, dim3(1), dim3(256), 0, s->stream, s->cacc, s->cout, s->cbins, s->n,
+                     s->cgeo[0], s->cgeo[1], s->quasi2d, (double)s->lz);
   return hipGetLastError();
 }
 

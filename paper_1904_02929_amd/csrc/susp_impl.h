@@ -150,6 +150,8 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub);
 hipError_t launch_map_full(Sim *s, const Box &b);
 hipError_t launch_map_update(Sim *s, const Box &b, int phase);
 hipError_t launch_stress(Sim *s);
+hipError_t launch_contact_sample(Sim *s);
+hipError_t launch_contact_final(Sim *s);
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_clock(Sim *s, int reset);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
@@ -213,6 +215,16 @@ struct Sim {
   int32_t *hstart;           // contact at the start of the step per entry
   int32_t *rev;              // per entry: entry (of the lower id) holding the pair's history
   int hfin;                  // history buffer holding the final state of the last step
+  // contact statistics (cbins > 0): records of the last substep's contacts, per-step
+  // partial sums and the running sums since the last read-out
+  int cbins;
+  int cchunks;               // sphere chunks of 256 per bin in the partial sums
+  double cgeo[2];            // mean radius, volume (monolayer: area) fraction
+  double *crec;              // [n][NCAP][4] n_x, n_y, F_nor, F_tan of the entry's contact
+  int32_t *cflag;            // [n][NCAP] 1 if the entry holds a contact record, else 0
+  double *cpart;             // [(cbins + 1) * cchunks][6]
+  double *cacc;              // [cbins + 1][6] sums, then the total stress sum [6], samples
+  double *cout;              // [5 * cbins + 12] read-out staging
   // reductions
   double *pineq;  // [lbm_blocks][6]
   double *acc;    // sig_last[30] sig_sum[30] count gp_cos gp_sin gp_count ledger

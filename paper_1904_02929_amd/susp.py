@@ -35,7 +35,7 @@ class Params(C.Structure):
         ("shear_kind", C.c_int32), ("gamma_dot", C.c_double), ("g0_I", C.c_double),
         ("g0_F", C.c_double), ("period", C.c_int32), ("theta", C.c_double),
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32), ("fp16_exp", C.c_int32),
-        ("brick_y", C.c_int32), ("brick_z", C.c_int32),
+        ("brick_y", C.c_int32), ("brick_z", C.c_int32), ("contact_bins", C.c_int32),
     ]
 
 
@@ -62,6 +62,7 @@ def lib():
         L.susp_create.argtypes = [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]
         L.susp_step.argtypes = [vp, C.c_int64]
         L.susp_stress.argtypes = [vp, _PD, _PD]
+        L.susp_contact_stats.argtypes = [vp, C.c_int32, _PD, _PD]
         L.susp_destroy.argtypes = [vp]
         L.susp_get_populations.argtypes = [vp, _PD]
         L.susp_set_populations.argtypes = [vp, _PD]
@@ -205,6 +206,13 @@ class Simulation:
         out = np.zeros((5, 6)); gg = np.zeros(2)
         _chk(lib().susp_stress(self.h, _pd(out), _pd(gg)))
         return out, gg
+
+    def contact_stats(self, nbins):
+        """(hist[5][nbins] = rho, xi_N, xi_T, zeta_N, zeta_T; summary[12]) since the last
+        call, then reset (susp_contact_stats)."""
+        hist = np.zeros((5, nbins)); summ = np.zeros(12)
+        _chk(lib().susp_contact_stats(self.h, int(nbins), _pd(hist), _pd(summ)))
+        return hist, summ
 
     # ---- state ----------------------------------------------------------------------
     def get_populations(self):
