@@ -44,7 +44,8 @@ class Params(C.Structure):
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32),
         ("wall_y", C.c_int32), ("wall_u_bot", C.c_double), ("wall_u_top", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
-        ("contact_bins", C.c_int32),
+        ("contact_bins", C.c_int32), ("collision", C.c_int32), ("tau_bulk", C.c_double),
+        ("tau_ghost", C.c_double),
     ]
 
 
@@ -124,7 +125,7 @@ DEFAULTS = dict(
     lub_delta=-1.0, lub_hc=0.5, lub_subtract_hc=1, F0=-1.0, debye_lambda=-1.0, pair_cutoff=1.0,
     n_sub=8, quasi2d=0, shear_kind=0, gamma_dot=0.0, g0_I=0.0, g0_F=0.0, period=1, theta=0.0,
     ncyc_I=0, ncyc_F=0, wall_y=0, wall_u_bot=0.0, wall_u_top=0.0, gx=0.0, gy=0.0, gz=0.0,
-    contact_bins=0,
+    contact_bins=0, collision=0, tau_bulk=1.0, tau_ghost=1.0,
 )
 
 

@@ -10,7 +10,9 @@
  *   total stress                     eq. (15)
  *   oscillatory strain, G', G''      eqs. (16)-(18)
  *   contact statistics               eqs. (19)-(23), (26)-(27), App. C; Delta lambda / P
- *   LB update, moments, collision    App. A eqs. (3)-(5) (collision taken as single-time BGK)
+ *   LB update, moments, collision    App. A eqs. (3)-(5): single-time BGK, or the linearised
+ *                                    operator of eq. (5) with separate eigenvalues for the
+ *                                    shear stress, its trace and the ghost modes
  *   moving bounce-back, link force   App. A eqs. (6)-(8); force and torque sums eqs. (9)-(10)
  *   mapped radius, lubrication       App. A (mapped radius 0.95 a; grand-resistance matrix
  *                                    with the leading-order scalar functions)
@@ -635,19 +637,57 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
               a[21] += lev[0] * rl[1] - lev[1] * rl[0];
             }
           }
-          /* eq. (4) moments, BGK collision (eq. (5) with a single eigenvalue -1/tau) */
+          /* eq. (4) moments */
           double rho = 0, jx = 0, jy = 0, jz = 0;
           for (int q = 0; q < 19; ++q) {
             rho += n[q]; jx += n[q] * CX[q]; jy += n[q] * CY[q]; jz += n[q] * CZ[q];
           }
           double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-          double fe[19];
+          double fe[19], ne[19];
           orc_feq(rho, ux, uy, uz, fe);
+          for (int q = 0; q < 19; ++q) ne[q] = n[q] - fe[q];
+          double Pn[3][3] = {{0}};  /* non-equilibrium momentum flux Pi^neq */
           for (int q = 0; q < 19; ++q) {
-            double ne = n[q] - fe[q];
-            pa[0] += ne * CX[q] * CX[q]; pa[1] += ne * CY[q] * CY[q]; pa[2] += ne * CZ[q] * CZ[q];
-            pa[3] += ne * CX[q] * CY[q]; pa[4] += ne * CX[q] * CZ[q]; pa[5] += ne * CY[q] * CZ[q];
-            double v = n[q] - ne / tau;
+            const int c[3] = {CX[q], CY[q], CZ[q]};
+            for (int a = 0; a < 3; ++a)
+              for (int b = 0; b < 3; ++b) Pn[a][b] += ne[q] * c[a] * c[b];
+          }
+          pa[0] += Pn[0][0]; pa[1] += Pn[1][1]; pa[2] += Pn[2][2];
+          pa[3] += Pn[0][1]; pa[4] += Pn[0][2]; pa[5] += Pn[1][2];
+          /* eq. (5).  BGK: n* = n^eq + (1 - 1/tau) n^neq.  Linearised multi-eigenvalue form
+           * (Ladd): with Q(M)_q = w_q (M : (c_q c_q - cs^2 I)) / (2 cs^4) the stress part of
+           * a non-equilibrium distribution, the traceless part of Pi^neq is multiplied by
+           * 1 + lambda, its trace by 1 + lambda_v, and the remainder n^neq - Q(Pi^neq) (the
+           * ghost modes) by 1 + lambda_g; mass and momentum are unchanged.               */
+          double post[19];
+          if (P->collision == 1) {
+            const double lam = -1.0 / tau, lamv = -1.0 / P->tau_bulk, lamg = -1.0 / P->tau_ghost;
+            const double cs2 = 1.0 / 3.0;
+            double tr = Pn[0][0] + Pn[1][1] + Pn[2][2];
+            double Ps[3][3];
+            for (int a = 0; a < 3; ++a)
+              for (int b = 0; b < 3; ++b) {
+                double dl = a == b ? 1.0 : 0.0;
+                Ps[a][b] = (1.0 + lam) * (Pn[a][b] - dl * tr / 3.0) + (1.0 + lamv) * dl * tr / 3.0;
+              }
+            for (int q = 0; q < 19; ++q) {
+              const int c[3] = {CX[q], CY[q], CZ[q]};
+              double qs = 0.0, qn = 0.0;
+              for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                  double h = c[a] * c[b] - (a == b ? cs2 : 0.0);
+                  qs += Ps[a][b] * h;
+                  qn += Pn[a][b] * h;
+                }
+              qs *= WQ(q) / (2.0 * cs2 * cs2);
+              qn *= WQ(q) / (2.0 * cs2 * cs2);
+              post[q] = fe[q] + qs + (1.0 + lamg) * (ne[q] - qn);
+            }
+          } else {
+            for (int q = 0; q < 19; ++q) post[q] = n[q] - ne[q] / tau;
+          }
+          for (int q = 0; q < 19; ++q) {
+            double v = post[q];
             if (P->gx != 0.0 || P->gy != 0.0 || P->gz != 0.0)
               v += 3.0 * WQ(q) * (CX[q] * P->gx + CY[q] * P->gy + CZ[q] * P->gz);
             S->fn[q * nodes + X] = v;
@@ -955,8 +995,15 @@ static void one_step(orc_sim *S) {
 
   /* stress of this step, eq. (15) with the fluid, particle and lubrication parts */
   double sig[5][6];
+  /* fluid stress: the mean of the non-equilibrium momentum flux before and after collision,
+   * -(1 + lambda/2) for the traceless part and -(1 + lambda_v/2) for the trace */
   double cf = -(1.0 - 0.5 / P->tau) / V;
   for (int c = 0; c < 6; ++c) sig[0][c] = cf * pineq[c];
+  if (P->collision == 1) {
+    double cb = -(1.0 - 0.5 / P->tau_bulk) / V;
+    double t3 = (pineq[0] + pineq[1] + pineq[2]) / 3.0;
+    for (int c = 0; c < 3; ++c) sig[0][c] = cf * (pineq[c] - t3) + cb * t3;
+  }
   double sh[6] = {0, 0, 0, 0, 0, 0};
   for (int p = 0; p < np; ++p) {
     const double *m = &S->Sh[9 * p];

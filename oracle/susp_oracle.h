@@ -46,6 +46,11 @@ typedef struct {
   double gx, gy, gz;           /* uniform body force per node                         */
   int32_t contact_bins;        /* > 0: contact statistics (Sec. 4.2) in this many angular
                                   bins over [0, pi), sampled once per step              */
+  int32_t collision;           /* 0: BGK (one eigenvalue -1/tau); 1: linearised operator
+                                  with separate eigenvalues -1/tau (shear stress),
+                                  -1/tau_bulk (trace of the stress), -1/tau_ghost (the
+                                  nine non-hydrodynamic modes)                          */
+  double tau_bulk, tau_ghost;
 } orc_params;
 
 /* Fully resolved constants after defaults are applied. */

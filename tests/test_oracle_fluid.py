@@ -44,8 +44,8 @@ def test_equilibrium_moments(orc):
         assert np.allclose(np.diag(Pi), np.diag(ref), atol=5 * np.abs(u).max() ** 3)
 
 
-def _shear_wave_nu(orc, L, tau, T):
-    p = orc.make_params(lx=2, ly=L, lz=2, tau=tau)
+def _shear_wave_nu(orc, L, tau, T, **kw):
+    p = orc.make_params(lx=2, ly=L, lz=2, tau=tau, **kw)
     o = orc.Oracle(p)
     f = o.f
     U0 = 1e-5
