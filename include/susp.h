@@ -3,7 +3,8 @@
  * non-Brownian suspensions (Pradipto & Hayakawa, arXiv:1904.02929).
  *
  * One call of susp_step advances the coupled system by whole lattice-Boltzmann steps:
- *   - D3Q19 collide-and-stream (App. A, eqs. 3-5; collision taken as single-time BGK)
+ *   - D3Q19 collide-and-stream (App. A, eqs. 3-5; collision single-time BGK, or the
+ *     linearised operator with separate shear, bulk and ghost eigenvalues)
  *     with a Lees-Edwards sliding boundary in y (interpolated, Galilean-corrected ghost
  *     rows; periodic in x and z),
  *   - moving-sphere bounce-back on links cut by the mapped spheres (App. A, eqs. 7-8),
@@ -96,10 +97,16 @@ typedef struct {
                                 0 = chosen from the lattice size (brick_y a multiple of 4) */
   int32_t contact_bins;      /* 0: off; 1..360: contact statistics (susp_contact_stats)
                                 sampled every step in this many orientation bins          */
+  int32_t collision;         /* eq. (5): 0 single-time BGK (eigenvalue -1/tau); 1 the
+                                linearised operator with eigenvalue -1/tau for the traceless
+                                stress, -1/tau_bulk for its trace and -1/tau_ghost for the
+                                nine non-hydrodynamic modes (mass and momentum conserved) */
+  double tau_bulk, tau_ghost;  /* > 1/2 each (collision 1)                               */
 } susp_params;
 
 /* Fill *p with the paper's defaults (tau 1, rho0 1, map_ratio 0.95, rho_p 1, kt 0.5 kn,
- * mu 1, lub_hc 0.5 with subtraction, pair_cutoff 1, n_sub 8, FP32, no shear).           */
+ * mu 1, lub_hc 0.5 with subtraction, pair_cutoff 1, n_sub 8, FP32, no shear, BGK with
+ * tau_bulk = tau_ghost = 1).                                                             */
 void susp_default_params(susp_params *p);
 
 /* Exact device bytes a simulation of these parameters needs (workspace size).  Returns 0

@@ -46,6 +46,8 @@ extern "C" void susp_default_params(susp_params *p) {
   p->rho0 = 1.0;
   p->map_ratio = 0.95;
   p->rho_p = 1.0;
+  p->tau_bulk = 1.0;
+  p->tau_ghost = 1.0;
   p->kn = -1.0;
   p->kt_ratio = 0.5;
   p->mu = 1.0;
@@ -158,6 +160,12 @@ static int resolve(const susp_params *p, Sim &s) {
   s.period = p->period; s.ncyc_I = p->ncyc_I; s.ncyc_F = p->ncyc_F;
   s.fp16_exp = p->fp16_exp;
   if (p->contact_bins < 0 || p->contact_bins > 360) return fail(SUSP_EINVAL, "contact_bins must be in [0, 360]");
+  if (p->collision < 0 || p->collision > 1) return fail(SUSP_EINVAL, "collision must be 0 or 1");
+  if (p->collision == 1 && !(p->tau_bulk > 0.5 && p->tau_ghost > 0.5))
+    return fail(SUSP_EINVAL, "tau_bulk and tau_ghost must exceed 1/2");
+  s.collision = p->collision;
+  s.tau_bulk = p->collision ? p->tau_bulk : p->tau;
+  s.tau_ghost = p->collision ? p->tau_ghost : p->tau;
   s.cbins = p->contact_bins;
   s.cchunks = p->n > 0 ? (p->n + 255) / 256 : 1;
   {

@@ -82,6 +82,7 @@ struct LbmArgs {
   Box b;              // static dimensions; offset and velocity come from clk
   const Clock *clk;
   double rho0, omega;
+  double om_ghost, om_bulk;  // multi-eigenvalue collision: -lambda_g, -lambda_v
   double kax, kdg;  // -6 w_q rho0 of the axis and of the diagonal directions
   H16 h16;
 };
@@ -406,7 +407,9 @@ __device__ inline bool same_image(const Box &b, double Dx, double Dy, double Dz,
 // node (link directions load the node's own opposite population instead of the pull), and
 // this node's stores.  The spheres' states come from LDS.  A node therefore waits only for
 // loads issued one step earlier.
-template <class ST>
+// COLL 0: BGK; 1: the linearised operator with separate eigenvalues for the traceless
+// stress (-1/tau), its trace (-1/tau_bulk) and the ghost modes (-1/tau_ghost).
+template <class ST, int COLL>
 __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   using CT = typename Store<ST>::CT;
   __shared__ int32_t smap[NRING][SPLANE];
@@ -659,18 +662,66 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
       const CT a1 = w1 * a, a2 = w2 * a;
       const CT b1 = (CT)4.5 * w1 * rho, b2 = (CT)4.5 * w2 * rho;
       const CT c1 = (CT)3 * w1 * rho, c2 = (CT)3 * w2 * rho;
-      n[0] = fmaT(-om, n[0] - w0 * a, n[0]);
       CT ps[9];
+      if constexpr (COLL == 0) {
+        n[0] = fmaT(-om, n[0] - w0 * a, n[0]);
 #pragma unroll
-      for (int pi = 0; pi < 9; ++pi) {
-        const int q = 2 * pi + 1, b = q + 1;
-        const CT cu = cdot<CT>(q, ux, uy, uz);
-        const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
-        const CT anti = (q <= 6 ? c1 : c2) * cu;
-        const CT neq = n[q] - (sym + anti), neb = n[b] - (sym - anti);
-        ps[pi] = neq + neb;
-        n[q] = fmaT(-om, neq, n[q]);
-        n[b] = fmaT(-om, neb, n[b]);
+        for (int pi = 0; pi < 9; ++pi) {
+          const int q = 2 * pi + 1, b = q + 1;
+          const CT cu = cdot<CT>(q, ux, uy, uz);
+          const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+          const CT anti = (q <= 6 ? c1 : c2) * cu;
+          const CT neq = n[q] - (sym + anti), neb = n[b] - (sym - anti);
+          ps[pi] = neq + neb;
+          n[q] = fmaT(-om, neq, n[q]);
+          n[b] = fmaT(-om, neb, n[b]);
+        }
+      } else {
+        // n* = n^eq + (1 - om_g) n^neq + Q_q, Q_q = 4.5 w_q [g1 (Pi:c c - t/3) + g2 t (|c|^2 - 1)/3]
+        // with Pi = Pi^neq, t its trace, g1 = om_g - om, g2 = om - om_v: the traceless
+        // stress relaxes with om, its trace with om_v, every other mode with om_g
+        const CT omg = (CT)A.om_ghost, g1 = omg - om, g2 = om - (CT)A.om_bulk;
+        const CT ne0 = n[0] - w0 * a;
+#pragma unroll
+        for (int pi = 0; pi < 9; ++pi) {  // n^neq into n, pair sums for the flux
+          const int q = 2 * pi + 1, b = q + 1;
+          const CT cu = cdot<CT>(q, ux, uy, uz);
+          const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+          const CT anti = (q <= 6 ? c1 : c2) * cu;
+          n[q] = n[q] - (sym + anti);
+          n[b] = n[b] - (sym - anti);
+          ps[pi] = n[q] + n[b];
+        }
+        CT P[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+        for (int pi = 0; pi < 9; ++pi) {
+          const int q = 2 * pi + 1;
+          if (cx(q) != 0) P[0] += ps[pi];
+          if (cy(q) != 0) P[1] += ps[pi];
+          if (cz(q) != 0) P[2] += ps[pi];
+          addc(P[3], cx(q) * cy(q), ps[pi]);
+          addc(P[4], cx(q) * cz(q), ps[pi]);
+          addc(P[5], cy(q) * cz(q), ps[pi]);
+        }
+        const CT t3 = (P[0] + P[1] + P[2]) * (CT)(1.0 / 3.0);
+        const CT P2xy = (CT)2 * P[3], P2xz = (CT)2 * P[4], P2yz = (CT)2 * P[5];
+        const CT keep = (CT)1 - omg;
+        n[0] = w0 * a + keep * ne0 - (CT)1.5 * w0 * 3 * (g1 + g2) * t3;
+#pragma unroll
+        for (int pi = 0; pi < 9; ++pi) {
+          const int q = 2 * pi + 1, b = q + 1;
+          const CT cu = cdot<CT>(q, ux, uy, uz);
+          const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+          const CT anti = (q <= 6 ? c1 : c2) * cu;
+          CT pcc = (cx(q) != 0 ? P[0] : (CT)0) + (cy(q) != 0 ? P[1] : (CT)0) + (cz(q) != 0 ? P[2] : (CT)0);
+          addc(pcc, cx(q) * cy(q), P2xy);  // Pi : c c = sum_a Pi_aa c_a^2 + 2 sum_a<b Pi_ab c_a c_b
+          addc(pcc, cx(q) * cz(q), P2xz);
+          addc(pcc, cy(q) * cz(q), P2yz);
+          const int c2q = cx(q) * cx(q) + cy(q) * cy(q) + cz(q) * cz(q);
+          const CT Q = (CT)4.5 * (q <= 6 ? w1 : w2) * (g1 * (pcc - t3) + g2 * t3 * (CT)(c2q - 1));
+          n[q] = (sym + anti) + fmaT(keep, n[q], Q);
+          n[b] = (sym - anti) + fmaT(keep, n[b], Q);
+        }
       }
       // non-equilibrium momentum flux Pi^neq = sum_q (n_q - feq_q) c_q c_q (pairs add)
       CT s[6] = {0, 0, 0, 0, 0, 0};
@@ -775,6 +826,8 @@ static LbmArgs lbm_args(Sim *s, const Box &b) {
   A.clk = s->clk;
   A.rho0 = s->rho0;
   A.omega = 1.0 / s->tau;
+  A.om_ghost = 1.0 / s->tau_ghost;
+  A.om_bulk = 1.0 / s->tau_bulk;
   A.kax = -6.0 * wq(1) * s->rho0;
   A.kdg = -6.0 * wq(7) * s->rho0;
   A.h16 = s->h16;
@@ -784,9 +837,15 @@ static LbmArgs lbm_args(Sim *s, const Box &b) {
 hipError_t launch_lbm(Sim *s, const Box &b) {
   const LbmArgs A = lbm_args(s, b);
   dim3 grid(A.per_xcd * 8), blk(256);
-  if (s->precision == 0) hipLaunchKernelGGL(k_lbm<double>, grid, blk, 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_lbm<float>, grid, blk, 0, s->stream, A);
-  else hipLaunchKernelGGL(k_lbm<__half>, grid, blk, 0, s->stream, A);
+  if (s->collision == 0) {
+    if (s->precision == 0) hipLaunchKernelGGL((k_lbm<double, 0>), grid, blk, 0, s->stream, A);
+    else if (s->precision == 1) hipLaunchKernelGGL((k_lbm<float, 0>), grid, blk, 0, s->stream, A);
+    else hipLaunchKernelGGL((k_lbm<__half, 0>), grid, blk, 0, s->stream, A);
+  } else {
+    if (s->precision == 0) hipLaunchKernelGGL((k_lbm<double, 1>), grid, blk, 0, s->stream, A);
+    else if (s->precision == 1) hipLaunchKernelGGL((k_lbm<float, 1>), grid, blk, 0, s->stream, A);
+    else hipLaunchKernelGGL((k_lbm<__half, 1>), grid, blk, 0, s->stream, A);
+  }
   return hipGetLastError();
 }
 

@@ -993,8 +993,10 @@ __global__ __launch_bounds__(256) void k_reduce1(const double *pineq, int nblk, 
 
 // acc layout: [0,30) sig_last, [30,60) sig_sum, 60 count, 61 gp_cos, 62 gp_sin, 63 gp_count,
 // 64 ledger
-__global__ void k_reduce2(const double *part, double *acc, double cf, double invV, double invns,
-                          const Clock *clk, int has_particles) {
+// cf: fluid stress factor -(1 - 1/(2 tau)) / V; cfb the same with tau_bulk for the trace
+// (multi-eigenvalue collision, split = 1)
+__global__ void k_reduce2(const double *part, double *acc, double cf, double cfb, int split, double invV,
+                          double invns, const Clock *clk, int has_particles) {
   __shared__ double v[32];
   const int c = threadIdx.x;
   if (c < 31) {
@@ -1005,8 +1007,9 @@ __global__ void k_reduce2(const double *part, double *acc, double cf, double inv
   __syncthreads();
   if (c != 0) return;
   double sig[30];
+  const double t3 = (v[0] + v[1] + v[2]) / 3.0;
   for (int k = 0; k < 6; ++k) {
-    sig[k] = cf * v[k];
+    sig[k] = (split && k < 3) ? cf * (v[k] - t3) + cfb * t3 : cf * v[k];
     sig[6 + k] = has_particles ? v[6 + k] * invV : 0.0;
     sig[12 + k] = v[12 + k] * invV * invns;  // lubrication
     sig[18 + k] = v[18 + k] * invV * invns;  // contact
@@ -1027,7 +1030,8 @@ hipError_t launch_stress(Sim *s) {
                      s->lbm_blocks, s->hyd[s->hcur], s->pst, s->dp, s->n, part);
   const double V = (double)s->lx * s->ly * s->lz;
   const double cf = -(1.0 - 0.5 / s->tau) / V;
-  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, 1.0 / V,
+  const double cfb = -(1.0 - 0.5 / s->tau_bulk) / V;
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, cfb, s->collision, 1.0 / V,
                      1.0 / (double)s->n_sub, s->clk, s->n > 0 ? 1 : 0);
   return hipGetLastError();
 }

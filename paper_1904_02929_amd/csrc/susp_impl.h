@@ -171,6 +171,8 @@ struct Sim {
   double gamma_dot, g0_I, g0_F, theta;
   int period, ncyc_I, ncyc_F;
   int fp16_exp;
+  int collision;           // 0 BGK, 1 multi-eigenvalue (tau shear, tau_bulk, tau_ghost)
+  double tau_bulk, tau_ghost;
   H16 h16;                 // FP16 storage scale 2^k and its inverse
   Cells cells;
   int ncell;

@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("g0_F", C.c_double), ("period", C.c_int32), ("theta", C.c_double),
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32), ("fp16_exp", C.c_int32),
         ("brick_y", C.c_int32), ("brick_z", C.c_int32), ("contact_bins", C.c_int32),
+        ("collision", C.c_int32), ("tau_bulk", C.c_double), ("tau_ghost", C.c_double),
     ]
 
 

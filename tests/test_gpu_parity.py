@@ -176,6 +176,28 @@ def test_full_size_one_step_fp32():
     _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params), 1, presteps=0)
 
 
+# eq. (5) as the linearised operator with three distinct eigenvalues (shear, bulk, ghost)
+MULTI = dict(collision=1, tau=0.8, tau_bulk=0.65, tau_ghost=1.25)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_multi_eigenvalue_dense_one_step(precision):
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=13)
+    _one_step_parity(box, pos, vel, om, rad, dict(kw, **MULTI), precision, presteps=30)
+
+
+def test_multi_eigenvalue_monolayer_fp32():
+    from paper_1904_02929_amd import synth
+    w = synth.monolayer(96, 10, 0.75, seed=4, g0_I=0.05, period=400)
+    _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params, **MULTI), 1, presteps=25)
+
+
+def test_multi_eigenvalue_full_size_fp32():
+    from paper_1904_02929_amd import synth
+    w = synth.bulk3d(256, 0.55, 1e-4, seed=1)
+    _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params, **MULTI), 1, presteps=0)
+
+
 def test_multistep_fp64_from_create():
     # both sides start from their own initial state and run 25 steps
     box, pos, vel, om, rad, kw = PU.dense_workload(seed=11)
