@@ -45,7 +45,7 @@ class Params(C.Structure):
         ("wall_y", C.c_int32), ("wall_u_bot", C.c_double), ("wall_u_top", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
         ("contact_bins", C.c_int32), ("collision", C.c_int32), ("tau_bulk", C.c_double),
-        ("tau_ghost", C.c_double),
+        ("tau_ghost", C.c_double), ("boundary", C.c_int32),
     ]
 
 
@@ -74,6 +74,7 @@ class Sim(C.Structure):
         ("gp_count", C.c_int64), ("ledger", C.c_double), ("flags", C.c_int32),
         ("nthreads", C.c_int32),
         ("cst", _PD), ("ctot", C.c_double * 6), ("csig", C.c_double * 6), ("csamples", C.c_int64),
+        ("wall", _PI), ("wforce", (C.c_double * 3) * 2), ("wcount", C.c_int64), ("wspeed", C.c_double),
     ]
 
 
@@ -108,6 +109,11 @@ def lib():
         L.orc_contact_stats.argtypes = [C.POINTER(Sim), C.c_int32, _PD, _PD]
         L.orc_contact_stats.restype = C.c_int
         L.orc_sym3_eigen.argtypes = [_PD, _PD]
+        L.orc_set_walls.argtypes = [C.POINTER(Sim), _PI]
+        L.orc_set_walls.restype = C.c_int
+        L.orc_wall_speed.argtypes = [C.POINTER(Params), C.c_int64]
+        L.orc_wall_speed.restype = C.c_double
+        L.orc_wall_force.argtypes = [C.POINTER(Sim), _PD]
         _lib = L
     return _lib
 
@@ -125,7 +131,7 @@ DEFAULTS = dict(
     lub_delta=-1.0, lub_hc=0.5, lub_subtract_hc=1, F0=-1.0, debye_lambda=-1.0, pair_cutoff=1.0,
     n_sub=8, quasi2d=0, shear_kind=0, gamma_dot=0.0, g0_I=0.0, g0_F=0.0, period=1, theta=0.0,
     ncyc_I=0, ncyc_F=0, wall_y=0, wall_u_bot=0.0, wall_u_top=0.0, gx=0.0, gy=0.0, gz=0.0,
-    contact_bins=0, collision=0, tau_bulk=1.0, tau_ghost=1.0,
+    contact_bins=0, collision=0, tau_bulk=1.0, tau_ghost=1.0, boundary=0,
 )
 
 
@@ -202,6 +208,10 @@ def dlvo(params, derived, ai, aj, d):
     return Fi
 
 
+def wall_speed(params: Params, t: int) -> float:
+    return lib().orc_wall_speed(C.byref(params), int(t))
+
+
 def sym3_eigen(a6):
     """Eigenvalues (descending) of the symmetric 3x3 matrix xx yy zz xy xz yz."""
     a = np.ascontiguousarray(a6, np.float64).reshape(6)
@@ -213,7 +223,7 @@ def sym3_eigen(a6):
 class Oracle:
     """One simulation held by the C oracle; arrays are live numpy views of its memory."""
 
-    def __init__(self, params: Params, pos=None, vel=None, omega=None, radius=None):
+    def __init__(self, params: Params, pos=None, vel=None, omega=None, radius=None, wall=None):
         self.params = params
         pos = np.zeros((0, 3)) if pos is None else np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
         n = pos.shape[0]
@@ -223,6 +233,10 @@ class Oracle:
         self._keep = (pos, vel, omega, radius)
         self.ptr = lib().orc_create(C.byref(params), n, _pd(pos), _pd(vel), _pd(omega), _pd(radius))
         self.s = self.ptr.contents
+        if wall is not None:
+            wall = np.ascontiguousarray(wall, np.int32).reshape(-1)
+            if lib().orc_set_walls(self.ptr, _pi(wall)):
+                raise ValueError("wall spheres must keep pair_cutoff / 2 from their box face")
 
     def __del__(self):
         try:
@@ -293,6 +307,12 @@ class Oracle:
         out = np.zeros((5, 6)); gg = np.zeros(2)
         lib().orc_stress(self.ptr, _pd(out), _pd(gg))
         return out, gg
+
+    def wall_force(self):
+        """Mean force per step on the bottom and top walls since the last call, then reset."""
+        out = np.zeros(6)
+        lib().orc_wall_force(self.ptr, _pd(out))
+        return out.reshape(2, 3)
 
     def contact_stats(self, nbins):
         """(hist[5][nbins] = rho, xi_N, xi_T, zeta_N, zeta_T; summary[12]) since the last

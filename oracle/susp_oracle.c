@@ -81,7 +81,7 @@ void orc_minimage(const orc_params *p, double s, double dx, double dy, double dz
 static int wrapi(int i, int L) { i %= L; return i < 0 ? i + L : i; }
 
 /* ---------------- shear protocol: eq. (16) and its rate ---------------- */
-void orc_protocol(const orc_params *p, int64_t t, double *s, double *ule) {
+static void le_protocol(const orc_params *p, int64_t t, double *s, double *ule) {
   double Lx = p->lx, Ly = p->ly;
   if (p->shear_kind == 1) {
     double u = p->gamma_dot * Ly;
@@ -103,6 +103,19 @@ void orc_protocol(const orc_params *p, int64_t t, double *s, double *ule) {
   } else {
     *s = 0.0; *ule = 0.0;
   }
+}
+
+/* Lees-Edwards offset and sliding velocity at step t; with walls there is no sliding plane */
+void orc_protocol(const orc_params *p, int64_t t, double *s, double *ule) {
+  if (p->boundary == 1) { *s = 0.0; *ule = 0.0; return; }
+  le_protocol(p, t, s, ule);
+}
+
+/* walls: the same velocity difference L_y gamma_dot(t) across the box, split -/+ */
+double orc_wall_speed(const orc_params *p, int64_t t) {
+  double s, u;
+  le_protocol(p, t, &s, &u);
+  return 0.5 * u;
 }
 
 /* ---------------- derived constants (Sec. 2) ---------------- */
@@ -412,6 +425,7 @@ orc_sim *orc_create(const orc_params *p, int32_t np, const double *pos, const do
   S->Trest = (double *)xcalloc(3 * (size_t)np, sizeof(double));
   S->gown = (int32_t *)xcalloc(2 * (size_t)p->lx * p->lz, sizeof(int32_t));
   S->cst = (double *)xcalloc(3 * (size_t)(p->contact_bins > 0 ? p->contact_bins : 1), sizeof(double));
+  S->wall = (int32_t *)xcalloc((size_t)(np > 0 ? np : 1), sizeof(int32_t));
   for (int i = 0; i < np; ++i) {
     for (int c = 0; c < 3; ++c) {
       S->R[3 * i + c] = pos[3 * i + c];
@@ -434,7 +448,7 @@ orc_sim *orc_create(const orc_params *p, int32_t np, const double *pos, const do
   double s0, u0;
   orc_protocol(p, 0, &s0, &u0);
   S->s_next = s0;
-  double gd = u0 / (double)p->ly;
+  double gd = (p->boundary == 1 ? 2.0 * orc_wall_speed(p, 0) : u0) / (double)p->ly;
   for (int z = 0; z < p->lz; ++z)
     for (int y = 0; y < p->ly; ++y)
       for (int x = 0; x < p->lx; ++x) {
@@ -453,7 +467,7 @@ void orc_destroy(orc_sim *S) {
   free(S->f); free(S->fn); free(S->own); free(S->R); free(S->U); free(S->W); free(S->Q);
   free(S->a); free(S->m); free(S->I); free(S->amap); free(S->Fh); free(S->Th); free(S->Sh);
   free(S->nlinks); free(S->Frest); free(S->Trest); free(S->pi); free(S->pj); free(S->hi); free(S->hj); free(S->hxi);
-  free(S->gown); free(S->cst);
+  free(S->gown); free(S->cst); free(S->wall);
   free(S);
 }
 
@@ -551,7 +565,8 @@ static void build_ghosts(orc_sim *S, double s, double ule, ghost_t *G) {
 /* per-particle link sums: F[3] T[3] S[9] count, rest-state force[3] and torque[3] */
 #define ACC 22
 
-static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, double pineq[6]) {
+static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, double pineq[6],
+                       double wflat[6]) {
   const orc_params *P = &S->p;
   const int lx = P->lx, ly = P->ly, lz = P->lz, np = S->np;
   const int64_t nodes = S->nodes;
@@ -559,6 +574,7 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
   int nt = S->nthreads;
   double *acc = (double *)xcalloc((size_t)nt * (np > 0 ? np : 1) * ACC, sizeof(double));
   double *pacc = (double *)xcalloc((size_t)nt * 6, sizeof(double));
+  double *wacc = (double *)xcalloc((size_t)nt * 6, sizeof(double));
 #pragma omp parallel num_threads(nt)
   {
     int tid = 0;
@@ -567,6 +583,7 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
 #endif
     double *A = acc + (size_t)tid * (np > 0 ? np : 1) * ACC;
     double *pa = pacc + 6 * tid;
+    double *pw = wacc + 6 * tid;
 #pragma omp for schedule(static)
     for (int z = 0; z < lz; ++z)
       for (int y = 0; y < ly; ++y)
@@ -577,6 +594,18 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
           n[0] = S->f[X];
           for (int q = 1; q < 19; ++q) {
             int px = x - CX[q], py = y - CY[q], pz = z - CZ[q];
+            if (P->boundary == 1 && (py < 0 || py >= ly)) {
+              /* flat wall halfway between the edge row and its ghost, moving at -/+ U_w:
+               * bounce-back with the wall velocity (eq. 7) */
+              double uw = py < 0 ? -S->wspeed : S->wspeed;
+              double fo = S->f[OPP(q) * nodes + X];
+              n[q] = fo + 6.0 * WQ(q) * rho0 * uw * CX[q];
+              /* momentum the wall receives, measured from the rest state rho0 */
+              double mm = 2.0 * (fo - WQ(q) * rho0) + 6.0 * WQ(q) * rho0 * uw * CX[q];
+              double *wf = pw + (py < 0 ? 0 : 3);
+              wf[0] -= mm * CX[q]; wf[1] -= mm * CY[q]; wf[2] -= mm * CZ[q];
+              continue;
+            }
             int wx = wrapi(px, lx), wz = wrapi(pz, lz);
             int owner;
             double val = 0.0;
@@ -706,10 +735,12 @@ static void fluid_step(orc_sim *S, double s, double ule, const ghost_t *G, doubl
   }
   for (int c = 0; c < 6; ++c) {
     pineq[c] = 0;
-    for (int th = 0; th < nt; ++th) pineq[c] += pacc[6 * th + c];
+    wflat[c] = 0;
+    for (int th = 0; th < nt; ++th) { pineq[c] += pacc[6 * th + c]; wflat[c] += wacc[6 * th + c]; }
   }
   free(acc);
   free(pacc);
+  free(wacc);
   double *t = S->f; S->f = S->fn; S->fn = t;
 }
 
@@ -884,13 +915,26 @@ static void one_step(orc_sim *S) {
     }
   }
 
-  /* fluid: Lees-Edwards ghosts, then stream + bounce-back + collide with link forces */
+  /* fluid: Lees-Edwards ghosts (or moving walls), then stream + bounce-back + collide with
+   * link forces */
+  const int walls = P->boundary == 1;
+  S->wspeed = walls ? orc_wall_speed(P, S->step) : 0.0;
+  const double wsp1 = walls ? orc_wall_speed(P, S->step + 1) : 0.0;
   ghost_t G;
   G.val = (double *)xcalloc((size_t)2 * 5 * P->lx * P->lz, sizeof(double));
-  build_ghosts(S, s, ule, &G);
-  double pineq[6];
-  fluid_step(S, s, ule, &G, pineq);
+  if (walls) {
+    for (int i = 0; i < 2 * P->lx * P->lz; ++i) S->gown[i] = -1;
+  } else {
+    build_ghosts(S, s, ule, &G);
+  }
+  double pineq[6], wflat[6];
+  fluid_step(S, s, ule, &G, pineq, wflat);
   free(G.val);
+  double wf[2][3] = {{wflat[0], wflat[1], wflat[2]}, {wflat[3], wflat[4], wflat[5]}};
+  if (walls)
+    for (int i = 0; i < np; ++i)
+      if (S->wall[i] > 0)
+        for (int c = 0; c < 3; ++c) wf[S->wall[i] - 1][c] += S->Fh[3 * i + c];
 
   /* DEM substeps: eq. (1) with the hydrodynamic force and torque frozen over the step */
   double *Fp = (double *)xcalloc(3 * npa, sizeof(double));
@@ -927,6 +971,14 @@ static void one_step(orc_sim *S) {
     }
     for (int i = 0; i < np; ++i) {
       double *U = &S->U[3 * i], *W = &S->W[3 * i], *R = &S->R[3 * i];
+      if (walls && S->wall[i] > 0) {
+        /* a wall sphere moves with its wall; the pair forces on it load the wall */
+        for (int c = 0; c < 3; ++c) wf[S->wall[i] - 1][c] += Fp[3 * i + c] / (double)ns;
+        U[0] = S->wall[i] == 2 ? S->wspeed : -S->wspeed;
+        U[1] = 0.0; U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; W[2] = 0.0;
+        R[0] += dts * U[0];
+        continue;
+      }
       for (int c = 0; c < 3; ++c) {
         U[c] += dts * (S->Fh[3 * i + c] + Fp[3 * i + c]) / S->m[i];
         W[c] += dts * (S->Th[3 * i + c] + Tp[3 * i + c]) / S->I[i];
@@ -956,10 +1008,21 @@ static void one_step(orc_sim *S) {
   free(pxi);
   free(pon);
 
+  if (walls) {
+    /* the walls' velocity for the next step; a free sphere leaving the gap is a failure */
+    for (int i = 0; i < np; ++i) {
+      if (S->wall[i] > 0) S->U[3 * i] = S->wall[i] == 2 ? wsp1 : -wsp1;
+      else if (!(S->R[3 * i + 1] >= 0.0 && S->R[3 * i + 1] < (double)P->ly)) S->flags |= 2;
+    }
+    for (int g = 0; g < 2; ++g)
+      for (int c = 0; c < 3; ++c) S->wforce[g][c] += wf[g][c];
+    S->wcount += 1;
+  }
   /* Lees-Edwards wrap of the particles with the offset of the next step */
   for (int i = 0; i < np; ++i) {
     double *R = &S->R[3 * i], *U = &S->U[3 * i];
-    if (R[1] >= P->ly) { R[1] -= P->ly; R[0] -= s1; U[0] -= ule1; }
+    if (walls) {
+    } else if (R[1] >= P->ly) { R[1] -= P->ly; R[0] -= s1; U[0] -= ule1; }
     else if (R[1] < 0.0) { R[1] += P->ly; R[0] += s1; U[0] += ule1; }
     for (int it = 0; it < 4 && R[0] >= P->lx; ++it) R[0] -= P->lx;
     for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += P->lx;
@@ -978,6 +1041,11 @@ static void one_step(orc_sim *S) {
     for (int p = 0; p < np; ++p) for_footprint(S, R0, p, s, uncover_fn, &uc);
     for (int p = 0; p < np; ++p) {
       const double *a = dp + 7 * (size_t)p;
+      if (walls && S->wall[p] > 0) {  /* prescribed motion: the impulses load the wall */
+        for (int c = 0; c < 3; ++c) S->wforce[S->wall[p] - 1][c] += a[c];
+        S->ledger += a[6];
+        continue;
+      }
       for (int c = 0; c < 3; ++c) {
         S->U[3 * p + c] += a[c] / S->m[p];
         S->W[3 * p + c] += a[3 + c] / S->I[p];
@@ -1059,6 +1127,35 @@ void orc_stress(orc_sim *S, double out[5][6], double gg[2]) {
   } else {
     gg[0] = 0.0; gg[1] = 0.0;
   }
+}
+
+int orc_set_walls(orc_sim *S, const int32_t *member) {
+  const orc_params *P = &S->p;
+  double h = 0.5 * P->pair_cutoff;
+  for (int i = 0; i < S->np; ++i) {
+    int m = member[i];
+    if (m < 0 || m > 2) return -1;
+    double y = S->R[3 * i + 1], a = S->a[i];
+    if (m == 1 && !(y > a + h)) return -1;
+    if (m == 2 && !(y < (double)P->ly - a - h)) return -1;
+  }
+  double u = orc_wall_speed(P, S->step);
+  for (int i = 0; i < S->np; ++i) {
+    S->wall[i] = member[i];
+    if (member[i] > 0) {
+      S->U[3 * i] = member[i] == 2 ? u : -u;
+      S->U[3 * i + 1] = 0.0; S->U[3 * i + 2] = 0.0;
+      S->W[3 * i] = 0.0; S->W[3 * i + 1] = 0.0; S->W[3 * i + 2] = 0.0;
+    }
+  }
+  return 0;
+}
+
+void orc_wall_force(orc_sim *S, double out[6]) {
+  double n = S->wcount > 0 ? (double)S->wcount : 1.0;
+  for (int g = 0; g < 2; ++g)
+    for (int c = 0; c < 3; ++c) { out[3 * g + c] = S->wforce[g][c] / n; S->wforce[g][c] = 0.0; }
+  S->wcount = 0;
 }
 
 /* Eigenvalues of a symmetric 3x3 matrix by cyclic Jacobi rotations, sorted descending. */

@@ -51,6 +51,9 @@ typedef struct {
                                   -1/tau_bulk (trace of the stress), -1/tau_ghost (the
                                   nine non-hydrodynamic modes)                          */
   double tau_bulk, tau_ghost;
+  int32_t boundary;            /* 0: Lees-Edwards in y; 1: walls (Sec. 3): flat walls at
+                                  y = -1/2 and ly - 1/2 moving at -/+ U_w(t) in x, carrying
+                                  layers of wall spheres that move with them              */
 } orc_params;
 
 /* Fully resolved constants after defaults are applied. */
@@ -100,6 +103,12 @@ typedef struct {
                                 (xx, xy, yx, yy) over all contacts                     */
   double csig[6];            /* sum over sampled steps of the total stress (eq. 15)    */
   int64_t csamples;          /* sampled steps                                          */
+  /* walls (boundary 1): membership of each sphere, 0 free, 1 bottom wall, 2 top wall;
+   * force of the suspension on each wall summed over the steps since the last read-out */
+  int32_t *wall;
+  double wforce[2][3];
+  int64_t wcount;
+  double wspeed;             /* wall speed U_w of the current step                     */
 } orc_sim;
 
 /* D3Q19 lattice as used by the oracle (index q: velocity, weight, opposite). */
@@ -123,6 +132,18 @@ void orc_stress(orc_sim *s, double out[5][6], double gg[2]);
  * sigma_hat xx, xy, yx, yy, Delta lambda, P, Delta lambda / P, volume (area) fraction.
  * Returns -1 if nbins does not match, else 0.                                            */
 int orc_contact_stats(orc_sim *s, int32_t nbins, double *hist, double summary[12]);
+/* Walls (boundary 1): mark spheres as members of the bottom (1) or top (2) wall; their
+ * velocity becomes the wall's.  Each member must keep a gap of pair_cutoff / 2 to its own
+ * box face (centre y > a + cutoff / 2 for the bottom, < ly - a - cutoff / 2 for the top) so
+ * that the two walls never meet through the periodic image.  Returns -1 if violated.     */
+int orc_set_walls(orc_sim *s, const int32_t *member);
+/* Wall speed U_w(t) = L_y gamma_dot(t) / 2 of the protocol (the top wall moves at +U_w). */
+double orc_wall_speed(const orc_params *p, int64_t t);
+/* Mean force per step of the suspension on the bottom and top walls (flat wall plus its
+ * spheres: hydrodynamic force and the substep-mean pair forces) since the last call, then
+ * reset: out = {bottom x y z, top x y z}.  The flat-wall part is measured from the rest
+ * state rho0 (like the link sums).                                                        */
+void orc_wall_force(orc_sim *s, double out[6]);
 /* Eigenvalues of a symmetric 3x3 matrix (xx yy zz xy xz yz), descending (Jacobi). */
 void orc_sym3_eigen(const double a[6], double ev[3]);
 /* LE protocol at step t: offset s (wrapped to [0,lx)) and sliding velocity. */
