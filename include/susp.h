@@ -102,6 +102,15 @@ typedef struct {
                                 stress, -1/tau_bulk for its trace and -1/tau_ghost for the
                                 nine non-hydrodynamic modes (mass and momentum conserved) */
   double tau_bulk, tau_ghost;  /* > 1/2 each (collision 1)                               */
+  int32_t boundary;          /* 0: Lees-Edwards sliding boundary in y.  1: walls (Sec. 3):
+                                flat walls halfway outside rows 0 and ly-1, moving in x at
+                                -U_w and +U_w, U_w = ly gamma_dot(t) / 2 of the protocol,
+                                with the spheres marked in `wall` moving along with them   */
+  const int32_t *wall;       /* [n] (boundary 1; NULL: none) 0 free sphere, 1 bottom-wall
+                                sphere, 2 top-wall sphere.  A wall sphere keeps its y and z,
+                                moves at its wall's velocity with no spin, and must keep
+                                pair_cutoff / 2 from its own face (centre y > a + cutoff/2
+                                at the bottom, < ly - a - cutoff/2 at the top)            */
 } susp_params;
 
 /* Fill *p with the paper's defaults (tau 1, rho0 1, map_ratio 0.95, rho_p 1, kt 0.5 kn,
@@ -135,6 +144,15 @@ int susp_step(susp_sim *s, int64_t nsteps);
  * yz, each divided by the box volume (eqs. 12, 14, 15).  gg = {G', G''} from eqs. (17)-(18)
  * over the observation steps completed so far (0 if none).  Synchronises.                */
 int susp_stress(susp_sim *s, double out[5][6], double gg[2]);
+
+/* Walls (boundary 1): mean force per step of the suspension on the bottom and the top wall
+ * since the previous call (or creation), then reset.  out[6] (host) = bottom x y z, top
+ * x y z: the flat wall (momentum of the bounced populations, measured from the rest state
+ * rho0, so that its y part omits the constant rest pressure), plus, for every sphere of the
+ * wall, its hydrodynamic force, the substep mean of its pair forces and the momentum of the
+ * nodes it covers and releases.  The shear stress on the top wall is out[3] / (lx lz) with
+ * the sign of the force on the wall.  SUSP_EINVAL without walls.  Synchronises.           */
+int susp_wall_force(susp_sim *s, double out[6]);
 
 /* Contact-force statistics of Sec. 4.2 (eqs. 19-23) and the stress built from them (eq. 27
  * for 3D suspensions, eq. 26 for monolayers; App. C), over the steps since the previous call

@@ -66,7 +66,7 @@ extern "C" void susp_default_params(susp_params *p) {
 // ---------------------------------------------------------------------------------------
 // Shear protocol: offset and sliding velocity of the image box above at step t
 // (simple shear, or eq. (16) with the amplitude switched after ncyc_I periods).
-static void protocol(const Sim &s, int64_t t, double *off, double *ule) {
+static void le_protocol(const Sim &s, int64_t t, double *off, double *ule) {
   const double Lx = s.lx, Ly = s.ly;
   if (s.shear_kind == 1) {
     const double u = s.gamma_dot * Ly;
@@ -89,6 +89,19 @@ static void protocol(const Sim &s, int64_t t, double *off, double *ule) {
     *off = 0.0;
     *ule = 0.0;
   }
+}
+
+// Lees-Edwards offset and sliding velocity of step t (none with walls)
+static void protocol(const Sim &s, int64_t t, double *off, double *ule) {
+  if (s.boundary == 1) { *off = 0.0; *ule = 0.0; return; }
+  le_protocol(s, t, off, ule);
+}
+
+// Walls: speed of the top wall, half the velocity difference L_y gamma_dot(t) across the box
+static double wall_speed(const Sim &s, int64_t t) {
+  double off, ule;
+  le_protocol(s, t, &off, &ule);
+  return 0.5 * ule;
 }
 
 static Box make_box(const Sim &s, double off, double ule) {
@@ -163,6 +176,19 @@ static int resolve(const susp_params *p, Sim &s) {
   if (p->collision < 0 || p->collision > 1) return fail(SUSP_EINVAL, "collision must be 0 or 1");
   if (p->collision == 1 && !(p->tau_bulk > 0.5 && p->tau_ghost > 0.5))
     return fail(SUSP_EINVAL, "tau_bulk and tau_ghost must exceed 1/2");
+  if (p->boundary < 0 || p->boundary > 1) return fail(SUSP_EINVAL, "boundary must be 0 or 1");
+  s.boundary = p->boundary;
+  if (p->boundary == 1 && p->wall) {
+    // a wall sphere keeps pair_cutoff / 2 from its own face, so that the two walls never
+    // meet through the periodic image in y
+    for (int i = 0; i < p->n; ++i) {
+      const int m = p->wall[i];
+      const double y = p->pos[3 * i + 1], a = p->radius[i], h = 0.5 * p->pair_cutoff;
+      if (m < 0 || m > 2) return fail(SUSP_EINVAL, "wall membership %d of sphere %d not in 0..2", m, i);
+      if ((m == 1 && !(y > a + h)) || (m == 2 && !(y < p->ly - a - h)))
+        return fail(SUSP_EINVAL, "wall sphere %d closer than pair_cutoff / 2 to its face", i);
+    }
+  }
   s.collision = p->collision;
   s.tau_bulk = p->collision ? p->tau_bulk : p->tau;
   s.tau_ghost = p->collision ? p->tau_ghost : p->tau;
@@ -273,6 +299,12 @@ static size_t carve(Sim &s, char *base) {
   }
   s.hstart = (int32_t *)take(n * NCAP * 4);
   s.rev = (int32_t *)take(n * NCAP * 4);
+  if (s.boundary == 1) {
+    s.wmem = (int32_t *)take(n * 4);
+    s.wfs = (double *)take(n * 3 * 8);
+    s.wpart = (double *)take((size_t)((2 * s.lx * s.lz + 255) / 256) * 6 * 8);
+    s.wacc = (double *)take(8 * 8);
+  }
   if (s.cbins > 0) {
     s.crec = (double *)take(n * NCAP * 4 * 8);
     s.cflag = (int32_t *)take(n * NCAP * 4);
@@ -355,11 +387,30 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       I[i] = 0.4 * m[i] * a[i] * a[i];
       am[i] = p->map_ratio * a[i];
     }
+    // initial velocities; wall spheres move with their wall
+    std::vector<double> u0(n * 3, 0.0), w0(n * 3, 0.0);
+    std::vector<int32_t> wm(n, 0);
+    for (size_t i = 0; i < 3 * n; ++i) {
+      if (p->vel) u0[i] = p->vel[i];
+      if (p->omega) w0[i] = p->omega[i];
+    }
+    if (s.boundary == 1 && p->wall) {
+      const double uw = wall_speed(s, 0);
+      for (size_t i = 0; i < n; ++i) {
+        wm[i] = p->wall[i];
+        if (wm[i] == 0) continue;
+        u0[3 * i] = wm[i] == 2 ? uw : -uw;
+        u0[3 * i + 1] = u0[3 * i + 2] = 0.0;
+        w0[3 * i] = w0[3 * i + 1] = w0[3 * i + 2] = 0.0;
+      }
+    }
+    if (s.boundary == 1 && (hipMemcpyAsync(s.wmem, wm.data(), n * 4, hipMemcpyHostToDevice, s.stream) ||
+                            hipStreamSynchronize(s.stream)))
+      return bail(fail(SUSP_EDEVICE, "upload"));
     for (int b = 0; b < 2; ++b) {
       if (hipMemcpyAsync(s.R[b], p->pos, n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
-      std::vector<double> z(n * 3, 0.0);
-      if (hipMemcpyAsync(s.U[b], p->vel ? p->vel : z.data(), n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
-      if (hipMemcpyAsync(s.W[b], p->omega ? p->omega : z.data(), n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
+      if (hipMemcpyAsync(s.U[b], u0.data(), n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
+      if (hipMemcpyAsync(s.W[b], w0.data(), n * 24, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
       for (size_t i = 0; i < n; ++i) v[4 * i] = 1.0;
       if (hipMemcpyAsync(s.Q[b], v.data(), n * 32, hipMemcpyHostToDevice, s.stream)) return bail(fail(SUSP_EDEVICE, "upload"));
       if (hipStreamSynchronize(s.stream)) return bail(fail(SUSP_EDEVICE, "sync"));
@@ -389,6 +440,8 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       launch_fill_f64(s.pineq, (size_t)s.lbm_blocks * 6, 0.0, s.stream))
     return bail(fail(SUSP_EDEVICE, "fill"));
   if (launch_fill_i32(s.cell_start, (size_t)s.ncell + 1, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  if (s.boundary == 1 && (launch_fill_f64(s.wacc, 8, 0.0, s.stream) || (n && launch_fill_f64(s.wfs, n * 3, 0.0, s.stream))))
+    return bail(fail(SUSP_EDEVICE, "fill"));
   if (s.cbins > 0 && (launch_fill_f64(s.cacc, (size_t)(s.cbins + 1) * 6 + 8, 0.0, s.stream) ||
                       (n && launch_fill_i32(s.cflag, n * NCAP, 0, s.stream))))
     return bail(fail(SUSP_EDEVICE, "fill"));
@@ -424,6 +477,7 @@ static ClockEntry clock_entry(const Sim &s, int64_t t) {
   memset(&e, 0, sizeof e);
   protocol(s, t, &e.s, &e.ule);
   protocol(s, t + 1, &e.s1, &e.ule1);
+  if (s.boundary == 1) { e.uw = wall_speed(s, t); e.uw1 = wall_speed(s, t + 1); }
   if (s.shear_kind == 2) {
     const int64_t tI = (int64_t)s.ncyc_I * s.period, tF = tI + (int64_t)s.ncyc_F * s.period;
     if (t >= tI && t < tF) {
@@ -469,7 +523,8 @@ static int one_step(Sim &s) {
     HIPCHK(hipEventRecord(s.join_ev, s.aux));
   }
   HIPCHK(launch_brick_lists(&s));
-  HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
+  if (s.boundary == 1) HIPCHK(launch_walls(&s));
+  else HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
@@ -503,6 +558,7 @@ static int one_step(Sim &s) {
     HIPCHK(launch_map_update(&s, b, 1));
     HIPCHK(launch_map_update(&s, b, 2));
   }
+  if (s.boundary == 1) HIPCHK(launch_wall_force(&s));
   HIPCHK(launch_stress(&s));
   HIPCHK(launch_contact_sample(&s));
   s.step += 1;
@@ -618,6 +674,20 @@ extern "C" int susp_stress(susp_sim *h, double out[5][6], double gg[2]) {
     gg[1] = 0.0;
   }
   HIPCHK(launch_fill_f64(s.acc + 30, 31, 0.0, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+extern "C" int susp_wall_force(susp_sim *h, double out[6]) {
+  if (!h || !out) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  if (s.boundary != 1) return fail(SUSP_EINVAL, "no walls (boundary = 0)");
+  double w[8];
+  HIPCHK(hipMemcpyAsync(w, s.wacc, sizeof w, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  const double n = w[6] > 0 ? w[6] : 1.0;
+  for (int c = 0; c < 6; ++c) out[c] = w[c] / n;
+  HIPCHK(launch_fill_f64(s.wacc, 8, 0.0, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
   return SUSP_OK;
 }
@@ -848,7 +918,8 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     HIPCHK(hipMalloc((void **)&g, (size_t)2 * s.lx * s.lz * 4));
     hipError_t e = hipMalloc((void **)&lk, (size_t)NQ * s.nodes * 4);
     if (!e && n) e = launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr);
-    if (!e) e = n ? launch_ghosts(&s, b, g, s.gval, 0, nullptr, 0) : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
+    if (!e) e = n && s.boundary == 0 ? launch_ghosts(&s, b, g, s.gval, 0, nullptr, 0)
+                                     : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
     if (!e) e = launch_link_enum(&s, g, lk, b);
     std::vector<int32_t> all;
     if (!e) {

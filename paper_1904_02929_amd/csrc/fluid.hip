@@ -1228,6 +1228,73 @@ hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out
 }
 
 // ---------------------------------------------------------------------------------------
+// Moving walls (boundary 1, Sec. 3): flat walls halfway between the edge rows and their
+// ghost planes, moving at -uw (bottom) and +uw (top) in x.  The ghost value pulled along q
+// by the edge node X = (x + c_qx, edge row, z + c_qz) is that node's own opposite
+// population plus the wall's momentum (eq. 7): d_q = d_qbar(X) + 6 w_q rho0 u_w c_qx, so the
+// lattice kernel needs no change.  Each block also sums the momentum the walls receive from
+// fluid edge nodes, -(2 d_qbar + 6 w_q rho0 u_w c_qx) c_q (measured from the rest state).
+template <class ST>
+__global__ __launch_bounds__(256) void k_walls(const void *fin, size_t plane, const int32_t *own, int lx,
+                                               int ly, int lz, double rho0, H16 h16, const Clock *clk,
+                                               int32_t *gown, void *gval, double *wpart) {
+  using CT = typename Store<ST>::CT;
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+  const int idx = blockIdx.x * blockDim.x + t;
+  const int npl = lx * lz;
+  double mom[6] = {0, 0, 0, 0, 0, 0};
+  if (idx < 2 * npl) {
+    const int g = idx / npl;
+    const int rem = idx - g * npl;
+    const int z = rem / lx, x = rem - (rem / lx) * lx;
+    const double uw = g == 0 ? -clk->cur.uw : clk->cur.uw;
+    const int yrow = g == 0 ? 0 : ly - 1;
+    gown[idx] = -1;
+    CT *gv = (CT *)gval;
+    for (int m = 0; m < 5; ++m) {
+      const int q = gdir(g, m), qb = opp(q);
+      int xs = x + cx(q), zs = z + cz(q);
+      xs = xs < 0 ? xs + lx : (xs >= lx ? xs - lx : xs);
+      zs = zs < 0 ? zs + lz : (zs >= lz ? zs - lz : zs);
+      const int64_t node = xs + (int64_t)lx * (yrow + (int64_t)ly * zs);
+      const CT d = Store<ST>::ld((const ST *)fin + (size_t)qb * plane, node, qb, h16);
+      const double mw = 6.0 * wq(q) * rho0 * uw * cx(q);
+      gv[(size_t)((g * 5 + m) * lz + z) * lx + x] = d + (CT)mw;
+      if (own[node] == -1) {
+        const double mm = 2.0 * (double)d + mw;
+        mom[3 * g] -= mm * cx(q);
+        mom[3 * g + 1] -= mm * cy(q);
+        mom[3 * g + 2] -= mm * cz(q);
+      }
+    }
+  }
+  for (int c = 0; c < 6; ++c) red[c][t] = mom[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t < 6) wpart[(size_t)blockIdx.x * 6 + t] = red[t][0];
+}
+
+hipError_t launch_walls(Sim *s) {
+  const int tot = 2 * s->lx * s->lz;
+  dim3 grid((tot + 255) / 256), blk(256);
+  if (s->precision == 0)
+    hipLaunchKernelGGL(k_walls<double>, grid, blk, 0, s->stream, s->f[s->cur], s->plane, s->own, s->lx, s->ly,
+                       s->lz, s->rho0, s->h16, s->clk, s->gown, s->gval, s->wpart);
+  else if (s->precision == 1)
+    hipLaunchKernelGGL(k_walls<float>, grid, blk, 0, s->stream, s->f[s->cur], s->plane, s->own, s->lx, s->ly,
+                       s->lz, s->rho0, s->h16, s->clk, s->gown, s->gval, s->wpart);
+  else
+    hipLaunchKernelGGL(k_walls<__half>, grid, blk, 0, s->stream, s->f[s->cur], s->plane, s->own, s->lx, s->ly,
+                       s->lz, s->rho0, s->h16, s->clk, s->gown, s->gval, s->wpart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Start of a step: the table entry of the step becomes the current clock (reset: rewind the
 // cursor after a new table upload).
 __global__ void k_clock(const ClockEntry *tab, Clock *clk, int reset) {

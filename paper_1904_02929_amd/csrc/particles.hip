@@ -483,6 +483,8 @@ struct SubArgs {
   double *pst;
   double *crec;     // contact records of the last substep (null: statistics off)
   int32_t *cflag;
+  const int32_t *wmem;  // walls: membership (null: Lees-Edwards)
+  double *wfs;          // walls: force on each wall sphere this step
   Phys P;
   Box b;             // static dimensions; offsets of this and the next step from clk
   const Clock *clk;
@@ -574,6 +576,27 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
     for (int c = 0; c < PST; ++c) st[c] += A.pst[(size_t)i * PST + c];
   }
   for (int c = 0; c < PST; ++c) A.pst[(size_t)i * PST + c] = st[c];
+  if (A.wmem && A.wmem[i] > 0) {
+    // a wall sphere moves with its wall (Sec. 3); its hydrodynamic force and the
+    // substep mean of its pair forces load the wall
+    const double sg = A.wmem[i] == 2 ? 1.0 : -1.0;
+    for (int c = 0; c < 3; ++c) {
+      const double f = F[c] * A.dts;
+      A.wfs[3 * i + c] = A.sub == 0 ? A.hyd[(size_t)i * HYD + c] + f : A.wfs[3 * i + c] + f;
+    }
+    const double u = sg * (A.last ? A.clk->cur.uw1 : A.clk->cur.uw);
+    A.Ro[3 * i] = A.Ri[3 * i] + A.dts * (sg * A.clk->cur.uw);
+    A.Ro[3 * i + 1] = A.Ri[3 * i + 1];
+    A.Ro[3 * i + 2] = A.Ri[3 * i + 2];
+    if (A.last) {
+      for (int it = 0; it < 4 && A.Ro[3 * i] >= bx.Lx; ++it) A.Ro[3 * i] -= bx.Lx;
+      for (int it = 0; it < 4 && A.Ro[3 * i] < 0.0; ++it) A.Ro[3 * i] += bx.Lx;
+    }
+    A.Uo[3 * i] = u; A.Uo[3 * i + 1] = 0.0; A.Uo[3 * i + 2] = 0.0;
+    A.Wo[3 * i] = 0.0; A.Wo[3 * i + 1] = 0.0; A.Wo[3 * i + 2] = 0.0;
+    for (int c = 0; c < 4; ++c) A.Qo[4 * i + c] = A.Qi[4 * i + c];
+    return;
+  }
   // eq. (1), symplectic Euler with the hydrodynamic force and torque of this step
   double U[3], W[3], R[3];
   for (int c = 0; c < 3; ++c) {
@@ -590,8 +613,9 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   const double dz = W[2] * qw + (W[0] * qy - W[1] * qx);
   qw += 0.5 * A.dts * dw; qx += 0.5 * A.dts * dx; qy += 0.5 * A.dts * dy; qz += 0.5 * A.dts * dz;
   const double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  if (A.last) {  // Lees-Edwards wrap with the offset of the next step
-    if (R[1] >= bx.Ly) { R[1] -= bx.Ly; R[0] -= s1; U[0] -= ule1; }
+  if (A.last) {  // Lees-Edwards wrap with the offset of the next step (none with walls)
+    if (A.wmem) {
+    } else if (R[1] >= bx.Ly) { R[1] -= bx.Ly; R[0] -= s1; U[0] -= ule1; }
     else if (R[1] < 0.0) { R[1] += bx.Ly; R[0] += s1; U[0] += ule1; }
     for (int it = 0; it < 4 && R[0] >= bx.Lx; ++it) R[0] -= bx.Lx;
     for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += bx.Lx;
@@ -605,6 +629,7 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
     for (int c = 0; c < 3; ++c) ok = ok && isfinite(R[c]) && isfinite(U[c]) && isfinite(W[c]);
     ok = ok && R[0] > -bx.Lx && R[0] < 2.0 * bx.Lx && R[1] > -bx.Ly && R[1] < 2.0 * bx.Ly &&
          R[2] > -bx.Lz && R[2] < 2.0 * bx.Lz;
+    if (A.wmem) ok = ok && R[1] >= 0.0 && R[1] < bx.Ly;  // walls: a sphere left the gap
     if (!ok) atomicOr(A.flags, 2);
   }
 }
@@ -624,6 +649,8 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   A.xout = s->hxi[1 - hin]; A.onout = s->hon[1 - hin];
   A.pst = s->pst;
   A.crec = s->cbins > 0 ? s->crec : nullptr;
+  A.wmem = s->boundary == 1 ? s->wmem : nullptr;
+  A.wfs = s->wfs;
   A.cflag = s->cflag;
   A.P.kn = s->kn; A.P.kt = s->kt; A.P.eta_n = s->eta_n; A.P.mu = s->mu;
   A.P.delta = s->lub_delta; A.P.hc = s->lub_hc; A.P.F0 = s->F0; A.P.lambda = s->lambda;
@@ -769,6 +796,7 @@ struct MapArgs {
   double *dp;
   int32_t *flags;
   H16 h16;
+  const int32_t *wmem;  // walls: membership (null: Lees-Edwards)
 };
 
 __device__ inline bool inside_new(const MapArgs &A, const Box &bnew, int v, double x, double y, double z) {
@@ -930,6 +958,7 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
     return;
   }
   for (int c = 0; c < 7; ++c) dp[c] += acc[c];
+  if (A.wmem && A.wmem[p] > 0) return;  // prescribed motion: the impulses load the wall
   double U[3], W[3];
   for (int c = 0; c < 3; ++c) {
     U[c] = A.U[3 * p + c] + dp[c] / A.m[p];
@@ -950,6 +979,7 @@ hipError_t launch_map_update(Sim *s, const Box &box, int phase) {
   A.rho0 = s->rho0; A.quasi2d = s->quasi2d;
   A.dp = s->dp; A.flags = s->flags;
   A.h16 = s->h16;
+  A.wmem = s->boundary == 1 ? s->wmem : nullptr;
   if (s->n == 0) return hipSuccess;
   dim3 g(s->n), b(64);
   if (phase == 1) {
@@ -1212,6 +1242,40 @@ __global__ __launch_bounds__(256) void k_cstat_final(double *cacc, double *out, 
   }
   __syncthreads();
   for (int k = threadIdx.x; k < (nb + 1) * 6 + 8; k += blockDim.x) cacc[k] = 0.0;
+}
+
+// Force of the suspension on the bottom and top walls this step: the flat walls' block sums
+// in block order, then each wall sphere's force and its cover/uncover impulses in sphere
+// order (fixed orders), added to the running sums.  One work-group.
+__global__ __launch_bounds__(256) void k_wall_force(const double *wpart, int nblk, const int32_t *wmem,
+                                                    const double *wfs, const double *dp, int n,
+                                                    double *wacc) {
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = t; b < nblk; b += 256)
+    for (int c = 0; c < 6; ++c) v[c] += wpart[(size_t)b * 6 + c];
+  for (int i = t; i < n; i += 256) {
+    const int m = wmem[i];
+    if (m <= 0) continue;
+    for (int c = 0; c < 3; ++c) v[3 * (m - 1) + c] += wfs[3 * i + c] + dp[(size_t)i * 8 + c];
+  }
+  for (int c = 0; c < 6; ++c) red[c][t] = v[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t < 6) wacc[t] += red[t][0];
+  if (t == 0) wacc[6] += 1.0;
+}
+
+hipError_t launch_wall_force(Sim *s) {
+  const int nblk = (2 * s->lx * s->lz + 255) / 256;
+  hipLaunchKernelGGL(k_wall_force, dim3(1), dim3(256), 0, s->stream, s->wpart, nblk, s->wmem, s->wfs, s->dp,
+                     s->n, s->wacc);
+  return hipGetLastError();
 }
 
 hipError_t launch_contact_final(Sim *s) {

@@ -106,6 +106,7 @@ template <> struct Store<__half> {
 // kernel arguments.
 struct ClockEntry {
   double s, ule, s1, ule1, gcos, gsin;
+  double uw, uw1;  // walls: speed of the top wall at t and t+1 (the bottom one moves at -uw)
   int32_t gphase, pad;
 };
 struct Clock {
@@ -151,6 +152,8 @@ hipError_t launch_map_full(Sim *s, const Box &b);
 hipError_t launch_map_update(Sim *s, const Box &b, int phase);
 hipError_t launch_stress(Sim *s);
 hipError_t launch_contact_sample(Sim *s);
+hipError_t launch_walls(Sim *s);
+hipError_t launch_wall_force(Sim *s);
 hipError_t launch_contact_final(Sim *s);
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_clock(Sim *s, int reset);
@@ -172,6 +175,11 @@ struct Sim {
   int period, ncyc_I, ncyc_F;
   int fp16_exp;
   int collision;           // 0 BGK, 1 multi-eigenvalue (tau shear, tau_bulk, tau_ghost)
+  int boundary;            // 0 Lees-Edwards, 1 moving walls with wall spheres
+  int32_t *wmem;           // [n] 0 free, 1 bottom wall, 2 top wall
+  double *wfs;             // [n][3] force on each wall sphere this step (hydro + pair mean)
+  double *wpart;           // [ghost blocks][6] flat-wall momentum per block
+  double *wacc;            // [8] summed force on the bottom, top wall; steps
   double tau_bulk, tau_ghost;
   H16 h16;                 // FP16 storage scale 2^k and its inverse
   Cells cells;

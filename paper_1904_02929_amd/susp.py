@@ -37,6 +37,7 @@ class Params(C.Structure):
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32), ("fp16_exp", C.c_int32),
         ("brick_y", C.c_int32), ("brick_z", C.c_int32), ("contact_bins", C.c_int32),
         ("collision", C.c_int32), ("tau_bulk", C.c_double), ("tau_ghost", C.c_double),
+        ("boundary", C.c_int32), ("wall", _PI),
     ]
 
 
@@ -64,6 +65,7 @@ def lib():
         L.susp_step.argtypes = [vp, C.c_int64]
         L.susp_stress.argtypes = [vp, _PD, _PD]
         L.susp_contact_stats.argtypes = [vp, C.c_int32, _PD, _PD]
+        L.susp_wall_force.argtypes = [vp, _PD]
         L.susp_destroy.argtypes = [vp]
         L.susp_get_populations.argtypes = [vp, _PD]
         L.susp_set_populations.argtypes = [vp, _PD]
@@ -117,16 +119,21 @@ def default_params() -> Params:
     return p
 
 
-def make_params(box, radius=None, pos=None, vel=None, omega=None, precision=FP32, **kw):
-    """Build a Params with the paper's defaults; keyword names follow susp_params."""
+def make_params(box, radius=None, pos=None, vel=None, omega=None, precision=FP32, wall=None, **kw):
+    """Build a Params with the paper's defaults; keyword names follow susp_params (wall: the
+    per-sphere wall membership array for boundary = 1)."""
     p = default_params()
     p.lx, p.ly, p.lz = (int(v) for v in box)
     p.precision = int(precision)
     for k, v in kw.items():
-        if not hasattr(p, k):
+        if not hasattr(p, k) or k == "wall":
             raise KeyError(k)
         setattr(p, k, v)
     keep = []
+    if wall is not None:
+        wall = np.ascontiguousarray(wall, dtype=np.int32)
+        keep.append(wall)
+        p.wall = _pi(wall)
     n = 0 if radius is None else len(radius)
     p.n = n
     if n:
@@ -207,6 +214,12 @@ class Simulation:
         out = np.zeros((5, 6)); gg = np.zeros(2)
         _chk(lib().susp_stress(self.h, _pd(out), _pd(gg)))
         return out, gg
+
+    def wall_force(self):
+        """Mean force per step on the bottom and top walls since the last call (susp_wall_force)."""
+        out = np.zeros(6)
+        _chk(lib().susp_wall_force(self.h, _pd(out)))
+        return out.reshape(2, 3)
 
     def contact_stats(self, nbins):
         """(hist[5][nbins] = rho, xi_N, xi_T, zeta_N, zeta_T; summary[12]) since the last

@@ -1,0 +1,103 @@
+"""GPU parity of the wall geometry (Sec. 3: shear by moving walls of spheres) through the C ABI.
+
+Both sides start from their own creation with the same inputs and step together: plane
+Couette flow between bare walls, and walls carrying layers of spheres with free spheres that
+touch them.  Compared: owner map and spring-history pairs exactly, populations, particle
+states and the force on each wall within 1e-10 in FP64 and 1e-6 (relative) in FP32; graph
+replay bitwise equal to plain launches.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_02929_amd import susp as S
+    from oracle import oracle as O
+    S.lib()
+    return S, O
+
+
+def _config():
+    # the oracle pin's configuration (tests/test_oracle_walls.py)
+    import test_oracle_walls as W
+    return W._wall_config()
+
+
+def _pair(S, O, box, pos, vel, rad, member, prec, gd, tau=0.9):
+    kw = dict(boundary=1, shear_kind=1, gamma_dot=gd, tau=tau)
+    o = O.Oracle(O.make_params(lx=box[0], ly=box[1], lz=box[2], **kw), pos, vel, None, rad,
+                 wall=member)
+    p = S.make_params(box, radius=rad, pos=pos, vel=vel, precision=prec, wall=member, **kw)
+    return o, S.Simulation(p)
+
+
+def _rel(a, b, floor=0.0):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), floor, 1e-300))
+
+
+def test_couette_between_walls_fp64(env):
+    S, O = env
+    print("\n[walls] Couette (8, 32, 8), FP64", flush=True)
+    o, g = _pair(S, O, (8, 32, 8), None, None, None, None, S.FP64, 1e-3, tau=0.8)
+    assert o.step(60) == 0
+    g.step(60)
+    assert _rel(g.get_populations(), o.f) < 1e-13
+    Fo, Fg = o.wall_force(), g.wall_force()
+    assert _rel(Fg, Fo) < 1e-11
+    g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_wall_spheres(env, prec, tol):
+    S, O = env
+    box, pos, rad, member = _config()
+    vel = np.zeros_like(pos)
+    vel[member == 0] = np.random.default_rng(2).uniform(-1e-3, 1e-3, (3, 3))
+    print("\n[walls] %d wall + %d free spheres, box %s, precision %d"
+          % ((member > 0).sum(), (member == 0).sum(), box, prec), flush=True)
+    o, g = _pair(S, O, box, pos, vel, rad, member, prec, 2e-3)
+    seen = False
+    for steps in (3, 3):
+        assert o.step(steps) == 0
+        assert g.step(steps, check=False) == 0
+        assert np.array_equal(g.lists(S.LIST_OWNER), o.own)
+        hi, hj, _ = g.get_history()
+        oi, oj, _ = o.history()
+        assert np.array_equal(hi, oi) and np.array_equal(hj, oj)
+        seen = seen or len(hi) > 0
+        R, U, W, _ = g.get_particles()
+        assert np.abs(R - o.part("R")).max() < max(tol, 1e-12) * 10
+        assert _rel(U, o.part("U"), 1e-6) < tol and _rel(W, o.part("W"), 1e-7) < tol
+        fl = o.own == -1
+        assert _rel(g.get_populations()[:, fl], o.f[:, fl]) < tol
+        Fo, Fg = o.wall_force(), g.wall_force()
+        assert _rel(Fg, Fo) < max(tol, 1e-9) * 10, (Fg, Fo)
+    assert seen  # a free sphere touched a wall sphere
+    g.close()
+
+
+def test_graph_replay_bitwise(env):
+    import torch
+    S, O = env
+    box, pos, rad, member = _config()
+    print("\n[walls] graphs vs plain launches, 20 steps", flush=True)
+    out = []
+    for graphs in (False, True):
+        p = S.make_params(box, radius=rad, pos=pos, precision=S.FP32, wall=member, boundary=1,
+                          shear_kind=2, g0_I=0.05, period=200, ncyc_I=1, ncyc_F=1)
+        if graphs:
+            g = S.Simulation(p, stream=torch.cuda.Stream())
+            g.use_graphs(5)
+        else:
+            g = S.Simulation(p)
+        g.step(20)
+        out.append((g.wall_force(), g.get_particles()[0], g.get_populations()))
+        g.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
