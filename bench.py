@@ -46,6 +46,9 @@ def workload(name):
     if name == "bulk96":
         w = synth.bulk3d(96, 0.55, 1e-3, seed=1)
         return w, "bulk_3d_96cube_phi0.55"
+    if name == "walls256":
+        w = synth.walled3d(256, 0.50, 1e-4, seed=1)
+        return w, "walled_3d_256cube_phi0.50"
     if name == "empty256":
         from paper_1904_02929_amd.synth import Workload
         import numpy as np
@@ -73,7 +76,7 @@ def cpu_baseline(w, steps):
     from oracle import oracle as O
     p = O.make_params(lx=w.box[0], ly=w.box[1], lz=w.box[2], **w.params)
     t0 = time.perf_counter()
-    o = O.Oracle(p, w.pos, w.vel, w.omega, w.radius)
+    o = O.Oracle(p, w.pos, w.vel, w.omega, w.radius, wall=w.wall)
     t1 = time.perf_counter()
     rc = o.step(steps)
     t2 = time.perf_counter()
@@ -94,7 +97,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
-    ap.add_argument("--workload", default="large3d", choices=["large3d", "bulk96", "empty256"])
+    ap.add_argument("--workload", default="large3d", choices=["large3d", "bulk96", "walls256", "empty256"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "multi"],
                     help="eq. 5 as BGK, or the multi-eigenvalue operator (tau_bulk 0.75, "
                          "tau_ghost 1: ghost modes projected out)")
@@ -135,7 +138,7 @@ def main():
     w, wname = workload(args.workload)
     log("workload %s: box %s, %d spheres (%.1f s to generate)" % (wname, w.box, w.n, time.perf_counter() - t))
     p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
-                         precision=PREC[args.precision], contact_bins=args.contact_bins,
+                         precision=PREC[args.precision], contact_bins=args.contact_bins, wall=w.wall,
                          collision=1 if args.collision == "multi" else 0, tau_bulk=0.75, tau_ghost=1.0,
                          **w.params)
     sim = susp.Simulation(p)
@@ -203,7 +206,8 @@ def main():
             "lattice": list(w.box),
             "spheres": int(w.n),
             "radii": [4.5, 6.3] if w.n else [],
-            "phi": 0.55 if w.n else 0.0,
+            "phi": (0.50 if args.workload == "walls256" else 0.55) if w.n else 0.0,
+            "boundary": "walls" if w.params.get("boundary") == 1 else "lees-edwards",
             "shear_rate": w.params.get("gamma_dot"),
             "precision": args.precision,
             "n_sub": int(p.n_sub),

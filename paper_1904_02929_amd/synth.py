@@ -132,6 +132,7 @@ class Workload:
     omega: np.ndarray
     radius: np.ndarray
     params: dict = field(default_factory=dict)
+    wall: np.ndarray = None  # per-sphere wall membership (0 free, 1 bottom, 2 top) with walls
 
     @property
     def n(self):
@@ -184,3 +185,42 @@ def monolayer(L: int, lz: int, phi: float, seed: int, a: float = 4.5, g0_I=0.1, 
     return Workload("monolayer_%d_phi%.2f" % (L, phi), box, pos, vel, om, rad,
                     dict(shear_kind=2, g0_I=g0_I, g0_F=g0_F, theta=theta, period=period,
                          ncyc_I=ncyc_I, ncyc_F=ncyc_F, quasi2d=1))
+
+
+def walled3d(L: int, phi: float, gamma_dot: float, seed: int, a_small=4.5, a_large=6.3,
+             a_wall=4.5, margin: float = 0.1) -> Workload:
+    """Bidisperse 3D suspension sheared by two moving walls of spheres (boundary 1).
+
+    Each wall is a square layer of spheres of radius a_wall, centres 0.6 lattice units plus
+    a_wall from the box face (the pair cutoff is 1), spaced 2 a_wall + 1.2 apart in x and z
+    (rounded to divide L), the top layer shifted by half a spacing in x.  The free spheres
+    fill the gap between the two layers at volume fraction phi of the gap's volume; packed in
+    a box periodic in y, those within margin of the gap's faces are dropped.
+    """
+    rng = np.random.default_rng(seed)
+    box = (L, L, L)
+    yb, yt = a_wall + 0.6, L - a_wall - 0.6
+    nw = max(1, int(L // (2 * a_wall + 1.2)))
+    sp = L / nw
+    wall_pos = []
+    for y, shift, m in ((yb, 0.0, 1), (yt, 0.5 * sp, 2)):
+        for i in range(nw):
+            for k in range(nw):
+                wall_pos.append((((i + 0.5) * sp + shift) % L, y, (k + 0.5) * sp, m))
+    wall_pos = np.array(wall_pos)
+    lo, hi = yb + a_wall + margin, yt - a_wall - margin
+    gap = (L, hi - lo, L)
+    n = count_for_phi3(phi, gap, a_small, a_large)
+    rad = bidisperse_radii(n, a_small, a_large, rng)
+    pos = pack(gap, rad, rng, margin=margin)
+    keep = (pos[:, 1] - rad > margin) & (pos[:, 1] + rad < gap[1] - margin)
+    pos, rad = pos[keep], rad[keep]
+    pos[:, 1] += lo
+    allpos = np.concatenate([wall_pos[:, :3], pos])
+    allrad = np.concatenate([np.full(len(wall_pos), a_wall), rad])
+    wall = np.concatenate([wall_pos[:, 3].astype(np.int32), np.zeros(len(rad), np.int32)])
+    vel, om = affine_start(allpos, allrad, gamma_dot, L)
+    vel[wall > 0] = 0.0
+    om[wall > 0] = 0.0
+    return Workload("walled3d_%d_phi%.2f" % (L, phi), box, allpos, vel, om, allrad,
+                    dict(shear_kind=1, gamma_dot=gamma_dot, boundary=1), wall=wall)

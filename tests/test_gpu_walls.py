@@ -101,3 +101,31 @@ def test_graph_replay_bitwise(env):
         g.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+def test_walled_suspension_128_fp32(env):
+    # a 128^3 suspension between walls of spheres (the measured workload's kind), FP32,
+    # two steps from creation on both sides
+    S, O = env
+    from paper_1904_02929_amd import synth
+    w = synth.walled3d(128, 0.50, 1e-3, seed=2)
+    print("\n[walls] %s: %d spheres (%d in walls)" % (w.box, w.n, (w.wall > 0).sum()), flush=True)
+    kw = dict(w.params)
+    o = O.Oracle(O.make_params(lx=w.box[0], ly=w.box[1], lz=w.box[2], **kw), w.pos, w.vel, w.omega,
+                 w.radius, wall=w.wall)
+    p = S.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega, precision=S.FP32,
+                      wall=w.wall, **kw)
+    g = S.Simulation(p)
+    assert o.step(2) == 0
+    g.step(2)
+    assert np.array_equal(g.lists(S.LIST_OWNER), o.own)
+    R, U, W, _ = g.get_particles()
+    assert np.abs(R - o.part("R")).max() < 1e-8
+    assert _rel(U, o.part("U"), 1e-6) < 1e-5 and _rel(W, o.part("W"), 1e-7) < 1e-5
+    Fo, Fg = o.wall_force(), g.wall_force()
+    assert _rel(Fg, Fo) < 1e-5, (Fg, Fo)
+    so, _ = o.stress()
+    sg, _ = g.stress()
+    for k in range(5):
+        assert _rel(sg[k], so[k], 1e-12) < 1e-5, k
+    g.close()
