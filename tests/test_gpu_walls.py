@@ -129,3 +129,34 @@ def test_walled_suspension_128_fp32(env):
     for k in range(5):
         assert _rel(sg[k], so[k], 1e-12) < 1e-5, k
     g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 2e-3)])
+def test_walls_with_multi_eigenvalue_and_contact_statistics(env, prec, tol):
+    # the three added options together: walls of spheres, the multi-eigenvalue collision
+    # and the contact statistics, FP32 and FP16 storage, four steps from creation
+    S, O = env
+    box, pos, rad, member = _config()
+    vel = np.zeros_like(pos)
+    vel[member == 0] = np.random.default_rng(5).uniform(-1e-3, 1e-3, (3, 3))
+    kw = dict(boundary=1, shear_kind=2, g0_I=0.05, period=400, ncyc_I=1, ncyc_F=1, tau=0.8,
+              collision=1, tau_bulk=0.7, tau_ghost=1.1, contact_bins=18)
+    print("\n[walls] walls + multi-eigenvalue + contact statistics, precision %d" % prec, flush=True)
+    o = O.Oracle(O.make_params(lx=box[0], ly=box[1], lz=box[2], **kw), pos, vel, None, rad, wall=member)
+    p = S.make_params(box, radius=rad, pos=pos, vel=vel, precision=prec, wall=member, **kw)
+    g = S.Simulation(p)
+    assert o.step(4) == 0
+    assert g.step(4, check=False) == 0
+    assert np.array_equal(g.lists(S.LIST_OWNER), o.own)
+    R, U, W, _ = g.get_particles()
+    assert _rel(U, o.part("U"), 1e-6) < tol and _rel(W, o.part("W"), 1e-7) < tol
+    assert _rel(g.wall_force(), o.wall_force()) < tol * 10
+    ho, so = o.contact_stats(18)
+    hg, sg = g.contact_stats(18)
+    assert so[0] == sg[0] == 4 and so[1] == sg[1]
+    assert np.array_equal(np.rint(ho[0] * so[1] * 4 * np.pi / 18), np.rint(hg[0] * sg[1] * 4 * np.pi / 18))
+    sgo, _ = o.stress()
+    sgg, _ = g.stress()
+    for k in range(5):
+        assert _rel(sgg[k], sgo[k], 1e-12) < tol * 10, k
+    g.close()
