@@ -9,15 +9,18 @@ workloads and stores block averages of the stress (eq. 15) and the accumulated G
               averaged over blocks of 500 steps from step 2,000 (strain 2 to 8).  (At
               phi = 0.55 and this rate the default contact stiffness lets mapped spheres
               overlap after about 3,000 steps.)
-  mono256     256^2 x 10 monolayer of a = 4.5 spheres at area fraction 0.70 under
-              oscillatory shear (eq. 16), period 2,000 steps, 2 initial cycles at
-              strain amplitude 0.05 then 2 observation cycles at 0.01, Theta = 0,
-              seed 1; G', G'' after each observation cycle and the stress per 500-step block.
-              (At area fraction 0.75 some trajectories of the explicit particle update reach
-              a period-2 oscillation of a touching pair's hydrodynamic force and spin that
-              grows until the run fails, near step 9,400.)
+  mono256     256^2 x 10 monolayers of a = 4.5 spheres at area fraction 0.70 under
+              oscillatory shear (eq. 16), period 1,000 steps, 2 initial cycles at strain
+              amplitude 0.05 then 3 observation cycles at 0.01, Theta = 0; an ensemble of
+              three packings (seeds 1, 2, 3; Sec. 4.1 averages three ensembles); G', G''
+              after each observation cycle and the stress per 500-step block, per seed.
+              (Single cycles scatter by tens of percent at this amplitude, so the comparison
+              needs several of them; a single longer run is not an option because some
+              trajectories of the explicit particle update reach a period-2 oscillation of a
+              touching pair's hydrodynamic force and spin that grows until the run fails,
+              seen after about 9,000 steps.)
 
-Usage:  python tests/golden/make_longrun.py [bulk96|mono256 ...]   (about 17 + 15 minutes on
+Usage:  python tests/golden/make_longrun.py [bulk96|mono256 ...]   (about 17 + 25 minutes on
 8 cores).  Writes tests/golden/longrun_<name>.json.
 """
 import json
@@ -40,14 +43,33 @@ def workload(name):
         w = synth.bulk3d(96, 0.45, 1e-3, seed=1)
         return w, dict(total=8000, start=2000, block=500, cycles=None)
     if name == "mono256":
-        w = synth.monolayer(256, 10, 0.70, seed=1, g0_I=0.05, g0_F=0.01, theta=0.0, period=2000,
-                            ncyc_I=2, ncyc_F=2)
-        return w, dict(total=8000, start=4000, block=500, cycles=(4000, 2000, 2))
+        return [mono256(seed) for seed in MONO_SEEDS]
     raise ValueError(name)
 
 
+MONO_SEEDS = (1, 2, 3)
+
+
+def mono256(seed):
+    w = synth.monolayer(256, 10, 0.70, seed=seed, g0_I=0.05, g0_F=0.01, theta=0.0, period=1000,
+                        ncyc_I=2, ncyc_F=3)
+    return w, dict(total=5000, start=2000, block=500, cycles=(2000, 1000, 3))
+
+
 def run(name):
-    w, plan = workload(name)
+    if name == "mono256":
+        runs = [run_one("%s seed %d" % (name, sd), w, plan, sd)
+                for sd, (w, plan) in zip(MONO_SEEDS, workload(name))]
+        out = dict(name="monolayer_256_phi0.70", seeds=list(MONO_SEEDS), runs=runs,
+                   components=runs[0]["components"])
+    else:
+        w, plan = workload(name)
+        out = run_one(name, w, plan, 1)
+    with open(os.path.join(HERE, "longrun_%s.json" % name), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
+def run_one(name, w, plan, seed):
     p = O.make_params(lx=w.box[0], ly=w.box[1], lz=w.box[2],
                       **{k: v for k, v in w.params.items() if k in KEYS})
     o = O.Oracle(p, w.pos, w.vel, w.omega, w.radius)
@@ -70,12 +92,10 @@ def run(name):
             gg_after.append(gg.tolist())
         print("%s step %d  sigma_xy(total) %.6e  %.0f s" % (name, step, sig[:, 3].sum(), time.time() - t0),
               flush=True)
-    out = dict(name=w.name, box=list(w.box), n=int(len(w.radius)), params=w.params,
-               seed=1, steps=plan["total"], start=plan["start"], block=plan["block"],
-               components="fluid, particle surface, lubrication, contact, DLVO; xx yy zz xy xz yz",
-               block_stress=blocks, gg_after_cycle=gg_after, oracle_seconds=time.time() - t0)
-    with open(os.path.join(HERE, "longrun_%s.json" % name), "w") as fh:
-        json.dump(out, fh, indent=1)
+    return dict(name=w.name, box=list(w.box), n=int(len(w.radius)), params=w.params,
+                seed=seed, steps=plan["total"], start=plan["start"], block=plan["block"],
+                components="fluid, particle surface, lubrication, contact, DLVO; xx yy zz xy xz yz",
+                block_stress=blocks, gg_after_cycle=gg_after, oracle_seconds=time.time() - t0)
 
 
 if __name__ == "__main__":

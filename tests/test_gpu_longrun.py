@@ -5,7 +5,7 @@ compared through statistics: the time-averaged shear stress <sigma_xy> (eq. 15, 
 parts) of a 3D bulk suspension under simple shear, and G', G'' (eqs. 17-18) of a monolayer
 under oscillatory shear.  Bar: |gpu - oracle| <= 2 % of |oracle| + 2 standard errors, the
 standard errors from block averages (500-step blocks for the stress, one value per
-observation cycle for G', G'').  The oracle's values are written by
+observation cycle for G', G'': three cycles in each of three packings).  The oracle's values are written by
 tests/golden/make_longrun.py (oracle only) into tests/golden/longrun_*.json.
 """
 import json
@@ -75,6 +75,13 @@ def _sxy(blocks):
     return [sum(b[k][3] for k in range(5)) for b in blocks]
 
 
+def _per_cycle(avg):
+    """Per-cycle G', G'' from the running averages after 1, 2, ... observation cycles."""
+    k = np.arange(1, len(avg) + 1, dtype=float)[:, None]
+    tot = k * avg
+    return np.concatenate([tot[:1], np.diff(tot, axis=0)])
+
+
 def test_bulk_shear_stress(susp):
     gold = _golden("bulk96")
     w, plan = _workload("bulk96")
@@ -89,21 +96,28 @@ def test_bulk_shear_stress(susp):
 
 def test_monolayer_moduli(susp):
     gold = _golden("mono256")
-    w, plan = _workload("mono256")
-    print("\n[longrun] monolayer %s, %d spheres, %d steps" % (w.box, len(w.radius), plan["total"]), flush=True)
-    blocks, gg = _run(susp, w, plan)
-    go = np.asarray(gold["gg_after_cycle"])
-    gg = np.asarray(gg)
-    assert go.shape == gg.shape == (2, 2)
-    # per-cycle values from the running averages after one and two cycles
-    co = np.stack([go[0], 2 * go[1] - go[0]])
-    cg = np.stack([gg[0], 2 * gg[1] - gg[0]])
+    ws = _workload("mono256")
+    co, cg, so_, sg_ = [], [], [], []
+    for (w, plan), run in zip(ws, gold["runs"]):
+        print("\n[longrun] monolayer %s, %d spheres, %d steps, seed %d"
+              % (w.box, len(w.radius), plan["total"], run["seed"]), flush=True)
+        blocks, gg = _run(susp, w, plan)
+        go = np.asarray(run["gg_after_cycle"])
+        gg = np.asarray(gg)
+        ncyc = plan["cycles"][2]
+        assert go.shape == gg.shape == (ncyc, 2)
+        co.append(_per_cycle(go))
+        cg.append(_per_cycle(gg))
+        so_ += _sxy(run["block_stress"])
+        sg_ += _sxy(blocks)
+    co, cg = np.concatenate(co), np.concatenate(cg)
     for k, name in enumerate(("G'", "G''")):
         mo, so = _mean_se(co[:, k])
         mg, sg = _mean_se(cg[:, k])
         se = math.hypot(so, sg)
-        print("[longrun] %s oracle %.6e +- %.1e, gpu %.6e +- %.1e" % (name, mo, so, mg, sg), flush=True)
+        print("[longrun] %s oracle %.6e +- %.1e, gpu %.6e +- %.1e (%d cycles)"
+              % (name, mo, so, mg, sg, len(co)), flush=True)
         assert abs(mg - mo) <= 0.02 * abs(mo) + 2 * se
-    mo, so = _mean_se(_sxy(gold["block_stress"]))
-    mg, sg = _mean_se(_sxy(blocks))
+    mo, _ = _mean_se(so_)
+    mg, _ = _mean_se(sg_)
     print("[longrun] <sigma_xy> oracle %.6e, gpu %.6e" % (mo, mg), flush=True)
