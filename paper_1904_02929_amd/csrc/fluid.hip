@@ -182,6 +182,15 @@ template <> struct RowIO<__half> {
     const __half hv = __float2half_rn(v * ((float)(1.0 / wq(q)) * h.up));
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hv), r, off, 0, 0);
   }
+  // the lattice kernel keeps the 16 stored bits in a float register until the value is
+  // used (a step later), so that the conversion does not wait for the load
+  __device__ static float raw(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+  }
+  __device__ static float dec(float v, int q, H16 h) {
+    const unsigned short b = (unsigned short)__builtin_bit_cast(uint32_t, v);
+    return __half2float(__builtin_bit_cast(__half, b)) * ((float)wq(q) * h.dn);
+  }
 };
 
 // Wait here for every outstanding vector-memory access (s_waitcnt vmcnt(0); expcnt and
@@ -417,6 +426,7 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
   // 4-byte arithmetic: sphere states in LDS, FP32 stress partials; FP64: states read from
   // memory, FP64 partials (the LDS budget of two work-groups per compute unit)
   constexpr bool PF = sizeof(CT) == 4;
+  constexpr bool DEFER = std::is_same<ST, __half>::value;  // FP16 storage: convert at use
   using PT = typename std::conditional<PF, float, double>::type;
   __shared__ double sdat[PF ? TSLOT : 1][SDAT];  // R, U, W of each table entry
   __shared__ double sval[4][TSLOT][HYD];  // one copy per wave: a fixed summation order
@@ -464,7 +474,8 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
     const uint32_t pb = (uint32_t)opaque_uniform((int)(plane * es));  // plane stride, bytes
     const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
     const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
-    dst[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
+    if constexpr (DEFER) dst[0] = RowIO<ST>::raw(rin, rowc + xcb);
+    else dst[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
     // one load per direction, no branch (a pull across a sliding plane reads some row of
     // the array, or nothing, and is replaced below)
 #pragma unroll
@@ -475,7 +486,8 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
       const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
       const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
       const uint32_t pull_off = q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb;
-      dst[q] = RowIO<ST>::ld(rin, lq ? own_off : pull_off, q, A.h16);
+      if constexpr (DEFER) dst[q] = RowIO<ST>::raw(rin, lq ? own_off : pull_off);
+      else dst[q] = RowIO<ST>::ld(rin, lq ? own_off : pull_off, q, A.h16);
     }
     if (y == 0 || y == ly - 1) {  // uniform: directions across the sliding plane read the
                                   // Lees-Edwards ghost row (these rows do not overlap)
@@ -490,6 +502,10 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
         }
       }
       vm_settle();
+      if constexpr (DEFER) {  // an edge row's node is converted here, whole
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) dst[q] = RowIO<ST>::dec(dst[q], q, A.h16);
+      }
 #pragma unroll
       for (int q = 1; q < NQ; ++q) {
         if (cy(q) == (side == 0 ? 1 : -1)) {
@@ -538,6 +554,12 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
       for (int q = 0; q < NQ; ++q) pn[q] = 0;  // (the old values are dead on every path)
     }
     if (fl) {
+      if constexpr (DEFER) {  // the stored 16 bits to values (edge rows: done at the load)
+        if (!(y == 0 || y == ly - 1)) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) n[q] = RowIO<ST>::dec(n[q], q, A.h16);
+        }
+      }
       const int x = V.xc;
       const bool done = for_each_sphere(sm, s0, sp, cen, all, ph, [&](int p, uint32_t m) {
         // the sphere's state: from the brick's table, else (not listed) from memory
