@@ -377,6 +377,34 @@ __device__ inline bool for_each_sphere(const int32_t *sm, const int32_t *s0, con
   return rem == 0;
 }
 
+// Number of set bits of m below this lane; position of the r-th (from 0) set bit of m.
+__device__ inline int lane_rank(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ inline int nth_bit(uint64_t m, int r) {
+  int pos = 0;
+  const int c = __builtin_popcount((uint32_t)m);
+  if (r >= c) { r -= c; m >>= 32; pos = 32; }
+  uint32_t v = (uint32_t)m;
+#pragma unroll
+  for (int w = 16; w >= 1; w >>= 1) {
+    const int c2 = __builtin_popcount(v & ((1u << w) - 1u));
+    if (r >= c2) { r -= c2; v >>= w; pos += w; }
+  }
+  return pos;
+}
+// The value v of lane src (a 32-bit lane permute through LDS hardware; no LDS storage).
+__device__ inline int lane_pull(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+__device__ inline float lane_pull(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+__device__ inline double lane_pull(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)u);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Directions q whose component k (0 x, 1 y, 2 z) of c_q equals sgn, as a bit mask.
 __host__ __device__ constexpr uint32_t dir_mask(int k, int sgn) {
   uint32_t m = 0;
@@ -553,15 +581,16 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) pn[q] = 0;  // (the old values are dead on every path)
     }
-    if (fl) {
-      if constexpr (DEFER) {  // the stored 16 bits to values (edge rows: done at the load)
-        if (!(y == 0 || y == ly - 1)) {
+    if constexpr (DEFER) {  // the stored 16 bits to values (edge rows: done at the load)
+      if (fl && !(y == 0 || y == ly - 1)) {
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) n[q] = RowIO<ST>::dec(n[q], q, A.h16);
-        }
+        for (int q = 0; q < NQ; ++q) n[q] = RowIO<ST>::dec(n[q], q, A.h16);
       }
-      const int x = V.xc;
-      const bool done = for_each_sphere(sm, s0, sp, cen, all, ph, [&](int p, uint32_t m) {
+    }
+    // bounce-back and link sums of sphere p over the links m of the node in column x (the
+    // lane's own node, or, for a helper lane, the node it was handed); live: the node is
+    // not a copy, so its sums count
+    auto body = [&](int p, uint32_t m, int x, bool live) __attribute__((always_inline)) {
         // the sphere's state: from the brick's table, else (not listed) from memory
         const int slot = table_find(skey, p);
         double Rx, Ry, Rz, U0, U1, U2, w0, w1, w2;
@@ -663,8 +692,85 @@ __global__ __launch_bounds__(256, 2) void k_lbm(LbmArgs A) {
             for (int c = 0; c < HYD; ++c) unsafeAtomicAdd(&A.hyd_fb[(size_t)p * HYD + c], v[c]);
           }
         }
-      });
-      if (!done && live) atomicOr(A.flags, 8);
+    };
+    if constexpr (PF) {
+      // The node's first sphere (ph) and second sphere (p2) with their links m1, m2.  Nearly
+      // every row has some node between two spheres, and a second pass over the links
+      // would cost the whole wave a pass; instead each second sphere is handed to a lane of
+      // the wave whose own node is solid (its registers are free): it takes the node's
+      // populations, runs the same pass beside the first spheres and hands the corrected
+      // ones back.  Third spheres, and second spheres left over when the wave has too few
+      // solid nodes, take further passes.  The assignment depends only on the row's
+      // geometry, so the sums stay bitwise reproducible.
+      uint32_t m1 = 0, m2 = 0;
+      int p2 = -1;
+      if (fl && all) {
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+          const int o = src_owner(q, sm, s0, sp, cen);
+          if (o == ph) m1 |= 1u << q;
+          else if (o >= 0) p2 = max(p2, o);
+        }
+        if (p2 >= 0) {
+#pragma unroll
+          for (int q = 1; q < NQ; ++q) m2 |= src_owner(q, sm, s0, sp, cen) == p2 ? 1u << q : 0u;
+        }
+      }
+      const bool needs = p2 >= 0;
+      const uint64_t needm = __builtin_amdgcn_ballot_w64(needs), helpm = __builtin_amdgcn_ballot_w64(!fl);
+      const int nneed = __builtin_popcountll(needm), nhelp = __builtin_popcountll(helpm);
+      const int rneed = lane_rank(needm), rhelp = lane_rank(helpm);
+      const bool task = !fl && rhelp < nneed;       // a solid lane with a handed-over node
+      const bool handed = needs && rneed < nhelp;   // a node whose second sphere was handed over
+      const int src = task ? nth_bit(needm, rhelp) : lane;
+      const int hlp = handed ? nth_bit(helpm, rneed) : lane;
+      const int tp = lane_pull(p2, src), tx = lane_pull((int)V.xc, src), tl = lane_pull((int)live, src);
+      const uint32_t tm = (uint32_t)lane_pull((int)m2, src);
+#pragma unroll
+      for (int q = 1; q < NQ; ++q) {
+        const CT v = lane_pull(n[q], src);
+        n[q] = task ? v : n[q];
+      }
+      int pp = fl ? ph : (task ? tp : -1);
+      uint32_t mm = fl ? m1 : tm;
+      int xx = fl ? (int)V.xc : tx;
+      bool lv = fl ? live : (task && tl != 0);
+      uint32_t lrem = fl ? (all & ~m1 & ~(handed ? m2 : 0u)) : 0u;  // links of later passes
+      for (int it = 0; it < 6; ++it) {
+        if (it > 0) {  // the next sphere among the remaining links (largest id first)
+          int pnx = -1;
+#pragma unroll
+          for (int q = 1; q < NQ; ++q) {
+            const int o = src_owner(q, sm, s0, sp, cen);
+            pnx = (lrem >> q) & 1u ? max(pnx, o) : pnx;
+          }
+          uint32_t mn = 0;
+#pragma unroll
+          for (int q = 1; q < NQ; ++q) mn |= ((lrem >> q) & 1u) && src_owner(q, sm, s0, sp, cen) == pnx ? 1u << q : 0u;
+          pp = lrem ? pnx : -1;
+          mm = mn;
+          xx = (int)V.xc;
+          lv = live;
+          lrem &= ~mn;
+        }
+        if (pp >= 0 && mm) body(pp, mm, xx, lv);
+        if (it == 0) {  // the handed-over nodes' corrected populations go back
+#pragma unroll
+          for (int q = 1; q < NQ; ++q) {
+            const CT v = lane_pull(n[q], hlp);
+            n[q] = handed && ((m2 >> q) & 1u) ? v : n[q];
+          }
+        }
+        if (__builtin_amdgcn_ballot_w64(lrem != 0) == 0) break;
+      }
+      if (lrem != 0 && live) atomicOr(A.flags, 8);
+    }
+    if (fl) {
+      if constexpr (!PF) {
+        const bool done = for_each_sphere(sm, s0, sp, cen, all, ph,
+                                          [&](int p, uint32_t m) { body(p, m, (int)V.xc, live); });
+        if (!done && live) atomicOr(A.flags, 8);
+      }
       // ---- moments and BGK collision on the deviations d_q = n_q - w_q rho0, opposite
       //      directions paired: feq_q,qbar = w (a + 4.5 rho cu^2) +- 3 w rho cu ----
       CT rd = n[0], jx = 0, jy = 0, jz = 0;
