@@ -45,7 +45,7 @@ class Params(C.Structure):
         ("wall_y", C.c_int32), ("wall_u_bot", C.c_double), ("wall_u_top", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
         ("contact_bins", C.c_int32), ("collision", C.c_int32), ("tau_bulk", C.c_double),
-        ("tau_ghost", C.c_double), ("boundary", C.c_int32),
+        ("tau_ghost", C.c_double), ("lub_implicit", C.c_int32), ("boundary", C.c_int32),
     ]
 
 
@@ -114,6 +114,10 @@ def lib():
         L.orc_wall_speed.argtypes = [C.POINTER(Params), C.c_int64]
         L.orc_wall_speed.restype = C.c_double
         L.orc_wall_force.argtypes = [C.POINTER(Sim), _PD]
+        L.orc_lub_squeeze.argtypes = [C.POINTER(Params), C.POINTER(Derived), C.c_double, C.c_double, _PD]
+        L.orc_lub_squeeze.restype = C.c_double
+        L.orc_implicit_solve.argtypes = [C.c_int32, _PD, _PI, _PD, C.c_int32, _PI, _PI, _PD, _PD, _PD,
+                                         C.c_double, C.c_int32, _PD]
         _lib = L
     return _lib
 
@@ -131,7 +135,7 @@ DEFAULTS = dict(
     lub_delta=-1.0, lub_hc=0.5, lub_subtract_hc=1, F0=-1.0, debye_lambda=-1.0, pair_cutoff=1.0,
     n_sub=8, quasi2d=0, shear_kind=0, gamma_dot=0.0, g0_I=0.0, g0_F=0.0, period=1, theta=0.0,
     ncyc_I=0, ncyc_F=0, wall_y=0, wall_u_bot=0.0, wall_u_top=0.0, gx=0.0, gy=0.0, gz=0.0,
-    contact_bins=0, collision=0, tau_bulk=1.0, tau_ghost=1.0, boundary=0,
+    contact_bins=0, collision=0, tau_bulk=1.0, tau_ghost=1.0, lub_implicit=0, boundary=0,
 )
 
 
@@ -206,6 +210,25 @@ def dlvo(params, derived, ai, aj, d):
     Fi = np.zeros(3)
     lib().orc_dlvo(C.byref(params), C.byref(derived), float(ai), float(aj), _pd(_v3(d)), _pd(Fi))
     return Fi
+
+
+def lub_squeeze(params, derived, ai, aj, d):
+    return lib().orc_lub_squeeze(C.byref(params), C.byref(derived), float(ai), float(aj), _pd(_v3(d)))
+
+
+def implicit_solve(m, fixed, b, pi, pj, zeta, nvec, shift, dt, sweeps, U0):
+    """The substep's velocities with implicit squeeze terms (orc_implicit_solve)."""
+    m = np.ascontiguousarray(m, np.float64); n = len(m)
+    fixed = np.ascontiguousarray(fixed, np.int32)
+    b = np.ascontiguousarray(b, np.float64).reshape(n, 3)
+    pi = np.ascontiguousarray(pi, np.int32); pj = np.ascontiguousarray(pj, np.int32)
+    zeta = np.ascontiguousarray(zeta, np.float64)
+    nvec = np.ascontiguousarray(nvec, np.float64).reshape(-1, 3)
+    shift = np.ascontiguousarray(shift, np.float64).reshape(-1, 3)
+    U = np.ascontiguousarray(U0, np.float64).reshape(n, 3).copy()
+    lib().orc_implicit_solve(n, _pd(m), _pi(fixed), _pd(b), len(pi), _pi(pi), _pi(pj), _pd(zeta),
+                             _pd(nvec), _pd(shift), float(dt), int(sweeps), _pd(U))
+    return U
 
 
 def wall_speed(params: Params, t: int) -> float:

@@ -855,6 +855,76 @@ static void uncover_fn(orc_sim *S, int p, int64_t node, int x, int y, int z, voi
 static int finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 
 /* ---------------- the full step ---------------- */
+/* Squeeze coefficient of the pair (the X^A term of the force on i in orc_lubrication). */
+double orc_lub_squeeze(const orc_params *p, const orc_derived *d, double ai, double aj,
+                       const double dv[3]) {
+  double r = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  double h = r - ai - aj;
+  if (!(h < p->lub_hc)) return 0.0;
+  double hh = h > 0.0 ? h : 0.0;
+  double xg = 2.0 * (hh + d->lub_delta) / (ai + aj);
+  double inv = 1.0 / xg, lg = log(1.0 / xg);
+  if (p->lub_subtract_hc) {
+    double xc = 2.0 * (p->lub_hc + d->lub_delta) / (ai + aj);
+    inv = inv - 1.0 / xc;
+    lg = lg - log(1.0 / xc);
+  }
+  lubfun fi = lub_block(ai, aj / ai, inv, lg);
+  return d->eta0 * fi.XA;
+}
+
+/* x = A^-1 r for a symmetric positive definite 3x3 A (Cramer's rule). */
+static void solve3(const double A[3][3], const double r[3], double x[3]) {
+  double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+  double inv[3][3] = {
+      {c00, A[0][2] * A[2][1] - A[0][1] * A[2][2], A[0][1] * A[1][2] - A[0][2] * A[1][1]},
+      {c01, A[0][0] * A[2][2] - A[0][2] * A[2][0], A[0][2] * A[1][0] - A[0][0] * A[1][2]},
+      {c02, A[0][1] * A[2][0] - A[0][0] * A[2][1], A[0][0] * A[1][1] - A[0][1] * A[1][0]}};
+  for (int a = 0; a < 3; ++a) x[a] = (inv[a][0] * r[0] + inv[a][1] * r[1] + inv[a][2] * r[2]) / det;
+}
+
+void orc_implicit_solve(int32_t n, const double *m, const int32_t *fixed, const double *b,
+                        int32_t npairs, const int32_t *pi, const int32_t *pj, const double *zeta,
+                        const double *nv, const double *sh, double dt, int32_t sweeps, double *U) {
+  double *A = (double *)xcalloc(9 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  double *r = (double *)xcalloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  double *Un = (double *)xcalloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  for (int s = 0; s < sweeps; ++s) {
+    for (int i = 0; i < n; ++i) {
+      for (int c = 0; c < 9; ++c) A[9 * i + c] = (c % 4 == 0) ? m[i] : 0.0;
+      for (int c = 0; c < 3; ++c) r[3 * i + c] = b[3 * i + c];
+    }
+    for (int k = 0; k < npairs; ++k) {
+      int i = pi[k], j = pj[k];
+      const double *nk = &nv[3 * k], *sk = &sh[3 * k];
+      double w = dt * zeta[k];
+      /* row i: the partner's image moves at U_j + s_k; row j: the partner at U_i - s_k */
+      double uj = nk[0] * (U[3 * j] + sk[0]) + nk[1] * (U[3 * j + 1] + sk[1]) + nk[2] * (U[3 * j + 2] + sk[2]);
+      double ui = nk[0] * (U[3 * i] - sk[0]) + nk[1] * (U[3 * i + 1] - sk[1]) + nk[2] * (U[3 * i + 2] - sk[2]);
+      for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c) {
+          A[9 * i + 3 * a + c] += w * nk[a] * nk[c];
+          A[9 * j + 3 * a + c] += w * nk[a] * nk[c];
+        }
+        r[3 * i + a] += w * nk[a] * uj;
+        r[3 * j + a] += w * nk[a] * ui;
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      if (fixed && fixed[i]) { for (int c = 0; c < 3; ++c) Un[3 * i + c] = U[3 * i + c]; continue; }
+      double Ai[3][3] = {{A[9 * i], A[9 * i + 1], A[9 * i + 2]},
+                         {A[9 * i + 3], A[9 * i + 4], A[9 * i + 5]},
+                         {A[9 * i + 6], A[9 * i + 7], A[9 * i + 8]}};
+      solve3(Ai, &r[3 * i], &Un[3 * i]);
+    }
+    memcpy(U, Un, 3 * sizeof(double) * (size_t)n);
+  }
+  free(A); free(r); free(Un);
+}
+
 /* ---------------- contact statistics (Sec. 4.2, eqs. 19-23) ----------------
  * A contact is a pair whose surfaces overlap at the last DEM substep of a step; dv = R_i - R_j
  * (minimum image), Fn and Fc the normal and the total contact force on i at that substep.
@@ -942,9 +1012,20 @@ static void one_step(orc_sim *S) {
   double sc[6] = {0}, sr[6] = {0}, sl[6] = {0};
   const int ns = P->n_sub;
   const double dts = 1.0 / (double)ns;
+  /* implicit squeeze terms: per pair zeta, n, image shift; per sphere the squeeze force at
+   * the old velocities (for the explicit first guess) */
+  const int imp = P->lub_implicit > 0;
+  double *zk = (double *)xcalloc(npp, sizeof(double));
+  double *nk = (double *)xcalloc(3 * npp, sizeof(double));
+  double *sk = (double *)xcalloc(3 * npp, sizeof(double));
+  double *Fq = (double *)xcalloc(3 * npa, sizeof(double));
+  double *bq = (double *)xcalloc(3 * npa, sizeof(double));
+  double *Uq = (double *)xcalloc(3 * npa, sizeof(double));
+  int32_t *fixq = (int32_t *)xcalloc(npa, sizeof(int32_t));
   for (int sub = 0; sub < ns; ++sub) {
     memset(Fp, 0, 3 * sizeof(double) * npa);
     memset(Tp, 0, 3 * sizeof(double) * npa);
+    memset(Fq, 0, 3 * sizeof(double) * npa);
     for (int k = 0; k < S->npairs; ++k) {
       int i = S->pi[k], j = S->pj[k];
       double d[3]; int32_t kk;
@@ -958,8 +1039,20 @@ static void one_step(orc_sim *S) {
       if (P->contact_bins > 0 && sub == ns - 1 && pon[k]) contact_sample(S, d, Fn, Fc);
       orc_dlvo(P, &S->d, S->a[i], S->a[j], d, Fr);
       orc_lubrication(P, &S->d, S->a[i], S->a[j], d, Ui, Uj, Wi, Wj, Fl, Tli, Tlj, Si, Sj);
+      double Fs[3] = {0.0, 0.0, 0.0};
+      if (imp) {
+        /* the squeeze part of Fl, -zeta n (n . (U_i - U_j)), leaves the explicit sum */
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double nn[3] = {d[0] / r, d[1] / r, d[2] / r};
+        double z = orc_lub_squeeze(P, &S->d, S->a[i], S->a[j], d);
+        double un = nn[0] * (Ui[0] - Uj[0]) + nn[1] * (Ui[1] - Uj[1]) + nn[2] * (Ui[2] - Uj[2]);
+        zk[k] = z;
+        for (int c = 0; c < 3; ++c) { nk[3 * k + c] = nn[c]; Fs[c] = -z * un * nn[c]; }
+        sk[3 * k] = kk * ule; sk[3 * k + 1] = 0.0; sk[3 * k + 2] = 0.0;
+        for (int c = 0; c < 3; ++c) { Fq[3 * i + c] += Fs[c]; Fq[3 * j + c] -= Fs[c]; }
+      }
       for (int c = 0; c < 3; ++c) {
-        double F = Fc[c] + Fr[c] + Fl[c];
+        double F = Fc[c] + Fr[c] + (Fl[c] - Fs[c]);
         Fp[3 * i + c] += F; Fp[3 * j + c] -= F;
         Tp[3 * i + c] += Tci[c] + Tli[c];
         Tp[3 * j + c] += Tcj[c] + Tlj[c];
@@ -968,6 +1061,19 @@ static void one_step(orc_sim *S) {
       sym6(d, Fc, -0.5 / V, sc);
       sym6(d, Fr, -0.5 / V, sr);
       for (int c = 0; c < 6; ++c) sl[c] += (Si[c] + Sj[c]) / V;
+    }
+    if (imp) {
+      /* m U' + dt sum zeta n n . (U' - U'_j) = m U + dt (F^h + explicit pair forces),
+       * started from the explicit update */
+      for (int i = 0; i < np; ++i) {
+        fixq[i] = walls && S->wall[i] > 0;
+        for (int c = 0; c < 3; ++c) {
+          bq[3 * i + c] = S->m[i] * S->U[3 * i + c] + dts * (S->Fh[3 * i + c] + Fp[3 * i + c]);
+          Uq[3 * i + c] = fixq[i] ? S->U[3 * i + c]
+                                  : S->U[3 * i + c] + dts * (S->Fh[3 * i + c] + Fp[3 * i + c] + Fq[3 * i + c]) / S->m[i];
+        }
+      }
+      orc_implicit_solve(np, S->m, fixq, bq, S->npairs, S->pi, S->pj, zk, nk, sk, dts, P->lub_implicit, Uq);
     }
     for (int i = 0; i < np; ++i) {
       double *U = &S->U[3 * i], *W = &S->W[3 * i], *R = &S->R[3 * i];
@@ -980,7 +1086,7 @@ static void one_step(orc_sim *S) {
         continue;
       }
       for (int c = 0; c < 3; ++c) {
-        U[c] += dts * (S->Fh[3 * i + c] + Fp[3 * i + c]) / S->m[i];
+        U[c] = imp ? Uq[3 * i + c] : U[c] + dts * (S->Fh[3 * i + c] + Fp[3 * i + c]) / S->m[i];
         W[c] += dts * (S->Th[3 * i + c] + Tp[3 * i + c]) / S->I[i];
       }
       if (P->quasi2d) { U[2] = 0.0; W[0] = 0.0; W[1] = 0.0; }
@@ -990,6 +1096,7 @@ static void one_step(orc_sim *S) {
   }
   free(Fp);
   free(Tp);
+  free(zk); free(nk); free(sk); free(Fq); free(bq); free(Uq); free(fixq);
   /* surviving contacts become the new history (already in (i,j) order) */
   int nh = 0;
   for (int k = 0; k < S->npairs; ++k) nh += pon[k] ? 1 : 0;

@@ -51,6 +51,9 @@ typedef struct {
                                   -1/tau_bulk (trace of the stress), -1/tau_ghost (the
                                   nine non-hydrodynamic modes)                          */
   double tau_bulk, tau_ghost;
+  int32_t lub_implicit;        /* 0: every pair force explicit in each substep; K > 0: the
+                                  normal squeeze term of the lubrication force taken at the
+                                  new velocities, solved by K Jacobi sweeps              */
   int32_t boundary;            /* 0: Lees-Edwards in y; 1: walls (Sec. 3): flat walls at
                                   y = -1/2 and ly - 1/2 moving at -/+ U_w(t) in x, carrying
                                   layers of wall spheres that move with them              */
@@ -144,6 +147,18 @@ double orc_wall_speed(const orc_params *p, int64_t t);
  * reset: out = {bottom x y z, top x y z}.  The flat-wall part is measured from the rest
  * state rho0 (like the link sums).                                                        */
 void orc_wall_force(orc_sim *s, double out[6]);
+/* Normal squeeze coefficient zeta = eta0 X^A of the lubrication force on i (App. A), so that
+ * its squeeze part is -zeta n (n . (U_i - U_j)); 0 beyond lub_hc.                         */
+double orc_lub_squeeze(const orc_params *p, const orc_derived *d, double ai, double aj,
+                       const double dvec[3]);
+/* Velocities of one substep with the squeeze terms implicit: m_i U_i + dt sum_k zeta_k n_k
+ * n_k . (U_i - U_j - s_k) = b_i for every free sphere i (pair k = (i, j), s_k the velocity
+ * shift of j's image, the force on j opposite); fixed spheres keep U.  U holds the starting
+ * guess and receives the result of `sweeps` Jacobi sweeps (3x3 solves per sphere).        */
+void orc_implicit_solve(int32_t n, const double *m, const int32_t *fixed, const double *b,
+                        int32_t npairs, const int32_t *pi, const int32_t *pj, const double *zeta,
+                        const double *nvec, const double *shift, double dt, int32_t sweeps,
+                        double *U);
 /* Eigenvalues of a symmetric 3x3 matrix (xx yy zz xy xz yz), descending (Jacobi). */
 void orc_sym3_eigen(const double a[6], double ev[3]);
 /* LE protocol at step t: offset s (wrapped to [0,lx)) and sliding velocity. */
