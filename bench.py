@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--collision", default="bgk", choices=["bgk", "multi"],
                     help="eq. 5 as BGK, or the multi-eigenvalue operator (tau_bulk 0.75, "
                          "tau_ghost 1: ghost modes projected out)")
+    ap.add_argument("--lub-implicit", type=int, default=0,
+                    help="Jacobi sweeps of the implicit squeeze lubrication per substep (0: explicit)")
+    ap.add_argument("--n-sub", type=int, default=8, help="DEM substeps per lattice step")
     ap.add_argument("--contact-bins", type=int, default=0,
                     help="also sample the contact statistics every step in this many bins")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -139,6 +142,7 @@ def main():
     log("workload %s: box %s, %d spheres (%.1f s to generate)" % (wname, w.box, w.n, time.perf_counter() - t))
     p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
                          precision=PREC[args.precision], contact_bins=args.contact_bins, wall=w.wall,
+                         lub_implicit=args.lub_implicit, n_sub=args.n_sub,
                          collision=1 if args.collision == "multi" else 0, tau_bulk=0.75, tau_ghost=1.0,
                          **w.params)
     sim = susp.Simulation(p)
@@ -211,6 +215,7 @@ def main():
             "shear_rate": w.params.get("gamma_dot"),
             "precision": args.precision,
             "n_sub": int(p.n_sub),
+            "lub_implicit": int(args.lub_implicit),
             "collision": args.collision,
             "contact_bins": int(args.contact_bins),
             "status": int(rc),

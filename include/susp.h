@@ -102,6 +102,13 @@ typedef struct {
                                 stress, -1/tau_bulk for its trace and -1/tau_ghost for the
                                 nine non-hydrodynamic modes (mass and momentum conserved) */
   double tau_bulk, tau_ghost;  /* > 1/2 each (collision 1)                               */
+  int32_t lub_implicit;      /* 0: every pair force explicit in the DEM substeps.  K in
+                                1..64: the normal squeeze part -zeta n (n . (U_i - U_j)) of
+                                each pair's lubrication force (zeta = eta0 X^A, App. A) is
+                                taken at the substep's new velocities, solved by K Jacobi
+                                sweeps from the explicit update; spins, the other forces and
+                                the stresslets stay explicit.  With walls, the wall force
+                                then omits the squeeze part on wall spheres.               */
   int32_t boundary;          /* 0: Lees-Edwards sliding boundary in y.  1: walls (Sec. 3):
                                 flat walls halfway outside rows 0 and ly-1, moving in x at
                                 -U_w and +U_w, U_w = ly gamma_dot(t) / 2 of the protocol,

@@ -176,6 +176,8 @@ static int resolve(const susp_params *p, Sim &s) {
   if (p->collision < 0 || p->collision > 1) return fail(SUSP_EINVAL, "collision must be 0 or 1");
   if (p->collision == 1 && !(p->tau_bulk > 0.5 && p->tau_ghost > 0.5))
     return fail(SUSP_EINVAL, "tau_bulk and tau_ghost must exceed 1/2");
+  if (p->lub_implicit < 0 || p->lub_implicit > 64) return fail(SUSP_EINVAL, "lub_implicit must be in [0, 64]");
+  s.lub_implicit = p->lub_implicit;
   if (p->boundary < 0 || p->boundary > 1) return fail(SUSP_EINVAL, "boundary must be 0 or 1");
   s.boundary = p->boundary;
   if (p->boundary == 1 && p->wall) {
@@ -299,6 +301,10 @@ static size_t carve(Sim &s, char *base) {
   }
   s.hstart = (int32_t *)take(n * NCAP * 4);
   s.rev = (int32_t *)take(n * NCAP * 4);
+  if (s.lub_implicit > 0) {
+    s.lb = (double *)take(n * 3 * 8);
+    s.uimp = (double *)take(n * 3 * 8);
+  }
   if (s.boundary == 1) {
     s.wmem = (int32_t *)take(n * 4);
     s.wfs = (double *)take(n * 3 * 8);

@@ -289,6 +289,22 @@ struct Phys {
   int lub_sub;
 };
 
+// Squeeze coefficient zeta = eta0 X^A of the lubrication force on the sphere of radius ai
+// (the X^A term of the pair expression below, App. A); 0 beyond h_c.
+__device__ inline double lub_zeta(const Phys &P, double ai, double aj, double h) {
+  if (!(h < P.hc)) return 0.0;
+  const double PI = 3.14159265358979323846;
+  const double hh = h > 0.0 ? h : 0.0;
+  const double xg = 2.0 * (hh + P.delta) / (ai + aj);
+  double inv = 1.0 / xg;
+  if (P.lub_sub) {
+    const double xc = 2.0 * (P.hc + P.delta) / (ai + aj);
+    inv = inv - 1.0 / xc;
+  }
+  const double b = aj / ai, b1 = 1.0 + b;
+  return P.eta0 * (6.0 * PI * ai * (2.0 * b * b / (b1 * b1 * b1)) * inv);
+}
+
 __device__ inline void crs(double ax, double ay, double az, double bx, double by, double bz,
                            double &cx_, double &cy_, double &cz_) {
   cx_ = ay * bz - az * by;
@@ -485,6 +501,7 @@ struct SubArgs {
   int32_t *cflag;
   const int32_t *wmem;  // walls: membership (null: Lees-Edwards)
   double *wfs;          // walls: force on each wall sphere this step
+  double *lb;           // implicit squeeze: right-hand side m U + dt (F^h + explicit forces)
   Phys P;
   Box b;             // static dimensions; offsets of this and the next step from clk
   const Clock *clk;
@@ -529,7 +546,10 @@ __device__ inline void record_contact(const SubArgs &A, size_t e, bool keep, con
 // the sphere's neighbours.  Both spheres of a pair evaluate the identical pair expression;
 // the lower id owns the spring history and the pair's stress.
 // REC: the last substep of a step with contact statistics on (records each contact).
-template <bool REC>
+// IMP: the normal squeeze part of each pair's lubrication force is left out here and taken
+// at the new velocities by k_lub_sweep; this kernel then writes the right-hand side and the
+// explicit first guess, and k_lub_advance moves the spheres.
+template <bool REC, bool IMP>
 __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   const Box bx = clock_box(A.b, A.clk, 0);
   const double s1 = A.clk->cur.s1, ule1 = A.clk->cur.ule1;
@@ -537,7 +557,7 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int l = lane & 15;
   const bool ok = i < A.n;
-  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0}, st[PST];
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0}, Fq[3] = {0, 0, 0}, st[PST];
 #pragma unroll
   for (int c = 0; c < PST; ++c) st[c] = 0.0;
   const int c_i = ok ? A.cnt[i] : 0;
@@ -555,18 +575,31 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
     PairOut o;
     pair_forces(A.P, A.a[lo], A.a[hi], d, &A.Ui[3 * lo], Uh, &A.Wi[3 * lo], &A.Wi[3 * hi], A.dts,
                 xi, A.onin[e], o);
+    double Fs[3] = {0.0, 0.0, 0.0};
+    if (IMP) {  // the squeeze part -zeta n (n . (U_lo - U_hi)) of the lubrication force
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double nn[3] = {d[0] / r, d[1] / r, d[2] / r};
+      const double z = lub_zeta(A.P, A.a[lo], A.a[hi], r - A.a[lo] - A.a[hi]);
+      const double un = nn[0] * (A.Ui[3 * lo] - Uh[0]) + nn[1] * (A.Ui[3 * lo + 1] - Uh[1]) +
+                        nn[2] * (A.Ui[3 * lo + 2] - Uh[2]);
+      for (int c = 0; c < 3; ++c) Fs[c] = -z * un * nn[c];
+    }
     if (i == lo) {
-      for (int c = 0; c < 3; ++c) { F[c] += o.F[c]; T[c] += o.Tl[c]; }
+      for (int c = 0; c < 3; ++c) { F[c] += o.F[c] - Fs[c]; T[c] += o.Tl[c]; Fq[c] += Fs[c]; }
       A.xout[3 * e] = xi[0]; A.xout[3 * e + 1] = xi[1]; A.xout[3 * e + 2] = xi[2];
       A.onout[e] = o.on;
       for (int c = 0; c < 6; ++c) { st[c] += o.sl[c]; st[6 + c] += o.vc[c]; st[12 + c] += o.vr[c]; }
     } else {
-      for (int c = 0; c < 3; ++c) { F[c] -= o.F[c]; T[c] += o.Th[c]; }
+      for (int c = 0; c < 3; ++c) { F[c] -= o.F[c] - Fs[c]; T[c] += o.Th[c]; Fq[c] -= Fs[c]; }
     }
     if (REC) record_contact(A, own_e, i == lo && o.on, d, o);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) { F[c] = gsum16(F[c]); T[c] = gsum16(T[c]); }
+  if (IMP) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Fq[c] = gsum16(Fq[c]);
+  }
 #pragma unroll
   for (int c = 0; c < PST; ++c) st[c] = gsum16(st[c]);
   if (!ok || l != 0) return;
@@ -595,6 +628,29 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
     A.Uo[3 * i] = u; A.Uo[3 * i + 1] = 0.0; A.Uo[3 * i + 2] = 0.0;
     A.Wo[3 * i] = 0.0; A.Wo[3 * i + 1] = 0.0; A.Wo[3 * i + 2] = 0.0;
     for (int c = 0; c < 4; ++c) A.Qo[4 * i + c] = A.Qi[4 * i + c];
+    return;
+  }
+  if (IMP) {
+    // spin and orientation as usual; the velocity's right-hand side and explicit first
+    // guess for the sweeps; the position waits for the solved velocity (k_lub_advance)
+    double W[3];
+    for (int c = 0; c < 3; ++c) {
+      const double fh = A.hyd[(size_t)i * HYD + c];
+      A.lb[3 * i + c] = A.m[i] * A.Ui[3 * i + c] + A.dts * (fh + F[c]);
+      A.Uo[3 * i + c] = A.Ui[3 * i + c] + A.dts * (fh + F[c] + Fq[c]) / A.m[i];
+      W[c] = A.Wi[3 * i + c] + A.dts * (A.hyd[(size_t)i * HYD + 3 + c] + T[c]) / A.I[i];
+      A.Ro[3 * i + c] = A.Ri[3 * i + c];
+    }
+    if (A.quasi2d) { W[0] = 0.0; W[1] = 0.0; }
+    double qw = A.Qi[4 * i], qx = A.Qi[4 * i + 1], qy = A.Qi[4 * i + 2], qz = A.Qi[4 * i + 3];
+    const double dw = -(W[0] * qx + W[1] * qy + W[2] * qz);
+    const double dx = W[0] * qw + (W[1] * qz - W[2] * qy);
+    const double dy = W[1] * qw + (W[2] * qx - W[0] * qz);
+    const double dz = W[2] * qw + (W[0] * qy - W[1] * qx);
+    qw += 0.5 * A.dts * dw; qx += 0.5 * A.dts * dx; qy += 0.5 * A.dts * dy; qz += 0.5 * A.dts * dz;
+    const double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    for (int c = 0; c < 3; ++c) A.Wo[3 * i + c] = W[c];
+    A.Qo[4 * i] = qw / nn; A.Qo[4 * i + 1] = qx / nn; A.Qo[4 * i + 2] = qy / nn; A.Qo[4 * i + 3] = qz / nn;
     return;
   }
   // eq. (1), symplectic Euler with the hydrodynamic force and torque of this step
@@ -634,6 +690,100 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   }
 }
 
+// One Jacobi sweep of the implicit squeeze terms: for every free sphere
+// (m I + dt sum zeta n n) U_i = b_i + dt sum zeta n (n . U_partner) with the partners'
+// velocities from the previous sweep (16 lanes per sphere over its neighbours, shuffle sums
+// in a fixed order, a 3x3 solve by Cramer's rule); wall spheres keep theirs.
+struct SweepArgs {
+  const double *Ri, *a, *m, *lb;
+  const int32_t *cnt, *nj, *wmem;
+  const double *Uin;
+  double *Uout;
+  Phys P;
+  Box b;
+  const Clock *clk;
+  double dts;
+  int n;
+};
+
+__global__ __launch_bounds__(256) void k_lub_sweep(SweepArgs A) {
+  const Box bx = clock_box(A.b, A.clk, 0);
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l = lane & 15;
+  const bool ok = i < A.n;
+  double M[6] = {0, 0, 0, 0, 0, 0}, r[3] = {0, 0, 0};  // xx yy zz xy xz yz
+  const int c_i = ok ? A.cnt[i] : 0;
+  for (int u = l; u < c_i; u += 16) {
+    const int j = A.nj[(size_t)i * NCAP + u];
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    double d[3];
+    int k;
+    pair_geo(bx, A.Ri, lo, hi, d[0], d[1], d[2], k);
+    const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double z = lub_zeta(A.P, A.a[lo], A.a[hi], rr - A.a[lo] - A.a[hi]);
+    if (z == 0.0) continue;
+    const double n[3] = {d[0] / rr, d[1] / rr, d[2] / rr};
+    // the partner's image: hi's moves at U_hi + k U_LE, lo's (seen from hi) at U_lo - k U_LE
+    const double sx = i == lo ? k * bx.ule : -k * bx.ule;
+    const double up = n[0] * (A.Uin[3 * j] + sx) + n[1] * A.Uin[3 * j + 1] + n[2] * A.Uin[3 * j + 2];
+    const double w = A.dts * z;
+    M[0] += w * n[0] * n[0]; M[1] += w * n[1] * n[1]; M[2] += w * n[2] * n[2];
+    M[3] += w * n[0] * n[1]; M[4] += w * n[0] * n[2]; M[5] += w * n[1] * n[2];
+    for (int c = 0; c < 3; ++c) r[c] += w * n[c] * up;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) M[c] = gsum16(M[c]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = gsum16(r[c]);
+  if (!ok || l != 0) return;
+  if (A.wmem && A.wmem[i] > 0) {
+    for (int c = 0; c < 3; ++c) A.Uout[3 * i + c] = A.Uin[3 * i + c];
+    return;
+  }
+  const double mi = A.m[i];
+  const double a00 = mi + M[0], a11 = mi + M[1], a22 = mi + M[2], a01 = M[3], a02 = M[4], a12 = M[5];
+  const double b0 = A.lb[3 * i] + r[0], b1 = A.lb[3 * i + 1] + r[1], b2 = A.lb[3 * i + 2] + r[2];
+  const double c00 = a11 * a22 - a12 * a12, c01 = a12 * a02 - a01 * a22, c02 = a01 * a12 - a11 * a02;
+  const double det = a00 * c00 + a01 * c01 + a02 * c02;
+  const double c11 = a00 * a22 - a02 * a02, c12 = a02 * a01 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+  A.Uout[3 * i] = (c00 * b0 + c01 * b1 + c02 * b2) / det;
+  A.Uout[3 * i + 1] = (c01 * b0 + c11 * b1 + c12 * b2) / det;
+  A.Uout[3 * i + 2] = (c02 * b0 + c12 * b1 + c22 * b2) / det;
+}
+
+// The solved velocity moves the sphere (and, on a step's last substep, the Lees-Edwards and
+// periodic wraps and the checks of k_substep); wall spheres moved in k_substep.
+__global__ __launch_bounds__(256) void k_lub_advance(SubArgs A, const double *Ufin) {
+  const Box bx = clock_box(A.b, A.clk, 0);
+  const double s1 = A.clk->cur.s1, ule1 = A.clk->cur.ule1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  if (A.wmem && A.wmem[i] > 0) return;
+  double U[3], R[3];
+  for (int c = 0; c < 3; ++c) U[c] = Ufin[3 * i + c];
+  if (A.quasi2d) U[2] = 0.0;
+  for (int c = 0; c < 3; ++c) R[c] = A.Ri[3 * i + c] + A.dts * U[c];
+  if (A.last) {
+    if (A.wmem) {
+    } else if (R[1] >= bx.Ly) { R[1] -= bx.Ly; R[0] -= s1; U[0] -= ule1; }
+    else if (R[1] < 0.0) { R[1] += bx.Ly; R[0] += s1; U[0] += ule1; }
+    for (int it = 0; it < 4 && R[0] >= bx.Lx; ++it) R[0] -= bx.Lx;
+    for (int it = 0; it < 4 && R[0] < 0.0; ++it) R[0] += bx.Lx;
+    for (int it = 0; it < 4 && R[2] >= bx.Lz; ++it) R[2] -= bx.Lz;
+    for (int it = 0; it < 4 && R[2] < 0.0; ++it) R[2] += bx.Lz;
+  }
+  for (int c = 0; c < 3; ++c) { A.Uo[3 * i + c] = U[c]; A.Ro[3 * i + c] = R[c]; }
+  if (A.last) {
+    bool ok = true;
+    for (int c = 0; c < 3; ++c) ok = ok && isfinite(R[c]) && isfinite(U[c]) && isfinite(A.Wo[3 * i + c]);
+    ok = ok && R[0] > -bx.Lx && R[0] < 2.0 * bx.Lx && R[1] > -bx.Ly && R[1] < 2.0 * bx.Ly &&
+         R[2] > -bx.Lz && R[2] < 2.0 * bx.Lz;
+    if (A.wmem) ok = ok && R[1] >= 0.0 && R[1] < bx.Ly;
+    if (!ok) atomicOr(A.flags, 2);
+  }
+}
+
 hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   SubArgs A;
   const int pi = s->pcur, po = 1 - s->pcur;
@@ -660,11 +810,30 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   A.clk = s->clk;
   A.n = s->n; A.sub = sub; A.last = sub == s->n_sub - 1; A.quasi2d = s->quasi2d;
   A.flags = s->flags;
+  A.lb = s->lb;
   if (s->n > 0) {
-    if (A.crec && A.last)
-      hipLaunchKernelGGL(k_substep<true>, dim3((s->n + 15) / 16), dim3(256), 0, s->stream, A);
-    else
-      hipLaunchKernelGGL(k_substep<false>, dim3((s->n + 15) / 16), dim3(256), 0, s->stream, A);
+    const dim3 g((s->n + 15) / 16), blk(256);
+    const bool rec = A.crec && A.last;
+    if (s->lub_implicit == 0) {
+      if (rec) hipLaunchKernelGGL((k_substep<true, false>), g, blk, 0, s->stream, A);
+      else hipLaunchKernelGGL((k_substep<false, false>), g, blk, 0, s->stream, A);
+    } else {
+      if (rec) hipLaunchKernelGGL((k_substep<true, true>), g, blk, 0, s->stream, A);
+      else hipLaunchKernelGGL((k_substep<false, true>), g, blk, 0, s->stream, A);
+      // Jacobi sweeps between the new velocity buffer and the scratch buffer
+      SweepArgs W;
+      W.Ri = A.Ri; W.a = A.a; W.m = A.m; W.lb = s->lb;
+      W.cnt = A.cnt; W.nj = A.nj; W.wmem = A.wmem;
+      W.P = A.P; W.b = A.b; W.clk = A.clk; W.dts = A.dts; W.n = s->n;
+      double *buf[2] = {A.Uo, s->uimp};
+      for (int k = 0; k < s->lub_implicit; ++k) {
+        W.Uin = buf[k & 1];
+        W.Uout = buf[(k + 1) & 1];
+        hipLaunchKernelGGL(k_lub_sweep, g, blk, 0, s->stream, W);
+      }
+      hipLaunchKernelGGL(k_lub_advance, dim3((s->n + 255) / 256), dim3(256), 0, s->stream, A,
+                         (const double *)buf[s->lub_implicit & 1]);
+    }
   }
   return hipGetLastError();
 }

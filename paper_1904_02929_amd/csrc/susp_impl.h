@@ -175,6 +175,8 @@ struct Sim {
   int period, ncyc_I, ncyc_F;
   int fp16_exp;
   int collision;           // 0 BGK, 1 multi-eigenvalue (tau shear, tau_bulk, tau_ghost)
+  int lub_implicit;        // Jacobi sweeps of the implicit squeeze terms per substep (0: off)
+  double *lb, *uimp;       // [n][3] their right-hand sides and scratch velocities
   int boundary;            // 0 Lees-Edwards, 1 moving walls with wall spheres
   int32_t *wmem;           // [n] 0 free, 1 bottom wall, 2 top wall
   double *wfs;             // [n][3] force on each wall sphere this step (hydro + pair mean)

@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("ncyc_I", C.c_int32), ("ncyc_F", C.c_int32), ("fp16_exp", C.c_int32),
         ("brick_y", C.c_int32), ("brick_z", C.c_int32), ("contact_bins", C.c_int32),
         ("collision", C.c_int32), ("tau_bulk", C.c_double), ("tau_ghost", C.c_double),
-        ("boundary", C.c_int32), ("wall", _PI),
+        ("lub_implicit", C.c_int32), ("boundary", C.c_int32), ("wall", _PI),
     ]
 
 

@@ -198,6 +198,31 @@ def test_multi_eigenvalue_full_size_fp32():
     _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params, **MULTI), 1, presteps=0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_implicit_squeeze_dense_one_step(precision):
+    # the squeeze terms taken at the new velocities by 6 Jacobi sweeps per substep
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=9)
+    _one_step_parity(box, pos, vel, om, rad, dict(kw, lub_implicit=6), precision, presteps=20)
+
+
+def test_implicit_squeeze_closing_pair_fp64():
+    # a pair closing at a gap of 0.005 with one substep per step (the oracle pin's case):
+    # three steps from creation on both sides, the explicit update would blow up here
+    a, h = 4.5, 0.005
+    pos = np.array([[20.0, 20.0, 20.0], [20.0 + 2 * a + h, 20.0, 20.0]])
+    vel = np.array([[2e-4, 0, 0], [-2e-4, 0, 0]])
+    kw = dict(n_sub=1, lub_delta=1e-4, F0=0.0, lub_implicit=30)
+    _announce("implicit squeeze, closing pair")
+    o = PU.oracle_for((48, 40, 40), kw, pos, vel, np.zeros((2, 3)), np.full(2, a))
+    g = PU.gpu_for((48, 40, 40), kw, pos, vel, np.zeros((2, 3)), np.full(2, a), 0)
+    assert o.step(3) == 0
+    g.step(3)
+    Rg, Ug, Wg, _ = g.get_particles()
+    assert np.abs(Rg - o.part("R")).max() < 1e-12
+    assert PU.rel(Ug, o.part("U")) < 1e-10
+    g.close()
+
+
 def test_multistep_fp64_from_create():
     # both sides start from their own initial state and run 25 steps
     box, pos, vel, om, rad, kw = PU.dense_workload(seed=11)
