@@ -376,12 +376,6 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
   auto bail = [&](int code) { susp_destroy(h); return code; };
   s.clk_host = (ClockEntry *)malloc((size_t)CLK_CAP * sizeof(ClockEntry));
   if (!s.clk_host) return bail(fail(SUSP_ENOMEM, "clock table"));
-  if (s.n > 0 && s.nodes >= AUX_MIN_NODES) {
-    if (hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking) ||
-        hipEventCreateWithFlags(&s.fork_ev, hipEventDisableTiming) ||
-        hipEventCreateWithFlags(&s.join_ev, hipEventDisableTiming))
-      return bail(fail(SUSP_EDEVICE, "side stream"));
-  }
   if (launch_fill_i32((int32_t *)s.clk, sizeof(Clock) / 4, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   const size_t n = (size_t)s.n;
   if (n) {
@@ -466,11 +460,7 @@ extern "C" int susp_destroy(susp_sim *h) {
   for (int i = 0; i < 2 * h->s.prof_cap; ++i) (void)hipEventDestroy(h->s.prof_ev[i]);
   free(h->s.prof_ev);
   (void)hipStreamSynchronize(h->s.stream);
-  if (h->s.aux) (void)hipStreamSynchronize(h->s.aux);
   if (h->s.gexec) (void)hipGraphExecDestroy(h->s.gexec);
-  if (h->s.fork_ev) (void)hipEventDestroy(h->s.fork_ev);
-  if (h->s.join_ev) (void)hipEventDestroy(h->s.join_ev);
-  if (h->s.aux) (void)hipStreamDestroy(h->s.aux);
   free(h->s.clk_host);
   if (h->s.owns_block && h->s.block) (void)hipFree(h->s.block);
   delete h;
@@ -515,19 +505,6 @@ static int one_step(Sim &s) {
   HIPCHK(launch_clock(&s, 0));
   s.hcur ^= 1;
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
-  const bool fork = s.aux != nullptr && s.n > 0;
-  if (fork) {  // neighbour lists on the side stream, beside the lattice kernels
-    HIPCHK(hipEventRecord(s.fork_ev, s.stream));
-    HIPCHK(hipStreamWaitEvent(s.aux, s.fork_ev, 0));
-    const hipStream_t main = s.stream;
-    s.stream = s.aux;
-    hipError_t e = launch_pairs(&s, b);
-    s.lcur ^= 1;
-    if (e == hipSuccess) e = launch_pair_rev(&s);
-    s.stream = main;
-    HIPCHK(e);
-    HIPCHK(hipEventRecord(s.join_ev, s.aux));
-  }
   HIPCHK(launch_brick_lists(&s));
   if (s.boundary == 1) HIPCHK(launch_walls(&s));
   else HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
@@ -549,13 +526,9 @@ static int one_step(Sim &s) {
   HIPCHK(launch_hydro_gather(&s, b));
   s.cur ^= 1;
   if (s.n) {
-    if (fork) {
-      HIPCHK(hipStreamWaitEvent(s.stream, s.join_ev, 0));
-    } else {
-      HIPCHK(launch_pairs(&s, b));
-      s.lcur ^= 1;
-      HIPCHK(launch_pair_rev(&s));
-    }
+    HIPCHK(launch_pairs(&s, b));
+    s.lcur ^= 1;
+    HIPCHK(launch_pair_rev(&s));
     for (int k = 0; k < s.n_sub; ++k) {
       HIPCHK(launch_substep(&s, b, k));
       s.pcur ^= 1;

@@ -1201,12 +1201,13 @@ struct GhostArgs {
   int lists, bxn, byn, BZ;
 };
 
-// Galilean-corrected post-collision deviation of direction q at node (x,yrow,z) seen from
-// the neighbouring image box: sgn = +1 box below (u - ule), -1 box above (u + ule).
-template <class ST, class CT>
-__device__ inline CT nhat(const ST *fin, size_t plane, const int32_t *own, const double *R,
-                          const double *U, const double *W, Box b, double rho0, H16 h16, int q,
-                          int x, int yrow, int z, int sgn) {
+// Galilean-corrected post-collision deviations of the five directions of ghost plane G at
+// node (x,yrow,z) seen from the neighbouring image box: sgn = +1 box below (u - ule), -1 box
+// above (u + ule).  The node's moments are formed once for the five.
+template <int G, class ST, class CT>
+__device__ inline void nhat5(const ST *fin, size_t plane, const int32_t *own, const double *R,
+                             const double *U, const double *W, Box b, double rho0, H16 h16, int x,
+                             int yrow, int z, int sgn, CT out[5]) {
   const int64_t node = x + (int64_t)b.lx * (yrow + (int64_t)b.ly * z);
   const int o = own[node];
   if (o >= 0) {
@@ -1217,37 +1218,79 @@ __device__ inline CT nhat(const ST *fin, size_t plane, const int32_t *own, const
     double ux, uy, uz;
     surf_vel(U, W, o, k, b.ule, dx, dy, dz, ux, uy, uz);
     ux -= sgn * b.ule;
-    const double cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
     const double uu = ux * ux + uy * uy + uz * uz;
-    return (CT)(wq(q) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int q = gdir(G, m);
+      const double cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
+      out[m] = (CT)(wq(q) * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+    return;
   }
-  CT rd = 0, jx = 0, jy = 0, jz = 0, fq = 0;
+  CT rd = 0, jx = 0, jy = 0, jz = 0, fq[5];
 #pragma unroll
   for (int r = 0; r < NQ; ++r) {
     const CT v = Store<ST>::ld(fin, (size_t)r * plane + node, r, h16);
     rd += v; jx += v * (CT)cx(r); jy += v * (CT)cy(r); jz += v * (CT)cz(r);
-    if (r == q) fq = v;
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+      if (r == gdir(G, m)) fq[m] = v;
   }
   const CT rho = (CT)rho0 + rd;
   const CT ux = jx / rho, uy = jy / rho, uz = jz / rho;
   // feq(rho, u + du) - feq(rho, u) with du = -sgn ule x, written out to avoid cancellation
   const CT du = (CT)(-sgn * b.ule);
-  const CT cu = (CT)cx(q) * ux + (CT)cy(q) * uy + (CT)cz(q) * uz;
-  const CT cd = (CT)cx(q) * du;
-  const CT dfe = (CT)wq(q) * rho * ((CT)3 * cd + (CT)4.5 * cd * ((CT)2 * cu + cd) -
-                                    (CT)1.5 * du * ((CT)2 * ux + du));
-  return fq + dfe;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const int q = gdir(G, m);
+    const CT cu = (CT)cx(q) * ux + (CT)cy(q) * uy + (CT)cz(q) * uz;
+    const CT cd = (CT)cx(q) * du;
+    const CT dfe = (CT)wq(q) * rho * ((CT)3 * cd + (CT)4.5 * cd * ((CT)2 * cu + cd) -
+                                      (CT)1.5 * du * ((CT)2 * ux + du));
+    out[m] = fq[m] + dfe;
+  }
 }
 
+// Values of ghost plane G at (x, z): the row of the neighbouring image interpolated linearly
+// at the sheared position.
+template <int G, class ST, class CT>
+__device__ inline void ghost_values(const GhostArgs &A, const Box &bx, int x, int z) {
+  const ST *fin = (const ST *)A.fin;
+  CT *gval = (CT *)A.gval;
+  const int sgn = G == 0 ? 1 : -1;
+  const int yrow = G == 0 ? A.ly - 1 : 0;
+  const double xs = (double)x + sgn * bx.s;
+  const double x0f = floor(xs);
+  const double fr = xs - x0f;
+  int i0 = (int)x0f % A.lx;
+  i0 = i0 < 0 ? i0 + A.lx : i0;
+  const int i1 = i0 + 1 == A.lx ? 0 : i0 + 1;
+  CT v0[5], v1[5];
+  nhat5<G, ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, bx, A.rho0, A.h16, i0, yrow, z, sgn, v0);
+  nhat5<G, ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, bx, A.rho0, A.h16, i1, yrow, z, sgn, v1);
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+    gval[(size_t)((G * 5 + m) * A.lz + z) * A.lx + x] = ((CT)1 - (CT)fr) * v0[m] + (CT)fr * v1[m];
+}
+
+// One thread per ghost point (x, z) of the two ghost planes: owner, then (fluid points) the
+// values.  The spheres of the brick that holds the first lane's point are staged in LDS for
+// the wave (every lane's brick when the row length is a multiple of the brick width); a lane
+// in another brick reads its own list from memory, and a brick whose list overflowed falls
+// back to the cell list.
 template <class ST>
 __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   using CT = typename Store<ST>::CT;
+  __shared__ double s_sph[4][TSLOT][4];
+  __shared__ int32_t s_id[4][TSLOT];
   const Box bx = clock_box(A.b, A.clk, 0);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int npl = A.lx * A.lz;
-  if (idx >= 2 * npl) return;
-  const int g = idx / npl;
-  const int rem = idx - g * npl;
+  const bool live = idx < 2 * npl;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int id = live ? idx : 2 * npl - 1;  // lanes past the end take the last point (no stores)
+  const int g = id / npl;
+  const int rem = id - g * npl;
   const int z = rem / A.lx, x = rem - (rem / A.lx) * A.lx;
   const double gy = g == 0 ? -1.0 : (double)A.ly;
   // primary-box position of the ghost point, for the cell search only
@@ -1255,24 +1298,42 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
   px = px - bx.Lx * floor(px / bx.Lx);
   const double py = g == 0 ? (double)(A.ly - 1) : 0.0;
   int owner = -1, clash = 0;
-  auto test = [&](int p) {
+  auto test = [&](int p, double Rx, double Ry, double Rz, double am) {
     double dx, dy2, dz;
     int k;
-    minimage(bx, (double)x - A.R[3 * p], gy - A.R[3 * p + 1], (double)z - A.R[3 * p + 2], dx, dy2, dz, k);
+    minimage(bx, (double)x - Rx, gy - Ry, (double)z - Rz, dx, dy2, dz, k);
     const double r2 = dx * dx + dy2 * dy2 + dz * dz;
-    if (r2 < A.amap[p] * A.amap[p]) {
+    if (r2 < am * am) {
       if (owner >= 0 && owner != p) clash = 1;
       if (owner < 0 || p < owner) owner = p;
     }
   };
+  auto test_mem = [&](int p) { test(p, A.R[3 * p], A.R[3 * p + 1], A.R[3 * p + 2], A.amap[p]); };
+  const bool use_lists = A.n > 0 && A.lists;
+  const int brick = use_lists ? x / TX + A.bxn * ((g == 0 ? 0 : A.byn - 1) + A.byn * (z / A.BZ)) : 0;
+  const int b0 = __shfl(brick, 0, 64);
+  const int c0 = use_lists ? A.bt_cnt[b0] : 0;
+  const bool staged = use_lists && c0 <= TSLOT;
+  if (staged) {
+    const int32_t *key = A.bt_key + (size_t)b0 * TSLOT;
+    for (int i = lane; i < c0; i += 64) {
+      const int p = key[i];
+      s_id[wv][i] = p;
+      s_sph[wv][i][0] = A.R[3 * p]; s_sph[wv][i][1] = A.R[3 * p + 1]; s_sph[wv][i][2] = A.R[3 * p + 2];
+      s_sph[wv][i][3] = A.amap[p];
+    }
+  }
+  __syncthreads();
   bool listed = false;
-  if (A.n > 0 && A.lists) {
-    const int brick = x / TX + A.bxn * ((g == 0 ? 0 : A.byn - 1) + A.byn * (z / A.BZ));
+  if (staged && brick == b0) {
+#pragma unroll 4
+    for (int i = 0; i < c0; ++i) test(s_id[wv][i], s_sph[wv][i][0], s_sph[wv][i][1], s_sph[wv][i][2], s_sph[wv][i][3]);
+    listed = true;
+  } else if (use_lists) {
     const int cnt = A.bt_cnt[brick];
     if (cnt <= TSLOT) {
       const int32_t *key = A.bt_key + (size_t)brick * TSLOT;
-#pragma unroll 4
-      for (int i = 0; i < cnt; ++i) test(key[i]);
+      for (int i = 0; i < cnt; ++i) test_mem(key[i]);
       listed = true;
     }
   }
@@ -1298,30 +1359,17 @@ __global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
           int nx = C.nx >= 3 ? ccx + ix - 1 : ix;
           nx = nx < 0 ? nx + C.nx : (nx >= C.nx ? nx - C.nx : nx);
           const int c = nx + C.nx * (ny + C.ny * nz);
-          for (int t = A.cell_start[c]; t < A.cell_start[c + 1]; ++t) test(A.cell_ids[t]);
+          for (int t = A.cell_start[c]; t < A.cell_start[c + 1]; ++t) test_mem(A.cell_ids[t]);
         }
       }
     }
   }
+  if (!live) return;
   if (clash) atomicOr(A.flags, 1);
   A.gown[idx] = owner;
   if (!A.values || owner >= 0) return;
-  const ST *fin = (const ST *)A.fin;
-  CT *gval = (CT *)A.gval;
-  const int sgn = g == 0 ? 1 : -1;
-  const int yrow = g == 0 ? A.ly - 1 : 0;
-  const double xs = (double)x + sgn * bx.s;
-  const double x0f = floor(xs);
-  const double fr = xs - x0f;
-  int i0 = (int)x0f % A.lx;
-  i0 = i0 < 0 ? i0 + A.lx : i0;
-  const int i1 = i0 + 1 == A.lx ? 0 : i0 + 1;
-  for (int m = 0; m < 5; ++m) {
-    const int q = gdir(g, m);
-    const CT v0 = nhat<ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, bx, A.rho0, A.h16, q, i0, yrow, z, sgn);
-    const CT v1 = nhat<ST, CT>(fin, A.plane, A.own, A.R, A.U, A.W, bx, A.rho0, A.h16, q, i1, yrow, z, sgn);
-    gval[(size_t)((g * 5 + m) * A.lz + z) * A.lx + x] = ((CT)1 - (CT)fr) * v0 + (CT)fr * v1;
-  }
+  if (g == 0) ghost_values<0, ST, CT>(A, bx, x, z);
+  else ghost_values<1, ST, CT>(A, bx, x, z);
 }
 
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,

@@ -211,59 +211,104 @@ struct PairArgs {
   int32_t *flags;
 };
 
-__global__ __launch_bounds__(128) void k_pairs(PairArgs A) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
+// Neighbour list of one sphere per wave, four spheres per work-group.  The lanes take the
+// candidates of the near cells in visiting order (cell by cell, each cell in its stored
+// order); a ballot keeps those within the cutoff in that order (the first NCAP of them; more
+// raise flag 4), and each kept partner goes to its rank among them, so the list ascends in
+// partner id.  A pair that stays listed carries its spring history over from the previous
+// list, where the lower id holds it.
+__global__ __launch_bounds__(256) void k_pairs(PairArgs A) {
+  __shared__ int32_t s_cs[4][32], s_pre[4][32], s_js[4][NCAP], s_srt[4][NCAP], s_old[4][NCAP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  const bool ok = i < A.n;  // waves past the last sphere still reach the barriers
   const Box bx = clock_box(A.b, A.clk, 0);
-  int32_t js[NCAP];
-  int c = 0, over = 0, ovl = 0;
   const double *R = A.R;
-  near_cells(A.C, bx, R[3 * i], R[3 * i + 1], R[3 * i + 2], [&](int cell) {
-    for (int t = A.cell_start[cell]; t < A.cell_start[cell + 1]; ++t) {
-      const int j = A.cell_ids[t];
-      if (j == i) continue;
-      const int lo = i < j ? i : j, hi = i < j ? j : i;
-      double dx, dy, dz;
-      int k;
-      const double r2 = pair_geo(bx, R, lo, hi, dx, dy, dz, k);
-      const double rc = A.a[lo] + A.a[hi] + A.cutoff;
-      if (r2 < rc * rc) {
-        if (c < NCAP) js[c++] = j; else over = 1;
+  // the near cells: lane k takes the k-th cell visited (at most 27)
+  int ncv = 0, cell = -1;
+  if (ok)
+    near_cells(A.C, bx, R[3 * i], R[3 * i + 1], R[3 * i + 2], [&](int c) {
+      if (ncv == lane) cell = c;
+      ++ncv;
+    });
+  int cs = 0, cn = 0;
+  if (cell >= 0) { cs = A.cell_start[cell]; cn = A.cell_start[cell + 1] - cs; }
+  int incl = cn;  // inclusive scan of the cell counts over the lanes
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  const int total = __shfl(incl, 63, 64);
+  if (lane < 32) { s_cs[wv][lane] = cs; s_pre[wv][lane] = incl - cn; }
+  __syncthreads();
+  int c = 0;
+  bool ovl = false;
+  for (int base = 0; base < total; base += 64) {
+    const int t = base + lane;
+    bool hit = false;
+    int j = -1;
+    if (t < total) {
+      int k = 0;  // the cell holding candidate t: the last one starting at or before t
+      while (k + 1 < ncv && s_pre[wv][k + 1] <= t) ++k;
+      j = A.cell_ids[s_cs[wv][k] + (t - s_pre[wv][k])];
+      if (j != i) {
+        const int lo = i < j ? i : j, hi = i < j ? j : i;
+        double dx, dy, dz;
+        int kk;
+        const double r2 = pair_geo(bx, R, lo, hi, dx, dy, dz, kk);
+        const double rc = A.a[lo] + A.a[hi] + A.cutoff;
+        hit = r2 < rc * rc;
         const double rm = A.amap[lo] + A.amap[hi];
-        if (r2 < rm * rm) ovl = 1;
+        if (hit && r2 < rm * rm) ovl = true;
       }
     }
-  });
-  for (int u = 1; u < c; ++u) {  // ascending partner ids
-    const int32_t v = js[u];
-    int w = u - 1;
-    while (w >= 0 && js[w] > v) { js[w + 1] = js[w]; --w; }
-    js[w + 1] = v;
+    const uint64_t m = __ballot(hit);
+    const int pos = c + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (hit && pos < NCAP) s_js[wv][pos] = j;
+    c += __popcll(m);
   }
-  if (over) atomicOr(A.flags, 4);
-  if (ovl) atomicOr(A.flags, 1);
-  A.cnt[i] = c;
-  const int oc = A.ocnt[i];
-  for (int u = 0; u < c; ++u) {
-    const int j = js[u];
-    const size_t e = (size_t)i * NCAP + u;
-    A.nj[e] = j;
-    if (j < i) continue;  // the history of a pair lives with its lower id
-    double x0 = 0, x1 = 0, x2 = 0;
-    int on = 0;
-    for (int v = 0; v < oc; ++v)
-      if (A.onj[(size_t)i * NCAP + v] == j) {
-        const size_t oe = (size_t)i * NCAP + v;
-        if (A.oon[oe]) { x0 = A.oxi[3 * oe]; x1 = A.oxi[3 * oe + 1]; x2 = A.oxi[3 * oe + 2]; on = 1; }
-        break;
-      }
-    A.xi[3 * e] = x0; A.xi[3 * e + 1] = x1; A.xi[3 * e + 2] = x2;
-    A.on[e] = on;
-    double dx, dy, dz;
-    int k;
-    const double r2 = pair_geo(bx, R, i, j, dx, dy, dz, k);
-    A.hstart[e] = (sqrt(r2) - A.a[i] - A.a[j]) < 0.0 ? 1 : 0;
+  const int kept = c < NCAP ? c : NCAP;
+  const int oc = ok ? A.ocnt[i] : 0;
+  if (lane < oc) s_old[wv][lane] = A.onj[(size_t)i * NCAP + lane];
+  __syncthreads();
+  if (lane < kept) {  // rank among the kept partners (stable for equal ids)
+    const int v = s_js[wv][lane];
+    int r = 0;
+    for (int w = 0; w < kept; ++w) {
+      const int x = s_js[wv][w];
+      r += (x < v || (x == v && w < lane)) ? 1 : 0;
+    }
+    s_srt[wv][r] = v;
   }
+  __syncthreads();
+  if (!ok) return;
+  const uint64_t ov = __ballot(ovl);
+  if (lane == 0) {
+    if (c > NCAP) atomicOr(A.flags, 4);
+    if (ov) atomicOr(A.flags, 1);
+    A.cnt[i] = kept;
+  }
+  if (lane >= kept) return;
+  const int j = s_srt[wv][lane];
+  const size_t e = (size_t)i * NCAP + lane;
+  A.nj[e] = j;
+  if (j < i) return;  // the history of a pair lives with its lower id
+  double x0 = 0, x1 = 0, x2 = 0;
+  int on = 0;
+  for (int v = 0; v < oc; ++v)
+    if (s_old[wv][v] == j) {
+      const size_t oe = (size_t)i * NCAP + v;
+      if (A.oon[oe]) { x0 = A.oxi[3 * oe]; x1 = A.oxi[3 * oe + 1]; x2 = A.oxi[3 * oe + 2]; on = 1; }
+      break;
+    }
+  A.xi[3 * e] = x0; A.xi[3 * e + 1] = x1; A.xi[3 * e + 2] = x2;
+  A.on[e] = on;
+  double dx, dy, dz;
+  int k;
+  const double r2 = pair_geo(bx, R, i, j, dx, dy, dz, k);
+  A.hstart[e] = (sqrt(r2) - A.a[i] - A.a[j]) < 0.0 ? 1 : 0;
 }
 
 hipError_t launch_pairs(Sim *s, const Box &b) {
@@ -279,7 +324,7 @@ hipError_t launch_pairs(Sim *s, const Box &b) {
   A.hstart = s->hstart;
   A.flags = s->flags;
   if (s->n > 0)
-    hipLaunchKernelGGL(k_pairs, dim3((s->n + 127) / 128), dim3(128), 0, s->stream, A);
+    hipLaunchKernelGGL(k_pairs, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, A);
   return hipGetLastError();
 }
 
@@ -459,7 +504,8 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
 }
 
 // Entry of each neighbour-list slot that holds the pair's spring history (the slot of the
-// lower id); one wave per sphere, lanes over its neighbour slots.
+// lower id); one wave per sphere, lanes over its neighbour slots; the lower id's list
+// ascends, so its slot is found by bisection.
 __global__ __launch_bounds__(256) void k_pair_rev(const int32_t *cnt, const int32_t *nj, int32_t *rev,
                                                   int n) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -470,10 +516,14 @@ __global__ __launch_bounds__(256) void k_pair_rev(const int32_t *cnt, const int3
   const int j = nj[e];
   int r = (int)e;
   if (j < i) {
-    const int cj = cnt[j];
-    r = -1;
-    for (int v = 0; v < cj; ++v)
-      if (nj[(size_t)j * NCAP + v] == i) { r = j * NCAP + v; break; }
+    const int32_t *lj = &nj[(size_t)j * NCAP];
+    int lo = 0, hi = cnt[j];  // first slot holding an id >= i
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (lj[mid] < i) lo = mid + 1;
+      else hi = mid;
+    }
+    r = lo < cnt[j] && lj[lo] == i ? j * NCAP + lo : -1;
   }
   rev[e] = r;
 }
@@ -516,12 +566,13 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// sum over the 16 lanes of a lane group (xor offsets stay inside the group)
-__device__ inline double gsum16(double v) {
+// sum over the L lanes of a lane group (xor offsets stay inside the group)
+template <int L> __device__ inline double gsum(double v) {
 #pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ inline double gsum16(double v) { return gsum<16>(v); }
 
 // Contact statistics (Sec. 4.2, eqs. 19-23): record of a pair in contact at the last substep,
 // kept in the lower id's entry: the in-plane unit direction n of d = R_lo - R_hi ((1, 0) if d
@@ -542,26 +593,27 @@ __device__ inline void record_contact(const SubArgs &A, size_t e, bool keep, con
   A.cflag[e] = keep ? 1 : 0;
 }
 
-// One DEM substep; 16 lanes per sphere (four spheres per wave), the lanes striding over
-// the sphere's neighbours.  Both spheres of a pair evaluate the identical pair expression;
+// One DEM substep; SUB_L lanes per sphere, the lanes striding over the sphere's
+// neighbours.  Both spheres of a pair evaluate the identical pair expression;
 // the lower id owns the spring history and the pair's stress.
 // REC: the last substep of a step with contact statistics on (records each contact).
 // IMP: the normal squeeze part of each pair's lubrication force is left out here and taken
 // at the new velocities by k_lub_sweep; this kernel then writes the right-hand side and the
 // explicit first guess, and k_lub_advance moves the spheres.
+constexpr int SUB_L = 8;  // lanes per sphere in k_substep
 template <bool REC, bool IMP>
 __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   const Box bx = clock_box(A.b, A.clk, 0);
   const double s1 = A.clk->cur.s1, ule1 = A.clk->cur.ule1;
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int l = lane & 15;
+  const int i = blockIdx.x * (256 / SUB_L) + threadIdx.x / SUB_L;
+  const int l = lane % SUB_L;
   const bool ok = i < A.n;
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0}, Fq[3] = {0, 0, 0}, st[PST];
 #pragma unroll
   for (int c = 0; c < PST; ++c) st[c] = 0.0;
   const int c_i = ok ? A.cnt[i] : 0;
-  for (int u = l; u < c_i; u += 16) {
+  for (int u = l; u < c_i; u += SUB_L) {
     const size_t own_e = (size_t)i * NCAP + u;
     const int j = A.nj[own_e];
     const int lo = i < j ? i : j, hi = i < j ? j : i;
@@ -595,13 +647,13 @@ __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
     if (REC) record_contact(A, own_e, i == lo && o.on, d, o);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) { F[c] = gsum16(F[c]); T[c] = gsum16(T[c]); }
+  for (int c = 0; c < 3; ++c) { F[c] = gsum<SUB_L>(F[c]); T[c] = gsum<SUB_L>(T[c]); }
   if (IMP) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) Fq[c] = gsum16(Fq[c]);
+    for (int c = 0; c < 3; ++c) Fq[c] = gsum<SUB_L>(Fq[c]);
   }
 #pragma unroll
-  for (int c = 0; c < PST; ++c) st[c] = gsum16(st[c]);
+  for (int c = 0; c < PST; ++c) st[c] = gsum<SUB_L>(st[c]);
   if (!ok || l != 0) return;
   if (A.sub == 0) {
     for (int c = 0; c < 3; ++c) A.R0[3 * i + c] = A.Ri[3 * i + c];
@@ -812,14 +864,15 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   A.flags = s->flags;
   A.lb = s->lb;
   if (s->n > 0) {
-    const dim3 g((s->n + 15) / 16), blk(256);
+    const int per = 256 / SUB_L;
+    const dim3 gs((s->n + per - 1) / per), g((s->n + 15) / 16), blk(256);
     const bool rec = A.crec && A.last;
     if (s->lub_implicit == 0) {
-      if (rec) hipLaunchKernelGGL((k_substep<true, false>), g, blk, 0, s->stream, A);
-      else hipLaunchKernelGGL((k_substep<false, false>), g, blk, 0, s->stream, A);
+      if (rec) hipLaunchKernelGGL((k_substep<true, false>), gs, blk, 0, s->stream, A);
+      else hipLaunchKernelGGL((k_substep<false, false>), gs, blk, 0, s->stream, A);
     } else {
-      if (rec) hipLaunchKernelGGL((k_substep<true, true>), g, blk, 0, s->stream, A);
-      else hipLaunchKernelGGL((k_substep<false, true>), g, blk, 0, s->stream, A);
+      if (rec) hipLaunchKernelGGL((k_substep<true, true>), gs, blk, 0, s->stream, A);
+      else hipLaunchKernelGGL((k_substep<false, true>), gs, blk, 0, s->stream, A);
       // Jacobi sweeps between the new velocity buffer and the scratch buffer
       SweepArgs W;
       W.Ri = A.Ri; W.a = A.a; W.m = A.m; W.lb = s->lb;

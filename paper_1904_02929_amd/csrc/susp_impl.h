@@ -114,7 +114,6 @@ struct Clock {
   int32_t idx, pad;
 };
 constexpr int CLK_CAP = 4096;  // steps per table upload
-constexpr int64_t AUX_MIN_NODES = (int64_t)1 << 22;  // lattices that get the side stream
 
 // Box of the current step (next = 0: offset s, velocity ule) or of the next one (s1, ule1)
 // from the device clock; without a clock the box is used as given.
@@ -192,10 +191,6 @@ struct Sim {
   void *block;
   int owns_block;
   hipStream_t stream;
-  // large simulations: a second stream that builds the neighbour lists while the lattice
-  // kernels run (forked after the cell list, joined before the DEM substeps); null if unused
-  hipStream_t aux;
-  hipEvent_t fork_ev, join_ev;
   // populations
   void *f[2];
   int cur;  // index of the buffer holding the current state

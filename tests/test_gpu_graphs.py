@@ -62,13 +62,13 @@ def test_graph_replay_is_bit_identical(torch_mod, kind):
     graph.close()
 
 
-def test_graph_replay_with_side_stream(torch_mod):
-    # a lattice of 2^22 nodes: the neighbour lists are built on the side stream beside the
-    # lattice kernels; plain launches and graph replays must still agree bit for bit
+def test_graph_replay_large_lattice(torch_mod):
+    # a lattice of 2^22 nodes (several bricks along every axis, lists of many spheres):
+    # plain launches and graph replays must still agree bit for bit
     torch = torch_mod
     from paper_1904_02929_amd import susp
     box, pos, vel, om, rad, kw = PU.dense_workload((256, 128, 128), 0.30, 21, 2e-4)
-    print("\n[graphs] side stream, box %s, %d spheres" % (box, len(rad)), flush=True)
+    print("\n[graphs] large lattice, box %s, %d spheres" % (box, len(rad)), flush=True)
     sys.stdout.flush()
     p_a = susp.make_params(box, radius=rad, pos=pos, vel=vel, omega=om, precision=susp.FP32, **kw)
     p_b = susp.make_params(box, radius=rad, pos=pos, vel=vel, omega=om, precision=susp.FP32, **kw)
