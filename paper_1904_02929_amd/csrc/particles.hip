@@ -145,8 +145,74 @@ __global__ __launch_bounds__(1024) void k_cells_lds(const double *R, int n, Cell
   }
 }
 
+// The same list when the ids fit in LDS as well (n <= 16 x 1024): each thread keeps the cells
+// of its (at most 16) spheres in registers, so positions are read once, and the fill and the
+// sort inside each cell work in LDS; the ids are written out once at the end.
+constexpr int LDS_IDS = 16 * 1024;
+__global__ __launch_bounds__(1024) void k_cells_lds_ids(const double *R, int n, Cells C, int ncell,
+                                                        int32_t *start, int32_t *ids) {
+  __shared__ int32_t cnt[LDS_CELLS];
+  __shared__ int32_t part[1024];
+  __shared__ int32_t sid[LDS_IDS];
+  const int t = threadIdx.x, nt = 1024;
+  for (int c = t; c < ncell; c += nt) cnt[c] = 0;
+  int cof[LDS_IDS / 1024];
+#pragma unroll
+  for (int k = 0; k < LDS_IDS / 1024; ++k) {
+    const int i = t + k * nt;
+    cof[k] = i < n ? cell_of(C, R[3 * i], R[3 * i + 1], R[3 * i + 2]) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LDS_IDS / 1024; ++k)
+    if (t + k * nt < n) atomicAdd(&cnt[cof[k]], 1);
+  __syncthreads();
+  const int per = (ncell + nt - 1) / nt;
+  const int c0 = t * per, c1 = min(ncell, c0 + per);
+  int32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += cnt[c];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    int32_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = t > 0 ? part[t - 1] : 0;
+  for (int c = c0; c < c1; ++c) {
+    const int32_t k = cnt[c];
+    start[c] = run;
+    cnt[c] = run;
+    run += k;
+  }
+  if (t == nt - 1) start[ncell] = part[nt - 1];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LDS_IDS / 1024; ++k) {
+    const int i = t + k * nt;
+    if (i < n) sid[atomicAdd(&cnt[cof[k]], 1)] = i;
+  }
+  __syncthreads();
+  // after the fill cnt[c] is the end of cell c, i.e. the start of cell c + 1
+  for (int c = t; c < ncell; c += nt) {  // insertion sort inside each cell
+    const int a = c > 0 ? cnt[c - 1] : 0, b = cnt[c];
+    for (int u = a + 1; u < b; ++u) {
+      const int32_t v = sid[u];
+      int w = u - 1;
+      while (w >= a && sid[w] > v) { sid[w + 1] = sid[w]; --w; }
+      sid[w + 1] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += nt) ids[i] = sid[i];
+}
+
 hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch) {
-  if (s->ncell <= LDS_CELLS)
+  if (s->ncell <= LDS_CELLS && s->n <= LDS_IDS)
+    hipLaunchKernelGGL(k_cells_lds_ids, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n,
+                       s->cells, s->ncell, cell_start, cell_ids);
+  else if (s->ncell <= LDS_CELLS)
     hipLaunchKernelGGL(k_cells_lds, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n,
                        s->cells, s->ncell, cell_start, cell_ids);
   else
