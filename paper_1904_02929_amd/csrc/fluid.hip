@@ -1065,12 +1065,20 @@ __global__ __launch_bounds__(256) void k_brick_lists(ListArgs A) {
   const int lane = threadIdx.x & 63;
   if (p >= A.n) return;  // uniform per wave
   if (!(isfinite(A.R[3 * p]) && isfinite(A.R[3 * p + 1]) && isfinite(A.R[3 * p + 2]))) return;
+  // the enumeration keeps the first 256 distinct bricks in vis; their appends are issued by
+  // the lanes together afterwards (a returning atomic per brick in turn would serialise)
+  int ncall = 0;
+  auto append = [&](int brick) {
+    const int c = atomicAdd(&A.bt_cnt[brick], 1);
+    if (c < TSLOT) A.bt_key[(size_t)brick * TSLOT + c] = p;
+  };
   sphere_bricks(A.G, &A.R[3 * p], A.amap[p] + 2.0, A.clk->cur.s, vis[wv], lane, [&](int brick) {
-    if (lane == 0) {
-      const int c = atomicAdd(&A.bt_cnt[brick], 1);
-      if (c < TSLOT) A.bt_key[(size_t)brick * TSLOT + c] = p;
-    }
+    if (ncall >= 256 && lane == 0) append(brick);
+    ++ncall;
   });
+  __builtin_amdgcn_wave_barrier();
+  const int m = ncall < 256 ? ncall : 256;
+  for (int k = lane; k < m; k += 64) append(vis[wv][k]);
 }
 
 static BrickGeo brick_geo(const Sim *s) {
