@@ -58,6 +58,7 @@ constexpr int TX = 64, TY = 4;
 constexpr int TSLOT = 128;
 constexpr int SDAT = 10;  // doubles per LDS sphere state (R, U, W; padded to 16 bytes)
 constexpr int SPCAP = 64;  // table entries with links kept per sphere (past it: enumeration)
+static_assert(SPCAP == 64, "k_hydro_gather reads a sphere's entry slots with one wave");
 constexpr int SROW = TX + 2, SPLANE = (TY + 2) * SROW;  // staged owner plane: 6 rows of 66
 
 struct LbmArgs {
@@ -1126,13 +1127,18 @@ __global__ __launch_bounds__(256) void k_hydro_gather(GatherArgs A) {
   const int p = blockIdx.x * 4 + wv;
   const int lane = threadIdx.x & 63;
   if (p >= A.n) return;  // uniform per wave
-  double acc[HYD];
+  double acc[HYD], fb[HYD];
 #pragma unroll
   for (int c = 0; c < HYD; ++c) acc[c] = 0.0;
+  // the count, the entry slots (SPCAP per sphere, read whole) and the overflow accumulator are
+  // independent loads, issued together
   const int cnt = A.sp_cnt[p];
+  const int ent = A.sp_ent[(size_t)p * SPCAP + lane];
+#pragma unroll
+  for (int c = 0; c < HYD; ++c) fb[c] = lane == 0 ? A.hyd_fb[(size_t)p * HYD + c] : 0.0;
   if (cnt <= SPCAP) {
     // the entries, sorted ascending across the wave (bitonic; empty lanes sort last)
-    int e = lane < cnt ? A.sp_ent[(size_t)p * SPCAP + lane] : 0x7fffffff;
+    int e = lane < cnt ? ent : 0x7fffffff;
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -1164,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_hydro_gather(GatherArgs A) {
   }
   if (lane == 0) {
     for (int c = 0; c < HYD; ++c) {
-      A.hyd[(size_t)p * HYD + c] = acc[c] + A.hyd_fb[(size_t)p * HYD + c];
+      A.hyd[(size_t)p * HYD + c] = acc[c] + fb[c];
       A.hyd_fb[(size_t)p * HYD + c] = 0.0;
     }
     A.sp_cnt[p] = 0;
