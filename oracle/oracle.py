@@ -118,6 +118,11 @@ def lib():
         L.orc_lub_squeeze.restype = C.c_double
         L.orc_implicit_solve.argtypes = [C.c_int32, _PD, _PI, _PD, C.c_int32, _PI, _PI, _PD, _PD, _PD,
                                          C.c_double, C.c_int32, _PD]
+        L.orc_gg_weight.argtypes = [C.POINTER(Params), C.c_int64, _PD, _PD]
+        L.orc_gg_weight.restype = C.c_int
+        L.orc_gg_moduli.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_int64, _PD]
+        L.orc_gg_series.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64, _PD, _PD]
+        L.orc_quat_step.argtypes = [_PD, _PD, C.c_double]
         _lib = L
     return _lib
 
@@ -229,6 +234,21 @@ def implicit_solve(m, fixed, b, pi, pj, zeta, nvec, shift, dt, sweeps, U0):
     lib().orc_implicit_solve(n, _pd(m), _pi(fixed), _pd(b), len(pi), _pi(pi), _pi(pj), _pd(zeta),
                              _pd(nvec), _pd(shift), float(dt), int(sweeps), _pd(U))
     return U
+
+
+def gg_series(params: Params, t0: int, sxy):
+    """{G', G''} of eqs. (17)-(18) from the shear-stress history sxy (sxy[k]: step t0 + k)."""
+    a = np.ascontiguousarray(sxy, np.float64).reshape(-1)
+    gg = np.zeros(2)
+    lib().orc_gg_series(C.byref(params), int(t0), len(a), _pd(a), _pd(gg))
+    return gg
+
+
+def quat_step(q, W, dt):
+    """One substep's orientation update of a sphere with angular velocity W."""
+    q = np.ascontiguousarray(q, np.float64).reshape(4).copy()
+    lib().orc_quat_step(_pd(q), _pd(_v3(W)), float(dt))
+    return q
 
 
 def wall_speed(params: Params, t: int) -> float:

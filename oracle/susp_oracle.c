@@ -1199,14 +1199,12 @@ static void one_step(orc_sim *S) {
     S->csamples += 1;
   }
   /* G', G'' (eqs. 17-18, rectangle rule over the observation periods) */
-  if (P->shear_kind == 2) {
-    int64_t tI = (int64_t)P->ncyc_I * P->period, tF = tI + (int64_t)P->ncyc_F * P->period;
-    if (S->step >= tI && S->step < tF) {
-      double om = 2.0 * PI / (double)P->period;
-      double ph = om * (double)(S->step - tI) + P->theta;
+  {
+    double wc, ws;
+    if (orc_gg_weight(P, S->step, &wc, &ws)) {
       double sxy = sig[0][3] + sig[1][3] + sig[2][3] + sig[3][3] + sig[4][3];
-      S->gp_cos += sxy * cos(ph);
-      S->gp_sin += sxy * sin(ph);
+      S->gp_cos += sxy * wc;
+      S->gp_sin += sxy * ws;
       S->gp_count += 1;
     }
   }
@@ -1227,14 +1225,49 @@ void orc_stress(orc_sim *S, double out[5][6], double gg[2]) {
   for (int k = 0; k < 5; ++k)
     for (int c = 0; c < 6; ++c) { out[k][c] = S->sig_sum[k][c] / n; S->sig_sum[k][c] = 0.0; }
   S->sig_count = 0;
-  if (S->gp_count > 0 && S->p.g0_F != 0.0) {
-    double c = 2.0 / ((double)S->gp_count * S->p.g0_F);
-    gg[0] = -c * S->gp_cos;
-    gg[1] = c * S->gp_sin;
+  orc_gg_moduli(&S->p, S->gp_cos, S->gp_sin, S->gp_count, gg);
+}
+
+/* Eqs. (17)-(18) as a rectangle rule over whole observation periods of P steps: the
+ * integral (omega/pi) int_0^{2 pi/omega} dt f(t) over N periods becomes (2/(N P)) sum_t f(t).
+ * Step t enters with the phase omega (t - t_I) + Theta of eq. (16) (t_I = ncyc_I periods:
+ * the observation cycles restart the strain at the amplitude g0_F). */
+int orc_gg_weight(const orc_params *p, int64_t t, double *wc, double *ws) {
+  *wc = 0.0; *ws = 0.0;
+  if (p->shear_kind != 2) return 0;
+  int64_t tI = (int64_t)p->ncyc_I * p->period, tF = tI + (int64_t)p->ncyc_F * p->period;
+  if (t < tI || t >= tF) return 0;
+  double om = 2.0 * PI / (double)p->period;
+  double ph = om * (double)(t - tI) + p->theta;
+  *wc = cos(ph);
+  *ws = sin(ph);
+  return 1;
+}
+
+/* G' = -(2 / (n g0_F)) sum sigma_xy cos(phase), G'' = (2 / (n g0_F)) sum sigma_xy sin(phase)
+ * over the n observation steps summed so far (eqs. 17, 18); zero before the first. */
+void orc_gg_moduli(const orc_params *p, double sum_cos, double sum_sin, int64_t n, double gg[2]) {
+  if (n > 0 && p->g0_F != 0.0) {
+    double c = 2.0 / ((double)n * p->g0_F);
+    gg[0] = -c * sum_cos;
+    gg[1] = c * sum_sin;
   } else {
     gg[0] = 0.0; gg[1] = 0.0;
   }
 }
+
+/* G', G'' of a given shear-stress history: sxy[k] is the stress of step t0 + k. */
+void orc_gg_series(const orc_params *p, int64_t t0, int64_t n, const double *sxy, double gg[2]) {
+  double sc = 0.0, ss = 0.0;
+  int64_t cnt = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    double wc, ws;
+    if (orc_gg_weight(p, t0 + k, &wc, &ws)) { sc += sxy[k] * wc; ss += sxy[k] * ws; cnt += 1; }
+  }
+  orc_gg_moduli(p, sc, ss, cnt, gg);
+}
+
+void orc_quat_step(double q[4], const double W[3], double dt) { quat_step(q, W, dt); }
 
 int orc_set_walls(orc_sim *S, const int32_t *member) {
   const orc_params *P = &S->p;

@@ -159,6 +159,17 @@ void orc_implicit_solve(int32_t n, const double *m, const int32_t *fixed, const 
                         int32_t npairs, const int32_t *pi, const int32_t *pj, const double *zeta,
                         const double *nvec, const double *shift, double dt, int32_t sweeps,
                         double *U);
+/* G', G'' quadrature of eqs. (17)-(18) (rectangle rule over whole observation periods):
+ * orc_gg_weight gives cos and sin of the phase of step t and returns 1 if step t lies in the
+ * observation cycles (else 0); orc_gg_moduli turns the sums of sigma_xy times those weights
+ * over n observation steps into gg = {G', G''}; orc_gg_series does both for a stress
+ * history sxy[n] whose first entry is the stress of step t0.                              */
+int orc_gg_weight(const orc_params *p, int64_t t, double *wc, double *ws);
+void orc_gg_moduli(const orc_params *p, double sum_cos, double sum_sin, int64_t n, double gg[2]);
+void orc_gg_series(const orc_params *p, int64_t t0, int64_t n, const double *sxy, double gg[2]);
+/* One orientation update of a DEM substep: q <- normalize(q + dt/2 (0, W) (x) q), W the
+ * angular velocity in the space frame (the update the particle step applies).             */
+void orc_quat_step(double q[4], const double W[3], double dt);
 /* Eigenvalues of a symmetric 3x3 matrix (xx yy zz xy xz yz), descending (Jacobi). */
 void orc_sym3_eigen(const double a[6], double ev[3]);
 /* LE protocol at step t: offset s (wrapped to [0,lx)) and sliding velocity. */
