@@ -52,7 +52,10 @@ typedef enum {
   SUSP_EDEVICE = -3,    /* a HIP call failed                                            */
   SUSP_EUNSTABLE = -4,  /* mapped spheres overlap, non-finite particle state, a particle
                            exceeded the neighbour capacity, a node touches more than six
-                           spheres, or a sphere moved more than one node in one step     */
+                           spheres, a sphere moved more than one node in one step, a
+                           non-finite fluid density or velocity, or the fluid mass plus the
+                           ledger of covered nodes drifted by more than 1e-3 of the box's
+                           mass                                                           */
   SUSP_ESTATE = -5      /* a state buffer does not match the simulation                */
 } susp_status;
 
@@ -152,6 +155,15 @@ int susp_step(susp_sim *s, int64_t nsteps);
  * over the observation steps completed so far (0 if none).  Synchronises.                */
 int susp_stress(susp_sim *s, double out[5][6], double gg[2]);
 
+/* Health of the run since the previous call (or creation), then reset.  out[0] = fluid
+ * node-steps whose speed exceeded 0.3 c_s (past the low-Mach range of the lattice fluid; a
+ * node squeezed into a one-node gap between two surfaces passes it briefly in dense runs,
+ * so it is counted, not failed), out[1] = the largest |u| / c_s among them (0 if none),
+ * out[2] = the relative drift |M + L - M0| / M0 of the fluid mass M plus the ledger L of
+ * covered nodes at the last step against its value at the first step (or the last state
+ * load).  Synchronises.                                                                    */
+int susp_health(susp_sim *s, double out[3]);
+
 /* Walls (boundary 1): mean force per step of the suspension on the bottom and the top wall
  * since the previous call (or creation), then reset.  out[6] (host) = bottom x y z, top
  * x y z: the flat wall (momentum of the bounced populations, measured from the rest state
@@ -190,9 +202,22 @@ int susp_destroy(susp_sim *s);
 
 /* ---- state access (synchronising); used for checkpoints and parity checks ---- */
 /* Populations as full FP64 values n_q, [19][lz][ly][lx]; entries of solid nodes are
- * undefined on get and ignored on set.  Set rounds to the storage precision.             */
+ * undefined on get and ignored on set.  Set rounds to the storage precision.  Both stage
+ * one plane at a time through the simulation's spare population buffer (the one the next
+ * step overwrites) and allocate no device memory.                                         */
 int susp_get_populations(susp_sim *s, double *host);
 int susp_set_populations(susp_sim *s, const double *host);
+/* Running sums of the step's observables, for checkpoints and for checks that start two
+ * simulations from one state.  acc[0..29] = stress sums [5][6] (same order as susp_stress)
+ * since the previous susp_stress, acc[30] = the number of steps in them, acc[31], acc[32] =
+ * the sums of sigma_xy cos(phase) and sigma_xy sin(phase) over the observation steps so far
+ * (eqs. 17-18; the phase of eq. 16), acc[33] = their count, acc[34] = the mass ledger: fluid
+ * mass taken in by nodes that spheres covered minus the mass given back to released nodes
+ * (the fluid mass plus the ledger is conserved).  Set checks that every entry is finite and
+ * the counts are not negative (SUSP_EINVAL).  Both synchronise.                           */
+enum { SUSP_NACC = 35 };
+int susp_get_accumulators(susp_sim *s, double acc[SUSP_NACC]);
+int susp_set_accumulators(susp_sim *s, const double acc[SUSP_NACC]);
 /* Particle state: positions, velocities, angular velocities [n][3], orientations [n][4]
  * (any pointer may be NULL on get).  Set re-maps the spheres (no cover/uncover).         */
 int susp_get_particles(susp_sim *s, double *pos, double *vel, double *omega, double *quat);
@@ -247,12 +272,16 @@ int susp_get_derived(susp_sim *s, double out[10]);
  * 0, the null stream or profiling: every kernel is launched one by one.                   */
 int susp_use_graphs(susp_sim *s, int32_t pairs);
 
-/* Timing of the lattice kernel (fused stream/bounce-back/collide): while enabled, every
- * step records a pair of HIP events around that kernel on the simulation's stream.
- * susp_profile_read synchronises, returns the summed kernel time in milliseconds and the
- * number of timed launches since the previous read, and resets both.                     */
+/* Timing of the lattice step with HIP events on the simulation's stream: while enabled,
+ * every step records events around the bounce-back kernel (k_links: the links' bounce-back
+ * values and exchanged momentum, eqs. 6-10) and around the streaming kernel (k_stream: pull,
+ * collision, fluid stress; eqs. 3-5), the step's dominant kernel.  susp_profile_read
+ * synchronises, returns the summed k_stream time in milliseconds and the number of timed
+ * steps since the previous read, and resets both; susp_profile_read_parts returns ms[0] =
+ * the summed k_links time and ms[1] = the summed k_stream time the same way.               */
 int susp_profile(susp_sim *s, int32_t enable);
 int susp_profile_read(susp_sim *s, double *ms_total, int64_t *launches);
+int susp_profile_read_parts(susp_sim *s, double ms[2], int64_t *launches);
 
 /* ---- Batches: many independent simulations sharing one GPU --------------------------
  * A batch holds up to max_jobs simulations of any box size and parameters, each with its

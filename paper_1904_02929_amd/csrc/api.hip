@@ -231,8 +231,8 @@ static int resolve(const susp_params *p, Sim &s) {
   s.cells.iy = nc[1] / (double)p->ly;
   s.cells.iz = nc[2] / (double)p->lz;
   s.ncell = nc[0] * nc[1] * nc[2];
-  // bricks of 64 x BY x BZ nodes for the lattice kernel: as large as possible while
-  // leaving about 2048 of them to spread over the 256 compute units
+  // bricks of 64 x BY x BZ nodes for the lattice kernel: at most 64 x 8 x 8, smaller until
+  // at least 2048 of them spread over the 256 compute units
   s.bxn = (p->lx + 63) / 64;
   auto nbr = [&]() { return s.bxn * ((p->ly + s.BY - 1) / s.BY) * ((p->lz + s.BZ - 1) / s.BZ); };
   if (p->brick_y || p->brick_z) {
@@ -240,7 +240,7 @@ static int resolve(const susp_params *p, Sim &s) {
       return fail(SUSP_EINVAL, "brick_y must be a positive multiple of 4 and brick_z positive (<= 1024)");
     s.BY = p->brick_y; s.BZ = p->brick_z;
   } else {
-    s.BY = 16; s.BZ = 16;
+    s.BY = 8; s.BZ = 8;
     while (nbr() < 2048 && (s.BY > 4 || s.BZ > 1)) {
       if (s.BZ >= s.BY && s.BZ > 1) s.BZ /= 2;
       else if (s.BY > 4) s.BY /= 2;
@@ -250,7 +250,6 @@ static int resolve(const susp_params *p, Sim &s) {
   s.byn = (p->ly + s.BY - 1) / s.BY;
   s.bzn = (p->lz + s.BZ - 1) / s.BZ;
   s.nbricks = nbr();
-  s.lbm_blocks = s.nbricks;
   return SUSP_OK;
 }
 
@@ -267,8 +266,18 @@ static size_t carve(Sim &s, char *base) {
   const size_t cs = s.precision == 0 ? 8 : 4;
   const size_t n = (size_t)s.n;
   for (int b = 0; b < 2; ++b) s.f[b] = take(NQ * s.plane * es);
+  // the ghost owner planes right after the owner map: the lattice kernel reads both through
+  // one buffer resource
   s.own = (int32_t *)take((size_t)s.nodes * 4);
   s.gown = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
+  // link entries, 384 slots per 256-node row segment: a node links to at most six spheres,
+  // but only nodes next to a surface link at all, and packings stay far below 1.5 entries
+  // per node (overflow is reported as SUSP_EUNSTABLE)
+  s.lsegs = n ? ((s.lx + 255) / 256) * s.ly * s.lz : 0;
+  s.lcnt = (int32_t *)take((size_t)s.lsegs * 4);
+  s.lnode = (int32_t *)take((size_t)s.lsegs * 384 * 4);
+  s.lsph = (int32_t *)take((size_t)s.lsegs * 384 * 4);
+  s.lmask = (int32_t *)take((size_t)s.lsegs * 384 * 4);
   s.gval = take((size_t)2 * 5 * s.lx * s.lz * cs);
   for (int b = 0; b < 2; ++b) {
     s.R[b] = (double *)take(n * 3 * 8);
@@ -278,12 +287,7 @@ static size_t carve(Sim &s, char *base) {
     s.hyd[b] = (double *)take(n * HYD * 8);
   }
   s.R0 = (double *)take(n * 3 * 8);
-  s.bt_key = (int32_t *)take((size_t)s.nbricks * 128 * 4);
-  s.bt_cnt = (int32_t *)take((size_t)s.nbricks * 4);
-  s.sp_cnt = (int32_t *)take(n * 4);
-  s.sp_ent = (int32_t *)take(n * 64 * 4);
-  s.bt_val = (double *)take((size_t)s.nbricks * 128 * HYD * 8);
-  s.hyd_fb = (double *)take(n * HYD * 8);
+  s.hacc = (unsigned long long *)take(n * HYD * 2 * 8);
   s.a = (double *)take(n * 8);
   s.m = (double *)take(n * 8);
   s.I = (double *)take(n * 8);
@@ -318,8 +322,8 @@ static size_t carve(Sim &s, char *base) {
     s.cacc = (double *)take((size_t)((s.cbins + 1) * 6 + 8) * 8);
     s.cout = (double *)take((size_t)(5 * s.cbins + 12) * 8);
   }
-  s.pineq = (double *)take((size_t)s.lbm_blocks * 6 * 8);
-  s.acc = (double *)take((size_t)(128 + 128 * 32) * 8);
+  s.pin = (double *)take((size_t)s.nbricks * 8 * 8);
+  s.acc = (double *)take((size_t)ACC_DOUBLES * 8);
   s.flags = (int32_t *)take(256);
   s.clk_tab = (ClockEntry *)take((size_t)CLK_CAP * sizeof(ClockEntry));
   s.clk = (Clock *)take(sizeof(Clock));
@@ -333,12 +337,23 @@ extern "C" size_t susp_footprint_bytes(const susp_params *p) {
   return carve(s, nullptr);
 }
 
+static int reset_mass_reference(Sim &s);
+
 static int remap(Sim &s) {
   // both maps to fluid, then claim the current footprints (no cover/uncover)
+  int rc = reset_mass_reference(s);
+  if (rc) return rc;
   HIPCHK(launch_fill_i32(s.own, (size_t)s.nodes, -1, s.stream));
   double off, ule;
   protocol(s, s.step, &off, &ule);
   HIPCHK(launch_map_full(&s, make_box(s, off, ule)));
+  return SUSP_OK;
+}
+
+// The next step takes a new reference for the conserved fluid mass + ledger (the state was
+// replaced).
+static int reset_mass_reference(Sim &s) {
+  HIPCHK(launch_fill_f64(s.acc + 65, 4, 0.0, s.stream));
   return SUSP_OK;
 }
 
@@ -431,13 +446,12 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
               launch_fill_i32(s.hon[b], n * NCAP, 0, s.stream)))
       return bail(fail(SUSP_EDEVICE, "fill"));
   }
-  if (n && launch_fill_f64(s.hyd_fb, n * HYD, 0.0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
-  if (n && launch_fill_i32(s.sp_cnt, n, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  if (n && launch_fill_i32((int32_t *)s.hacc, n * HYD * 4, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   if (n && (launch_fill_f64(s.pst, n * PST, 0.0, s.stream) || launch_fill_f64(s.dp, n * 8, 0.0, s.stream) ||
             launch_fill_i32(s.hstart, n * NCAP, 0, s.stream)))
     return bail(fail(SUSP_EDEVICE, "fill"));
-  if (launch_fill_f64(s.acc, 128 + 128 * 32, 0.0, s.stream) || launch_fill_i32(s.flags, 64, 0, s.stream) ||
-      launch_fill_f64(s.pineq, (size_t)s.lbm_blocks * 6, 0.0, s.stream))
+  if (launch_fill_f64(s.acc, ACC_DOUBLES, 0.0, s.stream) || launch_fill_i32(s.flags, 64, 0, s.stream) ||
+      launch_fill_f64(s.pin, (size_t)s.nbricks * 8, 0.0, s.stream))
     return bail(fail(SUSP_EDEVICE, "fill"));
   if (launch_fill_i32(s.cell_start, (size_t)s.ncell + 1, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   if (s.boundary == 1 && (launch_fill_f64(s.wacc, 8, 0.0, s.stream) || (n && launch_fill_f64(s.wfs, n * 3, 0.0, s.stream))))
@@ -457,7 +471,7 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
 
 extern "C" int susp_destroy(susp_sim *h) {
   if (!h) return SUSP_OK;
-  for (int i = 0; i < 2 * h->s.prof_cap; ++i) (void)hipEventDestroy(h->s.prof_ev[i]);
+  for (int i = 0; i < PROF_EV * h->s.prof_cap; ++i) (void)hipEventDestroy(h->s.prof_ev[i]);
   free(h->s.prof_ev);
   (void)hipStreamSynchronize(h->s.stream);
   if (h->s.gexec) (void)hipGraphExecDestroy(h->s.gexec);
@@ -505,25 +519,27 @@ static int one_step(Sim &s) {
   HIPCHK(launch_clock(&s, 0));
   s.hcur ^= 1;
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
-  HIPCHK(launch_brick_lists(&s));
   if (s.boundary == 1) HIPCHK(launch_walls(&s));
   else HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
+  HIPCHK(launch_linklist(&s));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
       const int cap = s.prof_cap ? 2 * s.prof_cap : 256;
-      hipEvent_t *nev = (hipEvent_t *)realloc(s.prof_ev, sizeof(hipEvent_t) * 2 * cap);
+      hipEvent_t *nev = (hipEvent_t *)realloc(s.prof_ev, sizeof(hipEvent_t) * PROF_EV * cap);
       if (!nev) return fail(SUSP_ENOMEM, "event pool");
-      for (int i = 2 * s.prof_cap; i < 2 * cap; ++i) HIPCHK(hipEventCreate(&nev[i]));
+      for (int i = PROF_EV * s.prof_cap; i < PROF_EV * cap; ++i) HIPCHK(hipEventCreate(&nev[i]));
       s.prof_ev = nev;
       s.prof_cap = cap;
     }
-    ev = &s.prof_ev[2 * s.prof_used++];
+    ev = &s.prof_ev[PROF_EV * s.prof_used++];
     HIPCHK(hipEventRecord(ev[0], s.stream));
   }
-  HIPCHK(launch_lbm(&s, b));
+  HIPCHK(launch_links(&s, b));
   if (ev) HIPCHK(hipEventRecord(ev[1], s.stream));
-  HIPCHK(launch_hydro_gather(&s, b));
+  HIPCHK(launch_lbm(&s, b));
+  if (ev) HIPCHK(hipEventRecord(ev[2], s.stream));
+  HIPCHK(launch_hydro_final(&s));
   s.cur ^= 1;
   if (s.n) {
     HIPCHK(launch_pairs(&s, b));
@@ -619,9 +635,10 @@ int check_flags(susp_sim *h) {
   int rc = read_flags(h->s, &fl);
   if (rc) return rc;
   if (fl) {
-    return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite, 4 neighbour "
-                "overflow, 8 node touching more than six spheres, 16 sphere moved more than a node in "
-                "a step)", fl);
+    return fail(SUSP_EUNSTABLE, "instability flags 0x%x (1 mapped overlap, 2 non-finite particle state, "
+                "4 neighbour overflow, 8 node touching more than six spheres, 16 sphere moved more than "
+                "a node in a step, 32 fluid density or velocity not finite, 64 fluid mass plus "
+                "ledger drifted)", fl);
   }
   return SUSP_OK;
 }
@@ -657,6 +674,28 @@ extern "C" int susp_stress(susp_sim *h, double out[5][6], double gg[2]) {
   return SUSP_OK;
 }
 
+extern "C" int susp_health(susp_sim *h, double out[3]) {
+  if (!h || !out) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  int32_t w[4];
+  double a[5];
+  HIPCHK(hipMemcpyAsync(w, s.flags + FL_HEALTH, sizeof w, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipMemcpyAsync(a, s.acc + 64, sizeof a, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  uint64_t nfast;
+  memcpy(&nfast, w, 8);
+  float umax2;
+  memcpy(&umax2, &w[2], 4);
+  out[0] = (double)nfast;
+  out[1] = sqrt((double)umax2 * 3.0);  // |u| / c_s, c_s^2 = 1/3
+  // fluid mass of the last step a[1] with the ledger before that step's covers a[4], against
+  // the reference a[2] (taken at the first step after creation or a state load, a[3] = 1)
+  out[2] = a[3] != 0.0 && a[2] > 0 ? fabs(a[1] + a[4] - a[2]) / a[2] : 0.0;
+  HIPCHK(launch_fill_i32(s.flags + FL_HEALTH, 4, 0, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
 extern "C" int susp_wall_force(susp_sim *h, double out[6]) {
   if (!h || !out) return fail(SUSP_EINVAL, "NULL argument");
   Sim &s = h->s;
@@ -684,32 +723,57 @@ extern "C" int susp_contact_stats(susp_sim *h, int32_t nbins, double *hist, doub
 }
 
 // ---------------------------------------------------------------------------------------
+// The spare population buffer (the one the next step writes) stages FP64 values one plane
+// at a time: 19 planes of the storage type hold at least one FP64 plane plus its padding, so
+// no device memory is allocated (a batch's other jobs never wait for an allocation).
 extern "C" int susp_get_populations(susp_sim *h, double *host) {
   if (!h || !host) return fail(SUSP_EINVAL, "NULL argument");
   Sim &s = h->s;
-  double *tmp = nullptr;
-  const size_t bytes = (size_t)NQ * s.nodes * 8;
-  HIPCHK(hipMalloc((void **)&tmp, bytes));
-  hipError_t e = launch_pop_convert(&s, tmp, 0);
-  if (!e) e = hipMemcpyAsync(host, tmp, bytes, hipMemcpyDeviceToHost, s.stream);
-  if (!e) e = hipStreamSynchronize(s.stream);
-  (void)hipFree(tmp);
-  if (e) return fail(SUSP_EDEVICE, "get_populations: %s", hipGetErrorString(e));
+  double *stage = (double *)s.f[1 - s.cur];
+  for (int q = 0; q < NQ; ++q) {
+    HIPCHK(launch_pop_plane(&s, stage, q, 0));
+    HIPCHK(hipMemcpyAsync(host + (size_t)q * s.nodes, stage, (size_t)s.nodes * 8, hipMemcpyDeviceToHost, s.stream));
+  }
+  HIPCHK(hipStreamSynchronize(s.stream));
   return SUSP_OK;
 }
 
 extern "C" int susp_set_populations(susp_sim *h, const double *host) {
   if (!h || !host) return fail(SUSP_EINVAL, "NULL argument");
   Sim &s = h->s;
-  double *tmp = nullptr;
-  const size_t bytes = (size_t)NQ * s.nodes * 8;
+  double *stage = (double *)s.f[1 - s.cur];
   HIPCHK(hipStreamSynchronize(s.stream));
-  HIPCHK(hipMalloc((void **)&tmp, bytes));
-  hipError_t e = hipMemcpyAsync(tmp, host, bytes, hipMemcpyHostToDevice, s.stream);
-  if (!e) e = launch_pop_convert(&s, tmp, 1);
-  if (!e) e = hipStreamSynchronize(s.stream);
-  (void)hipFree(tmp);
-  if (e) return fail(SUSP_EDEVICE, "set_populations: %s", hipGetErrorString(e));
+  for (int q = 0; q < NQ; ++q) {
+    HIPCHK(hipMemcpyAsync(stage, host + (size_t)q * s.nodes, (size_t)s.nodes * 8, hipMemcpyHostToDevice, s.stream));
+    HIPCHK(launch_pop_plane(&s, stage, q, 1));
+  }
+  int rc = reset_mass_reference(s);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+// acc layout on the device: [0,30) stress of the last step, [30,60) stress sums, 60 their
+// count, 61 sum sigma_xy cos, 62 sum sigma_xy sin, 63 observation steps, 64 mass ledger
+extern "C" int susp_get_accumulators(susp_sim *h, double out[SUSP_NACC]) {
+  if (!h || !out) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  HIPCHK(hipMemcpyAsync(out, s.acc + 30, SUSP_NACC * 8, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+extern "C" int susp_set_accumulators(susp_sim *h, const double in[SUSP_NACC]) {
+  if (!h || !in) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  for (int k = 0; k < SUSP_NACC; ++k)
+    if (!isfinite(in[k])) return fail(SUSP_EINVAL, "accumulator %d is not finite", k);
+  if (in[30] < 0 || in[33] < 0) return fail(SUSP_EINVAL, "negative step counts");
+  HIPCHK(hipStreamSynchronize(s.stream));
+  HIPCHK(hipMemcpy(s.acc + 30, in, SUSP_NACC * 8, hipMemcpyHostToDevice));
+  int rc = reset_mass_reference(s);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s.stream));
   return SUSP_OK;
 }
 
@@ -890,25 +954,22 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
         }
     }
   } else if (kind == SUSP_LIST_LINKS) {
+    // staged through the spare population buffer: the ghost owners of the current offset
+    // after one plane of link owners (the buffer holds far more than nodes + 2 lx lz words)
     double off, ule;
     protocol(s, s.step, &off, &ule);
     const Box b = make_box(s, off, ule);
-    int32_t *g = nullptr, *lk = nullptr;
-    HIPCHK(hipMalloc((void **)&g, (size_t)2 * s.lx * s.lz * 4));
-    hipError_t e = hipMalloc((void **)&lk, (size_t)NQ * s.nodes * 4);
-    if (!e && n) e = launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr);
-    if (!e) e = n && s.boundary == 0 ? launch_ghosts(&s, b, g, s.gval, 0, nullptr, 0)
-                                     : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream);
-    if (!e) e = launch_link_enum(&s, g, lk, b);
-    std::vector<int32_t> all;
-    if (!e) {
-      all.resize((size_t)NQ * s.nodes);
-      e = hipMemcpyAsync(all.data(), lk, all.size() * 4, hipMemcpyDeviceToHost, s.stream);
+    int32_t *lk = (int32_t *)s.f[1 - s.cur];
+    int32_t *g = lk + ((size_t)s.nodes + 63) / 64 * 64;
+    if (n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
+    HIPCHK(n && s.boundary == 0 ? launch_ghosts(&s, b, g, s.gval, 0, nullptr, 0)
+                                : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream));
+    std::vector<int32_t> all((size_t)NQ * s.nodes, -1);
+    for (int q = 1; q < NQ; ++q) {
+      HIPCHK(launch_link_enum(&s, g, lk, q));
+      HIPCHK(hipMemcpyAsync(all.data() + (size_t)q * s.nodes, lk, (size_t)s.nodes * 4, hipMemcpyDeviceToHost, s.stream));
     }
-    if (!e) e = hipStreamSynchronize(s.stream);
-    (void)hipFree(g);
-    (void)hipFree(lk);
-    if (e) return fail(SUSP_EDEVICE, "link enumeration: %s", hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(s.stream));
     for (int64_t node = 0; node < s.nodes; ++node)
       for (int q = 1; q < NQ; ++q) {
         const int32_t o = all[(size_t)q * s.nodes + node];
@@ -946,16 +1007,26 @@ extern "C" int susp_profile(susp_sim *h, int32_t enable) {
 }
 
 extern "C" int susp_profile_read(susp_sim *h, double *ms_total, int64_t *launches) {
-  if (!h || !ms_total || !launches) return fail(SUSP_EINVAL, "NULL argument");
+  double parts[2];
+  int rc = susp_profile_read_parts(h, parts, launches);
+  if (rc == SUSP_OK && ms_total) *ms_total = parts[1];
+  return rc;
+}
+
+extern "C" int susp_profile_read_parts(susp_sim *h, double ms[2], int64_t *launches) {
+  if (!h || !ms || !launches) return fail(SUSP_EINVAL, "NULL argument");
   Sim &s = h->s;
   HIPCHK(hipStreamSynchronize(s.stream));
-  double tot = 0.0;
+  double tot[2] = {0.0, 0.0};
   for (int i = 0; i < s.prof_used; ++i) {
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, s.prof_ev[2 * i], s.prof_ev[2 * i + 1]));
-    tot += ms;
+    for (int k = 0; k < 2; ++k) {
+      float t = 0.0f;
+      HIPCHK(hipEventElapsedTime(&t, s.prof_ev[PROF_EV * i + k], s.prof_ev[PROF_EV * i + k + 1]));
+      tot[k] += t;
+    }
   }
-  *ms_total = tot;
+  ms[0] = tot[0];
+  ms[1] = tot[1];
   *launches = s.prof_used;
   s.prof_used = 0;
   return SUSP_OK;

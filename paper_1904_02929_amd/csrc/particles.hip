@@ -1283,41 +1283,46 @@ hipError_t launch_map_update(Sim *s, const Box &box, int phase) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Stress reduction.  Stage 1: block b sums a contiguous slice of the lattice-block partials
-// and of the spheres into part[b][32]; stage 2 (one block) adds the slices in order.
-constexpr int RED_BLOCKS = 128;
-constexpr int RED_W = 32;  // pineq 6 | hydro stresslet 6 | pair 18 | ledger 1 | pad
+// Stress reduction.  Stage 1: block b sums a contiguous slice of the lattice-brick partials
+// and of the spheres into part[b][RED_W]; stage 2 (one block) adds the slices in order.
+// part: pineq 6 | hydro stresslet 6 | pair 18 | ledger 1 | fluid mass deviation 1 | fluid nodes 1
+constexpr int RED_N = 33;
 
-__global__ __launch_bounds__(256) void k_reduce1(const double *pineq, int nblk, const double *hyd,
+__global__ __launch_bounds__(256) void k_reduce1(const double *pin, int nblk, const double *hyd,
                                                  const double *pst, const double *dp, int n,
                                                  double *part) {
-  double v[31];
-  for (int c = 0; c < 31; ++c) v[c] = 0.0;
+  double v[RED_N];
+  for (int c = 0; c < RED_N; ++c) v[c] = 0.0;
   const int b = blockIdx.x;
   const int pb0 = (int)((int64_t)nblk * b / RED_BLOCKS), pb1 = (int)((int64_t)nblk * (b + 1) / RED_BLOCKS);
-  for (int t = pb0 + threadIdx.x; t < pb1; t += blockDim.x)
-    for (int c = 0; c < 6; ++c) v[c] += pineq[(size_t)t * 6 + c];
+  for (int t = pb0 + threadIdx.x; t < pb1; t += blockDim.x) {
+    for (int c = 0; c < 6; ++c) v[c] += pin[(size_t)t * 8 + c];
+    v[31] += pin[(size_t)t * 8 + 6];
+    v[32] += pin[(size_t)t * 8 + 7];
+  }
   const int s0 = (int)((int64_t)n * b / RED_BLOCKS), s1 = (int)((int64_t)n * (b + 1) / RED_BLOCKS);
   for (int p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
     for (int c = 0; c < 6; ++c) v[6 + c] += hyd[(size_t)p * HYD + 6 + c];
     for (int c = 0; c < PST; ++c) v[12 + c] += pst[(size_t)p * PST + c];
     v[30] += dp[(size_t)p * 8 + 6];
   }
-  __shared__ double sh[31 * 16];
-  block_sum<31>(v, sh);
+  __shared__ double sh[RED_N * 16];
+  block_sum<RED_N>(v, sh);
   if (threadIdx.x == 0)
-    for (int c = 0; c < 31; ++c) part[(size_t)b * RED_W + c] = v[c];
+    for (int c = 0; c < RED_N; ++c) part[(size_t)b * RED_W + c] = v[c];
 }
 
-// acc layout: [0,30) sig_last, [30,60) sig_sum, 60 count, 61 gp_cos, 62 gp_sin, 63 gp_count,
-// 64 ledger
 // cf: fluid stress factor -(1 - 1/(2 tau)) / V; cfb the same with tau_bulk for the trace
-// (multi-eigenvalue collision, split = 1)
+// (multi-eigenvalue collision, split = 1).  The fluid mass plus the ledger is conserved by
+// the method (bounce-back links pair up along every lattice line, covered and released
+// nodes pass through the ledger); a drift above mass_tol from its value at the first step
+// reduced raises FL_MASS.
 __global__ void k_reduce2(const double *part, double *acc, double cf, double cfb, int split, double invV,
-                          double invns, const Clock *clk, int has_particles) {
-  __shared__ double v[32];
+                          double invns, const Clock *clk, int has_particles, double rho0, double mass_tol,
+                          int32_t *flags) {
+  __shared__ double v[RED_N];
   const int c = threadIdx.x;
-  if (c < 31) {
+  if (c < RED_N) {
     double x = 0.0;
     for (int b = 0; b < RED_BLOCKS; ++b) x += part[(size_t)b * RED_W + c];  // fixed order
     v[c] = x;
@@ -1339,18 +1344,30 @@ __global__ void k_reduce2(const double *part, double *acc, double cf, double cfb
   acc[60] += 1.0;
   const ClockEntry &ce = clk->cur;
   if (ce.gphase) { acc[61] += sxy * ce.gcos; acc[62] += sxy * ce.gsin; acc[63] += 1.0; }
+  // the lattice kernel measured the fluid mass before this step's map update, so it pairs
+  // with the ledger as it stood before this step's covers and releases
+  const double mass = v[31] + v[32] * rho0;
+  acc[65] = mass;
+  if (acc[67] == 0.0) {
+    acc[66] = mass + acc[64];
+    acc[67] = 1.0;
+  } else if (!(fabs(mass + acc[64] - acc[66]) <= mass_tol)) {
+    atomicOr(flags, FL_MASS);
+  }
+  acc[68] = acc[64];  // the ledger that pairs with this step's fluid mass
   acc[64] += v[30];
 }
 
 hipError_t launch_stress(Sim *s) {
-  double *part = s->acc + 128;
-  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, s->stream, s->pineq,
-                     s->lbm_blocks, s->hyd[s->hcur], s->pst, s->dp, s->n, part);
+  double *part = s->acc + ACC_PART;
+  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, s->stream, s->pin,
+                     s->nbricks, s->hyd[s->hcur], s->pst, s->dp, s->n, part);
   const double V = (double)s->lx * s->ly * s->lz;
   const double cf = -(1.0 - 0.5 / s->tau) / V;
   const double cfb = -(1.0 - 0.5 / s->tau_bulk) / V;
   hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, cfb, s->collision, 1.0 / V,
-                     1.0 / (double)s->n_sub, s->clk, s->n > 0 ? 1 : 0);
+                     1.0 / (double)s->n_sub, s->clk, s->n > 0 ? 1 : 0, s->rho0, MASS_TOL * V * s->rho0,
+                     s->flags);
   return hipGetLastError();
 }
 

@@ -24,6 +24,24 @@ constexpr int NQ = 19;
 constexpr int NCAP = 48;        // neighbour capacity per sphere
 constexpr int HYD = 13;         // F[3] T[3] S[6] nlinks  (per-sphere hydrodynamic sums)
 constexpr int PST = 18;         // lubrication, contact, DLVO stress partials (6 each)
+// acc (FP64): [0,30) stress of the last step, [30,60) stress sums, 60 their count, 61 sum
+// sigma_xy cos, 62 sum sigma_xy sin, 63 observation steps, 64 mass ledger, 65 fluid mass of
+// the last step, 66 reference of the conserved fluid mass + ledger, 67 reference taken (1),
+// 68 the ledger that pairs with the fluid mass of the last step;
+// from ACC_PART on, the partial sums of the stress reduction (RED_BLOCKS x RED_W)
+constexpr int RED_BLOCKS = 128;
+constexpr int RED_W = 40;
+constexpr int ACC_PART = 128;
+constexpr int ACC_DOUBLES = ACC_PART + RED_BLOCKS * RED_W;
+// largest drift of the conserved fluid mass + ledger, relative to the box's mass, before
+// FL_MASS (rounding and the sliding boundary drift far less; this catches a broken run)
+constexpr double MASS_TOL = 1e-3;
+// instability flags (SUSP_EUNSTABLE)
+constexpr int FL_OVERLAP = 1, FL_NONFINITE = 2, FL_NEIGHBOURS = 4, FL_LINKS = 8, FL_JUMP = 16,
+              FL_FLUID = 32, FL_MASS = 64;
+// the flags block (64 int32) also holds, from word FL_HEALTH on, the health counters: fluid
+// node-steps above 0.3 c_s (uint64) and the largest u^2 seen (float bits)
+constexpr int FL_HEALTH = 32;
 
 // D3Q19: 0 rest, 1..6 axes, 7..18 face diagonals; opposite of odd q is q+1.
 __host__ __device__ constexpr int cx(int q) {
@@ -114,6 +132,7 @@ struct Clock {
   int32_t idx, pad;
 };
 constexpr int CLK_CAP = 4096;  // steps per table upload
+constexpr int PROF_EV = 3;     // timing events per profiled step
 
 // Box of the current step (next = 0: offset s, velocity ule) or of the next one (s1, ule1)
 // from the device clock; without a clock the box is used as given.
@@ -137,11 +156,13 @@ struct Sim;
 hipError_t launch_init_populations(Sim *s);
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,
                          int lists);
+hipError_t launch_linklist(Sim *s);
+hipError_t launch_links(Sim *s, const Box &b);
 hipError_t launch_lbm(Sim *s, const Box &b);
-hipError_t launch_hydro_gather(Sim *s, const Box &b);
-hipError_t launch_brick_lists(Sim *s);
+hipError_t launch_hydro_final(Sim *s);
 hipError_t launch_pop_convert(Sim *s, double *dev64, int to_storage);
-hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[19][nodes]*/, const Box &b);
+hipError_t launch_pop_plane(Sim *s, double *dev64, int q, int to_storage);
+hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[nodes]*/, int q);
 // ---- launchers (particles.hip) ----
 hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch);
 hipError_t launch_pairs(Sim *s, const Box &b);
@@ -185,8 +206,7 @@ struct Sim {
   H16 h16;                 // FP16 storage scale 2^k and its inverse
   Cells cells;
   int ncell;
-  int lbm_blocks;  // lattice bricks (= partial sums of the fluid stress)
-  int bxn, byn, bzn, BY, BZ, nbricks;
+  int bxn, byn, bzn, BY, BZ, nbricks;  // lattice-kernel bricks of 64 x BY x BZ nodes
   // device block
   void *block;
   int owns_block;
@@ -195,6 +215,10 @@ struct Sim {
   void *f[2];
   int cur;  // index of the buffer holding the current state
   int32_t *own;  // owner map: sphere id of every node, -1 fluid
+  // links of the step (k_linklist): one entry per fluid node and sphere it links to
+  int32_t *lcnt;                  // [lsegs] entries of each 256-node row segment
+  int32_t *lnode, *lsph, *lmask;  // [lsegs][384] node, sphere, link directions (bit q)
+  int lsegs;
   int32_t *gown;
   void *gval;
   // particles (FP64)
@@ -204,13 +228,7 @@ struct Sim {
   double *a, *m, *I, *amap;
   double *hyd[2];
   int hcur;
-  int32_t *bt_key;  // [nbricks][128] spheres listed for each brick (k_brick_lists), then
-                    // the keys of its link table (k_lbm; -1 empty)
-  int32_t *bt_cnt;  // [nbricks] number of spheres listed for each brick
-  int32_t *sp_cnt;  // [n] table entries with links per sphere (k_lbm appends, gather clears)
-  int32_t *sp_ent;  // [n][64] those entries, brick * 128 + slot
-  double *bt_val;   // [nbricks][128][HYD]
-  double *hyd_fb;   // [n][HYD] overflow of full brick tables
+  unsigned long long *hacc;  // [n][HYD][2] fixed-point link sums of the step (k_lbm)
   double *pst;   // [n][PST]
   double *dp;    // [n][8] cover/uncover momentum, angular momentum, mass
   // lists
@@ -233,8 +251,9 @@ struct Sim {
   double *cacc;              // [cbins + 1][6] sums, then the total stress sum [6], samples
   double *cout;              // [5 * cbins + 12] read-out staging
   // reductions
-  double *pineq;  // [lbm_blocks][6]
-  double *acc;    // sig_last[30] sig_sum[30] count gp_cos gp_sin gp_count ledger
+  double *pin;    // [nbricks][8] fluid stress partials (6), mass deviation, fluid nodes
+  double *acc;    // sig_last[30] sig_sum[30] count gp_cos gp_sin gp_count ledger, fluid mass
+                  // deviation, conserved-mass reference and its flag; then reduction partials
   int32_t *flags;
   // clock
   int64_t step;
@@ -248,7 +267,7 @@ struct Sim {
   // optional timing of the lattice kernel with HIP events on the simulation's stream
   int prof_on;
   int prof_used, prof_cap;
-  hipEvent_t *prof_ev;  // [2 * prof_cap]: start, end of each timed launch
+  hipEvent_t *prof_ev;  // [PROF_EV * prof_cap]: before k_links, before k_stream, after it
 };
 
 // ---- stepping helpers shared by the single-simulation and batch entry points (api.hip) ----

@@ -78,6 +78,10 @@ def lib():
         L.susp_get_hydro.argtypes = [vp, _PD, _PD, _PD, _PI]
         L.susp_get_lists.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_size_t)]
         L.susp_get_derived.argtypes = [vp, _PD]
+        L.susp_get_accumulators.argtypes = [vp, _PD]
+        L.susp_profile_read_parts.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
+        L.susp_health.argtypes = [vp, _PD]
+        L.susp_set_accumulators.argtypes = [vp, _PD]
         L.susp_use_graphs.argtypes = [vp, C.c_int32]
         L.susp_profile.argtypes = [vp, C.c_int32]
         L.susp_profile_read.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
@@ -205,10 +209,16 @@ class Simulation:
         _chk(lib().susp_profile(self.h, 1 if enable else 0))
 
     def profile_read(self):
-        """(summed lattice-kernel milliseconds, number of launches) since the last read."""
+        """(summed k_stream milliseconds, number of timed steps) since the last read."""
         ms = C.c_double(); n = C.c_int64()
         _chk(lib().susp_profile_read(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def profile_read_parts(self):
+        """(summed k_links ms, summed k_stream ms, number of timed steps) since the last read."""
+        ms = np.zeros(2); n = C.c_int64()
+        _chk(lib().susp_profile_read_parts(self.h, _pd(ms), C.byref(n)))
+        return float(ms[0]), float(ms[1]), n.value
 
     def stress(self):
         out = np.zeros((5, 6)); gg = np.zeros(2)
@@ -238,6 +248,24 @@ class Simulation:
         f = np.ascontiguousarray(f, dtype=np.float64)
         assert f.shape == (19,) + self.shape
         _chk(lib().susp_set_populations(self.h, _pd(f)))
+
+    def health(self):
+        """(fluid node-steps above 0.3 c_s, largest |u| / c_s among them, relative drift of
+        the conserved fluid mass + ledger) since the last call (susp_health)."""
+        out = np.zeros(3)
+        _chk(lib().susp_health(self.h, _pd(out)))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def get_accumulators(self):
+        """Stress sums [5][6], their step count, the G', G'' sums and count, and the mass
+        ledger (susp_get_accumulators)."""
+        a = np.zeros(35)
+        _chk(lib().susp_get_accumulators(self.h, _pd(a)))
+        return a
+
+    def set_accumulators(self, a):
+        a = np.ascontiguousarray(a, np.float64).reshape(35)
+        _chk(lib().susp_set_accumulators(self.h, _pd(a)))
 
     def get_particles(self):
         n = self.n

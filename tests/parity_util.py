@@ -56,6 +56,16 @@ def load_oracle_state(o, g, precision):
     g.set_populations(f)
     hi, hj, hx = o.history()
     g.set_history(hi, hj, hx)
+    g.set_accumulators(oracle_accumulators(o))
+
+
+def oracle_accumulators(o):
+    """The oracle's running sums in the library's accumulator layout: stress sums [5][6],
+    their count, the G', G'' sums and count, the mass ledger."""
+    s = o.s
+    acc = [s.sig_sum[k][c] for k in range(5) for c in range(6)]
+    acc += [float(s.sig_count), s.gp_cos, s.gp_sin, float(s.gp_count), s.ledger]
+    return np.array(acc)
 
 
 def moments(f):
@@ -63,6 +73,16 @@ def moments(f):
     rho = f.sum(0)
     j = np.tensordot(c.T.astype(np.float64), f, axes=([1], [0]))
     return rho, j / rho
+
+
+def equilibrium(rho, u):
+    """Second-order D3Q19 equilibrium of every node, [19][nodes] (written out here from
+    the lattice's velocities and weights, independent of both implementations)."""
+    c, w, _ = O.lattice()
+    c = c.astype(np.float64)
+    cu = c @ u  # [19][nodes]
+    uu = (u * u).sum(0)
+    return w[:, None] * rho[None, :] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu[None, :])
 
 
 def rel(a, b, floor=0.0):

@@ -76,6 +76,42 @@ def test_batched_equals_alone(susp):
     batch.close()
 
 
+def test_batched_job_matches_oracle(susp):
+    # a job stepped inside a batch (beside another job) against the oracle: one step from
+    # the oracle's state at the FP32 per-step tolerance
+    S = susp
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=21)
+    o = PU.oracle_for(box, kw, pos, vel, om, rad)
+    assert o.step(20) == 0
+    print("\n[batch] job vs oracle, box %s, n=%d" % (box, len(rad)), flush=True)
+    batch = S.Batch(4, 1 << 33, autotune=True)
+    batch.add(_params(S, _jobs(S)[1]))
+    slot = batch.add(S.make_params(box, radius=rad, pos=pos, vel=vel, omega=om, precision=S.FP32, **kw))
+    g = batch.job(slot)
+    PU.load_oracle_state(o, g, 1)
+    o.stress(); batch.stress(slot)
+    batch.step(1)
+    assert o.step(1) == 0
+    tol = 1e-6
+    assert np.array_equal(g.lists(S.LIST_OWNER), o.own)
+    fluid = o.own == -1
+    wr = PU.weights()[:, None]
+    e_d = PU.rel(g.get_populations()[:, fluid] - wr, o.f[:, fluid] - wr)
+    F, T, Sg, nl = g.hydro()
+    Rg, Ug, Wg, Qg = g.get_particles()
+    errs = dict(d=e_d, F=PU.rel(F, o.part("Fh"), 1e-4), T=PU.rel(T, o.part("Th"), 1e-4),
+                U=PU.rel(Ug, o.part("U"), 1e-6), W=PU.rel(Wg, o.part("W"), 1e-7))
+    e_R = float(np.abs(Rg - o.part("R")).max())
+    print("[batch] " + " ".join("e_%s %.3e" % kv for kv in errs.items()) + " e_R %.3e" % e_R, flush=True)
+    assert np.array_equal(nl, o.nlinks)
+    assert max(errs.values()) <= tol and e_R <= 1e-10
+    sg, _ = batch.stress(slot)
+    so, _ = o.stress()
+    for k in range(5):
+        assert PU.rel(sg[k], so[k]) <= 1e-6
+    batch.close()
+
+
 def test_admission_and_slot_reuse(susp):
     S = susp
     jobs = _jobs(S)[:3]

@@ -5,7 +5,13 @@ the storage precision exactly as the library stores it, and compares:
   - lists bit-exactly: owner map, ghost owners, cell list, neighbour pairs, contacts at the
     start of the step, per-sphere boundary-link counts, the link list;
   - fields to the per-step tolerance: 1e-12 (FP64), 1e-6 (FP32), 1e-3 (FP16 storage) on
-    density, velocity, particle force/torque/velocity, spring history and stress.
+    all 19 population deviations d_q = n_q - w_q rho0 of every fluid node (relative to the
+    largest |d_q|: the stored post-collision state, so the collision output, ghost-mode
+    relaxation and FP16 rounding are all inside the comparison), density and velocity,
+    particle force/torque/stresslet, positions, velocities, spins and orientations, spring
+    history, the five stress parts and, inside the observation cycles, G' and G''.
+  - in FP64, also the non-equilibrium part n_q - n_q^eq(rho, u) of every fluid node
+    relative to its largest magnitude (1e-9), which BGK at tau = 1 sets to zero.
 """
 import sys
 
@@ -43,6 +49,7 @@ def _one_step_parity(box, pos, vel, om, rad, kw, precision, presteps):
     PU.load_oracle_state(o, g, precision)
     R0 = o.part("R").copy()
     s0 = o.s.s_next
+    assert np.array_equal(g.get_accumulators(), PU.oracle_accumulators(o))
     o.stress(); g.stress()
     _announce("one step from oracle step %d, precision %d, box %s, n=%d" % (o.s.step, precision, box, len(rad)))
     # link list of the start state vs an enumeration of the oracle's map and ghost points
@@ -71,12 +78,21 @@ def _one_step_parity(box, pos, vel, om, rad, kw, precision, presteps):
     fluid = own == -1
     fg = g.get_populations()[:, fluid]
     fo = o.f[:, fluid]
+    wr = PU.weights()[:, None] * o.params.rho0
+    e_d = PU.rel(fg - wr, fo - wr)  # all 19 deviations of every fluid node
     rg, ug = PU.moments(fg)
     ro, uo = PU.moments(fo)
     e_rho = float(np.abs(rg - ro).max())
     e_u = PU.rel(ug, uo)
-    _announce("e_rho %.3e e_u %.3e" % (e_rho, e_u))
-    assert e_rho <= tol and e_u <= tol
+    msg = "e_d %.3e e_rho %.3e e_u %.3e" % (e_d, e_rho, e_u)
+    if precision == 0 and fo.shape[1]:
+        neq_o = fo - PU.equilibrium(ro, uo)
+        if np.abs(neq_o).max() > 1e-14:
+            e_neq = PU.rel(fg - PU.equilibrium(rg, ug), neq_o)
+            msg += " e_neq %.3e" % e_neq
+            assert e_neq <= 1e-9, msg
+    _announce(msg)
+    assert e_d <= tol and e_rho <= tol and e_u <= tol, msg
     if len(rad):
         Fo, To = o.part("Fh"), o.part("Th")
         So = o.part("Sh").reshape(-1, 3, 3)
@@ -89,8 +105,9 @@ def _one_step_parity(box, pos, vel, om, rad, kw, precision, presteps):
         e_R = float(np.abs(Rg - o.part("R")).max())
         e_U = PU.rel(Ug, o.part("U"), 1e-6)
         e_W = PU.rel(Wg, o.part("W"), 1e-7)
-        _announce("e_F %.3e e_T %.3e e_S %.3e e_R %.3e e_U %.3e e_W %.3e" % (e_F, e_T, e_S, e_R, e_U, e_W))
-        assert max(e_F, e_T, e_S, e_U, e_W) <= max(tol, 1e-10) and e_R <= 1e-10
+        e_Q = float(np.abs(Qg - o.part("Q")).max())  # unit quaternions
+        _announce("e_F %.3e e_T %.3e e_S %.3e e_R %.3e e_U %.3e e_W %.3e e_Q %.3e" % (e_F, e_T, e_S, e_R, e_U, e_W, e_Q))
+        assert max(e_F, e_T, e_S, e_U, e_W) <= max(tol, 1e-10) and e_R <= 1e-10 and e_Q <= 1e-10
         hi, hj, hx = g.get_history()
         oi, oj, ox = o.history()
         assert np.array_equal(hi, oi) and np.array_equal(hj, oj)
@@ -100,12 +117,47 @@ def _one_step_parity(box, pos, vel, om, rad, kw, precision, presteps):
     so, go = o.stress()
     for k in range(5):
         assert PU.rel(sg[k], so[k]) <= max(tol, 1e-9), (k, sg[k], so[k])
+    # G', G'' of this step: 2 / g0_F times sigma_xy times cos, sin of its phase (zero
+    # outside the observation cycles), so the bar is the stress bar on that scale
+    if o.params.shear_kind == 2 and o.params.g0_F != 0.0:
+        scale = 2.0 / abs(o.params.g0_F) * max(float(np.abs(so[:, 3]).max()), 1e-30)
+        e_gg = float(np.abs(gg - go).max()) / scale
+        _announce("G' %.6e / %.6e  G'' %.6e / %.6e  e_gg %.3e" % (gg[0], go[0], gg[1], go[1], e_gg))
+        assert e_gg <= max(tol, 1e-9)
     return o, g
 
 
 def test_single_sphere_fp64():
     w = __import__("paper_1904_02929_amd.synth", fromlist=["x"]).single_sphere(32, 4.5, 1e-4)
     _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params), 0, presteps=20)
+
+
+def test_single_sphere_config_1000_steps_fp64():
+    # the single-sphere configuration as stated: FP64, 32^3, sphere of radius 4.5 at the
+    # centre starting at rest in the sheared fluid, 1000 steps; a torque-free sphere in
+    # simple shear spins at -gamma_dot / 2 (Stokes), and both sides give the same run
+    from paper_1904_02929_amd import synth
+    w = synth.single_sphere(32, 4.5, 1e-4)
+    kw = dict(w.params)
+    _announce("single sphere 32^3, 1000 steps, FP64")
+    o = PU.oracle_for(w.box, kw, w.pos, w.vel, w.omega, w.radius)
+    g = PU.gpu_for(w.box, kw, w.pos, w.vel, w.omega, w.radius, 0)
+    assert o.step(1000) == 0
+    g.step(1000)
+    Rg, Ug, Wg, Qg = g.get_particles()
+    gd = kw["gamma_dot"]
+    _announce("Omega_z gpu %.6e oracle %.6e, -gdot/2 %.6e" % (Wg[0, 2], o.part("W")[0, 2], -gd / 2))
+    assert abs(Wg[0, 2] / (-gd / 2) - 1) < 0.03
+    # the centred sphere does not translate: velocities relative to the shear scale gd L
+    assert PU.rel(Wg, o.part("W")) < 1e-9 and PU.rel(Ug, o.part("U"), gd * w.box[1]) < 1e-9
+    assert np.abs(Qg - o.part("Q")).max() < 1e-12 and np.abs(Rg - o.part("R")).max() < 1e-12
+    fluid = o.own == -1
+    wr = PU.weights()[:, None]
+    assert PU.rel(g.get_populations()[:, fluid] - wr, o.f[:, fluid] - wr) < 1e-9
+    sg, _ = g.stress()
+    so, _ = o.stress()
+    assert PU.rel(sg, so) < 1e-9
+    g.close()
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -150,6 +202,24 @@ def test_monolayer_oscillatory_fp32():
     from paper_1904_02929_amd import synth
     w = synth.monolayer(64, 10, 0.7, seed=2, g0_I=0.2, period=400, ncyc_I=1, ncyc_F=1)
     _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, dict(w.params), 1, presteps=30)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_monolayer_observation_window(precision):
+    # the compared step lies inside the observation cycles, so it adds to G' and G''
+    from paper_1904_02929_amd import synth
+    w = synth.monolayer(64, 10, 0.7, seed=6, g0_I=0.05, period=40, ncyc_I=1, ncyc_F=2)
+    kw = dict(w.params, g0_F=0.02)
+    o, g = _one_step_parity(w.box, w.pos, w.vel, w.omega, w.radius, kw, precision, presteps=57)
+    assert o.s.gp_count == 18  # steps 40 .. 57 (the last one compared)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_dense_bgk_tau07_one_step(precision):
+    # BGK with tau = 0.7: the post-collision state keeps (1 - 1/tau) of the
+    # non-equilibrium part, so the collision output is not fixed by rho and u alone
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=17)
+    _one_step_parity(box, pos, vel, om, rad, dict(kw, tau=0.7), precision, presteps=30)
 
 
 def test_pure_fluid_le_fp32():
