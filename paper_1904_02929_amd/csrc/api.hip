@@ -270,14 +270,6 @@ static size_t carve(Sim &s, char *base) {
   // one buffer resource
   s.own = (int32_t *)take((size_t)s.nodes * 4);
   s.gown = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
-  // link entries, 384 slots per 256-node row segment: a node links to at most six spheres,
-  // but only nodes next to a surface link at all, and packings stay far below 1.5 entries
-  // per node (overflow is reported as SUSP_EUNSTABLE)
-  s.lsegs = n ? ((s.lx + 255) / 256) * s.ly * s.lz : 0;
-  s.lcnt = (int32_t *)take((size_t)s.lsegs * 4);
-  s.lnode = (int32_t *)take((size_t)s.lsegs * 384 * 4);
-  s.lsph = (int32_t *)take((size_t)s.lsegs * 384 * 4);
-  s.lmask = (int32_t *)take((size_t)s.lsegs * 384 * 4);
   s.gval = take((size_t)2 * 5 * s.lx * s.lz * cs);
   for (int b = 0; b < 2; ++b) {
     s.R[b] = (double *)take(n * 3 * 8);
@@ -521,7 +513,6 @@ static int one_step(Sim &s) {
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
   if (s.boundary == 1) HIPCHK(launch_walls(&s));
   else HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
-  HIPCHK(launch_linklist(&s));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {

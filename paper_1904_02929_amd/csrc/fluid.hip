@@ -1,8 +1,7 @@
 // fluid.hip -- lattice-Boltzmann kernels for gfx950.
 //
-//  k_linklist the step's links: (fluid node, sphere, directions) entries
-//  k_links    moving bounce-back on the links and the exchanged momentum summed per sphere
-//             (App. A eqs. 6-10)
+//  k_links    the step's links, (fluid node, sphere, directions) per brick in LDS, their
+//             moving bounce-back and the exchanged momentum summed per sphere (App. A eqs. 6-10)
 //  k_stream   pull-stream + collision + fluid stress partials (App. A eqs. 3-5), one thread
 //             per fluid node, x fastest
 //  k_hydro_final  per-sphere force, torque, stresslet from the fixed-point sums
@@ -35,61 +34,53 @@ template <class T> __device__ inline T wave_sum(T v) {
 }
 
 // ---------------------------------------------------------------------------------------
-// The lattice step of App. A in three kernels.
-//   k_linklist  the links of the step: for every fluid node and every sphere that some of its
-//               pull sources x - c_q belong to, one entry (node, sphere, those directions q);
-//               across the sliding plane the source is a ghost point, whose owner k_ghosts
-//               decided against the sphere images.
-//   k_links     per entry: the bounce-back of eq. 7 on those links, written where the pull
-//               will read it -- the solid source's own slot (q, x - c_q), or the ghost plane
-//               when the source is a ghost point -- and the momentum each link exchanges
-//               (eq. 6) summed into the sphere's force, torque and stresslet (eqs. 9, 10).
+// The lattice step of App. A in two kernels.
+//   k_links     the links of the step: for every fluid node and every sphere that some of its
+//               pull sources x - c_q belong to, one entry (node, sphere, those directions q),
+//               listed per brick in LDS (across the sliding plane the source is a ghost
+//               point, whose owner k_ghosts decided against the sphere images); per entry
+//               the bounce-back of eq. 7 on those links, written where the pull will read
+//               it, and the momentum each link exchanges (eq. 6) summed into the sphere's
+//               force, torque and stresslet (eqs. 9, 10).
 //   k_stream    per fluid node: pull (eq. 3; a link now reads its prepared value), collision
 //               (eqs. 4, 5) on the deviations d_q = n_q - w_q rho0, the fluid stress and mass
-//               partials.
-// The slot (q, y) of a solid node y is pulled by exactly one fluid node, y + c_q, and no
-// later step reads the populations of solid nodes (a node released by a sphere is refilled
-// by the map update; ghost rows and covered nodes read fluid values only), so the solid
-// slots carry the bounce-back values from k_links to k_stream.  Solid nodes are otherwise
-// neither loaded nor stored.
+//               partials; rows are stored whole, a solid node as the rest state.
 constexpr int TX = 64;      // brick width: one wave per 64-node row segment
 constexpr int TS = 64;      // per-work-group table slots of k_links (spheres seen by its entries)
 constexpr int NPIN = 8;     // per-brick partials: Pi^neq xx yy zz xy xz yz, sum (rho - rho0), fluid nodes
 constexpr int LMAXS = 6;    // spheres one node can link to
-constexpr int LWS = 4;      // k_links: row segments each wave takes in turn
 
 // Per-sphere sums without a summation order.  A value v enters as two integers, hi =
 // rint(v 2^FXH) and lo = rint((v - hi 2^-FXH) 2^FXL), added with 64-bit integer atomics;
 // integer addition is associative, so the total is the same bits whatever order the
 // additions take (any brick shape, any interleaving of the work-groups).  The split is
-// exact (|lo| <= 2^(FXL-FXH-1)), |v| must stay below 2^42 and a sphere may take up to
-// 2^15 additions per step before lo can overflow; the rounding of lo costs 2^-69 per term.
+// exact (|lo| <= 2^(FXL-FXH-1)); each rounding adds 1.5 2^52 so that the integer lands in
+// the low mantissa bits (ties to even, as rint), which needs |v| < 2^(51-FXH); a sphere may
+// take up to 2^15 additions per step before lo can overflow; the rounding of lo costs 2^-69
+// per term.
 constexpr int FXH = 20, FXL = 68;
+__device__ inline void fx_split(double v, unsigned long long &h, unsigned long long &l) {
+  constexpr double M = 6755399441055744.0;  // 1.5 2^52
+  const double th = ldexp(v, FXH) + M;
+  const double hv = th - M;                                // rint(v 2^FXH), exact
+  const double tl = ldexp(v - ldexp(hv, -FXH), FXL) + M;  // the remainder is exact
+  h = (unsigned long long)(__double_as_longlong(th) - __double_as_longlong(M));
+  l = (unsigned long long)(__double_as_longlong(tl) - __double_as_longlong(M));
+}
 __device__ inline void fx_add(unsigned long long *dst, double v) {
-  const double h = rint(ldexp(v, FXH));
-  const double l = rint(ldexp(v - ldexp(h, -FXH), FXL));
-  atomicAdd(dst, (unsigned long long)(long long)h);
-  atomicAdd(dst + 1, (unsigned long long)(long long)l);
+  unsigned long long h, l;
+  fx_split(v, h, l);
+  atomicAdd(dst, h);
+  atomicAdd(dst + 1, l);
+}
+// the same into a work-group's LDS table entry
+__device__ inline void fx_lds(unsigned long long *e, double v) {
+  unsigned long long h, l;
+  fx_split(v, h, l);
+  atomicAdd(e, h);
+  atomicAdd(e + 1, l);
 }
 
-// A full table: an entry's 13 sums straight into the sphere's fixed-point sums (rare; kept
-// out of line, with the sums passed by value, so that the common path keeps its registers).
-struct HydSums { double v[HYD]; };
-__device__ __attribute__((noinline)) void hyd_overflow(unsigned long long *hacc, int p, HydSums s) {
-  for (int c = 0; c < HYD; ++c) fx_add(&hacc[((size_t)p * HYD + c) * 2], s.v[c]);
-}
-
-// Slot of sphere p in a work-group's LDS table (open addressing), or -1 if the table is full.
-__device__ inline int table_slot(int32_t *skey, int p) {
-  int h = p & (TS - 1);
-  for (int probe = 0; probe < TS; ++probe) {
-    int key = skey[h];
-    if (key == -1) key = atomicCAS(&skey[h], -1, p);
-    if (key == -1 || key == p) return h;
-    h = (h + 1) & (TS - 1);
-  }
-  return -1;
-}
 
 // c_q . (ax, ay, az) for a compile-time q, summed x, y, z in order without the zero terms.
 template <class T> __device__ inline T cdot(int q, T ax, T ay, T az) {
@@ -173,30 +164,20 @@ template <> struct RowIO<__half> {
   }
 };
 
-// Directions q whose component k (0 x, 1 y, 2 z) of c_q equals sgn, as a bit mask.
-__host__ __device__ constexpr uint32_t dir_mask(int k, int sgn) {
-  uint32_t m = 0;
-  for (int q = 1; q < NQ; ++q)
-    if ((k == 0 ? cx(q) : k == 1 ? cy(q) : cz(q)) == sgn) m |= 1u << q;
-  return m;
-}
 
-// The solid end X - c_q of every link in m lies in the image of the sphere nearest to X
-// (D = X - R in that image) when each component of D - c_q stays inside the half period
-// (with a small margin, so that no rounding can tip the choice); then the lever of each
-// link is D - c_q / 2 and one minimum image serves all of them.  Fails only for nodes
-// about half a period from the centre whose links point across it (thin boxes).
-__device__ inline bool same_image(const Box &b, double Dx, double Dy, double Dz, uint32_t m) {
-  constexpr double e = 1e-6;
-  const double hx = 0.5 * b.Lx - e, hy = 0.5 * b.Ly - e, hz = 0.5 * b.Lz - e;
-  bool ok = true;
-  if (m & dir_mask(0, 1)) ok = ok && Dx - 1.0 >= -hx;
-  if (m & dir_mask(0, -1)) ok = ok && Dx + 1.0 <= hx;
-  if (m & dir_mask(1, 1)) ok = ok && Dy - 1.0 >= -hy;
-  if (m & dir_mask(1, -1)) ok = ok && Dy + 1.0 <= hy;
-  if (m & dir_mask(2, 1)) ok = ok && Dz - 1.0 >= -hz;
-  if (m & dir_mask(2, -1)) ok = ok && Dz + 1.0 <= hz;
-  return ok && fabs(Dx) <= hx && fabs(Dy) <= hy && fabs(Dz) <= hz;
+
+// Minimum image of a node X against a sphere centre R, both inside the box (the particle
+// update keeps R in [0, L)): one sliding-plane crossing in y, then one wrap in x (after the
+// image's shift s) and z.  Agrees with minimage except exactly half a period apart, where
+// the links of the node take the per-link path anyway.
+__device__ inline void node_image(const Box &b, double ilx, double ilz, double dx, double dy, double dz,
+                                  double &ox, double &oy, double &oz, int &k) {
+  k = dy > 0.5 * b.Ly ? 1 : (dy < -0.5 * b.Ly ? -1 : 0);
+  dy -= k * b.Ly;
+  dx -= k * b.s;
+  ox = dx - b.Lx * rint(dx * ilx);
+  oy = dy;
+  oz = dz - b.Lz * rint(dz * ilz);
 }
 
 // A wave-uniform value the compiler must treat as unknown at this point: what derives from
@@ -208,134 +189,372 @@ __device__ inline int opaque_uniform(int v) {
   return v;
 }
 
-// Owner of the pull source x - c_q of node (x, y, z): periodic in x and z; rows past the box
-// edges are the ghost planes y = -1 (gown[0]) and y = ly (gown[1]).
-__device__ inline int32_t src_owner(const int32_t *own, const int32_t *gown, int lx, int ly, int lz,
-                                    int x, int y, int z, int q) {
-  int xs = x - cx(q), zs = z - cz(q);
-  const int ys = y - cy(q);
-  xs = xs < 0 ? xs + lx : (xs >= lx ? xs - lx : xs);
-  zs = zs < 0 ? zs + lz : (zs >= lz ? zs - lz : zs);
-  if (ys < 0) return gown[(size_t)zs * lx + xs];
-  if (ys >= ly) return gown[(size_t)(lz + zs) * lx + xs];
-  return own[(size_t)xs + (size_t)lx * ((size_t)ys + (size_t)ly * zs)];
-}
 
-// ---- k_linklist: one thread per node, a block per 256-node row segment.  The blocks are
-//      dealt to the 8 XCDs round-robin; each XCD takes a contiguous range of segments
-//      (z-major), so that the neighbouring rows a row needs sit in the same L2.  A segment
-//      writes its entries into its own LSEG slots (node order, then sphere rank), placed by a
-//      prefix sum over the block, so the list is the same every time. ----
-constexpr int LSEG = 384;  // entries a 256-node segment holds (1.5 per node)
-struct LinkListArgs {
-  const int32_t *own, *gown;
-  int lx, ly, lz, nseg, per_xcd;
-  int32_t *scnt;                    // [segments] entries of each segment
-  int32_t *lnode, *lsph, *lmask;    // [segments][LSEG] node, sphere, directions (bit q)
+// ---- k_links: a work-group per brick of LBX x LBY x LBZ nodes, the bricks dealt to the 8
+// XCDs in contiguous ranges (neighbouring bricks share an L2).
+//  list    wave w takes row y0 + w through the brick's z-slices, one lane per node: the owners
+//          of its 18 pull sources x - c_q (all slices' loads issued together) and the
+//          distinct spheres among them, one entry (sphere, node, link directions) each in an
+//          LDS list.  Where all linked sources belong to one sphere (most nodes) the largest
+//          and smallest owner agree; otherwise the spheres are taken in decreasing id.  The
+//          list order does not matter: each entry's sums are its own and the per-sphere
+//          totals are integers.
+//  table   the spheres of the entries get slots in an LDS table (open addressing); the lane
+//          that claims a slot stages the sphere's centre and velocities in LDS.
+//  links   one lane per entry.  With lever r_b - R = D - c_q/2 (D = node minus sphere
+//          centre, minimum image) the surface velocity along a link is u_b . c_q = u(X) . c_q,
+//          because (W x c) . c = 0: one rigid-body velocity per entry, and per link
+//            corr = -6 w_q rho0 u(X) . c_q,  n_q = n*_qbar - corr,  m = 2 n*_qbar - corr
+//          (the rest part 2 w_q rho0 of the exchanged momentum left out: the sums are
+//          measured from the rest state).  n_q goes where the pull will read it: the solid
+//          source's own slot (q, X - c_q), or the ghost plane when the source is a ghost
+//          point.  corr, m and the entry's sums F = -sum m c_q, T = D x F, S = sym(D (x) F)
+//          + 1/2 sum m c_q c_q are formed in FP64 (a sphere's sums cancel over its surface
+//          to a small remainder); a convex sphere links a node through at most one of two
+//          opposite directions, so they run over the 9 opposite pairs.  The entry's sums go
+//          into the table as fixed-point integers (order-free, see fx_add), and at the end
+//          into the spheres' sums.
+// The slot (q, y) of a solid node y is pulled by exactly one fluid node, y + c_q, and no
+// later step reads the populations of solid nodes (a node released by a sphere is refilled
+// by the map update; ghost rows and covered nodes read fluid values only), so the solid
+// slots carry the bounce-back values to k_stream.
+constexpr int LBX = 64, LBY = 4, LBZ = 4;  // k_links brick: one wave per row, through the z-slices
+constexpr int LCAP = 2560;                  // LDS list: 2.5 entries per node of the brick
+struct LinksArgs {
+  void *f;                 // the step's input populations (read at fluid nodes, written at solid slots)
+  size_t plane;
+  uint32_t pop_bytes, gval_bytes;
+  uint32_t ow_bytes;  // the owner map and the ghost owner planes after it, as one array
+  int goff;           // elements from the owner map's start to the ghost planes
+  void *gval;
+  const int32_t *own;
+  const double *R, *U, *W;
+  unsigned long long *hacc;  // [n][HYD][2]
   int32_t *flags;
+  int lx, ly, lz;
+  int bxn, byn, nbricks, per_xcd;
+  Box b;
+  const Clock *clk;
+  double kax, kdg;  // -6 w_q rho0 of the axis and of the diagonal directions
+  H16 h16;
 };
 
-__global__ __launch_bounds__(256) void k_linklist(LinkListArgs A) {
-  __shared__ int32_t wsum[4];
-  const int r = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
-  const int nrow = A.nseg * A.ly * A.lz;
-  if (r >= nrow) return;  // the whole block
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int lx = A.lx, ly = A.ly, lz = A.lz;
-  const int seg = r % A.nseg, row = r / A.nseg;
-  const int x = seg * 256 + threadIdx.x, y = row % ly, z = row / ly;
-  const bool live = x < lx;
-  const size_t node = (size_t)x + (size_t)lx * ((size_t)y + (size_t)ly * z);
-  int32_t so[NQ];
-  uint32_t rem = 0, all;
-  so[0] = -1;
-  const bool fl = live && A.own[node] < 0;
-#pragma unroll
-  for (int q = 1; q < NQ; ++q) {
-    so[q] = fl ? src_owner(A.own, A.gown, lx, ly, lz, x, y, z, q) : -1;
-    rem |= so[q] >= 0 ? 1u << q : 0u;
-  }
-  all = rem;
-  // the node's spheres (lowest remaining link direction's sphere first)
-  int ns = 0;
-  for (uint32_t t = rem; t != 0 && ns < LMAXS; ++ns) {
-    const int q0 = __builtin_ctz(t);
-    int p = -1;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) p = q == q0 ? so[q] : p;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) t &= (so[q] == p) ? ~(1u << q) : ~0u;
-    if (t == 0) { ++ns; break; }
-  }
-  // position of the node's first entry: prefix sum over the block
-  int incl = ns;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(incl, o, 64);
-    incl += lane >= o ? v : 0;
-  }
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  int base = 0;
-  for (int w = 0; w < wv; ++w) base += wsum[w];
-  const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-  int pos = base + incl - ns;
-  const size_t seg0 = (size_t)r * LSEG;
-  for (int k = 0; k < ns; ++k) {
-    const int q0 = __builtin_ctz(rem);
-    int p = -1;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) p = q == q0 ? so[q] : p;
-    uint32_t m = 0;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) m |= (((rem >> q) & 1u) && so[q] == p) ? 1u << q : 0u;
-    rem &= ~m;
-    if (pos < LSEG) {
-      A.lnode[seg0 + pos] = (int32_t)node;
-      A.lsph[seg0 + pos] = p;
-      A.lmask[seg0 + pos] = (int32_t)m;
-    }
-    ++pos;
-  }
-  if (threadIdx.x == 0) A.scnt[r] = min(total, LSEG);
-  if (rem != 0 || (threadIdx.x == 0 && total > LSEG)) atomicOr(A.flags, FL_LINKS);
-  (void)all;
+// bit q of a mask from a predicate: a 0/1 value shifted into place (no mask constants to keep)
+__device__ inline uint32_t pred_bit(bool c, int q) {
+  uint32_t b = c ? 1u : 0u;
+  asm volatile("" : "+v"(b));
+  return b << q;
+}
+__device__ inline int lane_rank(unsigned long long bl) {  // set bits of bl below this lane
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bl >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bl, 0u));
 }
 
-// Links of a node near half a period from the sphere centre, where some link's solid end
-// lies in another image of the sphere than the one nearest the node: each link with the
-// lever and velocity of the image holding its solid end (eq. 8).  Rare; out of line, with
-// everything passed and returned by value, so that the common path keeps its registers.
-template <class CT> struct NodePops { CT n[NQ]; };
-template <class CT> struct ImageLinks { CT n[NQ]; double v[12]; };
-template <class CT>
-__device__ __attribute__((noinline)) ImageLinks<CT> link_images(NodePops<CT> in, const double *R, const double *U,
-                                                                const double *W, double kax, double kdg, Box bx,
-                                                                uint32_t m, int x, int y, int z, int p) {
-  ImageLinks<CT> out;
-  const double Rx = R[3 * p], Ry = R[3 * p + 1], Rz = R[3 * p + 2];
-  const double U0 = U[3 * p], U1 = U[3 * p + 1], U2 = U[3 * p + 2];
-  const double w0 = W[3 * p], w1 = W[3 * p + 1], w2 = W[3 * p + 2];
-  for (int c = 0; c < 12; ++c) out.v[c] = 0.0;
+template <class ST>
+__global__ __launch_bounds__(256) void k_links(LinksArgs A) {
+  using CT = typename Store<ST>::CT;
+  __shared__ int32_t skey[TS];
+  __shared__ unsigned long long sacc[TS][HYD][2];
+  __shared__ double ssph[TS][9];  // R, U, W of the table's spheres
+  __shared__ int2 list[LCAP];     // (table slot, or -1 - sphere; node in the brick | link directions >> 1 << 10)
+  __shared__ int32_t lcount;
+  const int brick = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
+  if (brick >= A.nbricks) return;  // the whole work-group
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int i = t; i < TS; i += 256) skey[i] = -1;
+  for (int i = t; i < TS * HYD * 2; i += 256) (&sacc[0][0][0])[i] = 0ull;
+  if (t == 0) lcount = 0;
+  __syncthreads();
+  const int lx = A.lx, ly = A.ly, lz = A.lz;
+  const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
+  const int nsl = min(LBZ, lz - z0);
+  constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
+  constexpr uint32_t OOB = 0xfffffff0u;  // a buffer offset past every array: reads 0, writes nothing
+  uint32_t bad = 0;
+  // ---- list ----
+  {
+    const __amdgpu_buffer_rsrc_t rown = buf_rsrc(A.own, A.ow_bytes);
+    const int x = x0 + lane, y = y0 + wv;
+    const bool live = x < lx && y < ly;
+    const int xc = live ? x : 0, yc = opaque_uniform(live ? y : y0);
+    const int xm = xc == 0 ? lx - 1 : xc - 1, xp = xc + 1 >= lx ? 0 : xc + 1;
+    int32_t own0[LBZ], so[LBZ][NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) out.n[q] = in.n[q];
+    for (int sl = 0; sl < LBZ; ++sl) {
+      const bool ok = live && sl < nsl;
+      const int z = ok ? z0 + sl : z0;
+      own0[sl] = ok ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rown, (uint32_t)(xc + lx * (yc + ly * z)) * 4u, 0, 0)
+                    : 0;
+      // the nine source rows (y - c_y, z - c_z), wave-uniform; a row next to a sliding plane
+      // takes its ghost row there
+      const int zu = opaque_uniform(z0 + (sl < nsl ? sl : 0));
+      const int zm = zu == 0 ? lz - 1 : zu - 1, zp = zu == lz - 1 ? 0 : zu + 1;
+      const int zr[3] = {zp, zu, zm};  // c_z = -1, 0, 1
+      int rowb[3][3];
 #pragma unroll
-  for (int q = 1; q < NQ; ++q) {
-    if ((m >> q) & 1u) {
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rowb[a][c] = lx * (yc + 1 - a + ly * zr[c]);  // c_y = a - 1
+      if (yc == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rowb[2][c] = A.goff + zr[c] * lx;
+      }
+      if (yc == ly - 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rowb[0][c] = A.goff + (lz + zr[c]) * lx;
+      }
+#pragma unroll
+      for (int q = 1; q < NQ; ++q) {
+        const int xs = cx(q) == 1 ? xm : (cx(q) == -1 ? xp : xc);
+        so[sl][q] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(
+            rown, ok ? (uint32_t)(rowb[cy(q) + 1][cz(q) + 1] + xs) * 4u : OOB, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < LBZ; ++sl) {
+      const bool fl = live && sl < nsl && own0[sl] < 0;
+      uint32_t F = 0;       // fluid sources (bit q)
+      int32_t smax = -1;    // largest sphere among the sources
+      uint32_t smin = ~0u;  // smallest (a fluid source, -1, compares above every sphere)
+#pragma unroll
+      for (int q = 1; q < NQ; ++q) {
+        const int32_t o = so[sl][q];
+        F |= ((uint32_t)o >> 31) << q;
+        smax = max(smax, o);
+        smin = min(smin, (uint32_t)o);
+      }
+      const uint32_t M = fl ? ~F & 0x7fffeu : 0u;  // link directions
+      const bool single = M != 0 && (uint32_t)smax == smin;
+      const int loc = lane | (wv << 6) | (sl << 8);
+      const unsigned long long bs = __ballot(single);
+      int sb = 0;
+      if (lane == 0 && bs) sb = atomicAdd(&lcount, __builtin_popcountll(bs));
+      sb = __builtin_amdgcn_readfirstlane(sb) + lane_rank(bs);
+      if (single && sb < LCAP) list[sb] = make_int2(smax, loc | (int)((M >> 1) << 10));
+      if (M != 0 && !single) {  // more than one sphere: in decreasing id
+        uint32_t rem = M;
+        for (int k = 0; rem != 0; ++k) {
+          int32_t sp = -1;
+#pragma unroll
+          for (int q = 1; q < NQ; ++q) sp = max(sp, ((rem >> q) & 1u) ? so[sl][q] : -1);
+          if (k == LMAXS) { bad |= FL_LINKS; break; }
+          uint32_t m = 0;
+#pragma unroll
+          for (int q = 1; q < NQ; ++q) m |= pred_bit(so[sl][q] == sp, q);
+          m &= rem;
+          rem &= ~m;
+          const int pos = atomicAdd(&lcount, 1);
+          if (pos < LCAP) list[pos] = make_int2(sp, loc | (int)((m >> 1) << 10));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int cnt0 = lcount;
+  if (cnt0 > LCAP) bad |= FL_LINKS;  // links left out: the step reports it
+  const int cnt = min(cnt0, LCAP);
+  // ---- table: a slot per sphere, the sphere's state staged by the lane that claims it ----
+  for (int e = t; e < cnt; e += 256) {
+    const int p = list[e].x;
+    int h = p & (TS - 1), slot = -1;
+    for (int probe = 0; probe < TS; ++probe) {
+      int key = skey[h];
+      bool mine = false;
+      if (key == -1) {
+        key = atomicCAS(&skey[h], -1, p);
+        mine = key == -1;
+      }
+      if (mine) {
+        for (int c = 0; c < 3; ++c) {
+          ssph[h][c] = A.R[3 * p + c];
+          ssph[h][3 + c] = A.U[3 * p + c];
+          ssph[h][6 + c] = A.W[3 * p + c];
+        }
+      }
+      if (key == -1 || key == p) { slot = h; break; }
+      h = (h + 1) & (TS - 1);
+    }
+    list[e].x = slot >= 0 ? slot : -1 - p;
+  }
+  __syncthreads();
+  // ---- links: one lane per entry; an entry some of whose links end in another image of the
+  //      sphere than the one nearest the node is marked and done in a second pass ----
+  const Box bx = clock_box(A.b, A.clk, 0);
+  const uint32_t pb = (uint32_t)opaque_uniform((int)(A.plane * es));
+  const __amdgpu_buffer_rsrc_t rf = buf_rsrc(A.f, A.pop_bytes);
+  const bool gedge = y0 == 0 || y0 + LBY >= ly;  // the brick has a row next to a sliding plane
+  auto entry = [&](int e, int2 &en, int &key, uint32_t &m, int &x, int &y, int &z) {
+    en = list[e];
+    key = en.x;
+    m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
+    x = x0 + (en.y & 63); y = y0 + ((en.y >> 6) & 3); z = z0 + ((en.y >> 8) & 3);
+  };
+  // the sphere's centre and velocities: staged in LDS, or (a full table) from the arrays
+  auto sphere = [&](int key, int c) -> double {
+    if (key >= 0) return ssph[key][c];
+    const int p = -1 - key;
+    return c < 3 ? A.R[3 * p + c] : (c < 6 ? A.U[3 * p + c - 3] : A.W[3 * p + c - 6]);
+  };
+  // the node's own opposite populations n*_qbar(X) of the links (bounce-back sends them back)
+  auto pops = [&](CT (&n)[NQ], uint32_t m, int x, int y, int z) {
+    const uint32_t own_base = (uint32_t)(x + lx * (y + ly * z)) * es;
+    n[0] = 0;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe((int)m, q, 1);  // all ones on a link
+      n[q] = RowIO<ST>::ld(rf, ((opp(q) * pb + own_base) & sel) | (OOB & ~sel), q, A.h16);  // w_qbar = w_q
+    }
+  };
+  // a link's bounce-back value where the pull reads it: (q, X - c_q), or the ghost plane
+  auto put = [&](int q, CT v, uint32_t m, int x, int y, int z) {
+    const int xs = cx(q) == 1 ? (x == 0 ? lx - 1 : x - 1) : (cx(q) == -1 ? (x == lx - 1 ? 0 : x + 1) : x);
+    const int zs = cz(q) == 1 ? (z == 0 ? lz - 1 : z - 1) : (cz(q) == -1 ? (z == lz - 1 ? 0 : z + 1) : z);
+    const int ys = y - cy(q);
+    const bool lk = (m >> q) & 1u, in = cy(q) == 0 || (ys >= 0 && ys < ly);
+    RowIO<ST>::st(rf, lk && in ? q * pb + (uint32_t)(xs + lx * (ys + ly * zs)) * es : OOB, v, q, A.h16);
+    if (cy(q) != 0 && gedge) {
+      const __amdgpu_buffer_rsrc_t rg = buf_rsrc(A.gval, A.gval_bytes);
+      const int side = ys < 0 ? 0 : 1;
+      RowIO<CT>::st(rg, lk && !in ? (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx + xs) * ges : OOB, v, q,
+                    A.h16);
+    }
+  };
+  // the entry's sums into the table (a full table: straight into the sphere's sums)
+  auto add = [&](int key, uint32_t m, const double (&v)[HYD]) {
+    if (key >= 0) {
+#pragma unroll
+      for (int c = 0; c < HYD - 1; ++c) fx_lds(&sacc[key][c][0], v[c]);
+      atomicAdd(&sacc[key][HYD - 1][0], (unsigned long long)__builtin_popcount(m) << FXH);  // an integer
+    } else {
+      unsigned long long *d = &A.hacc[(size_t)(-1 - key) * HYD * 2];
+      for (int c = 0; c < HYD - 1; ++c) fx_add(d + 2 * c, v[c]);
+      atomicAdd(d + 2 * (HYD - 1), (unsigned long long)__builtin_popcount(m) << FXH);
+    }
+  };
+  const double ilx = 1.0 / bx.Lx, ilz = 1.0 / bx.Lz;
+  // the links of a node within one unit of the half period may end in another image
+  const double hx = 0.5 * bx.Lx - 1.0 - 1e-6, hy = 0.5 * bx.Ly - 1.0 - 1e-6, hz = 0.5 * bx.Lz - 1.0 - 1e-6;
+  for (int e = t; e < cnt; e += 256) {
+    int2 en;
+    int key, x, y, z;
+    uint32_t m;
+    entry(e, en, key, m, x, y, z);
+    CT n[NQ];
+    pops(n, m, x, y, z);
+    double Dx, Dy, Dz;
+    int k;
+    node_image(bx, ilx, ilz, (double)x - sphere(key, 0), (double)y - sphere(key, 1), (double)z - sphere(key, 2),
+               Dx, Dy, Dz, k);
+    if (!(fabs(Dx) <= hx && fabs(Dy) <= hy && fabs(Dz) <= hz)) {
+      list[e].y = en.y | (int)0x80000000;
+      continue;
+    }
+    const double w0 = sphere(key, 6), w1 = sphere(key, 7), w2 = sphere(key, 8);
+    // rigid-body velocity at the node (eq. 8)
+    const double ux = sphere(key, 3) + k * bx.ule + (w1 * Dz - w2 * Dy);
+    const double uy = sphere(key, 4) + (w2 * Dx - w0 * Dz);
+    const double uz = sphere(key, 5) + (w0 * Dy - w1 * Dx);
+    double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {
+      const int q = 2 * pi + 1, b = q + 1;
+      const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
+      const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
+      const double mq = lq ? fma(2.0, (double)n[q], -corr) : 0.0;
+      const double mb = lb ? fma(2.0, (double)n[b], corr) : 0.0;
+      const double sm2 = mq + mb, df = mq - mb;
+      // each sum starts at its first contributing pair (no addition to zero)
+      acc_pair(g0, pi, 0, cx(q), df); acc_pair(g1, pi, 1, cy(q), df); acc_pair(g2, pi, 2, cz(q), df);
+      acc_pair(mxx, pi, 0, cx(q) * cx(q), sm2);
+      acc_pair(myy, pi, 1, cy(q) * cy(q), sm2);
+      acc_pair(mzz, pi, 2, cz(q) * cz(q), sm2);
+      acc_pair(mxy, pi, 3, cx(q) * cy(q), sm2); acc_pair(mxz, pi, 4, cx(q) * cz(q), sm2);
+      acc_pair(myz, pi, 5, cy(q) * cz(q), sm2);
+    }
+    double v[HYD];
+    v[0] = -g0; v[1] = -g1; v[2] = -g2;
+    v[3] = Dy * v[2] - Dz * v[1];
+    v[4] = Dz * v[0] - Dx * v[2];
+    v[5] = Dx * v[1] - Dy * v[0];
+    v[6] = Dx * v[0] + 0.5 * mxx;
+    v[7] = Dy * v[1] + 0.5 * myy;
+    v[8] = Dz * v[2] + 0.5 * mzz;
+    v[9] = 0.5 * (Dx * v[1] + Dy * v[0]) + 0.5 * mxy;
+    v[10] = 0.5 * (Dx * v[2] + Dz * v[0]) + 0.5 * mxz;
+    v[11] = 0.5 * (Dy * v[2] + Dz * v[1]) + 0.5 * myz;
+    v[12] = 0.0;  // the link count is added from m
+    add(key, m, v);
+  }
+  // the bounce-back values, in a pass of their own so that the sums above keep fewer registers
+  // (the populations are read again, from the cache, and u(X) formed again); the source of link
+  // q is node + the offsets of c_q's components, periodic in x and z
+  for (int e = t; e < cnt; e += 256) {
+    int2 en;
+    int key, x, y, z;
+    uint32_t m;
+    entry(e, en, key, m, x, y, z);
+    if (en.y < 0) continue;  // the per-link pass below
+    CT n[NQ];
+    pops(n, m, x, y, z);
+    double Dx, Dy, Dz;
+    int k;
+    node_image(bx, ilx, ilz, (double)x - sphere(key, 0), (double)y - sphere(key, 1), (double)z - sphere(key, 2),
+               Dx, Dy, Dz, k);
+    const double w0 = sphere(key, 6), w1 = sphere(key, 7), w2 = sphere(key, 8);
+    const double ux = sphere(key, 3) + k * bx.ule + (w1 * Dz - w2 * Dy);
+    const double uy = sphere(key, 4) + (w2 * Dx - w0 * Dz);
+    const double uz = sphere(key, 5) + (w0 * Dy - w1 * Dx);
+    const int node = x + lx * (y + ly * z), lxly = lx * ly;
+    const int dxm = x == 0 ? lx - 1 : -1, dxp = x == lx - 1 ? 1 - lx : 1;
+    const int dzm = z == 0 ? (lz - 1) * lxly : -lxly, dzp = z == lz - 1 ? (1 - lz) * lxly : lxly;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
+      const CT nb = (CT)((double)n[q] - corr);
+      const int src = node + (cx(q) == 1 ? dxm : (cx(q) == -1 ? dxp : 0)) +
+                      (cz(q) == 1 ? dzm : (cz(q) == -1 ? dzp : 0)) - cy(q) * lx;
+      const bool lk = (m >> q) & 1u;
+      const bool in = cy(q) == 0 || (cy(q) == 1 ? y > 0 : y < ly - 1);
+      RowIO<ST>::st(rf, lk && in ? q * pb + (uint32_t)src * es : OOB, nb, q, A.h16);
+      if (cy(q) != 0 && gedge) put(q, nb, in ? 0u : m, x, y, z);  // the ghost plane only
+    }
+  }
+  // the marked entries: each link with the lever and velocity of the image holding its solid
+  // end (eq. 8); the lever of link q is its midpoint X - c_q/2 minus that image's centre
+  for (int e = t; e < cnt; e += 256) {
+    if (list[e].y >= 0) continue;
+    int2 en;
+    int key, x, y, z;
+    uint32_t m;
+    entry(e, en, key, m, x, y, z);
+    const int p = key >= 0 ? skey[key] : -1 - key;  // the sphere's state from its arrays here
+    const uint32_t own_base = (uint32_t)(x + lx * (y + ly * z)) * es;
+    double v[HYD];
+#pragma unroll
+    for (int c = 0; c < HYD; ++c) v[c] = 0.0;
+#pragma unroll 1
+    for (int q = 1; q < NQ; ++q) {  // not unrolled: a rare path, kept small
+      if (!((m >> q) & 1u)) continue;
+      const int qx = cx(q), qy = cy(q), qz = cz(q);
       double ex, ey, ez;
       int kq;
-      minimage(bx, (double)(x - cx(q)) - Rx, (double)(y - cy(q)) - Ry, (double)(z - cz(q)) - Rz, ex, ey, ez, kq);
-      const double lvx = ex + 0.5 * cx(q), lvy = ey + 0.5 * cy(q), lvz = ez + 0.5 * cz(q);
-      const double ubx = U0 + kq * bx.ule + (w1 * lvz - w2 * lvy);
-      const double uby = U1 + (w2 * lvx - w0 * lvz);
-      const double ubz = U2 + (w0 * lvy - w1 * lvx);
-      const double corr = (q <= 6 ? kax : kdg) * cdot<double>(q, ubx, uby, ubz);
-      const double fo = (double)in.n[q];
-      out.n[q] = (CT)(fo - corr);
+      minimage(bx, (double)(x - qx) - A.R[3 * p], (double)(y - qy) - A.R[3 * p + 1],
+               (double)(z - qz) - A.R[3 * p + 2], ex, ey, ez, kq);
+      const double lvx = ex + 0.5 * qx, lvy = ey + 0.5 * qy, lvz = ez + 0.5 * qz;
+      const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
+      const double ubx = A.U[3 * p] + kq * bx.ule + (w1 * lvz - w2 * lvy);
+      const double uby = A.U[3 * p + 1] + (w2 * lvx - w0 * lvz);
+      const double ubz = A.U[3 * p + 2] + (w0 * lvy - w1 * lvx);
+      double cu = 0.0;  // c_q . u_b, x y z in order
+      bool first = true;
+      if (qx != 0) { cu = qx > 0 ? ubx : -ubx; first = false; }
+      if (qy != 0) { const double t1 = qy > 0 ? uby : -uby; cu = first ? t1 : cu + t1; first = false; }
+      if (qz != 0) { const double t1 = qz > 0 ? ubz : -ubz; cu = first ? t1 : cu + t1; }
+      const double corr = (q <= 6 ? A.kax : A.kdg) * cu;
+      const double fo = (double)RowIO<ST>::ld(rf, opp(q) * pb + own_base, q, A.h16);
+      put(q, (CT)(fo - corr), 1u << q, x, y, z);
       const double mm = fma(2.0, fo, -corr);
       double f[3] = {0.0, 0.0, 0.0};
-      addc(f[0], -cx(q), mm); addc(f[1], -cy(q), mm); addc(f[2], -cz(q), mm);
-      double *v = out.v;
+      addc(f[0], -qx, mm); addc(f[1], -qy, mm); addc(f[2], -qz, mm);
       v[0] += f[0]; v[1] += f[1]; v[2] += f[2];
       v[3] += lvy * f[2] - lvz * f[1];
       v[4] += lvz * f[0] - lvx * f[2];
@@ -345,160 +564,9 @@ __device__ __attribute__((noinline)) ImageLinks<CT> link_images(NodePops<CT> in,
       v[10] += 0.5 * (lvx * f[2] + lvz * f[0]);
       v[11] += 0.5 * (lvy * f[2] + lvz * f[1]);
     }
+    add(key, m, v);
   }
-  return out;
-}
-
-// ---- k_links ----
-// One lane per entry: each wave takes LWS consecutive segments in turn, so that a block's
-// entries come from 4 LWS neighbouring row segments and its table holds their spheres.  With lever r_b - R = D - c_q/2 (D = node minus sphere
-// centre, minimum image) the surface velocity along a link is u_b . c_q = u(X) . c_q, because
-// (W x c) . c = 0: one rigid-body velocity per entry, and per link
-//   corr = -6 w_q rho0 u(X) . c_q,  n_q = n*_qbar - corr,  m = 2 n*_qbar - corr
-// (the rest part 2 w_q rho0 of the exchanged momentum left out: the sums are measured from
-// the rest state).  corr, m and the node's sums F = -sum m c_q, T = D x F, S = sym(D (x) F)
-// + 1/2 sum m c_q c_q are formed in FP64 (a sphere's sums cancel over its surface to a small
-// remainder; with corr in FP32 a torque moves by ~1e-6 of the largest one); a convex sphere
-// links a node through at most one of two opposite directions, so they run over the 9
-// opposite pairs.  The block adds its entries' sums per sphere in an LDS table of fixed-point
-// integers (order-free, see fx_add), then into the spheres' sums.
-struct LinksArgs {
-  void *f;                 // the step's input populations (read at fluid nodes, written at solid slots)
-  size_t plane;
-  uint32_t pop_bytes, gval_bytes;
-  void *gval;
-  const int32_t *scnt, *lnode, *lsph, *lmask;
-  int nsegs;                 // row segments of the list
-  const double *R, *U, *W;
-  unsigned long long *hacc;  // [n][HYD][2]
-  int lx, ly, lz;
-  Box b;
-  const Clock *clk;
-  double kax, kdg;  // -6 w_q rho0 of the axis and of the diagonal directions
-  H16 h16;
-};
-
-// a value into the block's fixed-point table entry (two words, see fx_add)
-__device__ inline void fx_lds(unsigned long long *e, double v) {
-  const double h = rint(ldexp(v, FXH));
-  const double l = rint(ldexp(v - ldexp(h, -FXH), FXL));
-  atomicAdd(e, (unsigned long long)(long long)h);
-  atomicAdd(e + 1, (unsigned long long)(long long)l);
-}
-
-template <class ST>
-__global__ __launch_bounds__(256) void k_links(LinksArgs A) {
-  using CT = typename Store<ST>::CT;
-  __shared__ int32_t skey[TS];
-  __shared__ unsigned long long sacc[TS][HYD][2];
-  const int t = threadIdx.x;
-  for (int i = t; i < TS; i += 256) skey[i] = -1;
-  for (int i = t; i < TS * HYD * 2; i += 256) (&sacc[0][0][0])[i] = 0ull;
-  __syncthreads();
-  const Box bx = clock_box(A.b, A.clk, 0);
-  const int lx = A.lx, ly = A.ly, lz = A.lz;
-  constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
-  const uint32_t pb = (uint32_t)(A.plane * es);
-  const __amdgpu_buffer_rsrc_t rf = buf_rsrc(A.f, A.pop_bytes), rg = buf_rsrc(A.gval, A.gval_bytes);
-  const int lane = t & 63, wv = t >> 6;
-  for (int sg = 0; sg < LWS; ++sg) {
-  const int seg = (blockIdx.x * 4 + wv) * LWS + sg;
-  const int ne = seg < A.nsegs ? A.scnt[seg] : 0;
-  for (int e = seg * LSEG + lane; e < seg * LSEG + ne; e += 64) {
-    const int node = A.lnode[e], p = A.lsph[e];
-    const uint32_t m = (uint32_t)A.lmask[e];
-    const int x = node % lx, yz = node / lx, y = yz % ly, z = yz / ly;
-    const double Rx = A.R[3 * p], Ry = A.R[3 * p + 1], Rz = A.R[3 * p + 2];
-    const double U0 = A.U[3 * p], U1 = A.U[3 * p + 1], U2 = A.U[3 * p + 2];
-    const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
-    // the node's own opposite populations n*_qbar(X) of the links (bounce-back sends them back)
-    CT n[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) n[q] = 0;
-    const uint32_t own_base = (uint32_t)node * es;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q)
-      if ((m >> q) & 1u) n[q] = RowIO<ST>::ld(rf, opp(q) * pb + own_base, q, A.h16);  // w_qbar = w_q
-    double Dx, Dy, Dz;
-    int k;
-    minimage(bx, (double)x - Rx, (double)y - Ry, (double)z - Rz, Dx, Dy, Dz, k);
-    double v[HYD];
-    CT nb[NQ];  // the bounce-back values of the links
-    if (same_image(bx, Dx, Dy, Dz, m)) {
-      // rigid-body velocity at the node (eq. 8)
-      const double ux = U0 + k * bx.ule + (w1 * Dz - w2 * Dy);
-      const double uy = U1 + (w2 * Dx - w0 * Dz);
-      const double uz = U2 + (w0 * Dy - w1 * Dx);
-      double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
-#pragma unroll
-      for (int pi = 0; pi < 9; ++pi) {
-        const int q = 2 * pi + 1, b = q + 1;
-        const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
-        const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
-        const double mq = lq ? fma(2.0, (double)n[q], -corr) : 0.0;
-        const double mb = lb ? fma(2.0, (double)n[b], corr) : 0.0;
-        const double sm2 = mq + mb, df = mq - mb;
-        // each sum starts at its first contributing pair (no addition to zero)
-        acc_pair(g0, pi, 0, cx(q), df); acc_pair(g1, pi, 1, cy(q), df); acc_pair(g2, pi, 2, cz(q), df);
-        acc_pair(mxx, pi, 0, cx(q) * cx(q), sm2);
-        acc_pair(myy, pi, 1, cy(q) * cy(q), sm2);
-        acc_pair(mzz, pi, 2, cz(q) * cz(q), sm2);
-        acc_pair(mxy, pi, 3, cx(q) * cy(q), sm2); acc_pair(mxz, pi, 4, cx(q) * cz(q), sm2);
-        acc_pair(myz, pi, 5, cy(q) * cz(q), sm2);
-        nb[q] = (CT)((double)n[q] - corr);
-        nb[b] = (CT)((double)n[b] + corr);
-      }
-      v[0] = -g0; v[1] = -g1; v[2] = -g2;
-      v[3] = Dy * v[2] - Dz * v[1];
-      v[4] = Dz * v[0] - Dx * v[2];
-      v[5] = Dx * v[1] - Dy * v[0];
-      v[6] = Dx * v[0] + 0.5 * mxx;
-      v[7] = Dy * v[1] + 0.5 * myy;
-      v[8] = Dz * v[2] + 0.5 * mzz;
-      v[9] = 0.5 * (Dx * v[1] + Dy * v[0]) + 0.5 * mxy;
-      v[10] = 0.5 * (Dx * v[2] + Dz * v[0]) + 0.5 * mxz;
-      v[11] = 0.5 * (Dy * v[2] + Dz * v[1]) + 0.5 * myz;
-    } else {
-      NodePops<CT> in;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) in.n[q] = n[q];
-      const ImageLinks<CT> r = link_images<CT>(in, A.R, A.U, A.W, A.kax, A.kdg, bx, m, x, y, z, p);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) nb[q] = r.n[q];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = r.v[c];
-    }
-    v[12] = (double)__builtin_popcount(m);
-    // the bounce-back values into the slots the pulls read: (q, X - c_q), or the ghost plane
-    const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
-    const int xm = x == 0 ? lx - 1 : x - 1, xp = x == lx - 1 ? 0 : x + 1;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-      if ((m >> q) & 1u) {
-        const int xs = cx(q) == 1 ? xm : (cx(q) == -1 ? xp : x);
-        const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
-        const int ys = y - cy(q);
-        if (ys >= 0 && ys < ly) {
-          RowIO<ST>::st(rf, q * pb + (uint32_t)(xs + lx * (ys + ly * zs)) * es, nb[q], q, A.h16);
-        } else {
-          const int side = ys < 0 ? 0 : 1;
-          RowIO<CT>::st(rg, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx + xs) * ges, nb[q], q, A.h16);
-        }
-      }
-    }
-    // the entry's sums into the block's table (a full table: straight into the sphere's sums)
-    const int slot = table_slot(skey, p);
-    if (slot >= 0) {
-#pragma unroll
-      for (int c = 0; c < HYD; ++c) fx_lds(&sacc[slot][c][0], v[c]);
-    } else {
-      HydSums hs;
-#pragma unroll
-      for (int c = 0; c < HYD; ++c) hs.v[c] = v[c];
-      hyd_overflow(A.hacc, p, hs);
-    }
-  }
-  }
+  if (bad) atomicOr(A.flags, (int32_t)bad);
   __syncthreads();
   for (int i = t; i < TS * HYD; i += 256) {
     const int slot = i / HYD, c = i - slot * HYD;
@@ -751,22 +819,7 @@ static uint32_t gval_bytes(const Sim *s) {
   return (uint32_t)(10 * (size_t)s->lx * s->lz * ges);
 }
 
-// The link list of the step (k_linklist): after the ghost planes.
-hipError_t launch_linklist(Sim *s) {
-  if (s->n == 0) return hipSuccess;
-  LinkListArgs L;
-  L.own = s->own; L.gown = s->gown;
-  L.lx = s->lx; L.ly = s->ly; L.lz = s->lz;
-  L.nseg = (s->lx + 255) / 256;
-  const int nrow = L.nseg * s->ly * s->lz;
-  L.per_xcd = (nrow + 7) / 8;
-  L.scnt = s->lcnt; L.lnode = s->lnode; L.lsph = s->lsph; L.lmask = s->lmask;
-  L.flags = s->flags;
-  hipLaunchKernelGGL(k_linklist, dim3(L.per_xcd * 8), dim3(256), 0, s->stream, L);
-  return hipGetLastError();
-}
-
-// The links (k_links): after the link list, before k_stream.
+// The links (k_links): after the ghost planes, before k_stream.
 hipError_t launch_links(Sim *s, const Box &b) {
   if (s->n == 0) return hipSuccess;
   LinksArgs A;
@@ -774,21 +827,27 @@ hipError_t launch_links(Sim *s, const Box &b) {
   A.plane = s->plane;
   A.pop_bytes = pop_bytes(s);
   A.gval_bytes = gval_bytes(s);
+  A.goff = (int)(s->gown - s->own);
+  A.ow_bytes = (uint32_t)(((size_t)A.goff + 2 * (size_t)s->lx * s->lz) * 4);
   A.gval = s->gval;
-  A.scnt = s->lcnt; A.lnode = s->lnode; A.lsph = s->lsph; A.lmask = s->lmask;
-  A.nsegs = s->lsegs;
+  A.own = s->own;
   A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
   A.hacc = s->hacc;
+  A.flags = s->flags;
   A.lx = s->lx; A.ly = s->ly; A.lz = s->lz;
+  A.bxn = (s->lx + LBX - 1) / LBX;
+  A.byn = (s->ly + LBY - 1) / LBY;
+  A.nbricks = A.bxn * A.byn * ((s->lz + LBZ - 1) / LBZ);
+  A.per_xcd = (A.nbricks + 7) / 8;
   A.b = b;
   A.clk = s->clk;
   A.kax = -6.0 * wq(1) * s->rho0;
   A.kdg = -6.0 * wq(7) * s->rho0;
   A.h16 = s->h16;
-  const int blocks = (s->lsegs + 4 * LWS - 1) / (4 * LWS);
-  if (s->precision == 0) hipLaunchKernelGGL(k_links<double>, dim3(blocks), dim3(256), 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_links<float>, dim3(blocks), dim3(256), 0, s->stream, A);
-  else hipLaunchKernelGGL(k_links<__half>, dim3(blocks), dim3(256), 0, s->stream, A);
+  const dim3 grid(A.per_xcd * 8), blk(256);
+  if (s->precision == 0) hipLaunchKernelGGL(k_links<double>, grid, blk, 0, s->stream, A);
+  else if (s->precision == 1) hipLaunchKernelGGL(k_links<float>, grid, blk, 0, s->stream, A);
+  else hipLaunchKernelGGL(k_links<__half>, grid, blk, 0, s->stream, A);
   return hipGetLastError();
 }
 

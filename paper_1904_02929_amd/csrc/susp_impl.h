@@ -156,7 +156,6 @@ struct Sim;
 hipError_t launch_init_populations(Sim *s);
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,
                          int lists);
-hipError_t launch_linklist(Sim *s);
 hipError_t launch_links(Sim *s, const Box &b);
 hipError_t launch_lbm(Sim *s, const Box &b);
 hipError_t launch_hydro_final(Sim *s);
@@ -215,10 +214,6 @@ struct Sim {
   void *f[2];
   int cur;  // index of the buffer holding the current state
   int32_t *own;  // owner map: sphere id of every node, -1 fluid
-  // links of the step (k_linklist): one entry per fluid node and sphere it links to
-  int32_t *lcnt;                  // [lsegs] entries of each 256-node row segment
-  int32_t *lnode, *lsph, *lmask;  // [lsegs][384] node, sphere, link directions (bit q)
-  int lsegs;
   int32_t *gown;
   void *gval;
   // particles (FP64)
