@@ -1119,8 +1119,13 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   // change of the Lees-Edwards offset, taken modulo the period (the offset wraps at Lx)
   double ds = bnew.s - bold.s;
   ds -= bnew.Lx * rint(ds / bnew.Lx);
-  const double delta = disp + fabs(ds) + 1e-6;
-  const double ro = a + delta, ri = a - delta;
+  // a node changes owner only within delta of the surface: the displacement, plus the offset
+  // change for the images across the sliding plane (all images when the sphere itself crossed
+  // it this step)
+  const bool crossed = fabs(Rn[1] - Ro[1]) > 0.5 * bnew.Ly;
+  const double delta1 = disp + fabs(ds) + 1e-6;
+  const double delta0 = crossed ? delta1 : disp + 1e-6;
+  const double ro = a + delta1;  // the widest shell, for the row bounds in z
   const Box &B = bnew;
   // rows (y, z) of the shell around each image of the new position
   int zlo = (int)floor(Rn[2] - ro), zhi = (int)ceil(Rn[2] + ro);
@@ -1131,7 +1136,8 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   int rows = 0;
   for (int k = -1; k <= 1; ++k) {
     const double cyy = Rn[1] + k * B.Ly;
-    int lo = (int)floor(cyy - ro), hi = (int)ceil(cyy + ro);
+    const double rok = a + (k == 0 ? delta0 : delta1);
+    int lo = (int)floor(cyy - rok), hi = (int)ceil(cyy + rok);
     if (lo < 0) lo = 0;
     if (hi > B.ly - 1) hi = B.ly - 1;
     ylo[k + 1] = lo;
@@ -1148,6 +1154,8 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
     int z = zu % B.lz;
     z = z < 0 ? z + B.lz : z;
     const double cxx = Rn[0] + k * B.s;
+    const double dk = k == 0 ? delta0 : delta1;
+    const double ro = a + dk, ri = a - dk;
     const double dyy = (double)y - (Rn[1] + k * B.Ly);
     const double dzz = zall ? 0.0 : (double)zu - Rn[2];
     const double oo = ro * ro - dyy * dyy - dzz * dzz;
