@@ -197,6 +197,14 @@ int susp_wall_force(susp_sim *s, double out[6]);
  * Synchronises.                                                                            */
 int susp_contact_stats(susp_sim *s, int32_t nbins, double *hist, double summary[12]);
 
+/* susp_contact_stats for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same read-out, with
+ * the final kernel's staging in a static device array that each device holds for the life
+ * of the process (at most 180 bins: nbins above that is SUSP_EINVAL) instead of the
+ * simulation's own staging.  Calls no allocating routine.  Calls from several host threads
+ * are serialised; the array keeps the last call's contents.  Synchronises.                  */
+int susp_contact_stats_noalloc(susp_sim *s, int32_t nbins, double *hist, double summary[12]);
+
 /* Release the simulation (and its device block unless it came from a workspace). */
 int susp_destroy(susp_sim *s);
 

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -366,6 +368,7 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
   int rc = resolve(p, s);
   if (rc) { delete h; return rc; }
   s.stream = (hipStream_t)stream;
+  if (hipGetDevice(&s.device) != hipSuccess) { delete h; return fail(SUSP_EDEVICE, "hipGetDevice"); }
   const size_t need = carve(s, nullptr);
   char *base = nullptr;
   if (workspace) {
@@ -706,9 +709,60 @@ extern "C" int susp_contact_stats(susp_sim *h, int32_t nbins, double *hist, doub
   Sim &s = h->s;
   if (s.cbins <= 0) return fail(SUSP_EINVAL, "contact statistics are off (contact_bins = 0)");
   if (nbins != s.cbins) return fail(SUSP_EINVAL, "nbins %d differs from contact_bins %d", nbins, s.cbins);
-  HIPCHK(launch_contact_final(&s));
+  HIPCHK(launch_contact_final(&s, s.cout));
   HIPCHK(hipMemcpyAsync(hist, s.cout, (size_t)5 * nbins * 8, hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipMemcpyAsync(summary, s.cout + (size_t)5 * nbins, 12 * 8, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  return SUSP_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// The contact read-out for callers that cannot allocate: the final kernel's staging (the
+// per-bin results and the summary) is a static device array instead of the simulation's
+// own.  Each device holds one copy for the life of the process; its address comes from
+// hipGetSymbolAddress once per device, with that device current, and only that address
+// (never the array's name, a host-side stand-in) reaches kernels and copies.  Calls are
+// serialised by the lock below, so calls from several host threads do not overlap on the
+// array; the kernel writes every element it hands back, so nothing is cleared first.
+constexpr int NOALLOC_BINS = 180;  // largest bin count the static staging holds (1 degree)
+static __device__ __align__(256) double scratch[5 * NOALLOC_BINS + 12];
+static std::mutex scratch_mu;
+static std::map<int, double *> scratch_ptr;  // device -> device address of scratch
+
+// Device address of the staging on device dev (scratch_mu held).
+static int scratch_on(int dev, double **out) {
+  auto it = scratch_ptr.find(dev);
+  if (it != scratch_ptr.end()) {
+    *out = it->second;
+    return SUSP_OK;
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(SUSP_EDEVICE, "hipGetDevice");
+  if (cur != dev && hipSetDevice(dev) != hipSuccess) return fail(SUSP_EDEVICE, "hipSetDevice(%d)", dev);
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p)
+    return fail(SUSP_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+  scratch_ptr[dev] = (double *)p;
+  *out = (double *)p;
+  return SUSP_OK;
+}
+
+extern "C" int susp_contact_stats_noalloc(susp_sim *h, int32_t nbins, double *hist, double summary[12]) {
+  if (!h || !hist || !summary) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  if (s.cbins <= 0) return fail(SUSP_EINVAL, "contact statistics are off (contact_bins = 0)");
+  if (nbins != s.cbins) return fail(SUSP_EINVAL, "nbins %d differs from contact_bins %d", nbins, s.cbins);
+  if (nbins > NOALLOC_BINS)
+    return fail(SUSP_EINVAL, "nbins %d is above the %d bins of the static staging", nbins, NOALLOC_BINS);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  double *stage = nullptr;
+  const int rc = scratch_on(s.device, &stage);
+  if (rc) return rc;
+  HIPCHK(launch_contact_final(&s, stage));
+  HIPCHK(hipMemcpyAsync(hist, stage, (size_t)5 * nbins * 8, hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipMemcpyAsync(summary, stage + (size_t)5 * nbins, 12 * 8, hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
   return SUSP_OK;
 }

@@ -1591,8 +1591,9 @@ hipError_t launch_wall_force(Sim *s) {
   return hipGetLastError();
 }
 
-hipError_t launch_contact_final(Sim *s) {
-  hipLaunchKernelGGL(k_cstat_final, dim3(1), dim3(256), 0, s->stream, s->cacc, s->cout, s->cbins, s->n,
+// The read-out into out[5 nb + 12] (the simulation's staging, or a caller's).
+hipError_t launch_contact_final(Sim *s, double *out) {
+  hipLaunchKernelGGL(k_cstat_final, dim3(1), dim3(256), 0, s->stream, s->cacc, out, s->cbins, s->n,
                      s->cgeo[0], s->cgeo[1], s->quasi2d, (double)s->lz);
   return hipGetLastError();
 }

@@ -173,7 +173,7 @@ hipError_t launch_stress(Sim *s);
 hipError_t launch_contact_sample(Sim *s);
 hipError_t launch_walls(Sim *s);
 hipError_t launch_wall_force(Sim *s);
-hipError_t launch_contact_final(Sim *s);
+hipError_t launch_contact_final(Sim *s, double *out);
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_clock(Sim *s, int reset);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
@@ -210,6 +210,7 @@ struct Sim {
   void *block;
   int owns_block;
   hipStream_t stream;
+  int device;  // the device current when the simulation was created (its block and stream)
   // populations
   void *f[2];
   int cur;  // index of the buffer holding the current state

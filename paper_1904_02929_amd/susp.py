@@ -65,6 +65,7 @@ def lib():
         L.susp_step.argtypes = [vp, C.c_int64]
         L.susp_stress.argtypes = [vp, _PD, _PD]
         L.susp_contact_stats.argtypes = [vp, C.c_int32, _PD, _PD]
+        L.susp_contact_stats_noalloc.argtypes = [vp, C.c_int32, _PD, _PD]
         L.susp_wall_force.argtypes = [vp, _PD]
         L.susp_destroy.argtypes = [vp]
         L.susp_get_populations.argtypes = [vp, _PD]
@@ -236,6 +237,13 @@ class Simulation:
         call, then reset (susp_contact_stats)."""
         hist = np.zeros((5, nbins)); summ = np.zeros(12)
         _chk(lib().susp_contact_stats(self.h, int(nbins), _pd(hist), _pd(summ)))
+        return hist, summ
+
+    def contact_stats_noalloc(self, nbins):
+        """contact_stats through the allocation-free entry point (static device staging,
+        nbins <= 180; susp_contact_stats_noalloc)."""
+        hist = np.zeros((5, nbins)); summ = np.zeros(12)
+        _chk(lib().susp_contact_stats_noalloc(self.h, int(nbins), _pd(hist), _pd(summ)))
         return hist, summ
 
     # ---- state ----------------------------------------------------------------------
