@@ -5,11 +5,14 @@ Workload (default): large 3D bulk suspension, 256^3 D3Q19 lattice, Lees-Edwards 
 shear at 1e-4, bidisperse spheres of radii 4.5/6.3 (1:1) at volume fraction 0.55, i.e.
 12,914 spheres, seeded synthetic packing; FP32 populations (FP64 particles).
 
-Prints one JSON line: whole-step throughput in MLUPS (all lattice nodes per second), the
-roofline of the dominant kernel (the fused stream/bounce-back/collide kernel, timed with HIP
-events on the simulation's stream), the FP64 CPU oracle timed on a bounded sample of the
-same workload, and the serving comparison: the same mixed requests served one at a time by
-the plain loop and by the batched server (jobs per hour, p50/p99 latency).
+Prints one JSON line: whole-step throughput in MLUPS (all lattice nodes per second); the
+roofline of the lattice update (k_links, the boundary links and their forces, plus
+k_stream, pull-stream and collision; each timed with HIP events on the simulation's stream)
+against the algorithmic bytes of the fluid nodes; the same with FP16 storage of the
+populations; the FP64 CPU oracle timed on the host's cores (20 steps of this workload on
+every thread, one step on one thread, and the small configurations); and the serving
+comparison: the same mixed requests served one at a time by the plain loop and by the
+batched server (jobs per hour, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -71,7 +74,29 @@ def traffic_for(kernel_key, src_hash):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, steps):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Thread count for oracles created from now on (the oracle takes omp_get_max_threads
+    when it is created)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def _time_oracle(w, steps):
     import numpy as np
     from oracle import oracle as O
     p = O.make_params(lx=w.box[0], ly=w.box[1], lz=w.box[2], **w.params)
@@ -81,14 +106,86 @@ def cpu_baseline(w, steps):
     rc = o.step(steps)
     t2 = time.perf_counter()
     nodes = float(np.prod(w.box))
+    return {"mlups": nodes * steps / (t2 - t1) / 1e6, "s_per_step": (t2 - t1) / steps,
+            "setup_s": t1 - t0, "threads": int(o.s.nthreads), "status": int(rc)}
+
+
+def cpu_baseline(w, steps):
+    """The FP64 oracle on the host: `steps` steps of the benchmark workload on every thread
+    (the reported value), one step of it on one thread, and a few steps of the small
+    configurations (single sphere 32^3 FP64; 3D bulk 96^3 at phi 0.55; quasi-2D monolayer
+    256 x 256 x 10 at area fraction 0.78)."""
+    from paper_1904_02929_amd import synth
+    ncpu = os.cpu_count()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = ncpu
+    full = _time_oracle(w, steps)
+    small = {}
+    for key, wl, n in (("single_sphere_32cube", synth.single_sphere(32, 4.5, 1e-4), 50),
+                       ("bulk_3d_96cube_phi0.55", synth.bulk3d(96, 0.55, 1e-3, seed=1), 10),
+                       ("monolayer_256x256x10_phi0.78", synth.monolayer(256, 10, 0.78, seed=1), 20)):
+        r = _time_oracle(wl, n)
+        small[key] = {"mlups": round(r["mlups"], 3), "s_per_step": round(r["s_per_step"], 5), "steps": n}
+    one = None
+    if _omp_threads(1):
+        r = _time_oracle(w, 1)
+        one = {"mlups": round(r["mlups"], 3), "s_per_step": round(r["s_per_step"], 3),
+               "threads": r["threads"]}
+        _omp_threads(full["threads"])
     return {
-        "value": round(nodes * steps / (t2 - t1) / 1e6, 3),
+        "value": round(full["mlups"], 3),
         "unit": "MLUPS",
-        "cores": int(o.s.nthreads),
+        "cores": full["threads"],
         "kind": "oracle",
-        "sample": "%d steps of the same workload (FP64, all lattice nodes), after a %.1f s "
-                  "set-up; %.2f s per step; status %d" % (steps, t1 - t0, (t2 - t1) / steps, rc),
+        "sample": "%d steps of the same workload measured (FP64, all lattice nodes), after a "
+                  "%.1f s set-up; %.3f s per step; status %d" % (steps, full["setup_s"],
+                                                                full["s_per_step"], full["status"]),
+        "cpu_model": _cpu_model(),
+        "nproc": ncpu,
+        "cpus_available": avail,
+        "one_thread": one,
+        "small_configs": small,
     }
+
+
+def lattice_run(susp, torch, w, args, precision, steps, warmup):
+    """Steps the workload with one storage precision; returns the timing of the whole step
+    and of the two lattice kernels."""
+    import numpy as np
+    p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
+                         precision=PREC[precision], contact_bins=args.contact_bins, wall=w.wall,
+                         lub_implicit=args.lub_implicit, n_sub=args.n_sub,
+                         collision=1 if args.collision == "multi" else 0, tau_bulk=0.75, tau_ghost=1.0,
+                         **w.params)
+    sim = susp.Simulation(p)
+    stream = sim.stream
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.profile(True)
+    sim.profile_read_parts()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rc = sim.step(steps, check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    links_ms, stream_ms, k_n = sim.profile_read_parts()
+    sim.profile(False)
+    own = sim.lists(susp.LIST_OWNER)
+    n_fluid = int((own == -1).sum())
+    health = sim.health()
+    sim.close()
+    nodes = int(np.prod(w.box))
+    k_links = links_ms / max(1, k_n)
+    k_stream = stream_ms / max(1, k_n)
+    alg = n_fluid * BYTES_PER_FLUID[precision]
+    return {"ms": ms, "rc": int(rc), "nodes": nodes, "n_fluid": n_fluid, "k_links_ms": k_links,
+            "k_stream_ms": k_stream, "alg_bytes": alg, "n_sub": int(p.n_sub), "health": health,
+            "mlups": nodes * steps / (ms / 1e3) / 1e6}
 
 
 def main():
@@ -106,8 +203,10 @@ def main():
     ap.add_argument("--n-sub", type=int, default=8, help="DEM substeps per lattice step")
     ap.add_argument("--contact-bins", type=int, default=0,
                     help="also sample the contact statistics every step in this many bins")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16-line", action="store_true",
+                    help="skip the second run of the workload with FP16 storage")
     ap.add_argument("--serve-jobs", type=int, default=24,
                     help="requests in the serving comparison (0: skip it)")
     ap.add_argument("--serve-steps", type=int, default=1000, help="lattice steps per request")
@@ -140,43 +239,31 @@ def main():
     t = time.perf_counter()
     w, wname = workload(args.workload)
     log("workload %s: box %s, %d spheres (%.1f s to generate)" % (wname, w.box, w.n, time.perf_counter() - t))
-    p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
-                         precision=PREC[args.precision], contact_bins=args.contact_bins, wall=w.wall,
-                         lub_implicit=args.lub_implicit, n_sub=args.n_sub,
-                         collision=1 if args.collision == "multi" else 0, tau_bulk=0.75, tau_ghost=1.0,
-                         **w.params)
-    sim = susp.Simulation(p)
-    stream = sim.stream
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    log("warmup %d steps done" % args.warmup)
-    sim.profile(True)
-    sim.profile_read()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    rc = sim.step(args.steps, check=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    k_ms, k_n = sim.profile_read()
-    sim.profile(False)
-    log("timed %d steps in %.1f ms (status %d)" % (args.steps, ms, rc))
-
-    nodes = int(np.prod(w.box))
-    own = sim.lists(susp.LIST_OWNER)
-    n_fluid = int((own == -1).sum())
-    n_solid = nodes - n_fluid
-    per_step = ms / args.steps
-    mlups = nodes * args.steps / (ms / 1e3) / 1e6
-    k_avg_ms = k_ms / max(1, k_n)
-    alg_bytes = n_fluid * BYTES_PER_FLUID[args.precision] + n_solid * 4
-    achieved = alg_bytes / (k_avg_ms / 1e3) / 1e9
+    r = lattice_run(susp, torch, w, args, args.precision, args.steps, args.warmup)
+    log("timed %d steps in %.1f ms (status %d)" % (args.steps, r["ms"], r["rc"]))
+    alt = None
+    if not args.no_fp16_line and args.precision == "fp32":
+        r16 = lattice_run(susp, torch, w, args, "fp16store", args.steps, args.warmup)
+        log("FP16 storage: %d steps in %.1f ms (status %d)" % (args.steps, r16["ms"], r16["rc"]))
+        lat16 = r16["k_links_ms"] + r16["k_stream_ms"]
+        alt = {
+            "precision": "fp16store",
+            "dtype": DTYPE["fp16store"],
+            "value": round(r16["mlups"], 2),
+            "unit": "MLUPS",
+            "ms_per_step": round(r16["ms"] / args.steps, 5),
+            "k_links_ms": round(r16["k_links_ms"], 5),
+            "k_stream_ms": round(r16["k_stream_ms"], 5),
+            "lattice_frac": round(r16["alg_bytes"] / (lat16 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "k_stream_frac": round(r16["alg_bytes"] / (r16["k_stream_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "status": r16["rc"],
+        }
+    per_step = r["ms"] / args.steps
+    lat_ms = r["k_links_ms"] + r["k_stream_ms"]
+    achieved = r["alg_bytes"] / (lat_ms / 1e3) / 1e9
     with open(os.path.join(ROOT, "paper_1904_02929_amd", "csrc", "fluid.hip"), "rb") as fh:
         src_hash = hashlib.sha256(fh.read()).hexdigest()
-    kernel_key = "k_lbm_%s_%s%s" % (wname, args.precision, "_multi" if args.collision == "multi" else "")
-    sim.close()
+    kernel_key = "lattice_%s_%s%s" % (wname, args.precision, "_multi" if args.collision == "multi" else "")
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on %d steps" % args.cpu_steps)
@@ -192,9 +279,10 @@ def main():
                                "(L 64-128, phi 0.50-0.56, simple shear); Poisson arrivals at "
                                "jobs / (0.25 x plain-loop time); FP32")
 
+    coll = "BGK" if args.collision == "bgk" else "multi-eigenvalue"
     out = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": round(r["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -214,27 +302,36 @@ def main():
             "boundary": "walls" if w.params.get("boundary") == 1 else "lees-edwards",
             "shear_rate": w.params.get("gamma_dot"),
             "precision": args.precision,
-            "n_sub": int(p.n_sub),
+            "n_sub": r["n_sub"],
             "lub_implicit": int(args.lub_implicit),
             "collision": args.collision,
             "contact_bins": int(args.contact_bins),
-            "status": int(rc),
+            "status": r["rc"],
         },
-        "fluid_mlups": round(n_fluid * args.steps / (ms / 1e3) / 1e6, 2),
-        "particle_steps_per_s": round(w.n * args.steps / (ms / 1e3), 1),
+        "fluid_mlups": round(r["n_fluid"] * args.steps / (r["ms"] / 1e3) / 1e6, 2),
+        "particle_steps_per_s": round(w.n * args.steps / (r["ms"] / 1e3), 1),
         "roofline": {
-            "kernel": "k_lbm (fused pull-stream, bounce-back, %s collision, link forces)"
-                      % ("BGK" if args.collision == "bgk" else "multi-eigenvalue"),
+            "kernel": "lattice update: k_links (link list, bounce-back, link forces) + k_stream "
+                      "(pull-stream, %s collision)" % coll,
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_for(kernel_key, src_hash),
-            "avg_kernel_ms": round(k_avg_ms, 5),
-            "algorithmic_bytes_per_launch": int(alg_bytes),
-            "fluid_nodes": n_fluid,
+            "avg_kernel_ms": round(lat_ms, 5),
+            "algorithmic_bytes_per_launch": int(r["alg_bytes"]),
+            "bytes_per_fluid_node": BYTES_PER_FLUID[args.precision],
+            "fluid_nodes": r["n_fluid"],
+            "parts": {
+                "k_links_ms": round(r["k_links_ms"], 5),
+                "k_stream_ms": round(r["k_stream_ms"], 5),
+                "k_stream_frac": round(r["alg_bytes"] / (r["k_stream_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            },
         },
+        "fp16_storage": alt,
+        "health": {"fast_node_steps": r["health"][0], "max_u_over_cs": round(r["health"][1], 4),
+                   "mass_drift": r["health"][2]},
         "cpu_baseline": cpu,
         "serving": serving,
     }

@@ -134,6 +134,10 @@ template <> struct RowIO<double> {
   __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, int, H16) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
   }
+  // a store no later kernel of the step reads (non-temporal: streamed past the caches)
+  __device__ static void st_stream(__amdgpu_buffer_rsrc_t r, uint32_t off, double v, int, H16) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 2);
+  }
 };
 template <> struct RowIO<float> {
   __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, int, H16) {
@@ -141,6 +145,9 @@ template <> struct RowIO<float> {
   }
   __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, int, H16) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+  }
+  __device__ static void st_stream(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, int, H16) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 2);
   }
 };
 // FP16 storage: same scaling as Store<__half>
@@ -152,6 +159,10 @@ template <> struct RowIO<__half> {
   __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, int q, H16 h) {
     const __half hv = __float2half_rn(v * ((float)(1.0 / wq(q)) * h.up));
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hv), r, off, 0, 0);
+  }
+  __device__ static void st_stream(__amdgpu_buffer_rsrc_t r, uint32_t off, float v, int q, H16 h) {
+    const __half hv = __float2half_rn(v * ((float)(1.0 / wq(q)) * h.up));
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hv), r, off, 0, 2);
   }
   // the lattice kernel keeps the 16 stored bits in a float register until the value is
   // used (a step later), so that the conversion does not wait for the load
@@ -786,7 +797,7 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
         uint32_t sb = rowc + (uint32_t)x * es;
         asm volatile("" : "+v"(sb));
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) RowIO<ST>::st(rout, q * pb + sb, n[q], q, A.h16);
+        for (int q = 0; q < NQ; ++q) RowIO<ST>::st_stream(rout, q * pb + sb, n[q], q, A.h16);
       }
     }
   }
