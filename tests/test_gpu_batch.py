@@ -176,3 +176,39 @@ def test_launch_and_poll_equal_alone(susp):
             assert np.array_equal(x, y), "box %s field %d differs" % (j[0], k)
         alone.close()
     batch.close()
+
+
+def test_failed_job_is_reported_alone(susp):
+    # a non-finite population in one job: that job reports SUSP_EUNSTABLE, the other runs on
+    # and gives the result it gives alone
+    S = susp
+    jobs = _jobs(S)[:2]
+    print("\n[batch] one failing job of 2", flush=True)
+    batch = S.Batch(4, 1 << 33, autotune=False)
+    slots = [batch.add(_params(S, j)) for j in jobs]
+    bad = batch.job(slots[0])
+    f = bad.get_populations()
+    own = bad.lists(S.LIST_OWNER).reshape(-1)
+    flat = f.reshape(19, -1)
+    flat[3, int(np.flatnonzero(own == -1)[100])] = np.nan
+    bad.set_populations(flat.reshape(f.shape))
+    for s in slots:
+        batch.launch(s, 12)
+    status = {}
+    import time
+    t0 = time.time()
+    while len(status) < 2 and time.time() - t0 < 60:
+        for s in slots:
+            if s not in status:
+                done, rc = batch.poll(s)
+                if done:
+                    status[s] = rc
+    assert status[slots[0]] == S.EUNSTABLE and status[slots[1]] == S.OK
+    got = _state(batch.job(slots[1]))
+    batch.close()
+    alone = S.Simulation(_params(S, jobs[1]))
+    alone.step(12)
+    ref = _state(alone)
+    alone.close()
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)

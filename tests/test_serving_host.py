@@ -152,3 +152,34 @@ def test_server_waits_for_the_head_of_the_queue():
     done = serve.Server(ex, budget=big, poll_s=0.5, clock=clock, sleep=clock.sleep).run(jobs)
     order = [d.jid for d in sorted(done, key=lambda d: d.finished)]
     assert order == [j.jid for j in jobs]
+
+
+class FailingExecutor(FakeExecutor):
+    """Job `bad` reports an unstable state when its first run completes."""
+
+    def __init__(self, budget, clock, bad):
+        super().__init__(budget, clock)
+        self.bad = bad
+
+    def poll(self, slot):
+        ok, _ = super().poll(slot)
+        return ok, (-4 if ok and self.jobs[slot].jid == self.bad else 0)
+
+
+def test_server_evicts_only_the_failed_job():
+    jobs = serve.mixed_jobs(8, seed=7, steps=500)
+    for j in jobs:
+        j.arrival = 0.0
+    clock = Clock()
+    ex = FailingExecutor(budget=10 ** 6, clock=clock, bad=3)
+    srv = serve.Server(ex, budget=10 ** 6, chunk=100, poll_s=1.0, clock=clock, sleep=clock.sleep)
+    done = srv.run(jobs)
+    assert sorted(d.jid for d in done) == list(range(8))
+    bad = [d for d in done if d.jid == 3][0]
+    assert bad.status == -4 and bad.result is None
+    # evicted after its first run of 100 steps, long before the others finish
+    assert bad.finished - bad.admitted < 0.5 * min(d.finished - d.admitted for d in done if d.jid != 3)
+    for d in done:
+        if d.jid != 3:
+            assert d.status == 0 and d.result == d.jid
+    assert ex.used == 0
