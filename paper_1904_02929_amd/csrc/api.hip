@@ -138,7 +138,7 @@ static int resolve(const susp_params *p, Sim &s) {
   {
     // the lattice kernel addresses one population array with 32-bit byte offsets
     const size_t es = p->precision == 0 ? 8 : p->precision == 1 ? 4 : 2;
-    if ((size_t)NQ * s.plane * es > 0xffffffffull)
+    if (((size_t)NQ * s.plane + link_values(p->lx, p->ly, p->lz)) * es > 0xffffffffull)
       return fail(SUSP_EINVAL, "one population array would exceed 4 GiB (%zu nodes, %zu-byte storage)",
                   (size_t)s.nodes, es);
   }
@@ -267,12 +267,15 @@ static size_t carve(Sim &s, char *base) {
   const size_t es = s.precision == 0 ? 8 : (s.precision == 1 ? 4 : 2);
   const size_t cs = s.precision == 0 ? 8 : 4;
   const size_t n = (size_t)s.n;
-  for (int b = 0; b < 2; ++b) s.f[b] = take(NQ * s.plane * es);
+  // each population buffer ends in the link values of the steps that read it
+  for (int b = 0; b < 2; ++b) s.f[b] = take((NQ * s.plane + link_values(s.lx, s.ly, s.lz)) * es);
   // the ghost owner planes right after the owner map: the lattice kernel reads both through
   // one buffer resource
   s.own = (int32_t *)take((size_t)s.nodes * 4);
   s.gown = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
   s.gval = take((size_t)2 * 5 * s.lx * s.lz * cs);
+  s.lrec = (uint32_t *)take((size_t)s.nodes * 4);
+  s.lrow = (int32_t *)take((size_t)((s.lx + 63) / 64) * s.ly * s.lz * 4);
   for (int b = 0; b < 2; ++b) {
     s.R[b] = (double *)take(n * 3 * 8);
     s.U[b] = (double *)take(n * 3 * 8);
@@ -449,6 +452,9 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
       launch_fill_f64(s.pin, (size_t)s.nbricks * 8, 0.0, s.stream))
     return bail(fail(SUSP_EDEVICE, "fill"));
   if (launch_fill_i32(s.cell_start, (size_t)s.ncell + 1, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
+  // every node fluid and without links until k_links writes the records (it never runs
+  // without spheres)
+  if (launch_fill_i32((int32_t *)s.lrec, (size_t)s.nodes, 0, s.stream)) return bail(fail(SUSP_EDEVICE, "fill"));
   if (s.boundary == 1 && (launch_fill_f64(s.wacc, 8, 0.0, s.stream) || (n && launch_fill_f64(s.wfs, n * 3, 0.0, s.stream))))
     return bail(fail(SUSP_EDEVICE, "fill"));
   if (s.cbins > 0 && (launch_fill_f64(s.cacc, (size_t)(s.cbins + 1) * 6 + 8, 0.0, s.stream) ||

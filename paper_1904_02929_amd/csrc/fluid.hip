@@ -217,31 +217,35 @@ __device__ inline int opaque_uniform(int v) {
 //          because (W x c) . c = 0: one rigid-body velocity per entry, and per link
 //            corr = -6 w_q rho0 u(X) . c_q,  n_q = n*_qbar - corr,  m = 2 n*_qbar - corr
 //          (the rest part 2 w_q rho0 of the exchanged momentum left out: the sums are
-//          measured from the rest state).  n_q goes where the pull will read it: the solid
-//          source's own slot (q, X - c_q), or the ghost plane when the source is a ghost
-//          point.  corr, m and the entry's sums F = -sum m c_q, T = D x F, S = sym(D (x) F)
+//          measured from the rest state).  n_q goes to the link values at the end of the
+//          population buffer, where k_stream's pull takes it (see the record below).
+//          corr, m and the entry's sums F = -sum m c_q, T = D x F, S = sym(D (x) F)
 //          + 1/2 sum m c_q c_q are formed in FP64 (a sphere's sums cancel over its surface
 //          to a small remainder); a convex sphere links a node through at most one of two
 //          opposite directions, so they run over the 9 opposite pairs.  The entry's sums go
 //          into the table as fixed-point integers (order-free, see fx_add), and at the end
 //          into the spheres' sums.
-// The slot (q, y) of a solid node y is pulled by exactly one fluid node, y + c_q, and no
-// later step reads the populations of solid nodes (a node released by a sphere is refilled
-// by the map update; ghost rows and covered nodes read fluid values only), so the solid
-// slots carry the bounce-back values to k_stream.
+// Link values: each brick owns a block of LINK_CAP values per node; the list phase gives each
+// 64-node row of the brick a run of it (one value per link of its nodes, in node order and
+// direction order within a node, placed by an LDS counter) and each node a record: its link
+// directions, whether it is solid, and the offset of its first value in the row's run.  The
+// writes are contiguous, and k_stream reads a node's values next to each other.
 constexpr int LBX = 64, LBY = 4, LBZ = 4;  // k_links brick: one wave per row, through the z-slices
-constexpr int LCAP = 2560;                  // LDS list: 2.5 entries per node of the brick
+constexpr int LCAP = 2048;                  // LDS list: 2 entries per node of the brick
 struct LinksArgs {
-  void *f;                 // the step's input populations (read at fluid nodes, written at solid slots)
+  void *f;                 // the step's input populations, then the link values after them
   size_t plane;
-  uint32_t pop_bytes, gval_bytes;
+  uint32_t pop_bytes;
   uint32_t ow_bytes;  // the owner map and the ghost owner planes after it, as one array
   int goff;           // elements from the owner map's start to the ghost planes
-  void *gval;
   const int32_t *own;
   const double *R, *U, *W;
   unsigned long long *hacc;  // [n][HYD][2]
   int32_t *flags;
+  uint32_t *lrec;            // [nodes] link records
+  int32_t *lrow;             // [rows] first link value of each 64-node row
+  uint32_t vbase;            // elements from the buffer's start to the link values
+  uint32_t vcap;             // link values the buffer holds
   int lx, ly, lz;
   int bxn, byn, nbricks, per_xcd;
   Box b;
@@ -267,18 +271,20 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
   __shared__ unsigned long long sacc[TS][HYD][2];
   __shared__ double ssph[TS][9];  // R, U, W of the table's spheres
   __shared__ int2 list[LCAP];     // (table slot, or -1 - sphere; node in the brick | link directions >> 1 << 10)
-  __shared__ int32_t lcount;
+  __shared__ int32_t lcount, vcount;
+  __shared__ uint32_t srec[LBX * LBY * LBZ];  // the brick's link records
+  __shared__ uint32_t srow[LBY * LBZ];        // first link value of each of its rows (vbase included)
   const int brick = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
   if (brick >= A.nbricks) return;  // the whole work-group
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   for (int i = t; i < TS; i += 256) skey[i] = -1;
   for (int i = t; i < TS * HYD * 2; i += 256) (&sacc[0][0][0])[i] = 0ull;
-  if (t == 0) lcount = 0;
+  if (t == 0) { lcount = 0; vcount = 0; }
   __syncthreads();
   const int lx = A.lx, ly = A.ly, lz = A.lz;
   const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
   const int nsl = min(LBZ, lz - z0);
-  constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
+  constexpr uint32_t es = sizeof(ST);
   constexpr uint32_t OOB = 0xfffffff0u;  // a buffer offset past every array: reads 0, writes nothing
   uint32_t bad = 0;
   // ---- list ----
@@ -336,6 +342,31 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       const uint32_t M = fl ? ~F & 0x7fffeu : 0u;  // link directions
       const bool single = M != 0 && (uint32_t)smax == smin;
       const int loc = lane | (wv << 6) | (sl << 8);
+      // the node's record and its row's block of link values
+      {
+        const int nl = __builtin_popcount(M);
+        int pre = 0, tot = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {  // exclusive prefix over the wave of nl < 32
+          const unsigned long long bl = __ballot((nl >> b) & 1);
+          pre += lane_rank(bl) << b;
+          tot += __builtin_popcountll(bl) << b;
+        }
+        const bool ok = live && sl < nsl;
+        const uint32_t rec = fl ? (M | ((uint32_t)pre << REC_OFF)) : REC_SOLID;
+        int rb = 0;
+        if (lane == 0 && ok && tot) rb = atomicAdd(&vcount, tot);
+        rb = __builtin_amdgcn_readfirstlane(rb);
+        if (rb + tot > LBX * LBY * LBZ * LINK_CAP) bad |= FL_LINKS;  // values past the block are not kept
+        rb += brick * (LBX * LBY * LBZ * LINK_CAP);
+        if (ok) {
+          const int z = z0 + sl;
+          A.lrec[(size_t)xc + (size_t)lx * ((size_t)yc + (size_t)ly * z)] = rec;
+          if (lane == 0) A.lrow[(z * ly + yc) * A.bxn + x0 / LBX] = rb;
+        }
+        srec[loc] = rec;
+        if (lane == 0) srow[wv + LBY * sl] = A.vbase + (uint32_t)rb;
+      }
       const unsigned long long bs = __ballot(single);
       int sb = 0;
       if (lane == 0 && bs) sb = atomicAdd(&lcount, __builtin_popcountll(bs));
@@ -392,7 +423,6 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
   const Box bx = clock_box(A.b, A.clk, 0);
   const uint32_t pb = (uint32_t)opaque_uniform((int)(A.plane * es));
   const __amdgpu_buffer_rsrc_t rf = buf_rsrc(A.f, A.pop_bytes);
-  const bool gedge = y0 == 0 || y0 + LBY >= ly;  // the brick has a row next to a sliding plane
   auto entry = [&](int e, int2 &en, int &key, uint32_t &m, int &x, int &y, int &z) {
     en = list[e];
     key = en.x;
@@ -415,19 +445,12 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       n[q] = RowIO<ST>::ld(rf, ((opp(q) * pb + own_base) & sel) | (OOB & ~sel), q, A.h16);  // w_qbar = w_q
     }
   };
-  // a link's bounce-back value where the pull reads it: (q, X - c_q), or the ghost plane
-  auto put = [&](int q, CT v, uint32_t m, int x, int y, int z) {
-    const int xs = cx(q) == 1 ? (x == 0 ? lx - 1 : x - 1) : (cx(q) == -1 ? (x == lx - 1 ? 0 : x + 1) : x);
-    const int zs = cz(q) == 1 ? (z == 0 ? lz - 1 : z - 1) : (cz(q) == -1 ? (z == lz - 1 ? 0 : z + 1) : z);
-    const int ys = y - cy(q);
-    const bool lk = (m >> q) & 1u, in = cy(q) == 0 || (ys >= 0 && ys < ly);
-    RowIO<ST>::st(rf, lk && in ? q * pb + (uint32_t)(xs + lx * (ys + ly * zs)) * es : OOB, v, q, A.h16);
-    if (cy(q) != 0 && gedge) {
-      const __amdgpu_buffer_rsrc_t rg = buf_rsrc(A.gval, A.gval_bytes);
-      const int side = ys < 0 ? 0 : 1;
-      RowIO<CT>::st(rg, lk && !in ? (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx + xs) * ges : OOB, v, q,
-                    A.h16);
-    }
+  // element of the link value of direction q of the node at loc (q must be a link of it)
+  auto vslot = [&](int loc, int q) -> uint32_t {
+    const uint32_t rec = srec[loc];
+    const uint32_t e = srow[(loc >> 6) & 15] + (rec >> REC_OFF) + __builtin_popcount(rec & ((1u << q) - 2u));
+    // past the brick's block (reported with FL_LINKS): the array's end, where nothing is written
+    return e < A.vbase + (uint32_t)(brick + 1) * (LBX * LBY * LBZ * LINK_CAP) ? e : A.vbase + A.vcap;
   };
   // the entry's sums into the table (a full table: straight into the sphere's sums)
   auto add = [&](int key, uint32_t m, const double (&v)[HYD]) {
@@ -480,6 +503,10 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       acc_pair(mzz, pi, 2, cz(q) * cz(q), sm2);
       acc_pair(mxy, pi, 3, cx(q) * cy(q), sm2); acc_pair(mxz, pi, 4, cx(q) * cz(q), sm2);
       acc_pair(myz, pi, 5, cy(q) * cz(q), sm2);
+      // the bounce-back values into the link values
+      const int loc = en.y & 1023;
+      RowIO<ST>::st(rf, lq ? vslot(loc, q) * es : OOB, (CT)((double)n[q] - corr), q, A.h16);
+      RowIO<ST>::st(rf, lb ? vslot(loc, b) * es : OOB, (CT)((double)n[b] + corr), b, A.h16);
     }
     double v[HYD];
     v[0] = -g0; v[1] = -g1; v[2] = -g2;
@@ -494,40 +521,6 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
     v[11] = 0.5 * (Dy * v[2] + Dz * v[1]) + 0.5 * myz;
     v[12] = 0.0;  // the link count is added from m
     add(key, m, v);
-  }
-  // the bounce-back values, in a pass of their own so that the sums above keep fewer registers
-  // (the populations are read again, from the cache, and u(X) formed again); the source of link
-  // q is node + the offsets of c_q's components, periodic in x and z
-  for (int e = t; e < cnt; e += 256) {
-    int2 en;
-    int key, x, y, z;
-    uint32_t m;
-    entry(e, en, key, m, x, y, z);
-    if (en.y < 0) continue;  // the per-link pass below
-    CT n[NQ];
-    pops(n, m, x, y, z);
-    double Dx, Dy, Dz;
-    int k;
-    node_image(bx, ilx, ilz, (double)x - sphere(key, 0), (double)y - sphere(key, 1), (double)z - sphere(key, 2),
-               Dx, Dy, Dz, k);
-    const double w0 = sphere(key, 6), w1 = sphere(key, 7), w2 = sphere(key, 8);
-    const double ux = sphere(key, 3) + k * bx.ule + (w1 * Dz - w2 * Dy);
-    const double uy = sphere(key, 4) + (w2 * Dx - w0 * Dz);
-    const double uz = sphere(key, 5) + (w0 * Dy - w1 * Dx);
-    const int node = x + lx * (y + ly * z), lxly = lx * ly;
-    const int dxm = x == 0 ? lx - 1 : -1, dxp = x == lx - 1 ? 1 - lx : 1;
-    const int dzm = z == 0 ? (lz - 1) * lxly : -lxly, dzp = z == lz - 1 ? (1 - lz) * lxly : lxly;
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-      const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
-      const CT nb = (CT)((double)n[q] - corr);
-      const int src = node + (cx(q) == 1 ? dxm : (cx(q) == -1 ? dxp : 0)) +
-                      (cz(q) == 1 ? dzm : (cz(q) == -1 ? dzp : 0)) - cy(q) * lx;
-      const bool lk = (m >> q) & 1u;
-      const bool in = cy(q) == 0 || (cy(q) == 1 ? y > 0 : y < ly - 1);
-      RowIO<ST>::st(rf, lk && in ? q * pb + (uint32_t)src * es : OOB, nb, q, A.h16);
-      if (cy(q) != 0 && gedge) put(q, nb, in ? 0u : m, x, y, z);  // the ghost plane only
-    }
   }
   // the marked entries: each link with the lever and velocity of the image holding its solid
   // end (eq. 8); the lever of link q is its midpoint X - c_q/2 minus that image's centre
@@ -562,7 +555,7 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       if (qz != 0) { const double t1 = qz > 0 ? ubz : -ubz; cu = first ? t1 : cu + t1; }
       const double corr = (q <= 6 ? A.kax : A.kdg) * cu;
       const double fo = (double)RowIO<ST>::ld(rf, opp(q) * pb + own_base, q, A.h16);
-      put(q, (CT)(fo - corr), 1u << q, x, y, z);
+      RowIO<ST>::st(rf, vslot(en.y & 1023, q) * es, (CT)(fo - corr), q, A.h16);
       const double mm = fma(2.0, fo, -corr);
       double f[3] = {0.0, 0.0, 0.0};
       addc(f[0], -qx, mm); addc(f[1], -qy, mm); addc(f[2], -qz, mm);
@@ -604,8 +597,10 @@ struct StreamArgs {
   const void *fin;
   void *fout;
   size_t plane;
-  uint32_t pop_bytes, gval_bytes, own_bytes;
-  const int32_t *own;
+  uint32_t pop_bytes, gval_bytes, rec_bytes;
+  const uint32_t *lrec;  // link records of the step (k_links)
+  const int32_t *lrow;   // first link value of each 64-node row
+  uint32_t vbase;        // elements from a population buffer's start to its link values
   const void *gval;
   double *pin;  // [nbricks][NPIN]
   int32_t *flags;
@@ -617,7 +612,7 @@ struct StreamArgs {
 };
 
 template <class ST, int COLL>
-__global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
+__global__ __launch_bounds__(256, (sizeof(ST) <= 4 && COLL == 0) ? 8 : 1) void k_stream(StreamArgs A) {
   using CT = typename Store<ST>::CT;
   __shared__ CT spn[NPIN][256];  // per-thread partials of the fluid stress and mass
   const int brick = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
@@ -634,21 +629,23 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
   constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
   const uint32_t pb0 = (uint32_t)(A.plane * es);  // plane stride in bytes
   const __amdgpu_buffer_rsrc_t rin = buf_rsrc(A.fin, A.pop_bytes), rout = buf_rsrc(A.fout, A.pop_bytes);
-  const __amdgpu_buffer_rsrc_t rgh = buf_rsrc(A.gval, A.gval_bytes), rown = buf_rsrc(A.own, A.own_bytes);
+  const __amdgpu_buffer_rsrc_t rgh = buf_rsrc(A.gval, A.gval_bytes), rrec = buf_rsrc(A.lrec, A.rec_bytes);
   CT pacc[NPIN];
 #pragma unroll
   for (int c = 0; c < NPIN; ++c) pacc[c] = 0;
   uint32_t bad = 0;  // flags raised by this lane
   uint32_t nfast = 0;  // fluid nodes of this lane above 0.3 c_s
   CT umax = 0;         // their largest u^2
-  // owner word of (x0, y, z); a lane past the box end reads as solid
-  auto owner = [&](int y, int z) -> int32_t {
-    return xin ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rown, (uint32_t)(x0 + lx * (y + ly * z)) * 4u, 0, 0)
-               : 0;
+  // link record of (x0, y, z) and the first link value of its row; a lane past the box end
+  // reads as solid
+  auto record = [&](int y, int z) -> uint32_t {
+    return xin ? __builtin_amdgcn_raw_buffer_load_b32(rrec, (uint32_t)(x0 + lx * (y + ly * z)) * 4u, 0, 0)
+               : REC_SOLID;
   };
+  auto rowv = [&](int y, int z) -> uint32_t { return A.vbase + (uint32_t)A.lrow[(z * ly + y) * A.bxn + bxi]; };
 #pragma unroll 1
   for (int yb = y_lo + wv; yb < y_hi; yb += 4) {
-    int32_t onext = owner(yb, z_lo);
+    uint32_t rnext = record(yb, z_lo), vnext = rowv(yb, z_lo);
 #pragma unroll 1
     for (int zb = z_lo; zb < z_hi; ++zb) {
       const int y = opaque_uniform(yb), z = opaque_uniform(zb);
@@ -657,18 +654,23 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
       // loop instead of being kept across it
       int x = x0;
       asm volatile("" : "+v"(x));
-      const int32_t o = onext;
-      if (zb + 1 < z_hi) onext = owner(y, z + 1);  // the next node's owner, a step ahead
+      const uint32_t rec = rnext, vrow = vnext;
+      if (zb + 1 < z_hi) {  // the next node's record, a step ahead
+        rnext = record(y, z + 1);
+        vnext = rowv(y, z + 1);
+      }
       const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
       CT n[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) n[q] = 0;  // a solid node stores the rest state
-      if (o < 0) {  // fluid node (a lane past the box end reads as solid)
+      if (!(rec & REC_SOLID)) {  // fluid node (a lane past the box end reads as solid)
       const int xm = x == 0 ? lx - 1 : x - 1, xp = x + 1 >= lx ? 0 : x + 1;
       const uint32_t xcb = x * es, xmb = xm * es, xpb = xp * es;
       const uint32_t xcg = x * ges, xmg = xm * ges, xpg = xp * ges;
       const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
-      // ---- pull (eq. 3): a link's source slot holds its bounce-back value (k_links) ----
+      // ---- pull (eq. 3); a link takes its bounce-back value from the link values (k_links),
+      //      the node's own after each other in direction order ----
+      const uint32_t v0 = vrow + (rec >> REC_OFF);
       n[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
 #pragma unroll
       for (int q = 1; q < NQ; ++q) {
@@ -676,7 +678,9 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
         const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
         const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
         // across a sliding plane this reads some other row, or nothing; replaced below
-        n[q] = RowIO<ST>::ld(rin, q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb, q, A.h16);
+        const uint32_t pull = q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb;
+        const uint32_t link = (v0 + __builtin_popcount(rec & ((1u << q) - 2u))) * es;
+        n[q] = RowIO<ST>::ld(rin, ((rec >> q) & 1u) ? link : pull, q, A.h16);
       }
       if (y == 0 || y == ly - 1) {  // directions across the sliding plane: the ghost row
         const int side = y == 0 ? 0 : 1;
@@ -685,7 +689,8 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
           if (cy(q) == (side == 0 ? 1 : -1)) {
             const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
             const uint32_t xsg = cx(q) == 1 ? xmg : (cx(q) == -1 ? xpg : xcg);
-            n[q] = RowIO<CT>::ld(rgh, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
+            if (!((rec >> q) & 1u))  // a link keeps its bounce-back value
+              n[q] = RowIO<CT>::ld(rgh, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
           }
         }
       }
@@ -821,9 +826,9 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs A) {
   }
 }
 
-static uint32_t pop_bytes(const Sim *s) {
+static uint32_t pop_bytes(const Sim *s) {  // the populations and the link values after them
   const size_t es = s->precision == 0 ? 8 : s->precision == 1 ? 4 : 2;
-  return (uint32_t)(NQ * s->plane * es);  // < 2^32, checked at creation
+  return (uint32_t)((NQ * s->plane + link_values(s->lx, s->ly, s->lz)) * es);  // < 2^32, checked at creation
 }
 static uint32_t gval_bytes(const Sim *s) {
   const size_t ges = s->precision == 0 ? 8 : 4;
@@ -837,11 +842,13 @@ hipError_t launch_links(Sim *s, const Box &b) {
   A.f = s->f[s->cur];
   A.plane = s->plane;
   A.pop_bytes = pop_bytes(s);
-  A.gval_bytes = gval_bytes(s);
   A.goff = (int)(s->gown - s->own);
   A.ow_bytes = (uint32_t)(((size_t)A.goff + 2 * (size_t)s->lx * s->lz) * 4);
-  A.gval = s->gval;
   A.own = s->own;
+  A.lrec = s->lrec;
+  A.lrow = s->lrow;
+  A.vbase = (uint32_t)(NQ * s->plane);
+  A.vcap = (uint32_t)link_values(s->lx, s->ly, s->lz);
   A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
   A.hacc = s->hacc;
   A.flags = s->flags;
@@ -871,8 +878,10 @@ hipError_t launch_lbm(Sim *s, const Box &b) {
   A.plane = s->plane;
   A.pop_bytes = pop_bytes(s);
   A.gval_bytes = gval_bytes(s);
-  A.own_bytes = (uint32_t)(s->nodes * 4);
-  A.own = s->own;
+  A.rec_bytes = (uint32_t)(s->nodes * 4);
+  A.lrec = s->lrec;
+  A.lrow = s->lrow;
+  A.vbase = (uint32_t)(NQ * s->plane);
   A.gval = s->gval;
   A.pin = s->pin;
   A.flags = s->flags;

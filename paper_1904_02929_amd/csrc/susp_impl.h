@@ -42,6 +42,17 @@ constexpr int FL_OVERLAP = 1, FL_NONFINITE = 2, FL_NEIGHBOURS = 4, FL_LINKS = 8,
 // the flags block (64 int32) also holds, from word FL_HEALTH on, the health counters: fluid
 // node-steps above 0.3 c_s (uint64) and the largest u^2 seen (float bits)
 constexpr int FL_HEALTH = 32;
+// Link values: each population buffer ends in LINK_CAP elements per node of every 64 x 4 x 4
+// brick (of its storage type) that hold the step's bounce-back values, row by row; the record
+// of a node (lrec) holds its link directions (bits 1-18), solid (bit 19) and the offset of its
+// first value in its row's run (bits 20-31); lrow holds the first value of each 64-node row.
+constexpr int LINK_CAP = 5;
+// link values a population buffer holds: LINK_CAP per node of every 64 x 4 x 4 brick
+inline size_t link_values(int lx, int ly, int lz) {
+  return (size_t)((lx + 63) / 64) * ((ly + 3) / 4) * ((lz + 3) / 4) * 1024 * LINK_CAP;
+}
+constexpr uint32_t REC_SOLID = 1u << 19;
+constexpr int REC_OFF = 20;
 
 // D3Q19: 0 rest, 1..6 axes, 7..18 face diagonals; opposite of odd q is q+1.
 __host__ __device__ constexpr int cx(int q) {
@@ -215,6 +226,8 @@ struct Sim {
   void *f[2];
   int cur;  // index of the buffer holding the current state
   int32_t *own;  // owner map: sphere id of every node, -1 fluid
+  uint32_t *lrec;  // [nodes] link record of every node (k_links), read by k_stream
+  int32_t *lrow;   // [lx/64 rounded up * ly * lz] first link value of each 64-node row
   int32_t *gown;
   void *gval;
   // particles (FP64)
