@@ -54,17 +54,17 @@ constexpr int LMAXS = 6;    // spheres one node can link to
 // rint(v 2^FXH) and lo = rint((v - hi 2^-FXH) 2^FXL), added with 64-bit integer atomics;
 // integer addition is associative, so the total is the same bits whatever order the
 // additions take (any brick shape, any interleaving of the work-groups).  The split is
-// exact (|lo| <= 2^(FXL-FXH-1)); each rounding adds 1.5 2^52 so that the integer lands in
-// the low mantissa bits (ties to even, as rint), which needs |v| < 2^(51-FXH); a sphere may
-// take up to 2^15 additions per step before lo can overflow; the rounding of lo costs 2^-69
-// per term.
+// exact (|lo| <= 2^(FXL-FXH-1)); hi is formed as a 32-bit integer and lo by adding 1.5 2^52,
+// which puts the rounded integer (ties to even, as rint) in the low mantissa bits, so one
+// term needs |v| < 2^(31-FXH) (the link sums of one node and sphere are far below); a sphere
+// may take up to 2^15 additions per step before lo can overflow; the rounding of lo costs
+// 2^-69 per term.
 constexpr int FXH = 20, FXL = 68;
 __device__ inline void fx_split(double v, unsigned long long &h, unsigned long long &l) {
   constexpr double M = 6755399441055744.0;  // 1.5 2^52
-  const double th = ldexp(v, FXH) + M;
-  const double hv = th - M;                                // rint(v 2^FXH), exact
+  const double hv = rint(ldexp(v, FXH));
   const double tl = ldexp(v - ldexp(hv, -FXH), FXL) + M;  // the remainder is exact
-  h = (unsigned long long)(__double_as_longlong(th) - __double_as_longlong(M));
+  h = (unsigned long long)(long long)(int)hv;
   l = (unsigned long long)(__double_as_longlong(tl) - __double_as_longlong(M));
 }
 __device__ inline void fx_add(unsigned long long *dst, double v) {
@@ -373,8 +373,26 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       sb = __builtin_amdgcn_readfirstlane(sb) + lane_rank(bs);
       if (single && sb < LCAP) list[sb] = make_int2(smax, loc | (int)((M >> 1) << 10));
       if (M != 0 && !single) {  // more than one sphere: in decreasing id
-        uint32_t rem = M;
-        for (int k = 0; rem != 0; ++k) {
+        // the largest first; when the largest of the others is the smallest (two spheres,
+        // nearly always) the rest is the second entry, else the others one by one
+        uint32_t m1 = 0;
+        int32_t s2 = -1;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+          const bool is1 = so[sl][q] == smax;
+          m1 |= pred_bit(is1, q);
+          s2 = max(s2, is1 ? -1 : so[sl][q]);
+        }
+        m1 &= M;
+        int pos = atomicAdd(&lcount, 1);
+        if (pos < LCAP) list[pos] = make_int2(smax, loc | (int)((m1 >> 1) << 10));
+        uint32_t rem = M & ~m1;
+        if ((uint32_t)s2 == smin) {
+          pos = atomicAdd(&lcount, 1);
+          if (pos < LCAP) list[pos] = make_int2(s2, loc | (int)((rem >> 1) << 10));
+          rem = 0;
+        }
+        for (int k = 1; rem != 0; ++k) {
           int32_t sp = -1;
 #pragma unroll
           for (int q = 1; q < NQ; ++q) sp = max(sp, ((rem >> q) & 1u) ? so[sl][q] : -1);
@@ -384,7 +402,7 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
           for (int q = 1; q < NQ; ++q) m |= pred_bit(so[sl][q] == sp, q);
           m &= rem;
           rem &= ~m;
-          const int pos = atomicAdd(&lcount, 1);
+          pos = atomicAdd(&lcount, 1);
           if (pos < LCAP) list[pos] = make_int2(sp, loc | (int)((m >> 1) << 10));
         }
       }
@@ -446,11 +464,17 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
     }
   };
   // element of the link value of direction q of the node at loc (q must be a link of it)
-  auto vslot = [&](int loc, int q) -> uint32_t {
-    const uint32_t rec = srec[loc];
-    const uint32_t e = srow[(loc >> 6) & 15] + (rec >> REC_OFF) + __builtin_popcount(rec & ((1u << q) - 2u));
-    // past the brick's block (reported with FL_LINKS): the array's end, where nothing is written
-    return e < A.vbase + (uint32_t)(brick + 1) * (LBX * LBY * LBZ * LINK_CAP) ? e : A.vbase + A.vcap;
+  // (the node's record and the element of its first value, read once per entry: vfirst)
+  auto vfirst = [&](int loc, uint32_t &rec) -> uint32_t {
+    rec = srec[loc];
+    const uint32_t e = srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+    // a node whose values pass the brick's block (reported with FL_LINKS): the array's end,
+    // where nothing is written
+    return e + __builtin_popcount(rec) <= A.vbase + (uint32_t)(brick + 1) * (LBX * LBY * LBZ * LINK_CAP)
+               ? e : A.vbase + A.vcap;
+  };
+  auto vslot = [&](uint32_t v0, uint32_t rec, int q) -> uint32_t {
+    return v0 + __builtin_popcount(rec & ((1u << q) - 2u));
   };
   // the entry's sums into the table (a full table: straight into the sphere's sums)
   auto add = [&](int key, uint32_t m, const double (&v)[HYD]) {
@@ -487,6 +511,8 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
     const double ux = sphere(key, 3) + k * bx.ule + (w1 * Dz - w2 * Dy);
     const double uy = sphere(key, 4) + (w2 * Dx - w0 * Dz);
     const double uz = sphere(key, 5) + (w0 * Dy - w1 * Dx);
+    uint32_t rec;
+    const uint32_t v0 = vfirst(en.y & 1023, rec);
     double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
 #pragma unroll
     for (int pi = 0; pi < 9; ++pi) {
@@ -504,9 +530,8 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       acc_pair(mxy, pi, 3, cx(q) * cy(q), sm2); acc_pair(mxz, pi, 4, cx(q) * cz(q), sm2);
       acc_pair(myz, pi, 5, cy(q) * cz(q), sm2);
       // the bounce-back values into the link values
-      const int loc = en.y & 1023;
-      RowIO<ST>::st(rf, lq ? vslot(loc, q) * es : OOB, (CT)((double)n[q] - corr), q, A.h16);
-      RowIO<ST>::st(rf, lb ? vslot(loc, b) * es : OOB, (CT)((double)n[b] + corr), b, A.h16);
+      RowIO<ST>::st(rf, lq ? vslot(v0, rec, q) * es : OOB, (CT)((double)n[q] - corr), q, A.h16);
+      RowIO<ST>::st(rf, lb ? vslot(v0, rec, b) * es : OOB, (CT)((double)n[b] + corr), b, A.h16);
     }
     double v[HYD];
     v[0] = -g0; v[1] = -g1; v[2] = -g2;
@@ -555,7 +580,9 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
       if (qz != 0) { const double t1 = qz > 0 ? ubz : -ubz; cu = first ? t1 : cu + t1; }
       const double corr = (q <= 6 ? A.kax : A.kdg) * cu;
       const double fo = (double)RowIO<ST>::ld(rf, opp(q) * pb + own_base, q, A.h16);
-      RowIO<ST>::st(rf, vslot(en.y & 1023, q) * es, (CT)(fo - corr), q, A.h16);
+      uint32_t rec;
+      const uint32_t v0 = vfirst(en.y & 1023, rec);
+      RowIO<ST>::st(rf, vslot(v0, rec, q) * es, (CT)(fo - corr), q, A.h16);
       const double mm = fma(2.0, fo, -corr);
       double f[3] = {0.0, 0.0, 0.0};
       addc(f[0], -qx, mm); addc(f[1], -qy, mm); addc(f[2], -qz, mm);
