@@ -1145,12 +1145,21 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
     rows += ny[k + 1] * nz;
   }
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  // row r: image kb (rows of image 0 first), then t = z index * ny + y index within it; the
+  // quotient by ny through a float reciprocal (exact: t < 2^16 keeps (t + 1/2) / ny at least
+  // 1/(2 ny) away from an integer, far beyond the float error)
+  const int n0 = ny[0] * nz, n01 = n0 + ny[1] * nz;
+  const float inv0 = 1.0f / (float)max(ny[0], 1), inv1 = 1.0f / (float)max(ny[1], 1),
+              inv2 = 1.0f / (float)max(ny[2], 1);
   for (int r = lane; r < rows; r += 64) {
-    int t = r, kb = 0;
-    while (t >= ny[kb] * nz) { t -= ny[kb] * nz; ++kb; }
+    const int kb = r < n0 ? 0 : (r < n01 ? 1 : 2);
+    const int t = r - (kb == 0 ? 0 : (kb == 1 ? n0 : n01));
+    const int nyk = kb == 0 ? ny[0] : (kb == 1 ? ny[1] : ny[2]);
+    const float invk = kb == 0 ? inv0 : (kb == 1 ? inv1 : inv2);
+    const int zi = (int)(((float)t + 0.5f) * invk);
     const int k = kb - 1;
-    const int y = ylo[kb] + t % ny[kb];
-    const int zu = zlo + t / ny[kb];
+    const int y = (kb == 0 ? ylo[0] : (kb == 1 ? ylo[1] : ylo[2])) + (t - zi * nyk);
+    const int zu = zlo + zi;
     int z = zu % B.lz;
     z = z < 0 ? z + B.lz : z;
     const double cxx = Rn[0] + k * B.s;
