@@ -154,11 +154,14 @@ def lattice_run(susp, torch, w, args, precision, steps, warmup):
     """Steps the workload with one storage precision; returns the timing of the whole step
     and of the two lattice kernels."""
     import numpy as np
+    kw = dict(w.params)
+    if args.brick:
+        kw["brick_y"], kw["brick_z"] = (int(v) for v in args.brick.lower().split("x"))
     p = susp.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
                          precision=PREC[precision], contact_bins=args.contact_bins, wall=w.wall,
                          lub_implicit=args.lub_implicit, n_sub=args.n_sub,
                          collision=1 if args.collision == "multi" else 0, tau_bulk=0.75, tau_ghost=1.0,
-                         **w.params)
+                         **kw)
     sim = susp.Simulation(p)
     stream = sim.stream
     sim.step(warmup)
@@ -201,6 +204,9 @@ def main():
     ap.add_argument("--lub-implicit", type=int, default=0,
                     help="Jacobi sweeps of the implicit squeeze lubrication per substep (0: explicit)")
     ap.add_argument("--n-sub", type=int, default=8, help="DEM substeps per lattice step")
+    ap.add_argument("--brick", default="",
+                    help="stream brick BYxBZ (e.g. 8x8; 4x4 fuses the link and stream kernels); "
+                         "default: the library's choice")
     ap.add_argument("--contact-bins", type=int, default=0,
                     help="also sample the contact statistics every step in this many bins")
     ap.add_argument("--cpu-steps", type=int, default=20)

@@ -233,14 +233,17 @@ static int resolve(const susp_params *p, Sim &s) {
   s.cells.iy = nc[1] / (double)p->ly;
   s.cells.iz = nc[2] / (double)p->lz;
   s.ncell = nc[0] * nc[1] * nc[2];
-  // bricks of 64 x BY x BZ nodes for the lattice kernel: at most 64 x 8 x 8, smaller until
-  // at least 2048 of them spread over the 256 compute units
+  // bricks of 64 x BY x BZ nodes for the stream kernel.  With spheres the default is 64 x 4 x 4,
+  // the link kernel's brick, so that one work-group takes both (k_lattice); without them at most
+  // 64 x 8 x 8, smaller until at least 2048 of them spread over the 256 compute units
   s.bxn = (p->lx + 63) / 64;
   auto nbr = [&]() { return s.bxn * ((p->ly + s.BY - 1) / s.BY) * ((p->lz + s.BZ - 1) / s.BZ); };
   if (p->brick_y || p->brick_z) {
     if (p->brick_y < 4 || p->brick_y % 4 || p->brick_y > 1024 || p->brick_z < 1 || p->brick_z > 1024)
       return fail(SUSP_EINVAL, "brick_y must be a positive multiple of 4 and brick_z positive (<= 1024)");
     s.BY = p->brick_y; s.BZ = p->brick_z;
+  } else if (p->n > 0) {
+    s.BY = 4; s.BZ = 4;
   } else {
     s.BY = 8; s.BZ = 8;
     while (nbr() < 2048 && (s.BY > 4 || s.BZ > 1)) {

@@ -264,18 +264,29 @@ __device__ inline int lane_rank(unsigned long long bl) {  // set bits of bl belo
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bl >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bl, 0u));
 }
 
+// LDS of a k_links work-group
+struct LinksLDS {
+  unsigned long long sacc[TS][HYD][2];  // the table's fixed-point sums
+  double ssph[TS][9];                    // R, U, W of the table's spheres
+  int2 list[LCAP];                       // (table slot, or -1 - sphere; node in the brick | link directions >> 1 << 10)
+  int32_t skey[TS];                      // the table's spheres
+  uint32_t srec[LBX * LBY * LBZ];        // the brick's link records
+  uint32_t srow[LBY * LBZ];              // first link value of each of its rows (vbase included)
+  int32_t lcount, vcount;
+};
+
+// The links of one brick (list, table, links, per-sphere sums); the records and row starts
+// stay in sh for a stream phase of the same work-group.
 template <class ST>
-__global__ __launch_bounds__(256) void k_links(LinksArgs A) {
+__device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksLDS &sh) {
   using CT = typename Store<ST>::CT;
-  __shared__ int32_t skey[TS];
-  __shared__ unsigned long long sacc[TS][HYD][2];
-  __shared__ double ssph[TS][9];  // R, U, W of the table's spheres
-  __shared__ int2 list[LCAP];     // (table slot, or -1 - sphere; node in the brick | link directions >> 1 << 10)
-  __shared__ int32_t lcount, vcount;
-  __shared__ uint32_t srec[LBX * LBY * LBZ];  // the brick's link records
-  __shared__ uint32_t srow[LBY * LBZ];        // first link value of each of its rows (vbase included)
-  const int brick = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
-  if (brick >= A.nbricks) return;  // the whole work-group
+  auto &skey = sh.skey;
+  auto &sacc = sh.sacc;
+  auto &ssph = sh.ssph;
+  auto &list = sh.list;
+  auto &lcount = sh.lcount, &vcount = sh.vcount;
+  auto &srec = sh.srec;
+  auto &srow = sh.srow;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   for (int i = t; i < TS; i += 256) skey[i] = -1;
   for (int i = t; i < TS * HYD * 2; i += 256) (&sacc[0][0][0])[i] = 0ull;
@@ -612,6 +623,14 @@ __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
   }
 }
 
+template <class ST>
+__global__ __launch_bounds__(256) void k_links(LinksArgs A) {
+  __shared__ LinksLDS sh;
+  const int brick = (blockIdx.x & 7) * A.per_xcd + (blockIdx.x >> 3);
+  if (brick >= A.nbricks) return;  // the whole work-group
+  links_body<ST>(A, brick, sh);
+}
+
 // ---- k_stream ----
 // A brick of 64 x BY x BZ nodes per work-group, dealt to the 8 XCDs in contiguous ranges so
 // that neighbouring bricks share an L2.  Wave w takes rows y_lo + w, y_lo + w + 4, ... and
@@ -638,6 +657,192 @@ struct StreamArgs {
   H16 h16;
 };
 
+// The end of a brick's stream phase: its lanes' flags and health counters, and the brick's
+// partials of the fluid stress and mass (the 256 per-thread partials of each component summed by
+// one wave in a fixed order; spn is LDS of the work-group).
+template <class CT>
+__device__ __forceinline__ void stream_tail(const StreamArgs &A, int brick, CT (*spn)[256], const CT (&pacc)[NPIN],
+                                            uint32_t bad, uint32_t nfast, CT umax) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (bad) atomicOr(A.flags, (int32_t)bad);  // rare
+  if (nfast) {  // rare: the health counters (count of fast node-steps, largest u^2 as bits)
+    atomicAdd((unsigned long long *)(A.flags + FL_HEALTH), (unsigned long long)nfast);
+    atomicMax(A.flags + FL_HEALTH + 2, __float_as_int((float)umax));
+  }
+#pragma unroll
+  for (int c = 0; c < NPIN; ++c) spn[c][t] = pacc[c];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int c = 0; c < NPIN; ++c) {
+      const double v = wave_sum(((double)spn[c][lane] + (double)spn[c][lane + 64]) +
+                                ((double)spn[c][lane + 128] + (double)spn[c][lane + 192]));
+      if (lane == 0) A.pin[(size_t)brick * NPIN + c] = v;
+    }
+  }
+}
+
+// One node of the stream phase: pull (eq. 3; a link takes its bounce-back value from the link
+// values, the node's own after each other in direction order), collision (eqs. 4, 5) on the
+// deviations, the node's partials, and its row store (every lane of a row stores, solid nodes
+// as the rest state, never read, so that the wave writes whole cache lines: HBM3E has no
+// write mask, and a partly written line costs a read-modify-write).  rec: the node's link
+// record (REC_SOLID for a lane past the box end); vrow: the element of its row's first link value.
+template <class ST, int COLL>
+__device__ __forceinline__ void stream_node(const StreamArgs &A, __amdgpu_buffer_rsrc_t rin,
+                                            __amdgpu_buffer_rsrc_t rout, __amdgpu_buffer_rsrc_t rgh, uint32_t pb,
+                                            int x, int y, int z, bool xin, uint32_t rec, uint32_t vrow,
+                                            typename Store<ST>::CT (&pacc)[NPIN], uint32_t &bad, uint32_t &nfast,
+                                            typename Store<ST>::CT &umax) {
+  using CT = typename Store<ST>::CT;
+  constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
+  const int lx = A.lx, ly = A.ly, lz = A.lz;
+  const CT om = (CT)A.omega;
+  const CT rho0 = (CT)A.rho0;
+  const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
+  CT n[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) n[q] = 0;  // a solid node stores the rest state
+  if (!(rec & REC_SOLID)) {  // fluid node (a lane past the box end reads as solid)
+  const int xm = x == 0 ? lx - 1 : x - 1, xp = x + 1 >= lx ? 0 : x + 1;
+  const uint32_t xcb = x * es, xmb = xm * es, xpb = xp * es;
+  const uint32_t xcg = x * ges, xmg = xm * ges, xpg = xp * ges;
+  const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
+  // ---- pull (eq. 3); a link takes its bounce-back value from the link values (k_links),
+  //      the node's own after each other in direction order ----
+  const uint32_t v0 = vrow + (rec >> REC_OFF);
+  n[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
+#pragma unroll
+  for (int q = 1; q < NQ; ++q) {
+    const int ys = y - cy(q);
+    const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
+    const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
+    // across a sliding plane this reads some other row, or nothing; replaced below
+    const uint32_t pull = q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb;
+    const uint32_t link = (v0 + __builtin_popcount(rec & ((1u << q) - 2u))) * es;
+    n[q] = RowIO<ST>::ld(rin, ((rec >> q) & 1u) ? link : pull, q, A.h16);
+  }
+  if (y == 0 || y == ly - 1) {  // directions across the sliding plane: the ghost row
+    const int side = y == 0 ? 0 : 1;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      if (cy(q) == (side == 0 ? 1 : -1)) {
+        const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
+        const uint32_t xsg = cx(q) == 1 ? xmg : (cx(q) == -1 ? xpg : xcg);
+        if (!((rec >> q) & 1u))  // a link keeps its bounce-back value
+          n[q] = RowIO<CT>::ld(rgh, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
+      }
+    }
+  }
+  // ---- moments and collision on the deviations d_q = n_q - w_q rho0, opposite
+  //      directions paired: feq_q,qbar = w (a + 4.5 rho cu^2) +- 3 w rho cu ----
+  CT rd = n[0], jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int pi = 0; pi < 9; ++pi) {
+    const int q = 2 * pi + 1;
+    const CT dq = n[q] - n[q + 1];
+    rd += n[q] + n[q + 1];
+    addc(jx, cx(q), dq); addc(jy, cy(q), dq); addc(jz, cz(q), dq);
+  }
+  const CT rho = rho0 + rd;
+  const CT ir = (CT)1 / rho;
+  const CT ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const CT uu = ux * ux + uy * uy + uz * uz;
+  // a non-finite density or velocity: the fluid has failed.  Speeds above 0.3 c_s (u^2 >
+  // 0.03, past the low-Mach range) are counted, not failed: a node squeezed into a one-node
+  // gap between two surfaces passes it briefly in dense runs
+  bad |= isfinite(uu) && isfinite(rho) ? 0u : (uint32_t)FL_FLUID;
+  nfast += uu > (CT)0.03 ? 1u : 0u;
+  umax = uu > umax ? uu : umax;
+  const CT a = rd - (CT)1.5 * rho * uu;
+  const CT w0 = (CT)(1.0 / 3.0), w1 = (CT)(1.0 / 18.0), w2 = (CT)(1.0 / 36.0);
+  const CT a1 = w1 * a, a2 = w2 * a;
+  const CT b1 = (CT)4.5 * w1 * rho, b2 = (CT)4.5 * w2 * rho;
+  const CT c1 = (CT)3 * w1 * rho, c2 = (CT)3 * w2 * rho;
+  CT ps[9];
+  if constexpr (COLL == 0) {
+    n[0] = fmaT(-om, n[0] - w0 * a, n[0]);
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {
+      const int q = 2 * pi + 1, b = q + 1;
+      const CT cu = cdot<CT>(q, ux, uy, uz);
+      const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+      const CT anti = (q <= 6 ? c1 : c2) * cu;
+      const CT neq = n[q] - (sym + anti), neb = n[b] - (sym - anti);
+      ps[pi] = neq + neb;
+      n[q] = fmaT(-om, neq, n[q]);
+      n[b] = fmaT(-om, neb, n[b]);
+    }
+  } else {
+    // n* = n^eq + (1 - om_g) n^neq + Q_q, Q_q = 4.5 w_q [g1 (Pi:c c - t/3) + g2 t (|c|^2 - 1)/3]
+    // with Pi = Pi^neq, t its trace, g1 = om_g - om, g2 = om - om_v: the traceless
+    // stress relaxes with om, its trace with om_v, every other mode with om_g
+    const CT omg = (CT)A.om_ghost, g1 = omg - om, g2 = om - (CT)A.om_bulk;
+    const CT ne0 = n[0] - w0 * a;
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {  // n^neq into n, pair sums for the flux
+      const int q = 2 * pi + 1, b = q + 1;
+      const CT cu = cdot<CT>(q, ux, uy, uz);
+      const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+      const CT anti = (q <= 6 ? c1 : c2) * cu;
+      n[q] = n[q] - (sym + anti);
+      n[b] = n[b] - (sym - anti);
+      ps[pi] = n[q] + n[b];
+    }
+    CT P[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {
+      const int q = 2 * pi + 1;
+      if (cx(q) != 0) P[0] += ps[pi];
+      if (cy(q) != 0) P[1] += ps[pi];
+      if (cz(q) != 0) P[2] += ps[pi];
+      addc(P[3], cx(q) * cy(q), ps[pi]);
+      addc(P[4], cx(q) * cz(q), ps[pi]);
+      addc(P[5], cy(q) * cz(q), ps[pi]);
+    }
+    const CT t3 = (P[0] + P[1] + P[2]) * (CT)(1.0 / 3.0);
+    const CT P2xy = (CT)2 * P[3], P2xz = (CT)2 * P[4], P2yz = (CT)2 * P[5];
+    const CT keep = (CT)1 - omg;
+    n[0] = w0 * a + keep * ne0 - (CT)1.5 * w0 * 3 * (g1 + g2) * t3;
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {
+      const int q = 2 * pi + 1, b = q + 1;
+      const CT cu = cdot<CT>(q, ux, uy, uz);
+      const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
+      const CT anti = (q <= 6 ? c1 : c2) * cu;
+      CT pcc = (cx(q) != 0 ? P[0] : (CT)0) + (cy(q) != 0 ? P[1] : (CT)0) + (cz(q) != 0 ? P[2] : (CT)0);
+      addc(pcc, cx(q) * cy(q), P2xy);  // Pi : c c = sum_a Pi_aa c_a^2 + 2 sum_a<b Pi_ab c_a c_b
+      addc(pcc, cx(q) * cz(q), P2xz);
+      addc(pcc, cy(q) * cz(q), P2yz);
+      const int c2q = cx(q) * cx(q) + cy(q) * cy(q) + cz(q) * cz(q);
+      const CT Q = (CT)4.5 * (q <= 6 ? w1 : w2) * (g1 * (pcc - t3) + g2 * t3 * (CT)(c2q - 1));
+      n[q] = (sym + anti) + fmaT(keep, n[q], Q);
+      n[b] = (sym - anti) + fmaT(keep, n[b], Q);
+    }
+  }
+  // non-equilibrium momentum flux Pi^neq = sum_q (n_q - feq_q) c_q c_q (pairs add), the
+  // node's mass deviation and the fluid node count
+#pragma unroll
+  for (int pi = 0; pi < 9; ++pi) {
+    const int q = 2 * pi + 1;
+    if (cx(q) != 0) pacc[0] += ps[pi];
+    if (cy(q) != 0) pacc[1] += ps[pi];
+    if (cz(q) != 0) pacc[2] += ps[pi];
+    addc(pacc[3], cx(q) * cy(q), ps[pi]);
+    addc(pacc[4], cx(q) * cz(q), ps[pi]);
+    addc(pacc[5], cy(q) * cz(q), ps[pi]);
+  }
+  pacc[6] += rd;
+  pacc[7] += (CT)1;
+  }
+  if (xin) {
+    uint32_t sb = rowc + (uint32_t)x * es;
+    asm volatile("" : "+v"(sb));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) RowIO<ST>::st_stream(rout, q * pb + sb, n[q], q, A.h16);
+  }
+}
+
 template <class ST, int COLL>
 __global__ __launch_bounds__(256, (sizeof(ST) <= 4 && COLL == 0) ? 8 : 1) void k_stream(StreamArgs A) {
   using CT = typename Store<ST>::CT;
@@ -651,9 +856,7 @@ __global__ __launch_bounds__(256, (sizeof(ST) <= 4 && COLL == 0) ? 8 : 1) void k
   const bool xin = x0 < lx;
   const int y_lo = byi * A.BY, y_hi = min(ly, y_lo + A.BY);
   const int z_lo = bzi * A.BZ, z_hi = min(lz, z_lo + A.BZ);
-  const CT om = (CT)A.omega;
-  const CT rho0 = (CT)A.rho0;
-  constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
+  constexpr uint32_t es = sizeof(ST);
   const uint32_t pb0 = (uint32_t)(A.plane * es);  // plane stride in bytes
   const __amdgpu_buffer_rsrc_t rin = buf_rsrc(A.fin, A.pop_bytes), rout = buf_rsrc(A.fout, A.pop_bytes);
   const __amdgpu_buffer_rsrc_t rgh = buf_rsrc(A.gval, A.gval_bytes), rrec = buf_rsrc(A.lrec, A.rec_bytes);
@@ -686,171 +889,57 @@ __global__ __launch_bounds__(256, (sizeof(ST) <= 4 && COLL == 0) ? 8 : 1) void k
         rnext = record(y, z + 1);
         vnext = rowv(y, z + 1);
       }
-      const uint32_t rowc = (uint32_t)((z * ly + y) * lx) * es;  // byte offset of the row in a plane
-      CT n[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) n[q] = 0;  // a solid node stores the rest state
-      if (!(rec & REC_SOLID)) {  // fluid node (a lane past the box end reads as solid)
-      const int xm = x == 0 ? lx - 1 : x - 1, xp = x + 1 >= lx ? 0 : x + 1;
-      const uint32_t xcb = x * es, xmb = xm * es, xpb = xp * es;
-      const uint32_t xcg = x * ges, xmg = xm * ges, xpg = xp * ges;
-      const int zm = z == 0 ? lz - 1 : z - 1, zp = z == lz - 1 ? 0 : z + 1;
-      // ---- pull (eq. 3); a link takes its bounce-back value from the link values (k_links),
-      //      the node's own after each other in direction order ----
-      const uint32_t v0 = vrow + (rec >> REC_OFF);
-      n[0] = RowIO<ST>::ld(rin, rowc + xcb, 0, A.h16);
-#pragma unroll
-      for (int q = 1; q < NQ; ++q) {
-        const int ys = y - cy(q);
-        const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
-        const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
-        // across a sliding plane this reads some other row, or nothing; replaced below
-        const uint32_t pull = q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb;
-        const uint32_t link = (v0 + __builtin_popcount(rec & ((1u << q) - 2u))) * es;
-        n[q] = RowIO<ST>::ld(rin, ((rec >> q) & 1u) ? link : pull, q, A.h16);
-      }
-      if (y == 0 || y == ly - 1) {  // directions across the sliding plane: the ghost row
-        const int side = y == 0 ? 0 : 1;
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-          if (cy(q) == (side == 0 ? 1 : -1)) {
-            const int zs = cz(q) == 1 ? zm : (cz(q) == -1 ? zp : z);
-            const uint32_t xsg = cx(q) == 1 ? xmg : (cx(q) == -1 ? xpg : xcg);
-            if (!((rec >> q) & 1u))  // a link keeps its bounce-back value
-              n[q] = RowIO<CT>::ld(rgh, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
-          }
-        }
-      }
-      // ---- moments and collision on the deviations d_q = n_q - w_q rho0, opposite
-      //      directions paired: feq_q,qbar = w (a + 4.5 rho cu^2) +- 3 w rho cu ----
-      CT rd = n[0], jx = 0, jy = 0, jz = 0;
-#pragma unroll
-      for (int pi = 0; pi < 9; ++pi) {
-        const int q = 2 * pi + 1;
-        const CT dq = n[q] - n[q + 1];
-        rd += n[q] + n[q + 1];
-        addc(jx, cx(q), dq); addc(jy, cy(q), dq); addc(jz, cz(q), dq);
-      }
-      const CT rho = rho0 + rd;
-      const CT ir = (CT)1 / rho;
-      const CT ux = jx * ir, uy = jy * ir, uz = jz * ir;
-      const CT uu = ux * ux + uy * uy + uz * uz;
-      // a non-finite density or velocity: the fluid has failed.  Speeds above 0.3 c_s (u^2 >
-      // 0.03, past the low-Mach range) are counted, not failed: a node squeezed into a one-node
-      // gap between two surfaces passes it briefly in dense runs
-      bad |= isfinite(uu) && isfinite(rho) ? 0u : (uint32_t)FL_FLUID;
-      nfast += uu > (CT)0.03 ? 1u : 0u;
-      umax = uu > umax ? uu : umax;
-      const CT a = rd - (CT)1.5 * rho * uu;
-      const CT w0 = (CT)(1.0 / 3.0), w1 = (CT)(1.0 / 18.0), w2 = (CT)(1.0 / 36.0);
-      const CT a1 = w1 * a, a2 = w2 * a;
-      const CT b1 = (CT)4.5 * w1 * rho, b2 = (CT)4.5 * w2 * rho;
-      const CT c1 = (CT)3 * w1 * rho, c2 = (CT)3 * w2 * rho;
-      CT ps[9];
-      if constexpr (COLL == 0) {
-        n[0] = fmaT(-om, n[0] - w0 * a, n[0]);
-#pragma unroll
-        for (int pi = 0; pi < 9; ++pi) {
-          const int q = 2 * pi + 1, b = q + 1;
-          const CT cu = cdot<CT>(q, ux, uy, uz);
-          const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
-          const CT anti = (q <= 6 ? c1 : c2) * cu;
-          const CT neq = n[q] - (sym + anti), neb = n[b] - (sym - anti);
-          ps[pi] = neq + neb;
-          n[q] = fmaT(-om, neq, n[q]);
-          n[b] = fmaT(-om, neb, n[b]);
-        }
-      } else {
-        // n* = n^eq + (1 - om_g) n^neq + Q_q, Q_q = 4.5 w_q [g1 (Pi:c c - t/3) + g2 t (|c|^2 - 1)/3]
-        // with Pi = Pi^neq, t its trace, g1 = om_g - om, g2 = om - om_v: the traceless
-        // stress relaxes with om, its trace with om_v, every other mode with om_g
-        const CT omg = (CT)A.om_ghost, g1 = omg - om, g2 = om - (CT)A.om_bulk;
-        const CT ne0 = n[0] - w0 * a;
-#pragma unroll
-        for (int pi = 0; pi < 9; ++pi) {  // n^neq into n, pair sums for the flux
-          const int q = 2 * pi + 1, b = q + 1;
-          const CT cu = cdot<CT>(q, ux, uy, uz);
-          const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
-          const CT anti = (q <= 6 ? c1 : c2) * cu;
-          n[q] = n[q] - (sym + anti);
-          n[b] = n[b] - (sym - anti);
-          ps[pi] = n[q] + n[b];
-        }
-        CT P[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
-#pragma unroll
-        for (int pi = 0; pi < 9; ++pi) {
-          const int q = 2 * pi + 1;
-          if (cx(q) != 0) P[0] += ps[pi];
-          if (cy(q) != 0) P[1] += ps[pi];
-          if (cz(q) != 0) P[2] += ps[pi];
-          addc(P[3], cx(q) * cy(q), ps[pi]);
-          addc(P[4], cx(q) * cz(q), ps[pi]);
-          addc(P[5], cy(q) * cz(q), ps[pi]);
-        }
-        const CT t3 = (P[0] + P[1] + P[2]) * (CT)(1.0 / 3.0);
-        const CT P2xy = (CT)2 * P[3], P2xz = (CT)2 * P[4], P2yz = (CT)2 * P[5];
-        const CT keep = (CT)1 - omg;
-        n[0] = w0 * a + keep * ne0 - (CT)1.5 * w0 * 3 * (g1 + g2) * t3;
-#pragma unroll
-        for (int pi = 0; pi < 9; ++pi) {
-          const int q = 2 * pi + 1, b = q + 1;
-          const CT cu = cdot<CT>(q, ux, uy, uz);
-          const CT sym = fmaT(q <= 6 ? b1 : b2, cu * cu, q <= 6 ? a1 : a2);
-          const CT anti = (q <= 6 ? c1 : c2) * cu;
-          CT pcc = (cx(q) != 0 ? P[0] : (CT)0) + (cy(q) != 0 ? P[1] : (CT)0) + (cz(q) != 0 ? P[2] : (CT)0);
-          addc(pcc, cx(q) * cy(q), P2xy);  // Pi : c c = sum_a Pi_aa c_a^2 + 2 sum_a<b Pi_ab c_a c_b
-          addc(pcc, cx(q) * cz(q), P2xz);
-          addc(pcc, cy(q) * cz(q), P2yz);
-          const int c2q = cx(q) * cx(q) + cy(q) * cy(q) + cz(q) * cz(q);
-          const CT Q = (CT)4.5 * (q <= 6 ? w1 : w2) * (g1 * (pcc - t3) + g2 * t3 * (CT)(c2q - 1));
-          n[q] = (sym + anti) + fmaT(keep, n[q], Q);
-          n[b] = (sym - anti) + fmaT(keep, n[b], Q);
-        }
-      }
-      // non-equilibrium momentum flux Pi^neq = sum_q (n_q - feq_q) c_q c_q (pairs add), the
-      // node's mass deviation and the fluid node count
-#pragma unroll
-      for (int pi = 0; pi < 9; ++pi) {
-        const int q = 2 * pi + 1;
-        if (cx(q) != 0) pacc[0] += ps[pi];
-        if (cy(q) != 0) pacc[1] += ps[pi];
-        if (cz(q) != 0) pacc[2] += ps[pi];
-        addc(pacc[3], cx(q) * cy(q), ps[pi]);
-        addc(pacc[4], cx(q) * cz(q), ps[pi]);
-        addc(pacc[5], cy(q) * cz(q), ps[pi]);
-      }
-      pacc[6] += rd;
-      pacc[7] += (CT)1;
-      }
-      // every node of the row is stored (solid nodes as the rest state, never read), so that
-      // the wave writes whole cache lines: HBM3E has no write mask, and a partly written line
-      // costs a read-modify-write
-      if (xin) {
-        uint32_t sb = rowc + (uint32_t)x * es;
-        asm volatile("" : "+v"(sb));
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) RowIO<ST>::st_stream(rout, q * pb + sb, n[q], q, A.h16);
-      }
+      stream_node<ST, COLL>(A, rin, rout, rgh, pb, x, y, z, xin, rec, vrow, pacc, bad, nfast, umax);
     }
   }
-  if (bad) atomicOr(A.flags, (int32_t)bad);  // rare
-  if (nfast) {  // rare: the health counters (count of fast node-steps, largest u^2 as bits)
-    atomicAdd((unsigned long long *)(A.flags + FL_HEALTH), (unsigned long long)nfast);
-    atomicMax(A.flags + FL_HEALTH + 2, __float_as_int((float)umax));
-  }
+  stream_tail<CT>(A, brick, spn, pacc, bad, nfast, umax);
+}
+
+// ---- k_lattice: k_links and k_stream of one 64 x 4 x 4 brick in one work-group.  The link
+// phase loads the brick's own populations of the link directions (whole lines of its rows from
+// HBM); the stream phase, right after it in the same work-group, finds most of those lines
+// still in the L2 and reads the link values the work-group has just written (a barrier apart;
+// each brick's block of link values is a whole number of cache lines, so no other work-group
+// brings a stale copy of them into this CU's L1).  Wave w streams row y0 + w through the
+// brick's z-slices.  The stream partials reuse the list's LDS. ----
+struct LatticeArgs {
+  LinksArgs L;
+  StreamArgs S;
+};
+
+template <class ST, int COLL>
+__global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(LatticeArgs P) {
+  using CT = typename Store<ST>::CT;
+  __shared__ LinksLDS sh;
+  const int brick = (blockIdx.x & 7) * P.L.per_xcd + (blockIdx.x >> 3);
+  if (brick >= P.L.nbricks) return;  // the whole work-group
+  links_body<ST>(P.L, brick, sh);
+  __syncthreads();  // the brick's link values written, the list free
+  const StreamArgs &A = P.S;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lx = A.lx, ly = A.ly, lz = A.lz;
+  const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
+  const int nsl = min(LBZ, lz - z0);
+  constexpr uint32_t es = sizeof(ST);
+  const uint32_t pb = (uint32_t)opaque_uniform((int)(A.plane * es));
+  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(A.fin, A.pop_bytes), rout = buf_rsrc(A.fout, A.pop_bytes);
+  const __amdgpu_buffer_rsrc_t rgh = buf_rsrc(A.gval, A.gval_bytes);
+  CT pacc[NPIN];
 #pragma unroll
-  for (int c = 0; c < NPIN; ++c) spn[c][t] = pacc[c];
-  __syncthreads();
-  // the brick's partials: the 256 per-thread partials of each component summed by one wave
-  // in a fixed order
-  if (wv == 0) {
-#pragma unroll
-    for (int c = 0; c < NPIN; ++c) {
-      const double v = wave_sum(((double)spn[c][lane] + (double)spn[c][lane + 64]) +
-                                ((double)spn[c][lane + 128] + (double)spn[c][lane + 192]));
-      if (lane == 0) A.pin[(size_t)brick * NPIN + c] = v;
+  for (int c = 0; c < NPIN; ++c) pacc[c] = 0;
+  uint32_t bad = 0, nfast = 0;
+  CT umax = 0;
+  const int x = x0 + lane;
+  const bool xin = x < lx;
+  if (y0 + wv < ly) {
+#pragma unroll 1
+    for (int sl = 0; sl < nsl; ++sl) {
+      const int loc = lane | (wv << 6) | (sl << 8);
+      stream_node<ST, COLL>(A, rin, rout, rgh, pb, x, opaque_uniform(y0 + wv), opaque_uniform(z0 + sl), xin,
+                            sh.srec[loc], sh.srow[wv + LBY * sl], pacc, bad, nfast, umax);
     }
   }
+  stream_tail<CT>(A, brick, reinterpret_cast<CT (*)[256]>(&sh.list[0]), pacc, bad, nfast, umax);
 }
 
 static uint32_t pop_bytes(const Sim *s) {  // the populations and the link values after them
@@ -862,9 +951,7 @@ static uint32_t gval_bytes(const Sim *s) {
   return (uint32_t)(10 * (size_t)s->lx * s->lz * ges);
 }
 
-// The links (k_links): after the ghost planes, before k_stream.
-hipError_t launch_links(Sim *s, const Box &b) {
-  if (s->n == 0) return hipSuccess;
+static LinksArgs links_args(const Sim *s, const Box &b) {
   LinksArgs A;
   A.f = s->f[s->cur];
   A.plane = s->plane;
@@ -889,16 +976,10 @@ hipError_t launch_links(Sim *s, const Box &b) {
   A.kax = -6.0 * wq(1) * s->rho0;
   A.kdg = -6.0 * wq(7) * s->rho0;
   A.h16 = s->h16;
-  const dim3 grid(A.per_xcd * 8), blk(256);
-  if (s->precision == 0) hipLaunchKernelGGL(k_links<double>, grid, blk, 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_links<float>, grid, blk, 0, s->stream, A);
-  else hipLaunchKernelGGL(k_links<__half>, grid, blk, 0, s->stream, A);
-  return hipGetLastError();
+  return A;
 }
 
-// The streaming kernel (k_stream): pull, collision, partials.
-hipError_t launch_lbm(Sim *s, const Box &b) {
-  (void)b;
+static StreamArgs stream_args(const Sim *s) {
   StreamArgs A;
   A.fin = s->f[s->cur];
   A.fout = s->f[1 - s->cur];
@@ -921,6 +1002,45 @@ hipError_t launch_lbm(Sim *s, const Box &b) {
   A.om_ghost = 1.0 / s->tau_ghost;
   A.om_bulk = 1.0 / s->tau_bulk;
   A.h16 = s->h16;
+  return A;
+}
+
+// Whether the step runs k_lattice (links and stream of a brick in one work-group): the stream
+// bricks are the link bricks (64 x 4 x 4) and there are spheres.
+static bool fused(const Sim *s) { return s->n > 0 && s->BY == LBY && s->BZ == LBZ; }
+
+// The links (k_links, or k_lattice): after the ghost planes, before k_stream.
+hipError_t launch_links(Sim *s, const Box &b) {
+  if (s->n == 0) return hipSuccess;
+  if (fused(s)) {
+    LatticeArgs P;
+    P.L = links_args(s, b);
+    P.S = stream_args(s);
+    const dim3 grid(P.L.per_xcd * 8), blk(256);
+    if (s->collision == 0) {
+      if (s->precision == 0) hipLaunchKernelGGL((k_lattice<double, 0>), grid, blk, 0, s->stream, P);
+      else if (s->precision == 1) hipLaunchKernelGGL((k_lattice<float, 0>), grid, blk, 0, s->stream, P);
+      else hipLaunchKernelGGL((k_lattice<__half, 0>), grid, blk, 0, s->stream, P);
+    } else {
+      if (s->precision == 0) hipLaunchKernelGGL((k_lattice<double, 1>), grid, blk, 0, s->stream, P);
+      else if (s->precision == 1) hipLaunchKernelGGL((k_lattice<float, 1>), grid, blk, 0, s->stream, P);
+      else hipLaunchKernelGGL((k_lattice<__half, 1>), grid, blk, 0, s->stream, P);
+    }
+    return hipGetLastError();
+  }
+  const LinksArgs A = links_args(s, b);
+  const dim3 grid(A.per_xcd * 8), blk(256);
+  if (s->precision == 0) hipLaunchKernelGGL(k_links<double>, grid, blk, 0, s->stream, A);
+  else if (s->precision == 1) hipLaunchKernelGGL(k_links<float>, grid, blk, 0, s->stream, A);
+  else hipLaunchKernelGGL(k_links<__half>, grid, blk, 0, s->stream, A);
+  return hipGetLastError();
+}
+
+// The streaming kernel (k_stream): pull, collision, partials (nothing when k_lattice ran).
+hipError_t launch_lbm(Sim *s, const Box &b) {
+  (void)b;
+  if (fused(s)) return hipSuccess;
+  const StreamArgs A = stream_args(s);
   dim3 grid(A.per_xcd * 8), blk(256);
   if (s->collision == 0) {
     if (s->precision == 0) hipLaunchKernelGGL((k_stream<double, 0>), grid, blk, 0, s->stream, A);
