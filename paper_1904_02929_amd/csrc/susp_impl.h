@@ -237,7 +237,7 @@ struct Sim {
   double *a, *m, *I, *amap;
   double *hyd[2];
   int hcur;
-  unsigned long long *hacc;  // [n][HYD][2] fixed-point link sums of the step (k_lbm)
+  unsigned long long *hacc;  // [n][HYD][2] fixed-point link sums of the step (link phase)
   double *pst;   // [n][PST]
   double *dp;    // [n][8] cover/uncover momentum, angular momentum, mass
   // lists
