@@ -46,7 +46,7 @@ template <class T> __device__ inline T wave_sum(T v) {
 //               (eqs. 4, 5) on the deviations d_q = n_q - w_q rho0, the fluid stress and mass
 //               partials; rows are stored whole, a solid node as the rest state.
 constexpr int TX = 64;      // brick width: one wave per 64-node row segment
-constexpr int TS = 64;      // per-work-group table slots of k_links (spheres seen by its entries)
+constexpr int TS = 32;      // per-work-group table slots of k_links (spheres seen by its entries)
 constexpr int NPIN = 8;     // per-brick partials: Pi^neq xx yy zz xy xz yz, sum (rho - rho0), fluid nodes
 constexpr int LMAXS = 6;    // spheres one node can link to
 
@@ -242,8 +242,8 @@ struct LinksArgs {
   const double *R, *U, *W;
   unsigned long long *hacc;  // [n][HYD][2]
   int32_t *flags;
-  uint32_t *lrec;            // [nodes] link records
-  int32_t *lrow;             // [rows] first link value of each 64-node row
+  uint32_t *lrec;            // [nodes] link records (null: kept in LDS only, for k_lattice)
+  int32_t *lrow;             // [rows] first link value of each 64-node row (null with lrec)
   uint32_t vbase;            // elements from the buffer's start to the link values
   uint32_t vcap;             // link values the buffer holds
   int lx, ly, lz;
@@ -271,15 +271,17 @@ struct LinksLDS {
   int2 list[LCAP];                       // (table slot, or -1 - sphere; node in the brick | link directions >> 1 << 10)
   int32_t skey[TS];                      // the table's spheres
   uint32_t srec[LBX * LBY * LBZ];        // the brick's link records
-  uint32_t srow[LBY * LBZ];              // first link value of each of its rows (vbase included)
+  uint32_t srow[LBY * LBZ];              // first link value of each of its rows (k_links: vbase
+                                         // included; k_lattice: its index in the brick's slots)
+  double spw[4][NPIN];                   // k_lattice: the stream partials of each wave
   int32_t lcount, vcount;
 };
 
-// The links of one brick (list, table, links, per-sphere sums); the records and row starts
-// stay in sh for a stream phase of the same work-group.
-template <class ST>
-__device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksLDS &sh) {
-  using CT = typename Store<ST>::CT;
+// The list and table of one brick; returns the entry count (flags raised go to bad).  The
+// records and row starts stay in sh.  FUSED: the row starts index the brick's link slots
+// (k_lattice) instead of the link values after the populations.
+template <class ST, bool FUSED>
+__device__ __forceinline__ int links_list(const LinksArgs &A, int brick, LinksLDS &sh, uint32_t &bad) {
   auto &skey = sh.skey;
   auto &sacc = sh.sacc;
   auto &ssph = sh.ssph;
@@ -295,9 +297,7 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
   const int lx = A.lx, ly = A.ly, lz = A.lz;
   const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
   const int nsl = min(LBZ, lz - z0);
-  constexpr uint32_t es = sizeof(ST);
   constexpr uint32_t OOB = 0xfffffff0u;  // a buffer offset past every array: reads 0, writes nothing
-  uint32_t bad = 0;
   // ---- list ----
   {
     const __amdgpu_buffer_rsrc_t rown = buf_rsrc(A.own, A.ow_bytes);
@@ -369,14 +369,15 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
         if (lane == 0 && ok && tot) rb = atomicAdd(&vcount, tot);
         rb = __builtin_amdgcn_readfirstlane(rb);
         if (rb + tot > LBX * LBY * LBZ * LINK_CAP) bad |= FL_LINKS;  // values past the block are not kept
+        const int rl = rb;  // in the brick
         rb += brick * (LBX * LBY * LBZ * LINK_CAP);
-        if (ok) {
+        if (!FUSED && ok && A.lrec) {
           const int z = z0 + sl;
           A.lrec[(size_t)xc + (size_t)lx * ((size_t)yc + (size_t)ly * z)] = rec;
           if (lane == 0) A.lrow[(z * ly + yc) * A.bxn + x0 / LBX] = rb;
         }
         srec[loc] = rec;
-        if (lane == 0) srow[wv + LBY * sl] = A.vbase + (uint32_t)rb;
+        if (lane == 0) srow[wv + LBY * sl] = FUSED ? (uint32_t)rl : A.vbase + (uint32_t)rb;
       }
       const unsigned long long bs = __ballot(single);
       int sb = 0;
@@ -447,6 +448,27 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
     list[e].x = slot >= 0 ? slot : -1 - p;
   }
   __syncthreads();
+  return cnt;
+}
+
+// The links of one brick (list, table, links, per-sphere sums) for k_stream: each link's
+// bounce-back value goes to the link values after the populations.
+template <class ST>
+__device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksLDS &sh) {
+  using CT = typename Store<ST>::CT;
+  auto &skey = sh.skey;
+  auto &sacc = sh.sacc;
+  auto &ssph = sh.ssph;
+  auto &list = sh.list;
+  auto &srec = sh.srec;
+  auto &srow = sh.srow;
+  uint32_t bad = 0;
+  const int cnt = links_list<ST, false>(A, brick, sh, bad);
+  const int t = threadIdx.x;
+  const int lx = A.lx, ly = A.ly;
+  const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
+  constexpr uint32_t es = sizeof(ST);
+  constexpr uint32_t OOB = 0xfffffff0u;
   // ---- links: one lane per entry; an entry some of whose links end in another image of the
   //      sphere than the one nearest the node is marked and done in a second pass ----
   const Box bx = clock_box(A.b, A.clk, 0);
@@ -623,6 +645,288 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
   }
 }
 
+// ---- k_lattice's link phases.  Its stream phase takes a link's own opposite population
+// n*_qbar(X) from the populations itself (those lines are in the L2 for the brick's own pulls)
+// and the link's correction from the brick's link slots, where it leaves n*_qbar(X) for the
+// sums; so no phase reads the populations twice, and the slots live in LDS:
+//   pre   one lane per entry: corr = -6 w_q rho0 u(X) . c_q of each link into its slot
+//   sums  one lane per entry, m = 2 n*_qbar - corr and the entry's F, T, S as in k_links; the
+//         entries are taken in a scattered order, so that the lanes of a wave meet at fewer
+//         spheres in the table's atomics
+// Slot k of a brick (k < LINK_CAP values per node): LDS for k < VLDS, else the brick's block
+// of link values after the populations, read as the compute type (a brick with more links
+// than VLDS; the 256^3 bulk suspension at phi 0.55 has 1,573 per brick on average, 2,564 at
+// most).  Bricks within VLDS (OVF false) run without branches: a direction that is no link
+// of the lane's node takes the lane's spare slot VLDS + lane, which always holds 0.
+constexpr int VLDS = 2560;
+constexpr int BRICK_VALUES = LBX * LBY * LBZ * LINK_CAP;
+template <class CT> struct CtIO;
+template <> struct CtIO<float> {
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+  }
+};
+template <> struct CtIO<double> {
+  __device__ static double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  }
+};
+template <class CT> struct LinkSlots {
+  CT *lds;
+  __amdgpu_buffer_rsrc_t r;  // the population buffer
+  uint32_t block;            // byte offset of the brick's block of link values
+  bool ovf;                  // more than VLDS links in the brick (work-group uniform)
+  __device__ uint32_t goff(uint32_t k) const {  // past the block: nothing kept (FL_LINKS raised)
+    return k < (uint32_t)BRICK_VALUES ? block + (k - VLDS) * (uint32_t)sizeof(CT) : 0xfffffff0u;
+  }
+  __device__ CT ld(uint32_t k) const {
+    if (!ovf) return lds[k];
+    return k < (uint32_t)VLDS ? lds[k] : CtIO<CT>::ld(r, goff(k));
+  }
+  __device__ void st(uint32_t k, CT v) const {
+    if (!ovf) { lds[k] = v; return; }
+    if (k < (uint32_t)VLDS) lds[k] = v;
+    else CtIO<CT>::st(r, goff(k), v);
+  }
+};
+
+// centre, velocity and spin of an entry's sphere: staged in the table, or (a full table) from
+// the arrays
+__device__ inline double sph_state(const LinksArgs &A, const LinksLDS &sh, int key, int c) {
+  if (key >= 0) return sh.ssph[key][c];
+  const int p = -1 - key;
+  return c < 3 ? A.R[3 * p + c] : (c < 6 ? A.U[3 * p + c - 3] : A.W[3 * p + c - 6]);
+}
+// The node's lever D (node minus the nearest image of the centre) and the rigid-body velocity
+// there (eq. 8); false when some link may end in another image (the per-link path).
+__device__ inline bool entry_motion(const LinksArgs &A, const LinksLDS &sh, const Box &bx, int key, int x, int y,
+                                    int z, double &Dx, double &Dy, double &Dz, double &ux, double &uy, double &uz) {
+  const double ilx = 1.0 / bx.Lx, ilz = 1.0 / bx.Lz;
+  const double hx = 0.5 * bx.Lx - 1.0 - 1e-6, hy = 0.5 * bx.Ly - 1.0 - 1e-6, hz = 0.5 * bx.Lz - 1.0 - 1e-6;
+  int k;
+  node_image(bx, ilx, ilz, (double)x - sph_state(A, sh, key, 0), (double)y - sph_state(A, sh, key, 1),
+             (double)z - sph_state(A, sh, key, 2), Dx, Dy, Dz, k);
+  if (!(fabs(Dx) <= hx && fabs(Dy) <= hy && fabs(Dz) <= hz)) return false;
+  const double w0 = sph_state(A, sh, key, 6), w1 = sph_state(A, sh, key, 7), w2 = sph_state(A, sh, key, 8);
+  ux = sph_state(A, sh, key, 3) + k * bx.ule + (w1 * Dz - w2 * Dy);
+  uy = sph_state(A, sh, key, 4) + (w2 * Dx - w0 * Dz);
+  uz = sph_state(A, sh, key, 5) + (w0 * Dy - w1 * Dx);
+  return true;
+}
+// Per-link path: the lever of link q (its midpoint X - c_q/2 minus the centre of the image
+// holding its solid end) and its correction -6 w_q rho0 u_b . c_q.
+__device__ inline double link_corr(const LinksArgs &A, const Box &bx, int p, int x, int y, int z, int q,
+                                   double &lvx, double &lvy, double &lvz) {
+  const int qx = cx(q), qy = cy(q), qz = cz(q);
+  double ex, ey, ez;
+  int kq;
+  minimage(bx, (double)(x - qx) - A.R[3 * p], (double)(y - qy) - A.R[3 * p + 1], (double)(z - qz) - A.R[3 * p + 2],
+           ex, ey, ez, kq);
+  lvx = ex + 0.5 * qx; lvy = ey + 0.5 * qy; lvz = ez + 0.5 * qz;
+  const double w0 = A.W[3 * p], w1 = A.W[3 * p + 1], w2 = A.W[3 * p + 2];
+  const double ubx = A.U[3 * p] + kq * bx.ule + (w1 * lvz - w2 * lvy);
+  const double uby = A.U[3 * p + 1] + (w2 * lvx - w0 * lvz);
+  const double ubz = A.U[3 * p + 2] + (w0 * lvy - w1 * lvx);
+  double cu = 0.0;  // c_q . u_b, x y z in order
+  bool first = true;
+  if (qx != 0) { cu = qx > 0 ? ubx : -ubx; first = false; }
+  if (qy != 0) { const double t1 = qy > 0 ? uby : -uby; cu = first ? t1 : cu + t1; first = false; }
+  if (qz != 0) { const double t1 = qz > 0 ? ubz : -ubz; cu = first ? t1 : cu + t1; }
+  return (q <= 6 ? A.kax : A.kdg) * cu;
+}
+// An entry's sums into the table (a full table: straight into the sphere's sums).
+__device__ inline void table_add(const LinksArgs &A, LinksLDS &sh, int key, uint32_t m, const double (&v)[HYD]) {
+  if (key >= 0) {
+#pragma unroll
+    for (int c = 0; c < HYD - 1; ++c) fx_lds(&sh.sacc[key][c][0], v[c]);
+    atomicAdd(&sh.sacc[key][HYD - 1][0], (unsigned long long)__builtin_popcount(m) << FXH);  // an integer
+  } else {
+    unsigned long long *d = &A.hacc[(size_t)(-1 - key) * HYD * 2];
+    for (int c = 0; c < HYD - 1; ++c) fx_add(d + 2 * c, v[c]);
+    atomicAdd(d + 2 * (HYD - 1), (unsigned long long)__builtin_popcount(m) << FXH);
+  }
+}
+// the table's sums into the spheres' sums
+__device__ inline void table_flush(const LinksArgs &A, const LinksLDS &sh) {
+  for (int i = threadIdx.x; i < TS * HYD; i += 256) {
+    const int slot = i / HYD, c = i - slot * HYD;
+    const int key = sh.skey[slot];
+    if (key >= 0) {
+      const unsigned long long h = sh.sacc[slot][c][0], l = sh.sacc[slot][c][1];
+      if (h | l) {
+        atomicAdd(&A.hacc[((size_t)key * HYD + c) * 2], h);
+        atomicAdd(&A.hacc[((size_t)key * HYD + c) * 2 + 1], l);
+      }
+    }
+  }
+}
+// slot of link q of a node whose first slot is v0 (q a link of the record)
+__device__ inline uint32_t rec_slot(uint32_t v0, uint32_t rec, int q) {
+  return v0 + __builtin_popcount(rec & ((1u << q) - 2u));
+}
+
+// pre: the corrections of the brick's links into their slots; entries whose links may end in
+// another image are marked and done per link.
+template <class ST, bool OVF>
+__device__ __forceinline__ void lattice_pre(const LinksArgs &A, int brick, LinksLDS &sh,
+                                            const LinkSlots<typename Store<ST>::CT> &S, int cnt) {
+  using CT = typename Store<ST>::CT;
+  const int t = threadIdx.x;
+  const uint32_t spare = VLDS + (t & 63);
+  const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
+  const Box bx = clock_box(A.b, A.clk, 0);
+  for (int e = t; e < cnt; e += 256) {
+    const int2 en = sh.list[e];
+    const int key = en.x, loc = en.y & 1023;
+    const uint32_t m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
+    const int x = x0 + (loc & 63), y = y0 + ((loc >> 6) & 3), z = z0 + ((loc >> 8) & 3);
+    double Dx, Dy, Dz, ux, uy, uz;
+    if (!entry_motion(A, sh, bx, key, x, y, z, Dx, Dy, Dz, ux, uy, uz)) {
+      sh.list[e].y = en.y | (int)0x80000000;
+      continue;
+    }
+    const uint32_t rec = sh.srec[loc];
+    const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {
+      const int q = 2 * pi + 1, b = q + 1;
+      const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
+      const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
+      if constexpr (OVF) {
+        if (lq) S.st(rec_slot(v0, rec, q), (CT)corr);
+        if (lb) S.st(rec_slot(v0, rec, b), (CT)(-corr));  // c_b = -c_q
+      } else {
+        S.lds[lq ? rec_slot(v0, rec, q) : spare] = lq ? (CT)corr : (CT)0;
+        S.lds[lb ? rec_slot(v0, rec, b) : spare] = lb ? (CT)(-corr) : (CT)0;
+      }
+    }
+  }
+  for (int e = t; e < cnt; e += 256) {  // the marked entries (this thread's own)
+    const int2 en = sh.list[e];
+    if (en.y >= 0) continue;
+    const int key = en.x, loc = en.y & 1023;
+    const uint32_t m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
+    const int x = x0 + (loc & 63), y = y0 + ((loc >> 6) & 3), z = z0 + ((loc >> 8) & 3);
+    const int p = key >= 0 ? sh.skey[key] : -1 - key;
+    const uint32_t rec = sh.srec[loc];
+    const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+#pragma unroll 1
+    for (int q = 1; q < NQ; ++q) {  // a rare path, kept small
+      if (!((m >> q) & 1u)) continue;
+      double lvx, lvy, lvz;
+      S.st(rec_slot(v0, rec, q), (CT)link_corr(A, bx, p, x, y, z, q, lvx, lvy, lvz));
+    }
+  }
+}
+
+// sums: the exchanged momentum of every link from n*_qbar(X) left in its slot by the stream
+// phase, summed per entry (F = -sum m c_q, T = D x F, S = sym(D (x) F) + 1/2 sum m c_q c_q) into
+// the table, then into the spheres' sums.
+template <class ST, bool OVF>
+__device__ __forceinline__ void lattice_sums(const LinksArgs &A, int brick, LinksLDS &sh,
+                                             const LinkSlots<typename Store<ST>::CT> &S, int cnt, uint32_t bad) {
+  const int t = threadIdx.x;
+  const uint32_t spare = VLDS + (t & 63);
+  const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
+  const Box bx = clock_box(A.b, A.clk, 0);
+  // entry (j P) mod cnt for j = t, t + 256, ...: a permutation (P prime, not a divisor of cnt)
+  const int P = cnt % 97 ? 97 : 89;
+  const int cn = cnt > 0 ? cnt : 1;
+  const int stride = (256 * P) % cn;
+  int e = (t * P) % cn;
+  for (int j = t; j < cnt; j += 256) {
+    const int2 en = sh.list[e];
+    e += stride;
+    e -= e >= cnt ? cnt : 0;
+    if (en.y < 0) continue;  // marked: below
+    const int key = en.x, loc = en.y & 1023;
+    const uint32_t m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
+    const int x = x0 + (loc & 63), y = y0 + ((loc >> 6) & 3), z = z0 + ((loc >> 8) & 3);
+    double Dx, Dy, Dz, ux, uy, uz;
+    entry_motion(A, sh, bx, key, x, y, z, Dx, Dy, Dz, ux, uy, uz);  // true: not marked
+    const uint32_t rec = sh.srec[loc];
+    const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+    double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+#pragma unroll
+    for (int pi = 0; pi < 9; ++pi) {
+      const int q = 2 * pi + 1, b = q + 1;
+      const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
+      const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
+      double nq, nb;  // n*_qbar(X), n*_bbar(X)
+      if constexpr (OVF) {
+        nq = lq ? (double)S.ld(rec_slot(v0, rec, q)) : 0.0;
+        nb = lb ? (double)S.ld(rec_slot(v0, rec, b)) : 0.0;
+      } else {
+        nq = (double)S.lds[lq ? rec_slot(v0, rec, q) : spare];
+        nb = (double)S.lds[lb ? rec_slot(v0, rec, b) : spare];
+      }
+      const double mq = lq ? fma(2.0, nq, -corr) : 0.0;
+      const double mb = lb ? fma(2.0, nb, corr) : 0.0;
+      const double sm2 = mq + mb, df = mq - mb;
+      // each sum starts at its first contributing pair (no addition to zero)
+      acc_pair(g0, pi, 0, cx(q), df); acc_pair(g1, pi, 1, cy(q), df); acc_pair(g2, pi, 2, cz(q), df);
+      acc_pair(mxx, pi, 0, cx(q) * cx(q), sm2);
+      acc_pair(myy, pi, 1, cy(q) * cy(q), sm2);
+      acc_pair(mzz, pi, 2, cz(q) * cz(q), sm2);
+      acc_pair(mxy, pi, 3, cx(q) * cy(q), sm2); acc_pair(mxz, pi, 4, cx(q) * cz(q), sm2);
+      acc_pair(myz, pi, 5, cy(q) * cz(q), sm2);
+    }
+    double v[HYD];
+    v[0] = -g0; v[1] = -g1; v[2] = -g2;
+    v[3] = Dy * v[2] - Dz * v[1];
+    v[4] = Dz * v[0] - Dx * v[2];
+    v[5] = Dx * v[1] - Dy * v[0];
+    v[6] = Dx * v[0] + 0.5 * mxx;
+    v[7] = Dy * v[1] + 0.5 * myy;
+    v[8] = Dz * v[2] + 0.5 * mzz;
+    v[9] = 0.5 * (Dx * v[1] + Dy * v[0]) + 0.5 * mxy;
+    v[10] = 0.5 * (Dx * v[2] + Dz * v[0]) + 0.5 * mxz;
+    v[11] = 0.5 * (Dy * v[2] + Dz * v[1]) + 0.5 * myz;
+    v[12] = 0.0;  // the link count is added from m
+    table_add(A, sh, key, m, v);
+  }
+  for (int e2 = t; e2 < cnt; e2 += 256) {  // the marked entries: each link with its own lever
+    const int2 en = sh.list[e2];
+    if (en.y >= 0) continue;
+    const int key = en.x, loc = en.y & 1023;
+    const uint32_t m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
+    const int x = x0 + (loc & 63), y = y0 + ((loc >> 6) & 3), z = z0 + ((loc >> 8) & 3);
+    const int p = key >= 0 ? sh.skey[key] : -1 - key;
+    const uint32_t rec = sh.srec[loc];
+    const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+    double v[HYD];
+#pragma unroll
+    for (int c = 0; c < HYD; ++c) v[c] = 0.0;
+#pragma unroll 1
+    for (int q = 1; q < NQ; ++q) {
+      if (!((m >> q) & 1u)) continue;
+      double lvx, lvy, lvz;
+      const double corr = link_corr(A, bx, p, x, y, z, q, lvx, lvy, lvz);
+      const double mm = fma(2.0, (double)S.ld(rec_slot(v0, rec, q)), -corr);
+      double f[3] = {0.0, 0.0, 0.0};
+      addc(f[0], -cx(q), mm); addc(f[1], -cy(q), mm); addc(f[2], -cz(q), mm);
+      v[0] += f[0]; v[1] += f[1]; v[2] += f[2];
+      v[3] += lvy * f[2] - lvz * f[1];
+      v[4] += lvz * f[0] - lvx * f[2];
+      v[5] += lvx * f[1] - lvy * f[0];
+      v[6] += lvx * f[0]; v[7] += lvy * f[1]; v[8] += lvz * f[2];
+      v[9] += 0.5 * (lvx * f[1] + lvy * f[0]);
+      v[10] += 0.5 * (lvx * f[2] + lvz * f[0]);
+      v[11] += 0.5 * (lvy * f[2] + lvz * f[1]);
+    }
+    table_add(A, sh, key, m, v);
+  }
+  if (bad) atomicOr(A.flags, (int32_t)bad);
+  __syncthreads();
+  table_flush(A, sh);
+}
+
 template <class ST>
 __global__ __launch_bounds__(256) void k_links(LinksArgs A) {
   __shared__ LinksLDS sh;
@@ -682,18 +986,21 @@ __device__ __forceinline__ void stream_tail(const StreamArgs &A, int brick, CT (
   }
 }
 
-// One node of the stream phase: pull (eq. 3; a link takes its bounce-back value from the link
-// values, the node's own after each other in direction order), collision (eqs. 4, 5) on the
-// deviations, the node's partials, and its row store (every lane of a row stores, solid nodes
-// as the rest state, never read, so that the wave writes whole cache lines: HBM3E has no
-// write mask, and a partly written line costs a read-modify-write).  rec: the node's link
-// record (REC_SOLID for a lane past the box end); vrow: the element of its row's first link value.
-template <class ST, int COLL>
+// One node of the stream phase: pull (eq. 3), collision (eqs. 4, 5) on the deviations, the
+// node's partials, and its row store (every lane of a row stores, solid nodes as the rest
+// state, never read, so that the wave writes whole cache lines: HBM3E has no write mask, and a
+// partly written line costs a read-modify-write).  rec: the node's link record (REC_SOLID for a
+// lane past the box end); vrow: its row's first link value.  A link takes its bounce-back value
+// n*_qbar(X) - corr (eq. 7): k_stream reads it whole from the link values (k_links wrote it);
+// in k_lattice (FUSED) the node loads its own n*_qbar(X), takes corr from the link's slot and
+// leaves n*_qbar(X) there for the sums.
+template <class ST, int COLL, int FUSED>  // FUSED 0: k_stream; 1, 2: k_lattice (2: slots past VLDS)
 __device__ __forceinline__ void stream_node(const StreamArgs &A, __amdgpu_buffer_rsrc_t rin,
                                             __amdgpu_buffer_rsrc_t rout, __amdgpu_buffer_rsrc_t rgh, uint32_t pb,
                                             int x, int y, int z, bool xin, uint32_t rec, uint32_t vrow,
                                             typename Store<ST>::CT (&pacc)[NPIN], uint32_t &bad, uint32_t &nfast,
-                                            typename Store<ST>::CT &umax) {
+                                            typename Store<ST>::CT &umax,
+                                            const LinkSlots<typename Store<ST>::CT> &S) {
   using CT = typename Store<ST>::CT;
   constexpr uint32_t es = sizeof(ST), ges = sizeof(CT);
   const int lx = A.lx, ly = A.ly, lz = A.lz;
@@ -719,7 +1026,8 @@ __device__ __forceinline__ void stream_node(const StreamArgs &A, __amdgpu_buffer
     const uint32_t xsb = cx(q) == 1 ? xmb : (cx(q) == -1 ? xpb : xcb);
     // across a sliding plane this reads some other row, or nothing; replaced below
     const uint32_t pull = q * pb + (uint32_t)((zs * ly + ys) * lx) * es + xsb;
-    const uint32_t link = (v0 + __builtin_popcount(rec & ((1u << q) - 2u))) * es;
+    const uint32_t link = FUSED ? opp(q) * pb + rowc + xcb  // n*_qbar at the node itself
+                                : (v0 + __builtin_popcount(rec & ((1u << q) - 2u))) * es;
     n[q] = RowIO<ST>::ld(rin, ((rec >> q) & 1u) ? link : pull, q, A.h16);
   }
   if (y == 0 || y == ly - 1) {  // directions across the sliding plane: the ghost row
@@ -731,6 +1039,25 @@ __device__ __forceinline__ void stream_node(const StreamArgs &A, __amdgpu_buffer
         const uint32_t xsg = cx(q) == 1 ? xmg : (cx(q) == -1 ? xpg : xcg);
         if (!((rec >> q) & 1u))  // a link keeps its bounce-back value
           n[q] = RowIO<CT>::ld(rgh, (uint32_t)(((side * 5 + gslot(q)) * lz + zs) * lx) * ges + xsg, q, A.h16);
+      }
+    }
+  }
+  if constexpr (FUSED == 1) {  // the corrections out of the slots, n*_qbar(X) in (one exchange)
+    const uint32_t spare = VLDS + (threadIdx.x & 63);
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      const bool lk = (rec >> q) & 1u;
+      CT *const slot = S.lds + (lk ? rec_slot(v0, rec, q) : spare);
+      n[q] -= __hip_atomic_exchange(slot, lk ? n[q] : (CT)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  } else if constexpr (FUSED == 2) {
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+      if ((rec >> q) & 1u) {
+        const uint32_t k = rec_slot(v0, rec, q);
+        const CT c = S.ld(k);
+        S.st(k, n[q]);
+        n[q] -= c;
       }
     }
   }
@@ -889,32 +1216,29 @@ __global__ __launch_bounds__(256, (sizeof(ST) <= 4 && COLL == 0) ? 8 : 1) void k
         rnext = record(y, z + 1);
         vnext = rowv(y, z + 1);
       }
-      stream_node<ST, COLL>(A, rin, rout, rgh, pb, x, y, z, xin, rec, vrow, pacc, bad, nfast, umax);
+      stream_node<ST, COLL, 0>(A, rin, rout, rgh, pb, x, y, z, xin, rec, vrow, pacc, bad, nfast, umax,
+                               LinkSlots<CT>{});
     }
   }
   stream_tail<CT>(A, brick, spn, pacc, bad, nfast, umax);
 }
 
-// ---- k_lattice: k_links and k_stream of one 64 x 4 x 4 brick in one work-group.  The link
-// phase loads the brick's own populations of the link directions (whole lines of its rows from
-// HBM); the stream phase, right after it in the same work-group, finds most of those lines
-// still in the L2 and reads the link values the work-group has just written (a barrier apart;
-// each brick's block of link values is a whole number of cache lines, so no other work-group
-// brings a stale copy of them into this CU's L1).  Wave w streams row y0 + w through the
-// brick's z-slices.  The stream partials reuse the list's LDS. ----
+// ---- k_lattice: the links and the stream of one 64 x 4 x 4 brick in one work-group: list and
+// table, pre (link corrections into the slots), stream (wave w streams row y0 + w through the
+// brick's z-slices), sums.  The slots past VLDS and the records of the list stay within the
+// work-group (a barrier apart; the slots' global overflow block is the brick's own). ----
 struct LatticeArgs {
   LinksArgs L;
   StreamArgs S;
 };
 
-template <class ST, int COLL>
-__global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(LatticeArgs P) {
+// pre, stream, sums of a brick (OVF: the brick has more links than the LDS slots)
+template <class ST, int COLL, bool OVF>
+__device__ __forceinline__ void lattice_rest(const LatticeArgs &P, int brick, LinksLDS &sh,
+                                             const LinkSlots<typename Store<ST>::CT> &S, int cnt, uint32_t bad) {
   using CT = typename Store<ST>::CT;
-  __shared__ LinksLDS sh;
-  const int brick = (blockIdx.x & 7) * P.L.per_xcd + (blockIdx.x >> 3);
-  if (brick >= P.L.nbricks) return;  // the whole work-group
-  links_body<ST>(P.L, brick, sh);
-  __syncthreads();  // the brick's link values written, the list free
+  lattice_pre<ST, OVF>(P.L, brick, sh, S, cnt);
+  __syncthreads();  // the corrections in their slots
   const StreamArgs &A = P.S;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lx = A.lx, ly = A.ly, lz = A.lz;
@@ -927,7 +1251,7 @@ __global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(Lattic
   CT pacc[NPIN];
 #pragma unroll
   for (int c = 0; c < NPIN; ++c) pacc[c] = 0;
-  uint32_t bad = 0, nfast = 0;
+  uint32_t nfast = 0;
   CT umax = 0;
   const int x = x0 + lane;
   const bool xin = x < lx;
@@ -935,11 +1259,47 @@ __global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(Lattic
 #pragma unroll 1
     for (int sl = 0; sl < nsl; ++sl) {
       const int loc = lane | (wv << 6) | (sl << 8);
-      stream_node<ST, COLL>(A, rin, rout, rgh, pb, x, opaque_uniform(y0 + wv), opaque_uniform(z0 + sl), xin,
-                            sh.srec[loc], sh.srow[wv + LBY * sl], pacc, bad, nfast, umax);
+      stream_node<ST, COLL, OVF ? 2 : 1>(A, rin, rout, rgh, pb, x, opaque_uniform(y0 + wv), opaque_uniform(z0 + sl),
+                                         xin, sh.srec[loc], sh.srow[wv + LBY * sl], pacc, bad, nfast, umax, S);
     }
   }
-  stream_tail<CT>(A, brick, reinterpret_cast<CT (*)[256]>(&sh.list[0]), pacc, bad, nfast, umax);
+  if (nfast) {  // rare: the health counters (count of fast node-steps, largest u^2 as bits)
+    atomicAdd((unsigned long long *)(A.flags + FL_HEALTH), (unsigned long long)nfast);
+    atomicMax(A.flags + FL_HEALTH + 2, __float_as_int((float)umax));
+  }
+  // the brick's partials of the fluid stress and mass: each wave's lanes by a fixed butterfly,
+  // then the four waves in order
+#pragma unroll
+  for (int c = 0; c < NPIN; ++c) {
+    const double v = wave_sum((double)pacc[c]);
+    if (lane == 0) sh.spw[wv][c] = v;
+  }
+  __syncthreads();  // the slots hold n*_qbar(X); the partials are in
+  if (threadIdx.x < NPIN) {
+    const int c = threadIdx.x;
+    A.pin[(size_t)brick * NPIN + c] = (sh.spw[0][c] + sh.spw[1][c]) + (sh.spw[2][c] + sh.spw[3][c]);
+  }
+  lattice_sums<ST, OVF>(P.L, brick, sh, S, cnt, bad);
+}
+
+template <class ST, int COLL>
+__global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(LatticeArgs P) {
+  using CT = typename Store<ST>::CT;
+  __shared__ LinksLDS sh;
+  __shared__ CT sval[VLDS + 64];  // the slots and the lanes' spare slots
+  const int brick = (blockIdx.x & 7) * P.L.per_xcd + (blockIdx.x >> 3);
+  if (brick >= P.L.nbricks) return;  // the whole work-group
+  if (threadIdx.x < 64) sval[VLDS + threadIdx.x] = (CT)0;
+  uint32_t bad = 0;
+  const int cnt = links_list<ST, true>(P.L, brick, sh, bad);  // (its barriers order the spares' zeros)
+  constexpr uint32_t es = sizeof(ST);
+  LinkSlots<CT> S;
+  S.lds = sval;
+  S.r = buf_rsrc(P.L.f, P.L.pop_bytes);
+  S.block = (P.L.vbase + (uint32_t)brick * BRICK_VALUES) * es;
+  S.ovf = __builtin_amdgcn_readfirstlane(sh.vcount) > VLDS;
+  if (S.ovf) lattice_rest<ST, COLL, true>(P, brick, sh, S, cnt, bad);
+  else lattice_rest<ST, COLL, false>(P, brick, sh, S, cnt, bad);
 }
 
 static uint32_t pop_bytes(const Sim *s) {  // the populations and the link values after them
@@ -1015,6 +1375,8 @@ hipError_t launch_links(Sim *s, const Box &b) {
   if (fused(s)) {
     LatticeArgs P;
     P.L = links_args(s, b);
+    P.L.lrec = nullptr;  // the stream phase takes the records from LDS
+    P.L.lrow = nullptr;
     P.S = stream_args(s);
     const dim3 grid(P.L.per_xcd * 8), blk(256);
     if (s->collision == 0) {

@@ -406,14 +406,10 @@ __device__ inline double lub_zeta(const Phys &P, double ai, double aj, double h)
   if (!(h < P.hc)) return 0.0;
   const double PI = 3.14159265358979323846;
   const double hh = h > 0.0 ? h : 0.0;
-  const double xg = 2.0 * (hh + P.delta) / (ai + aj);
-  double inv = 1.0 / xg;
-  if (P.lub_sub) {
-    const double xc = 2.0 * (P.hc + P.delta) / (ai + aj);
-    inv = inv - 1.0 / xc;
-  }
-  const double b = aj / ai, b1 = 1.0 + b;
-  return P.eta0 * (6.0 * PI * ai * (2.0 * b * b / (b1 * b1 * b1)) * inv);
+  const double sa = ai + aj, s = 1.0 / sa;
+  double inv = 0.5 * sa / (hh + P.delta);  // 1 / xi
+  if (P.lub_sub) inv -= 0.5 * sa / (P.hc + P.delta);
+  return P.eta0 * (12.0 * PI * (ai * ai) * (aj * aj) * (s * s * s) * inv);
 }
 
 __device__ inline void crs(double ax, double ay, double az, double bx, double by, double bz,
@@ -423,24 +419,26 @@ __device__ inline void crs(double ax, double ay, double az, double bx, double by
   cz_ = ax * by - ay * bx;
 }
 
-// Scalar resistance functions of App. A for the block of a sphere of radius a with partner
-// ratio b, at 1/xi (inv) and ln(1/xi) (lg).
+// Scalar resistance functions of App. A for the block of a sphere of radius a against a partner
+// of radius c (ratio b = c/a), at 1/xi (inv) and ln(1/xi) (lg).  With 1 + b = (a + c)/a the
+// leading-order forms are polynomials in a, c and s = 1/(a + c), e.g. 6 pi a 2 b^2/(1 + b)^3 =
+// 12 pi a^2 c^2 s^3: one division per pair for all of them.
 struct LubF {
   double XA, YA, YB, XG, YG, YC, YCp, YH, YHp;
 };
-__device__ inline LubF lubf(double a, double b, double inv, double lg) {
+__device__ inline LubF lubf(double a, double c, double s, double inv, double lg) {
   const double PI = 3.14159265358979323846;
-  const double b1 = 1.0 + b;
+  const double a2 = a * a, c2 = c * c, s2 = s * s, s3 = s2 * s;
   LubF f;
-  f.XA = 6.0 * PI * a * (2.0 * b * b / (b1 * b1 * b1)) * inv;
-  f.YA = 6.0 * PI * a * (4.0 * b * (2.0 + b + 2.0 * b * b) / (15.0 * b1 * b1 * b1)) * lg;
-  f.YB = 4.0 * PI * a * a * (b * (4.0 + b) / (5.0 * b1 * b1)) * lg;
-  f.XG = 4.0 * PI * a * a * (3.0 * b * b / (b1 * b1 * b1)) * inv;
-  f.YG = 4.0 * PI * a * a * (b * (4.0 - b + 7.0 * b * b) / (10.0 * b1 * b1 * b1)) * lg;
-  f.YC = 8.0 * PI * a * a * a * (2.0 * b / (5.0 * b1)) * lg;
-  f.YCp = 8.0 * PI * a * a * a * (b * b / (10.0 * b1)) * lg;
-  f.YH = 8.0 * PI * a * a * a * (b * (2.0 - b) / (10.0 * b1 * b1)) * lg;
-  f.YHp = 8.0 * PI * a * a * a * (b * b * (1.0 + 7.0 * b) / (20.0 * b1 * b1)) * lg;
+  f.XA = 12.0 * PI * a2 * c2 * s3 * inv;
+  f.YA = 1.6 * PI * a * c * (2.0 * a2 + a * c + 2.0 * c2) * s3 * lg;
+  f.YB = 0.8 * PI * a2 * c * (4.0 * a + c) * s2 * lg;
+  f.XG = 12.0 * PI * a2 * a * c2 * s3 * inv;
+  f.YG = 0.4 * PI * a2 * c * (4.0 * a2 - a * c + 7.0 * c2) * s3 * lg;
+  f.YC = 3.2 * PI * a2 * a * c * s * lg;
+  f.YCp = 0.8 * PI * a2 * c2 * s * lg;
+  f.YH = 0.8 * PI * a2 * a * c * (2.0 * a - c) * s2 * lg;
+  f.YHp = 0.4 * PI * a2 * c2 * (a + 7.0 * c) * s2 * lg;
   return f;
 }
 
@@ -471,7 +469,8 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
   const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
   const double r = sqrt(r2);
   const double h = r - ai - aj;
-  const double n[3] = {d[0] / r, d[1] / r, d[2] / r};
+  const double ir = 1.0 / r;
+  const double n[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
   const double Uij[3] = {Ui[0] - Uj[0], Ui[1] - Uj[1], Ui[2] - Uj[2]};
   double Fc[3] = {0, 0, 0};
   // ---- contact: normal spring-dashpot, tangential spring with Coulomb cap ----
@@ -519,21 +518,21 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
   if (h < P.cutoff) {
     const double hh = h > 0.0 ? h : 0.0;
     const double f = P.F0 * exp(-hh / P.lambda);
-    Fr[0] = f * d[0] / r; Fr[1] = f * d[1] / r; Fr[2] = f * d[2] / r;
+    Fr[0] = f * n[0]; Fr[1] = f * n[1]; Fr[2] = f * n[2];
   }
   // ---- lubrication correction (App. A grand-resistance matrix, leading order) ----
   double Fl[3] = {0, 0, 0};
   if (h < P.hc) {
     const double hh = h > 0.0 ? h : 0.0;
-    const double xg = 2.0 * (hh + P.delta) / (ai + aj);
-    double inv = 1.0 / xg, lg = log(1.0 / xg);
-    if (P.lub_sub) {
-      const double xc = 2.0 * (P.hc + P.delta) / (ai + aj);
-      inv = inv - 1.0 / xc;
-      lg = lg - log(1.0 / xc);
+    const double sa = ai + aj, s = 1.0 / sa;
+    double inv = 0.5 * sa / (hh + P.delta);  // 1 / xi, xi = 2 (h + delta)/(ai + aj)
+    double lg = log(inv);
+    if (P.lub_sub) {  // minus the same at the cut-off h_c
+      inv -= 0.5 * sa / (P.hc + P.delta);
+      lg = log((P.hc + P.delta) / (hh + P.delta));
     }
-    const LubF fi = lubf(ai, aj / ai, inv, lg);
-    const LubF fj = lubf(aj, ai / aj, inv, lg);
+    const LubF fi = lubf(ai, aj, s, inv, lg);
+    const LubF fj = lubf(aj, ai, s, inv, lg);
     const double un = Uij[0] * n[0] + Uij[1] * n[1] + Uij[2] * n[2];
     double wix, wiy, wiz, wjx, wjy, wjz, ux_, uy_, uz_;
     crs(Wi[0], Wi[1], Wi[2], n[0], n[1], n[2], wix, wiy, wiz);
