@@ -277,6 +277,7 @@ static size_t carve(Sim &s, char *base) {
   s.own = (int32_t *)take((size_t)s.nodes * 4);
   s.gown = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
   s.gval = take((size_t)2 * 5 * s.lx * s.lz * cs);
+  s.gcnt = (int32_t *)take((size_t)2 * s.lx * s.lz * 4);
   s.lrec = (uint32_t *)take((size_t)s.nodes * 4);
   s.lrow = (int32_t *)take((size_t)((s.lx + 63) / 64) * s.ly * s.lz * 4);
   for (int b = 0; b < 2; ++b) {
@@ -524,7 +525,7 @@ static int one_step(Sim &s) {
   s.hcur ^= 1;
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
   if (s.boundary == 1) HIPCHK(launch_walls(&s));
-  else HIPCHK(launch_ghosts(&s, b, s.gown, s.gval, 1, s.clk, 1));
+  else HIPCHK(launch_ghosts(&s, b, s.gown, s.gcnt, s.gval, 1, s.clk));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
@@ -1016,7 +1017,7 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     int32_t *lk = (int32_t *)s.f[1 - s.cur];
     int32_t *g = lk + ((size_t)s.nodes + 63) / 64 * 64;
     if (n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
-    HIPCHK(n && s.boundary == 0 ? launch_ghosts(&s, b, g, s.gval, 0, nullptr, 0)
+    HIPCHK(n && s.boundary == 0 ? launch_ghosts(&s, b, g, g + 2 * (size_t)s.lx * s.lz, s.gval, 0, nullptr)
                                 : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream));
     std::vector<int32_t> all((size_t)NQ * s.nodes, -1);
     for (int q = 1; q < NQ; ++q) {

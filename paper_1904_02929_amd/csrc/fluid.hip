@@ -1,13 +1,15 @@
 // fluid.hip -- lattice-Boltzmann kernels for gfx950.
 //
+//  k_lattice  links and stream of one 64 x 4 x 4 brick per work-group (the default with spheres)
 //  k_links    the step's links, (fluid node, sphere, directions) per brick in LDS, their
 //             moving bounce-back and the exchanged momentum summed per sphere (App. A eqs. 6-10)
 //  k_stream   pull-stream + collision + fluid stress partials (App. A eqs. 3-5), one thread
 //             per fluid node, x fastest
 //  k_hydro_final  per-sphere force, torque, stresslet from the fixed-point sums
-//  k_ghosts   Lees-Edwards ghost planes y=-1 and y=ly: geometric owner test of each ghost
-//             point, else linear interpolation of the Galilean-corrected post-collision
-//             row shifted by the offset (Wagner & Pagonabarraga).
+//  k_ghost_raster, k_ghost_values  Lees-Edwards ghost planes y=-1 and y=ly: the owner of each
+//             ghost point by the geometric test against the spheres' images, else linear
+//             interpolation of the Galilean-corrected post-collision row shifted by the offset
+//             (Wagner & Pagonabarraga).
 //  helpers    equilibrium fill, FP64 <-> storage conversion, link enumeration.
 #include "susp_impl.h"
 
@@ -38,7 +40,7 @@ template <class T> __device__ inline T wave_sum(T v) {
 //   k_links     the links of the step: for every fluid node and every sphere that some of its
 //               pull sources x - c_q belong to, one entry (node, sphere, those directions q),
 //               listed per brick in LDS (across the sliding plane the source is a ghost
-//               point, whose owner k_ghosts decided against the sphere images); per entry
+//               point, whose owner k_ghost_raster decided against the sphere images); per entry
 //               the bounce-back of eq. 7 on those links, written where the pull will read
 //               it, and the momentum each link exchanges (eq. 6) summed into the sphere's
 //               force, torque and stresslet (eqs. 9, 10).
@@ -1448,6 +1450,7 @@ struct GhostArgs {
   double rho0;
   int values;
   int32_t *gown;
+  int32_t *gcnt;  // spheres covering each ghost point
   void *gval;
   int32_t *flags;
   H16 h16;
@@ -1525,76 +1528,87 @@ __device__ inline void ghost_values(const GhostArgs &A, const Box &bx, int x, in
     gval[(size_t)((G * 5 + m) * A.lz + z) * A.lx + x] = ((CT)1 - (CT)fr) * v0[m] + (CT)fr * v1[m];
 }
 
-// One thread per ghost point (x, z) of the two ghost planes: owner (geometric test against
-// the spheres of the cells around the point, with their sliding images), then (fluid
-// points) the values.
-template <class ST>
-__global__ __launch_bounds__(256) void k_ghosts(GhostArgs A) {
-  using CT = typename Store<ST>::CT;
+// Ghost owners by footprint: a wave per sphere; each image of the sphere within reach of a
+// ghost plane visits the ghost points of its footprint there and applies the geometric test
+// (minimum image, squared distance below the mapped radius squared).  A covered point takes
+// the smallest id (the owners start at INT32_MAX; k_ghost_values marks uncovered points -1);
+// the count of spheres covering it finds overlaps.  Each point is visited at
+// most once per sphere: only through the image the minimum image picks, and the footprint
+// ranges are taken modulo the box without repeats.
+__device__ inline void ghost_range(double c, double r, int L, int &lo, int &cnt) {
+  int a = (int)ceil(c - r - 1e-6), b = (int)floor(c + r + 1e-6);
+  if (b - a + 1 >= L) { a = 0; b = L - 1; }
+  lo = a;
+  cnt = b - a + 1;
+}
+__global__ __launch_bounds__(256) void k_ghost_raster(GhostArgs A) {
   const Box bx = clock_box(A.b, A.clk, 0);
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int npl = A.lx * A.lz;
-  const bool live = idx < 2 * npl;
-  const int id = live ? idx : 2 * npl - 1;  // lanes past the end take the last point (no stores)
-  const int g = id / npl;
-  const int rem = id - g * npl;
-  const int z = rem / A.lx, x = rem - (rem / A.lx) * A.lx;
-  const double gy = g == 0 ? -1.0 : (double)A.ly;
-  // primary-box position of the ghost point, for the cell search only
-  double px = g == 0 ? (double)x + bx.s : (double)x - bx.s;
-  px = px - bx.Lx * floor(px / bx.Lx);
-  const double py = g == 0 ? (double)(A.ly - 1) : 0.0;
-  int owner = -1, clash = 0;
-  auto test = [&](int p, double Rx, double Ry, double Rz, double am) {
-    double dx, dy2, dz;
-    int k;
-    minimage(bx, (double)x - Rx, gy - Ry, (double)z - Rz, dx, dy2, dz, k);
-    const double r2 = dx * dx + dy2 * dy2 + dz * dz;
-    if (r2 < am * am) {
-      if (owner >= 0 && owner != p) clash = 1;
-      if (owner < 0 || p < owner) owner = p;
-    }
-  };
-  auto test_mem = [&](int p) { test(p, A.R[3 * p], A.R[3 * p + 1], A.R[3 * p + 2], A.amap[p]); };
-  if (A.n > 0) {  // the spheres of the cells around the point, with the sliding images
-    const Cells &C = A.C;
-    int ccy = (int)floor(py * C.iy);
-    ccy = ccy < 0 ? 0 : (ccy >= C.ny ? C.ny - 1 : ccy);
-    int ccz = (int)floor((double)z * C.iz);
-    ccz = ccz < 0 ? 0 : (ccz >= C.nz ? C.nz - 1 : ccz);
-    const int zn = C.nz >= 3 ? 3 : C.nz, xn = C.nx >= 3 ? 3 : C.nx;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int ny = ccy + dy;
-      double xs = px;
-      if (ny < 0) { ny += C.ny; xs = px + bx.s; }
-      else if (ny >= C.ny) { ny -= C.ny; xs = px - bx.s; }
-      xs = xs - bx.Lx * floor(xs / bx.Lx);
-      int ccx = (int)floor(xs * C.ix);
-      ccx = ccx < 0 ? 0 : (ccx >= C.nx ? C.nx - 1 : ccx);
-      for (int iz = 0; iz < zn; ++iz) {
-        int nz = C.nz >= 3 ? ccz + iz - 1 : iz;
-        nz = nz < 0 ? nz + C.nz : (nz >= C.nz ? nz - C.nz : nz);
-        for (int ix = 0; ix < xn; ++ix) {
-          int nx = C.nx >= 3 ? ccx + ix - 1 : ix;
-          nx = nx < 0 ? nx + C.nx : (nx >= C.nx ? nx - C.nx : nx);
-          const int c = nx + C.nx * (ny + C.ny * nz);
-          for (int t = A.cell_start[c]; t < A.cell_start[c + 1]; ++t) test_mem(A.cell_ids[t]);
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= A.n) return;  // the whole wave
+  const double Rx = A.R[3 * p], Ry = A.R[3 * p + 1], Rz = A.R[3 * p + 2], am = A.amap[p];
+  if (!(isfinite(Rx) && isfinite(Ry) && isfinite(Rz))) return;  // covers nothing (the step reports it)
+  const double am2 = am * am;
+#pragma unroll 1
+  for (int g = 0; g < 2; ++g) {
+    const double gy = g == 0 ? -1.0 : (double)A.ly;
+#pragma unroll 1
+    for (int k = -1; k <= 1; ++k) {
+      // the image at (Rx + k s, Ry + k Ly); a margin of one node keeps the rounding of the
+      // minimum image inside the footprint
+      if (!(fabs(gy - (Ry + k * bx.Ly)) < am + 1.0)) continue;
+      int xa, nx, za, nz;
+      ghost_range(Rx + k * bx.s, am + 1.0, A.lx, xa, nx);
+      ghost_range(Rz, am + 1.0, A.lz, za, nz);
+      const int tot = nx * nz;
+      for (int t = lane; t < tot; t += 64) {
+        const int iz = t / nx, ix = t - iz * nx;
+        int x = (xa + ix) % A.lx;
+        x = x < 0 ? x + A.lx : x;
+        int z = (za + iz) % A.lz;
+        z = z < 0 ? z + A.lz : z;
+        double dx, dy, dz;
+        int kk;
+        minimage(bx, (double)x - Rx, gy - Ry, (double)z - Rz, dx, dy, dz, kk);
+        if (kk != k) continue;
+        if (dx * dx + dy * dy + dz * dz < am2) {
+          const int pt = (g * A.lz + z) * A.lx + x;
+          atomicMin(&A.gown[pt], p);
+          atomicAdd(&A.gcnt[pt], 1);
         }
       }
     }
   }
-  if (!live) return;
-  if (clash) atomicOr(A.flags, 1);
-  A.gown[idx] = owner;
-  if (!A.values || owner >= 0) return;
+}
+
+// One thread per ghost point: -1 where no sphere covers it, an overlap where two do, and
+// (fluid points) the values.
+template <class ST>
+__global__ __launch_bounds__(256) void k_ghost_values(GhostArgs A) {
+  using CT = typename Store<ST>::CT;
+  const Box bx = clock_box(A.b, A.clk, 0);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npl = A.lx * A.lz;
+  if (idx >= 2 * npl) return;
+  const int cover = A.gcnt[idx];
+  if (cover == 0) A.gown[idx] = -1;
+  if (cover > 1) atomicOr(A.flags, 1);
+  if (!A.values || cover > 0) return;
+  const int g = idx / npl;
+  const int rem = idx - g * npl;
+  const int z = rem / A.lx, x = rem - z * A.lx;
   if (g == 0) ghost_values<0, ST, CT>(A, bx, x, z);
   else ghost_values<1, ST, CT>(A, bx, x, z);
 }
 
-hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,
-                         int lists) {
+__global__ __launch_bounds__(256) void k_ghost_clear(int32_t *gown, int32_t *gcnt, int npts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npts) { gown[i] = 0x7fffffff; gcnt[i] = 0; }
+}
+
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, int32_t *gcnt, void *gval_out, int values,
+                         const Clock *clk) {
   GhostArgs A;
-  (void)lists;
   A.fin = s->f[s->cur];
   A.plane = s->plane;
   A.own = s->own;
@@ -1609,14 +1623,17 @@ hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out
   A.rho0 = s->rho0;
   A.values = values;
   A.gown = gown_out;
+  A.gcnt = gcnt;
   A.gval = gval_out;
   A.flags = s->flags;
   A.h16 = s->h16;
   const int tot = 2 * s->lx * s->lz;
   dim3 grid((tot + 255) / 256), blk(256);
-  if (s->precision == 0) hipLaunchKernelGGL(k_ghosts<double>, grid, blk, 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_ghosts<float>, grid, blk, 0, s->stream, A);
-  else hipLaunchKernelGGL(k_ghosts<__half>, grid, blk, 0, s->stream, A);
+  hipLaunchKernelGGL(k_ghost_clear, grid, blk, 0, s->stream, gown_out, gcnt, tot);
+  if (s->n > 0) hipLaunchKernelGGL(k_ghost_raster, dim3((s->n + 3) / 4), blk, 0, s->stream, A);
+  if (s->precision == 0) hipLaunchKernelGGL(k_ghost_values<double>, grid, blk, 0, s->stream, A);
+  else if (s->precision == 1) hipLaunchKernelGGL(k_ghost_values<float>, grid, blk, 0, s->stream, A);
+  else hipLaunchKernelGGL(k_ghost_values<__half>, grid, blk, 0, s->stream, A);
   return hipGetLastError();
 }
 

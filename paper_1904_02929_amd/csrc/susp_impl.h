@@ -165,8 +165,8 @@ struct Sim;
 
 // ---- launchers (fluid.hip) ----
 hipError_t launch_init_populations(Sim *s);
-hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, void *gval_out, int values, const Clock *clk,
-                         int lists);
+hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, int32_t *gcnt, void *gval_out, int values,
+                         const Clock *clk);
 hipError_t launch_links(Sim *s, const Box &b);
 hipError_t launch_lbm(Sim *s, const Box &b);
 hipError_t launch_hydro_final(Sim *s);
@@ -229,6 +229,7 @@ struct Sim {
   uint32_t *lrec;  // [nodes] link record of every node (k_links), read by k_stream
   int32_t *lrow;   // [lx/64 rounded up * ly * lz] first link value of each 64-node row
   int32_t *gown;
+  int32_t *gcnt;  // [2][lz][lx] spheres covering each ghost point
   void *gval;
   // particles (FP64)
   double *R[2], *U[2], *W[2], *Q[2];
