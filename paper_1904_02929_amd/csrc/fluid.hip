@@ -307,13 +307,16 @@ __device__ __forceinline__ int links_list(const LinksArgs &A, int brick, LinksLD
     const bool live = x < lx && y < ly;
     const int xc = live ? x : 0, yc = opaque_uniform(live ? y : y0);
     const int xm = xc == 0 ? lx - 1 : xc - 1, xp = xc + 1 >= lx ? 0 : xc + 1;
+    // the lane's byte offsets in a row; the row's goes in the scalar offset (a lane past the
+    // box end loads a valid node, whose owner is not used)
+    const uint32_t xc4 = (uint32_t)xc * 4u, xm4 = (uint32_t)xm * 4u, xp4 = (uint32_t)xp * 4u;
     int32_t own0[LBZ], so[LBZ][NQ];
 #pragma unroll
     for (int sl = 0; sl < LBZ; ++sl) {
       const bool ok = live && sl < nsl;
-      const int z = ok ? z0 + sl : z0;
-      own0[sl] = ok ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rown, (uint32_t)(xc + lx * (yc + ly * z)) * 4u, 0, 0)
-                    : 0;
+      const int zo = opaque_uniform(z0 + (sl < nsl ? sl : 0));
+      const int32_t o0 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rown, xc4, (uint32_t)(lx * (yc + ly * zo)) * 4u, 0);
+      own0[sl] = ok ? o0 : 0;
       // the nine source rows (y - c_y, z - c_z), wave-uniform; a row next to a sliding plane
       // takes its ghost row there
       const int zu = opaque_uniform(z0 + (sl < nsl ? sl : 0));
@@ -334,9 +337,8 @@ __device__ __forceinline__ int links_list(const LinksArgs &A, int brick, LinksLD
       }
 #pragma unroll
       for (int q = 1; q < NQ; ++q) {
-        const int xs = cx(q) == 1 ? xm : (cx(q) == -1 ? xp : xc);
-        so[sl][q] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(
-            rown, ok ? (uint32_t)(rowb[cy(q) + 1][cz(q) + 1] + xs) * 4u : OOB, 0, 0);
+        const uint32_t xs4 = cx(q) == 1 ? xm4 : (cx(q) == -1 ? xp4 : xc4);
+        so[sl][q] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rown, xs4, (uint32_t)rowb[cy(q) + 1][cz(q) + 1] * 4u, 0);
       }
     }
 #pragma unroll
