@@ -75,12 +75,15 @@ __device__ inline void fx_add(unsigned long long *dst, double v) {
   atomicAdd(dst, h);
   atomicAdd(dst + 1, l);
 }
-// the same into a work-group's LDS table entry
-__device__ inline void fx_lds(unsigned long long *e, double v) {
+// the same into a work-group's LDS table entry (an LDS-typed pointer, so that the additions
+// are LDS atomics even where the code beside them adds into global memory)
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ inline lds_u64 *as_lds(unsigned long long *p) { return (lds_u64 *)p; }
+__device__ inline void fx_lds(lds_u64 *e, double v) {
   unsigned long long h, l;
   fx_split(v, h, l);
-  atomicAdd(e, h);
-  atomicAdd(e + 1, l);
+  __hip_atomic_fetch_add(e, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(e + 1, l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 
@@ -118,6 +121,9 @@ __device__ inline void acc_pair(double &acc, int pi, int sel, int c, double v) {
   if (c > 0) acc = first ? v : acc + v;
   else if (c < 0) acc = first ? -v : acc - v;
 }
+// 1/x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fmaT(double a, double b, double c) { return fma(a, b, c); }
 
@@ -517,8 +523,9 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
   auto add = [&](int key, uint32_t m, const double (&v)[HYD]) {
     if (key >= 0) {
 #pragma unroll
-      for (int c = 0; c < HYD - 1; ++c) fx_lds(&sacc[key][c][0], v[c]);
-      atomicAdd(&sacc[key][HYD - 1][0], (unsigned long long)__builtin_popcount(m) << FXH);  // an integer
+      for (int c = 0; c < HYD - 1; ++c) fx_lds(as_lds(&sacc[key][c][0]), v[c]);
+      __hip_atomic_fetch_add(as_lds(&sacc[key][HYD - 1][0]), (unsigned long long)__builtin_popcount(m) << FXH,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // an integer
     } else {
       unsigned long long *d = &A.hacc[(size_t)(-1 - key) * HYD * 2];
       for (int c = 0; c < HYD - 1; ++c) fx_add(d + 2 * c, v[c]);
@@ -748,8 +755,9 @@ __device__ inline double link_corr(const LinksArgs &A, const Box &bx, int p, int
 __device__ inline void table_add(const LinksArgs &A, LinksLDS &sh, int key, uint32_t m, const double (&v)[HYD]) {
   if (key >= 0) {
 #pragma unroll
-    for (int c = 0; c < HYD - 1; ++c) fx_lds(&sh.sacc[key][c][0], v[c]);
-    atomicAdd(&sh.sacc[key][HYD - 1][0], (unsigned long long)__builtin_popcount(m) << FXH);  // an integer
+    for (int c = 0; c < HYD - 1; ++c) fx_lds(as_lds(&sh.sacc[key][c][0]), v[c]);
+    __hip_atomic_fetch_add(as_lds(&sh.sacc[key][HYD - 1][0]), (unsigned long long)__builtin_popcount(m) << FXH,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // an integer
   } else {
     unsigned long long *d = &A.hacc[(size_t)(-1 - key) * HYD * 2];
     for (int c = 0; c < HYD - 1; ++c) fx_add(d + 2 * c, v[c]);
@@ -1076,7 +1084,7 @@ __device__ __forceinline__ void stream_node(const StreamArgs &A, __amdgpu_buffer
     addc(jx, cx(q), dq); addc(jy, cy(q), dq); addc(jz, cz(q), dq);
   }
   const CT rho = rho0 + rd;
-  const CT ir = (CT)1 / rho;
+  const CT ir = recip(rho);
   const CT ux = jx * ir, uy = jy * ir, uz = jz * ir;
   const CT uu = ux * ux + uy * uy + uz * uz;
   // a non-finite density or velocity: the fluid has failed.  Speeds above 0.3 c_s (u^2 >
