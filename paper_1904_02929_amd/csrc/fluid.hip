@@ -305,7 +305,6 @@ __device__ __forceinline__ int links_list(const LinksArgs &A, int brick, LinksLD
   const int lx = A.lx, ly = A.ly, lz = A.lz;
   const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
   const int nsl = min(LBZ, lz - z0);
-  constexpr uint32_t OOB = 0xfffffff0u;  // a buffer offset past every array: reads 0, writes nothing
   // ---- list ----
   {
     const __amdgpu_buffer_rsrc_t rown = buf_rsrc(A.own, A.ow_bytes);
@@ -804,18 +803,22 @@ __device__ __forceinline__ void lattice_pre(const LinksArgs &A, int brick, Links
       continue;
     }
     const uint32_t rec = sh.srec[loc];
-    const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+    uint32_t kn = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);  // the slot of the node's next link
 #pragma unroll
     for (int pi = 0; pi < 9; ++pi) {
       const int q = 2 * pi + 1, b = q + 1;
       const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
       const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
+      const uint32_t kq = kn;
+      kn += (rec >> q) & 1u;
+      const uint32_t kb = kn;
+      kn += (rec >> b) & 1u;
       if constexpr (OVF) {
-        if (lq) S.st(rec_slot(v0, rec, q), (CT)corr);
-        if (lb) S.st(rec_slot(v0, rec, b), (CT)(-corr));  // c_b = -c_q
+        if (lq) S.st(kq, (CT)corr);
+        if (lb) S.st(kb, (CT)(-corr));  // c_b = -c_q
       } else {
-        S.lds[lq ? rec_slot(v0, rec, q) : spare] = lq ? (CT)corr : (CT)0;
-        S.lds[lb ? rec_slot(v0, rec, b) : spare] = lb ? (CT)(-corr) : (CT)0;
+        S.lds[lq ? kq : spare] = lq ? (CT)corr : (CT)0;
+        S.lds[lb ? kb : spare] = lb ? (CT)(-corr) : (CT)0;
       }
     }
   }
@@ -844,7 +847,6 @@ template <class ST, bool OVF>
 __device__ __forceinline__ void lattice_sums(const LinksArgs &A, int brick, LinksLDS &sh,
                                              const LinkSlots<typename Store<ST>::CT> &S, int cnt, uint32_t bad) {
   const int t = threadIdx.x;
-  const uint32_t spare = VLDS + (t & 63);
   const int x0 = (brick % A.bxn) * LBX, y0 = ((brick / A.bxn) % A.byn) * LBY, z0 = (brick / (A.bxn * A.byn)) * LBZ;
   const Box bx = clock_box(A.b, A.clk, 0);
   // entry (j P) mod cnt for j = t, t + 256, ...: a permutation (P prime, not a divisor of cnt)
@@ -864,19 +866,26 @@ __device__ __forceinline__ void lattice_sums(const LinksArgs &A, int brick, Link
     entry_motion(A, sh, bx, key, x, y, z, Dx, Dy, Dz, ux, uy, uz);  // true: not marked
     const uint32_t rec = sh.srec[loc];
     const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
+    // the slot of the node's next link direction (a running count over the record's bits);
+    // a direction that is no link of the entry reads some slot within the array, unused
+    uint32_t kn = v0;
     double g0 = 0, g1 = 0, g2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
 #pragma unroll
     for (int pi = 0; pi < 9; ++pi) {
       const int q = 2 * pi + 1, b = q + 1;
       const double corr = (q <= 6 ? A.kax : A.kdg) * cdot<double>(q, ux, uy, uz);
       const bool lq = (m >> q) & 1u, lb = (m >> b) & 1u;
+      const uint32_t kq = kn;
+      kn += (rec >> q) & 1u;
+      const uint32_t kb = kn;
+      kn += (rec >> b) & 1u;
       double nq, nb;  // n*_qbar(X), n*_bbar(X)
       if constexpr (OVF) {
-        nq = lq ? (double)S.ld(rec_slot(v0, rec, q)) : 0.0;
-        nb = lb ? (double)S.ld(rec_slot(v0, rec, b)) : 0.0;
+        nq = lq ? (double)S.ld(kq) : 0.0;
+        nb = lb ? (double)S.ld(kb) : 0.0;
       } else {
-        nq = (double)S.lds[lq ? rec_slot(v0, rec, q) : spare];
-        nb = (double)S.lds[lb ? rec_slot(v0, rec, b) : spare];
+        nq = (double)S.lds[kq];
+        nb = (double)S.lds[kb];
       }
       const double mq = lq ? fma(2.0, nq, -corr) : 0.0;
       const double mb = lb ? fma(2.0, nb, corr) : 0.0;
@@ -1056,10 +1065,12 @@ __device__ __forceinline__ void stream_node(const StreamArgs &A, __amdgpu_buffer
   }
   if constexpr (FUSED == 1) {  // the corrections out of the slots, n*_qbar(X) in (one exchange)
     const uint32_t spare = VLDS + (threadIdx.x & 63);
+    uint32_t kn = v0;  // the slot of the node's next link direction
 #pragma unroll
     for (int q = 1; q < NQ; ++q) {
       const bool lk = (rec >> q) & 1u;
-      CT *const slot = S.lds + (lk ? rec_slot(v0, rec, q) : spare);
+      CT *const slot = S.lds + (lk ? kn : spare);
+      kn += lk ? 1u : 0u;
       n[q] -= __hip_atomic_exchange(slot, lk ? n[q] : (CT)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   } else if constexpr (FUSED == 2) {
