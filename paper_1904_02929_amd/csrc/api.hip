@@ -525,7 +525,7 @@ static int one_step(Sim &s) {
   s.hcur ^= 1;
   if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
   if (s.boundary == 1) HIPCHK(launch_walls(&s));
-  else HIPCHK(launch_ghosts(&s, b, s.gown, s.gcnt, s.gval, 1, s.clk));
+  else HIPCHK(launch_ghosts(&s, b, s.gown, s.gcnt, s.gval, 1, s.clk, 1));
   hipEvent_t *ev = nullptr;
   if (s.prof_on) {
     if (s.prof_used == s.prof_cap) {
@@ -543,7 +543,6 @@ static int one_step(Sim &s) {
   if (ev) HIPCHK(hipEventRecord(ev[1], s.stream));
   HIPCHK(launch_lbm(&s, b));
   if (ev) HIPCHK(hipEventRecord(ev[2], s.stream));
-  HIPCHK(launch_hydro_final(&s));
   s.cur ^= 1;
   if (s.n) {
     HIPCHK(launch_pairs(&s, b));
@@ -1017,7 +1016,7 @@ extern "C" int susp_get_lists(susp_sim *h, int32_t kind, void *host, size_t *byt
     int32_t *lk = (int32_t *)s.f[1 - s.cur];
     int32_t *g = lk + ((size_t)s.nodes + 63) / 64 * 64;
     if (n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
-    HIPCHK(n && s.boundary == 0 ? launch_ghosts(&s, b, g, g + 2 * (size_t)s.lx * s.lz, s.gval, 0, nullptr)
+    HIPCHK(n && s.boundary == 0 ? launch_ghosts(&s, b, g, g + 2 * (size_t)s.lx * s.lz, s.gval, 0, nullptr, 0)
                                 : launch_fill_i32(g, (size_t)2 * s.lx * s.lz, -1, s.stream));
     std::vector<int32_t> all((size_t)NQ * s.nodes, -1);
     for (int q = 1; q < NQ; ++q) {

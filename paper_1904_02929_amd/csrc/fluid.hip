@@ -5,7 +5,6 @@
 //             moving bounce-back and the exchanged momentum summed per sphere (App. A eqs. 6-10)
 //  k_stream   pull-stream + collision + fluid stress partials (App. A eqs. 3-5), one thread
 //             per fluid node, x fastest
-//  k_hydro_final  per-sphere force, torque, stresslet from the fixed-point sums
 //  k_ghost_raster, k_ghost_values  Lees-Edwards ghost planes y=-1 and y=ly: the owner of each
 //             ghost point by the geometric test against the spheres' images, else linear
 //             interpolation of the Galilean-corrected post-collision row shifted by the offset
@@ -61,7 +60,6 @@ constexpr int LMAXS = 6;    // spheres one node can link to
 // term needs |v| < 2^(31-FXH) (the link sums of one node and sphere are far below); a sphere
 // may take up to 2^15 additions per step before lo can overflow; the rounding of lo costs
 // 2^-69 per term.
-constexpr int FXH = 20, FXL = 68;
 __device__ inline void fx_split(double v, unsigned long long &h, unsigned long long &l) {
   constexpr double M = 6755399441055744.0;  // 1.5 2^52
   const double hv = rint(ldexp(v, FXH));
@@ -1439,24 +1437,6 @@ hipError_t launch_lbm(Sim *s, const Box &b) {
   return hipGetLastError();
 }
 
-// Per-sphere results of the step from the fixed-point sums (F, T, S, link count), which are
-// cleared for the next step.
-__global__ __launch_bounds__(256) void k_hydro_final(unsigned long long *hacc, double *hyd, int nv) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= nv) return;
-  const long long h = (long long)hacc[2 * i], l = (long long)hacc[2 * i + 1];
-  hyd[i] = ldexp((double)h, -FXH) + ldexp((double)l, -FXL);
-  hacc[2 * i] = 0ull;
-  hacc[2 * i + 1] = 0ull;
-}
-
-hipError_t launch_hydro_final(Sim *s) {
-  const int nv = s->n * HYD;
-  if (nv > 0)
-    hipLaunchKernelGGL(k_hydro_final, dim3((nv + 255) / 256), dim3(256), 0, s->stream, s->hacc, s->hyd[s->hcur], nv);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------------------
 struct GhostArgs {
   const void *fin;
@@ -1628,7 +1608,7 @@ __global__ __launch_bounds__(256) void k_ghost_clear(int32_t *gown, int32_t *gcn
 }
 
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, int32_t *gcnt, void *gval_out, int values,
-                         const Clock *clk) {
+                         const Clock *clk, int cleared) {
   GhostArgs A;
   A.fin = s->f[s->cur];
   A.plane = s->plane;
@@ -1650,7 +1630,7 @@ hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, int32_t *gcnt,
   A.h16 = s->h16;
   const int tot = 2 * s->lx * s->lz;
   dim3 grid((tot + 255) / 256), blk(256);
-  hipLaunchKernelGGL(k_ghost_clear, grid, blk, 0, s->stream, gown_out, gcnt, tot);
+  if (!cleared) hipLaunchKernelGGL(k_ghost_clear, grid, blk, 0, s->stream, gown_out, gcnt, tot);
   if (s->n > 0) hipLaunchKernelGGL(k_ghost_raster, dim3((s->n + 3) / 4), blk, 0, s->stream, A);
   if (s->precision == 0) hipLaunchKernelGGL(k_ghost_values<double>, grid, blk, 0, s->stream, A);
   else if (s->precision == 1) hipLaunchKernelGGL(k_ghost_values<float>, grid, blk, 0, s->stream, A);
@@ -1728,8 +1708,13 @@ hipError_t launch_walls(Sim *s) {
 // ---------------------------------------------------------------------------------------
 // Start of a step: the table entry of the step becomes the current clock (reset: rewind the
 // cursor after a new table upload).
-__global__ void k_clock(const ClockEntry *tab, Clock *clk, int reset) {
-  if (threadIdx.x != 0) return;
+// The clock of the step (thread 0), and the cleared ghost owner planes for k_ghost_raster
+// (gown: no owner yet, INT32_MAX; gcnt: no cover), so that the step needs no launch for them.
+__global__ __launch_bounds__(256) void k_clock(const ClockEntry *tab, Clock *clk, int reset, int32_t *gown,
+                                               int32_t *gcnt, int npts) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < npts) { gown[g] = 0x7fffffff; gcnt[g] = 0; }
+  if (g != 0) return;
   if (reset) {
     clk->idx = 0;
     return;
@@ -1740,7 +1725,10 @@ __global__ void k_clock(const ClockEntry *tab, Clock *clk, int reset) {
 }
 
 hipError_t launch_clock(Sim *s, int reset) {
-  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s->stream, s->clk_tab, s->clk, reset);
+  // the step's ghost planes are cleared here (Lees-Edwards steps)
+  const int npts = !reset && s->boundary == 0 ? 2 * s->lx * s->lz : 0;
+  hipLaunchKernelGGL(k_clock, dim3(npts > 0 ? (npts + 255) / 256 : 1), dim3(256), 0, s->stream, s->clk_tab, s->clk,
+                     reset, s->gown, s->gcnt, npts);
   return hipGetLastError();
 }
 

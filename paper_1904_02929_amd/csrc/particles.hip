@@ -1,16 +1,17 @@
 // particles.hip -- sphere-side kernels for gfx950 (all geometry and forces in FP64).
 //
-//  k_cells         cell list: cell of each sphere, counting sort, ascending ids per cell
+//  k_cells_lds_ids cell list: cell of each sphere, counting sort, ascending ids per cell
 //  k_pairs         Lees-Edwards cell search -> neighbour list (ascending ids, both
-//                  directions), contact-at-start flags, spring history carried over
+//                  directions), contact-at-start flags, spring history carried over; also
+//                  the step's per-sphere link sums into F, T, S (a wave per sphere)
 //  k_substep       one DEM substep per sphere: contact (spring-dashpot + Cundall-Strack with
 //                  Coulomb cap, Sec. 2), DLVO (eq. 13), lubrication (App. A), eq. (1)
-//  k_map_claim     new mapped-sphere footprints; fluid nodes covered by a sphere give it
+//  k_map_update<1> new mapped-sphere footprints; fluid nodes covered by a sphere give it
 //                  their mass and momentum
-//  k_map_release   old footprints; released nodes are refilled at equilibrium with the
+//  k_map_update<2> old footprints; released nodes are refilled at equilibrium with the
 //                  surface velocity, the sphere pays that momentum; impulses applied
-//  k_reduce1/2     deterministic two-stage stress reduction (eqs. 12, 14, 15) and the
-//                  G', G'' quadratures (eqs. 17-18)
+//  k_reduce        deterministic two-level stress reduction (eqs. 12, 14, 15) and the
+//                  G', G'' quadratures (eqs. 17-18), its last work-group doing the second level
 #include "susp_impl.h"
 
 namespace susp {
@@ -275,6 +276,8 @@ struct PairArgs {
   double *xi;                        // carried history for this step
   int32_t *on, *hstart;
   int32_t *flags;
+  unsigned long long *hacc;          // the step's fixed-point link sums [n][HYD][2] (cleared here)
+  double *hyd;                       // their values [n][HYD]
 };
 
 // Neighbour list of one sphere per wave, four spheres per work-group.  The lanes take the
@@ -288,6 +291,13 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs A) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + wv;
   const bool ok = i < A.n;  // waves past the last sphere still reach the barriers
+  if (ok && lane < HYD) {  // the sphere's force, torque, stresslet and link count of the step
+    const size_t k = (size_t)i * HYD + lane;
+    const long long h = (long long)A.hacc[2 * k], l = (long long)A.hacc[2 * k + 1];
+    A.hyd[k] = ldexp((double)h, -FXH) + ldexp((double)l, -FXL);
+    A.hacc[2 * k] = 0ull;
+    A.hacc[2 * k + 1] = 0ull;
+  }
   const Box bx = clock_box(A.b, A.clk, 0);
   const double *R = A.R;
   // the near cells: lane k takes the k-th cell visited (at most 27)
@@ -389,6 +399,8 @@ hipError_t launch_pairs(Sim *s, const Box &b) {
   A.xi = s->hxi[1 - s->hfin]; A.on = s->hon[1 - s->hfin];
   A.hstart = s->hstart;
   A.flags = s->flags;
+  A.hacc = s->hacc;
+  A.hyd = s->hyd[s->hcur];
   if (s->n > 0)
     hipLaunchKernelGGL(k_pairs, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, A);
   return hipGetLastError();
@@ -1006,24 +1018,6 @@ __device__ inline bool foot_node(const Box &bx, const double *R, int p, double r
   return true;
 }
 
-template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double *sh /*[NV][blockDim/64]*/) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int c = 0; c < NV; ++c) {
-    double x = v[c];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) sh[c * 16 + wv] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int c = 0; c < NV; ++c) {
-      double x = 0;
-      for (int w = 0; w < nw; ++w) x += sh[c * 16 + w];
-      v[c] = x;
-    }
-  __syncthreads();
-}
-
 // Full mapping of every sphere into an all-fluid map (creation and state loads).
 struct MapFullArgs {
   const double *R, *amap;
@@ -1299,91 +1293,138 @@ hipError_t launch_map_update(Sim *s, const Box &box, int phase) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Stress reduction.  Stage 1: block b sums a contiguous slice of the lattice-brick partials
-// and of the spheres into part[b][RED_W]; stage 2 (one block) adds the slices in order.
+// Stress reduction in one launch.  Block b sums a contiguous slice of the lattice-brick
+// partials and of the spheres into part[b][RED_W]; the block that finishes last (a counter in
+// the flags block, reset by that block) adds the slices in order and updates the accumulators.
 // part: pineq 6 | hydro stresslet 6 | pair 18 | ledger 1 | fluid mass deviation 1 | fluid nodes 1
 constexpr int RED_N = 33;
+struct ReduceArgs {
+  const double *pin, *hyd, *pst, *dp;
+  int nblk, n;
+  double *part, *acc;
+  // cf: fluid stress factor -(1 - 1/(2 tau)) / V; cfb the same with tau_bulk for the trace
+  // (multi-eigenvalue collision, split = 1)
+  double cf, cfb, invV, invns, rho0, mass_tol;
+  int split, has_particles;
+  const Clock *clk;
+  int32_t *flags;
+};
 
-__global__ __launch_bounds__(256) void k_reduce1(const double *pin, int nblk, const double *hyd,
-                                                 const double *pst, const double *dp, int n,
-                                                 double *part) {
-  double v[RED_N];
-  for (int c = 0; c < RED_N; ++c) v[c] = 0.0;
-  const int b = blockIdx.x;
-  const int pb0 = (int)((int64_t)nblk * b / RED_BLOCKS), pb1 = (int)((int64_t)nblk * (b + 1) / RED_BLOCKS);
-  for (int t = pb0 + threadIdx.x; t < pb1; t += blockDim.x) {
-    for (int c = 0; c < 6; ++c) v[c] += pin[(size_t)t * 8 + c];
-    v[31] += pin[(size_t)t * 8 + 6];
-    v[32] += pin[(size_t)t * 8 + 7];
-  }
-  const int s0 = (int)((int64_t)n * b / RED_BLOCKS), s1 = (int)((int64_t)n * (b + 1) / RED_BLOCKS);
-  for (int p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
-    for (int c = 0; c < 6; ++c) v[6 + c] += hyd[(size_t)p * HYD + 6 + c];
-    for (int c = 0; c < PST; ++c) v[12 + c] += pst[(size_t)p * PST + c];
-    v[30] += dp[(size_t)p * 8 + 6];
-  }
-  __shared__ double sh[RED_N * 16];
-  block_sum<RED_N>(v, sh);
-  if (threadIdx.x == 0)
-    for (int c = 0; c < RED_N; ++c) part[(size_t)b * RED_W + c] = v[c];
-}
-
-// cf: fluid stress factor -(1 - 1/(2 tau)) / V; cfb the same with tau_bulk for the trace
-// (multi-eigenvalue collision, split = 1).  The fluid mass plus the ledger is conserved by
-// the method (bounce-back links pair up along every lattice line, covered and released
-// nodes pass through the ledger); a drift above mass_tol from its value at the first step
-// reduced raises FL_MASS.
-__global__ void k_reduce2(const double *part, double *acc, double cf, double cfb, int split, double invV,
-                          double invns, const Clock *clk, int has_particles, double rho0, double mass_tol,
-                          int32_t *flags) {
-  __shared__ double v[RED_N];
-  const int c = threadIdx.x;
-  if (c < RED_N) {
+// The fluid mass plus the ledger is conserved by the method (bounce-back links pair up along
+// every lattice line, covered and released nodes pass through the ledger); a drift above
+// mass_tol from its value at the first step reduced raises FL_MASS.
+//
+// The slices in a fixed order: 7 groups of threads per component take every 7th slice, then
+// the groups in order; a thread per stress component updates the accumulators.
+constexpr int RED_G = 7;  // RED_G * RED_N <= 256
+__device__ void reduce_final(const ReduceArgs &A) {
+  __shared__ double gs[RED_G][RED_N];
+  __shared__ double v[RED_N], sig[30];
+  const int t = threadIdx.x;
+  if (t < RED_G * RED_N) {
+    const int g = t / RED_N, c = t - g * RED_N;
     double x = 0.0;
-    for (int b = 0; b < RED_BLOCKS; ++b) x += part[(size_t)b * RED_W + c];  // fixed order
-    v[c] = x;
+#pragma unroll 4
+    for (int b = g; b < RED_BLOCKS; b += RED_G) x += A.part[(size_t)b * RED_W + c];
+    gs[g][c] = x;
   }
   __syncthreads();
-  if (c != 0) return;
-  double sig[30];
-  const double t3 = (v[0] + v[1] + v[2]) / 3.0;
-  for (int k = 0; k < 6; ++k) {
-    sig[k] = (split && k < 3) ? cf * (v[k] - t3) + cfb * t3 : cf * v[k];
-    sig[6 + k] = has_particles ? v[6 + k] * invV : 0.0;
-    sig[12 + k] = v[12 + k] * invV * invns;  // lubrication
-    sig[18 + k] = v[18 + k] * invV * invns;  // contact
-    sig[24 + k] = v[24 + k] * invV * invns;  // DLVO
+  if (t < RED_N) {
+    double x = gs[0][t];
+    for (int g = 1; g < RED_G; ++g) x += gs[g][t];
+    v[t] = x;
   }
+  __syncthreads();
+  double *acc = A.acc;
+  if (t < 30) {  // fluid, hydrodynamic, lubrication, contact, DLVO: six components each
+    const int kk = t / 6, k = t - 6 * kk;
+    const double t3 = (v[0] + v[1] + v[2]) / 3.0;
+    double x;
+    if (kk == 0) x = (A.split && k < 3) ? A.cf * (v[k] - t3) + A.cfb * t3 : A.cf * v[k];
+    else if (kk == 1) x = A.has_particles ? v[6 + k] * A.invV : 0.0;
+    else x = v[6 * kk + k] * A.invV * A.invns;
+    sig[t] = x;
+    acc[t] = x;
+    acc[30 + t] += x;
+  }
+  __syncthreads();
+  if (t != 0) return;
   double sxy = 0;
   for (int k = 0; k < 5; ++k) sxy += sig[6 * k + 3];
-  for (int k = 0; k < 30; ++k) { acc[k] = sig[k]; acc[30 + k] += sig[k]; }
   acc[60] += 1.0;
-  const ClockEntry &ce = clk->cur;
+  const ClockEntry &ce = A.clk->cur;
   if (ce.gphase) { acc[61] += sxy * ce.gcos; acc[62] += sxy * ce.gsin; acc[63] += 1.0; }
   // the lattice kernel measured the fluid mass before this step's map update, so it pairs
   // with the ledger as it stood before this step's covers and releases
-  const double mass = v[31] + v[32] * rho0;
+  const double mass = v[31] + v[32] * A.rho0;
   acc[65] = mass;
   if (acc[67] == 0.0) {
     acc[66] = mass + acc[64];
     acc[67] = 1.0;
-  } else if (!(fabs(mass + acc[64] - acc[66]) <= mass_tol)) {
-    atomicOr(flags, FL_MASS);
+  } else if (!(fabs(mass + acc[64] - acc[66]) <= A.mass_tol)) {
+    atomicOr(A.flags, FL_MASS);
   }
   acc[68] = acc[64];  // the ledger that pairs with this step's fluid mass
   acc[64] += v[30];
 }
 
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs A) {
+  double v[RED_N];
+  for (int c = 0; c < RED_N; ++c) v[c] = 0.0;
+  const int b = blockIdx.x;
+  const int pb0 = (int)((int64_t)A.nblk * b / RED_BLOCKS), pb1 = (int)((int64_t)A.nblk * (b + 1) / RED_BLOCKS);
+  for (int t = pb0 + threadIdx.x; t < pb1; t += blockDim.x) {
+    for (int c = 0; c < 6; ++c) v[c] += A.pin[(size_t)t * 8 + c];
+    v[31] += A.pin[(size_t)t * 8 + 6];
+    v[32] += A.pin[(size_t)t * 8 + 7];
+  }
+  const int s0 = (int)((int64_t)A.n * b / RED_BLOCKS), s1 = (int)((int64_t)A.n * (b + 1) / RED_BLOCKS);
+  for (int p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
+    for (int c = 0; c < 6; ++c) v[6 + c] += A.hyd[(size_t)p * HYD + 6 + c];
+    for (int c = 0; c < PST; ++c) v[12 + c] += A.pst[(size_t)p * PST + c];
+    v[30] += A.dp[(size_t)p * 8 + 6];
+  }
+  // each wave's lanes by a fixed butterfly, then the four waves in order, a thread per component
+  __shared__ double sh[RED_N][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < RED_N; ++c) {
+    const double x = wsum(v[c]);
+    if (lane == 0) sh[c][wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < RED_N) {
+    const int c = threadIdx.x;
+    A.part[(size_t)b * RED_W + c] = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
+    __threadfence();  // the slice is visible before the count
+  }
+  __syncthreads();
+  __shared__ int last;
+  if (threadIdx.x == 0) last = atomicAdd(A.flags + FL_REDCNT, 1) == RED_BLOCKS - 1;
+  __syncthreads();
+  if (!last) return;  // the whole block
+  __threadfence();  // every slice visible to this block's loads
+  if (threadIdx.x == 0) A.flags[FL_REDCNT] = 0;  // for the next step's reduction
+  reduce_final(A);
+}
+
 hipError_t launch_stress(Sim *s) {
-  double *part = s->acc + ACC_PART;
-  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, s->stream, s->pin,
-                     s->nbricks, s->hyd[s->hcur], s->pst, s->dp, s->n, part);
+  ReduceArgs A;
+  A.pin = s->pin; A.hyd = s->hyd[s->hcur]; A.pst = s->pst; A.dp = s->dp;
+  A.nblk = s->nbricks; A.n = s->n;
+  A.part = s->acc + ACC_PART; A.acc = s->acc;
   const double V = (double)s->lx * s->ly * s->lz;
-  const double cf = -(1.0 - 0.5 / s->tau) / V;
-  const double cfb = -(1.0 - 0.5 / s->tau_bulk) / V;
-  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, s->stream, part, s->acc, cf, cfb, s->collision, 1.0 / V,
-                     1.0 / (double)s->n_sub, s->clk, s->n > 0 ? 1 : 0, s->rho0, MASS_TOL * V * s->rho0,
-                     s->flags);
+  A.cf = -(1.0 - 0.5 / s->tau) / V;
+  A.cfb = -(1.0 - 0.5 / s->tau_bulk) / V;
+  A.invV = 1.0 / V;
+  A.invns = 1.0 / (double)s->n_sub;
+  A.rho0 = s->rho0;
+  A.mass_tol = MASS_TOL * V * s->rho0;
+  A.split = s->collision;
+  A.has_particles = s->n > 0 ? 1 : 0;
+  A.clk = s->clk;
+  A.flags = s->flags;
+  hipLaunchKernelGGL(k_reduce, dim3(RED_BLOCKS), dim3(256), 0, s->stream, A);
   return hipGetLastError();
 }
 

@@ -23,6 +23,8 @@ namespace susp {
 constexpr int NQ = 19;
 constexpr int NCAP = 48;        // neighbour capacity per sphere
 constexpr int HYD = 13;         // F[3] T[3] S[6] nlinks  (per-sphere hydrodynamic sums)
+// scales of the two words of the per-sphere fixed-point link sums: hi 2^-FXH, lo 2^-FXL
+constexpr int FXH = 20, FXL = 68;
 constexpr int PST = 18;         // lubrication, contact, DLVO stress partials (6 each)
 // acc (FP64): [0,30) stress of the last step, [30,60) stress sums, 60 their count, 61 sum
 // sigma_xy cos, 62 sum sigma_xy sin, 63 observation steps, 64 mass ledger, 65 fluid mass of
@@ -42,6 +44,8 @@ constexpr int FL_OVERLAP = 1, FL_NONFINITE = 2, FL_NEIGHBOURS = 4, FL_LINKS = 8,
 // the flags block (64 int32) also holds, from word FL_HEALTH on, the health counters: fluid
 // node-steps above 0.3 c_s (uint64) and the largest u^2 seen (float bits)
 constexpr int FL_HEALTH = 32;
+// word of the flags block that counts the finished blocks of the stress reduction
+constexpr int FL_REDCNT = 48;
 // Link values: each population buffer ends in LINK_CAP elements per node of every 64 x 4 x 4
 // brick (of its storage type) that hold the step's bounce-back values, row by row; the record
 // of a node (lrec) holds its link directions (bits 1-18), solid (bit 19) and the offset of its
@@ -165,11 +169,11 @@ struct Sim;
 
 // ---- launchers (fluid.hip) ----
 hipError_t launch_init_populations(Sim *s);
+// cleared: the planes were cleared by the step's clock kernel
 hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, int32_t *gcnt, void *gval_out, int values,
-                         const Clock *clk);
+                         const Clock *clk, int cleared);
 hipError_t launch_links(Sim *s, const Box &b);
 hipError_t launch_lbm(Sim *s, const Box &b);
-hipError_t launch_hydro_final(Sim *s);
 hipError_t launch_pop_convert(Sim *s, double *dev64, int to_storage);
 hipError_t launch_pop_plane(Sim *s, double *dev64, int q, int to_storage);
 hipError_t launch_link_enum(Sim *s, const int32_t *gown, int32_t *out /*[nodes]*/, int q);
