@@ -325,8 +325,12 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs A) {
     bool hit = false;
     int j = -1;
     if (t < total) {
-      int k = 0;  // the cell holding candidate t: the last one starting at or before t
-      while (k + 1 < ncv && s_pre[wv][k + 1] <= t) ++k;
+      // the cell holding candidate t: the last one starting at or before t (a bisection over
+      // the ncv <= 27 starts, which ascend)
+      int k = 0;
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1)
+        if (k + step < ncv && s_pre[wv][k + step] <= t) k += step;
       j = A.cell_ids[s_cs[wv][k] + (t - s_pre[wv][k])];
       if (j != i) {
         const int lo = i < j ? i : j, hi = i < j ? j : i;
@@ -677,7 +681,7 @@ __device__ inline void record_contact(const SubArgs &A, size_t e, bool keep, con
 // IMP: the normal squeeze part of each pair's lubrication force is left out here and taken
 // at the new velocities by k_lub_sweep; this kernel then writes the right-hand side and the
 // explicit first guess, and k_lub_advance moves the spheres.
-constexpr int SUB_L = 8;  // lanes per sphere in k_substep
+constexpr int SUB_L = 4;  // lanes per sphere in k_substep
 template <bool REC, bool IMP>
 __global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
   const Box bx = clock_box(A.b, A.clk, 0);
