@@ -25,9 +25,6 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# the batched server runs one stream per job; give them their own hardware queues (read by
-# the HIP runtime when it starts, so set before torch is imported; 32 measured best of 8, 16, 32)
-os.environ["GPU_MAX_HW_QUEUES"] = "32"
 
 METRIC = "MLUPS & % HBM roofline; batched jobs/hr + p99 latency vs plain loop"
 HBM_PEAK_GBS = 8000.0
@@ -213,13 +210,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16-line", action="store_true",
                     help="skip the second run of the workload with FP16 storage")
-    ap.add_argument("--serve-jobs", type=int, default=24,
+    ap.add_argument("--serve-jobs", type=int, default=48,
                     help="requests in the serving comparison (0: skip it)")
     ap.add_argument("--serve-steps", type=int, default=1000, help="lattice steps per request")
+    ap.add_argument("--serve-mode", default="lockstep", choices=["lockstep", "streams"],
+                    help="batched server: lockstep runs with one launch per kernel over all jobs, "
+                         "or one stream per job")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "reference kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
+    if args.serve_mode == "streams":
+        # one stream per job: give them their own hardware queues (read by the HIP runtime when
+        # it starts, so set before torch is imported; 32 measured best of 8, 16, 32).  The
+        # lockstep server keeps the runtime's default: with 32 queues its launches took ~15x
+        # longer on the host and its runs twice as long.
+        os.environ["GPU_MAX_HW_QUEUES"] = "32"
     if args.gpus != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (the lattice would shard "
               "into z-slabs with halo planes exchanged over RCCL). Run with --gpus 1.",
@@ -277,7 +283,8 @@ def main():
         from paper_1904_02929_amd import serve
         log("serving %d requests of %d steps: plain loop, then the batched server"
             % (args.serve_jobs, args.serve_steps))
-        serving = serve.serve_benchmark(n_jobs=args.serve_jobs, steps=args.serve_steps, log=log)
+        serving = serve.serve_benchmark(n_jobs=args.serve_jobs, steps=args.serve_steps, log=log,
+                                        mode=args.serve_mode)
         serving["workload"] = ("mixed requests: half quasi-2D monolayers L x L x 10 (L 128-384, "
                                "area fraction 0.70-0.80, oscillatory), half 3D bulk L^3 "
                                "(L 64-128, phi 0.50-0.56, simple shear); Poisson arrivals at "

@@ -617,6 +617,46 @@ static int run_steps(Sim &s, int m) {
 
 namespace susp {
 
+// ---- multi-job batches (batch.hip) ----
+Sim &sim_of(susp_sim *h) { return h->s; }
+
+// Whether the simulation's step can run in multi-job launches: every kernel of its step has
+// a multi-job form (Lees-Edwards, spheres in the fused lattice kernel, explicit lubrication,
+// no contact statistics, no profiling events).
+bool multi_ok(const susp_sim *h) {
+  const Sim &s = h->s;
+  return s.boundary == 0 && s.n > 0 && s.BY == 4 && s.BZ == 4 && s.cbins == 0 && s.lub_implicit == 0 &&
+         !s.prof_on;
+}
+
+// Record the launches of the next two steps into c without issuing them; the simulation's
+// step counter and buffer parities are as before afterwards (they repeat every two steps).
+int record_two_steps(susp_sim *h, Collect *c) {
+  Sim &s = h->s;
+  const int64_t step = s.step;
+  const int par = parity(s);
+  c->clear();
+  s.col = c;
+  int rc = one_step(s);
+  if (!rc) rc = one_step(s);
+  s.col = nullptr;
+  s.step = step;
+  if (rc) return rc;
+  if (c->overflow) return fail(SUSP_ESTATE, "too many launches to record");
+  if (parity(s) != par) return fail(SUSP_ESTATE, "step parities do not repeat");
+  return SUSP_OK;
+}
+
+// Upload the protocol values of the next m <= CLK_CAP steps (waits for the simulation's
+// stream), and count the steps as taken.
+int prepare_run(susp_sim *h, int m) {
+  if (m < 0 || m > CLK_CAP) return fail(SUSP_EINVAL, "run length out of range");
+  int rc = upload_clock(h->s, m);
+  return rc;
+}
+void advance_steps(susp_sim *h, int m) { h->s.step += m; }
+int step_parity(const susp_sim *h) { return parity(h->s); }
+
 // Queue nsteps steps on the simulation's stream (clock uploads wait only for their own copy).
 int launch_steps(susp_sim *h, int64_t nsteps) {
   if (!h) return fail(SUSP_EINVAL, "NULL simulation");

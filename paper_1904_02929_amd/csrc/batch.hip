@@ -9,6 +9,7 @@
 #include <array>
 #include <iterator>
 #include <map>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -54,6 +55,15 @@ struct Arena {
   }
 };
 
+// One launch of a multi-job step: kernel, total work-groups, block size, and where its
+// argument table and work-group offsets sit in the batch's device tables.
+struct MultiLaunch {
+  const void *fn;
+  unsigned total, blk;
+  size_t tab, pre;
+  int nj;
+};
+
 struct susp_batch {
   int max_jobs = 0;
   size_t budget = 0, used = 0;
@@ -64,6 +74,16 @@ struct susp_batch {
   std::vector<size_t> bytes, offset;
   std::vector<hipEvent_t> done;   // recorded after a job's queued steps
   std::map<std::array<int, 5>, std::pair<int, int>> shape;  // tuned brick per lattice kind
+  // lockstep runs (susp_batch_launch_all): one stream, the launches of two steps of every
+  // group of jobs with the same kernel sequence, built from each job's recorded launches
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev = nullptr;                  // after the last lockstep run
+  std::vector<std::unique_ptr<Collect>> col;  // per slot
+  std::vector<MultiLaunch> seq;              // the groups' sequences, one after the other
+  std::vector<std::array<int64_t, 3>> key;   // slot, parity, handle the sequence was built for
+  std::vector<char> host;                    // staging of the tables
+  char *mt = nullptr;                        // device tables
+  size_t mt_cap = 0;
 };
 
 static std::array<int, 5> shape_key(const susp_params *p) {
@@ -134,12 +154,19 @@ extern "C" int susp_batch_create(int32_t max_jobs, size_t hbm_budget, int32_t au
   b->arena.free_[0] = hbm_budget / 256 * 256;
   b->stream.assign(max_jobs, nullptr);
   b->done.assign(max_jobs, nullptr);
+  b->col.resize(max_jobs);
   for (int i = 0; i < max_jobs; ++i) {
     if (hipStreamCreateWithFlags(&b->stream[i], hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess) {
       susp_batch_destroy(b);
       return set_error(SUSP_EDEVICE, "stream or event creation failed");
     }
+  }
+  if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->gev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(b->gev, b->gstream) != hipSuccess) {
+    susp_batch_destroy(b);
+    return set_error(SUSP_EDEVICE, "stream or event creation failed");
   }
   *out = b;
   return SUSP_OK;
@@ -174,6 +201,8 @@ extern "C" int susp_batch_add(susp_batch *b, const susp_params *p, int32_t *slot
     return rc;
   }
   b->job[k] = h;
+  b->key.clear();  // the lockstep sequence is rebuilt for the new set of jobs
+  b->seq.clear();
   b->bytes[k] = need;
   b->offset[k] = off;
   b->used += need;
@@ -183,8 +212,11 @@ extern "C" int susp_batch_add(susp_batch *b, const susp_params *p, int32_t *slot
 
 extern "C" int susp_batch_remove(susp_batch *b, int32_t slot) {
   if (!b || slot < 0 || slot >= b->max_jobs || !b->job[slot]) return set_error(SUSP_EINVAL, "no such job");
+  if (hipEventSynchronize(b->gev) != hipSuccess) return set_error(SUSP_EDEVICE, "event wait failed");
   susp_destroy(b->job[slot]);  // waits for the job's stream only; its block is the arena's
   b->job[slot] = nullptr;
+  b->key.clear();
+  b->seq.clear();
   b->arena.give(b->offset[slot], b->bytes[slot]);
   b->used -= b->bytes[slot];
   b->bytes[slot] = 0;
@@ -197,6 +229,7 @@ extern "C" int susp_batch_step(susp_batch *b, int64_t nsteps) {
   // queue every job first, then wait: the streams run side by side
   for (int k = 0; k < b->max_jobs; ++k) {
     if (!b->job[k]) continue;
+    if (hipStreamWaitEvent(b->stream[k], b->gev, 0) != hipSuccess) return set_error(SUSP_EDEVICE, "stream wait");
     int rc = launch_steps(b->job[k], nsteps);
     if (rc) return rc;
   }
@@ -213,6 +246,7 @@ extern "C" int susp_batch_step(susp_batch *b, int64_t nsteps) {
 
 extern "C" int susp_batch_launch(susp_batch *b, int32_t slot, int64_t nsteps) {
   if (!b || slot < 0 || slot >= b->max_jobs || !b->job[slot]) return set_error(SUSP_EINVAL, "no such job");
+  if (hipStreamWaitEvent(b->stream[slot], b->gev, 0) != hipSuccess) return set_error(SUSP_EDEVICE, "stream wait");
   int rc = launch_steps(b->job[slot], nsteps);
   if (rc) return rc;
   if (hipEventRecord(b->done[slot], b->stream[slot]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
@@ -233,6 +267,7 @@ extern "C" int susp_batch_poll(susp_batch *b, int32_t slot, int32_t *done) {
 
 extern "C" int susp_batch_stress(susp_batch *b, int32_t slot, double out[5][6], double gg[2]) {
   if (!b || slot < 0 || slot >= b->max_jobs || !b->job[slot]) return set_error(SUSP_EINVAL, "no such job");
+  if (hipEventSynchronize(b->gev) != hipSuccess) return set_error(SUSP_EDEVICE, "event wait failed");
   return susp_stress(b->job[slot], out, gg);
 }
 
@@ -245,13 +280,153 @@ extern "C" size_t susp_batch_bytes(const susp_batch *b) { return b ? b->used : 0
 
 extern "C" int susp_batch_destroy(susp_batch *b) {
   if (!b) return SUSP_OK;
+  if (b->gstream) (void)hipStreamSynchronize(b->gstream);
   for (int k = 0; k < b->max_jobs; ++k)
     if (b->job[k]) susp_destroy(b->job[k]);
   for (hipStream_t st : b->stream)
     if (st) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->done)
     if (ev) (void)hipEventDestroy(ev);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  if (b->gev) (void)hipEventDestroy(b->gev);
+  if (b->mt) (void)hipFree(b->mt);
   if (b->arena.base) (void)hipFree(b->arena.base);
   delete b;
+  return SUSP_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Lockstep runs: every job of the batch takes the same number of steps, and each kernel of a
+// step runs once for all jobs whose steps have the same kernel sequence (one multi-job launch
+// per kernel, its work-groups dealt to the jobs by the offsets table), instead of once per job.
+// The kernels are the ones a job runs alone, with its own arguments, so its results are the
+// same bit for bit.
+
+// (Re)build the multi-job launch sequence of two steps for the jobs now in the batch, if the
+// jobs or their buffer parities differ from the last build.  The lockstep stream is idle.
+static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
+  std::vector<std::array<int64_t, 3>> key;
+  for (int k : slots) key.push_back({k, step_parity(b->job[k]), (int64_t)(intptr_t)b->job[k]});
+  if (key == b->key && !b->seq.empty()) return SUSP_OK;
+  b->key.clear();
+  b->seq.clear();
+  // each job's launches of two steps, grouped by kernel sequence
+  std::map<std::vector<std::pair<const void *, unsigned>>, std::vector<int>> groups;
+  for (int k : slots) {
+    if (!b->col[k]) b->col[k].reset(new Collect);
+    Collect *c = b->col[k].get();
+    int rc = record_two_steps(b->job[k], c);
+    if (rc) return rc;
+    std::vector<std::pair<const void *, unsigned>> sig;
+    for (int r = 0; r < c->nrec; ++r) sig.push_back({c->rec[r].fn, c->rec[r].blk});
+    groups[sig].push_back(k);
+  }
+  std::vector<char> &h = b->host;
+  h.clear();
+  auto align = [&](size_t a) { h.resize((h.size() + a - 1) / a * a); };
+  for (auto &g : groups) {
+    const std::vector<int> &js = g.second;
+    const int nrec = (int)g.first.size();
+    for (int r = 0; r < nrec; ++r) {
+      MultiLaunch L;
+      L.fn = g.first[r].first;
+      L.blk = g.first[r].second;
+      L.nj = (int)js.size();
+      // the kernel indexes its table as an array of the argument struct: entries sizeof apart
+      const size_t sz = b->col[js[0]]->rec[r].sz;
+      const size_t stride = sz;
+      align(256);
+      L.tab = h.size();
+      h.resize(h.size() + stride * js.size());
+      int64_t tot = 0;
+      std::vector<int32_t> pre;
+      for (size_t u = 0; u < js.size(); ++u) {
+        const Collect::Rec &rr = b->col[js[u]]->rec[r];
+        if (rr.sz != sz) return set_error(SUSP_ESTATE, "argument sizes of one kernel differ");
+        memcpy(h.data() + L.tab + u * stride, b->col[js[u]]->bytes + rr.off, sz);
+        pre.push_back((int32_t)tot);
+        tot += rr.grid;
+      }
+      if (tot <= 0 || tot > 0x7fffffff) return set_error(SUSP_EINVAL, "work-groups of a lockstep launch out of range");
+      pre.push_back((int32_t)tot);
+      L.total = (unsigned)tot;
+      align(16);
+      L.pre = h.size();
+      h.resize(h.size() + pre.size() * sizeof(int32_t));
+      memcpy(h.data() + L.pre, pre.data(), pre.size() * sizeof(int32_t));
+      b->seq.push_back(L);
+    }
+  }
+  if (h.size() > b->mt_cap) {
+    if (b->mt) (void)hipFree(b->mt);
+    b->mt = nullptr;
+    b->mt_cap = 0;
+    const size_t cap = h.size() * 2 + 4096;
+    if (hipMalloc((void **)&b->mt, cap) != hipSuccess) {
+      b->mt = nullptr;
+      b->seq.clear();
+      return set_error(SUSP_ENOMEM, "lockstep launch tables could not be allocated");
+    }
+    b->mt_cap = cap;
+  }
+  if (hipMemcpy(b->mt, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    b->seq.clear();
+    return set_error(SUSP_EDEVICE, "upload of the lockstep launch tables failed");
+  }
+  b->key = key;
+  return SUSP_OK;
+}
+
+extern "C" int susp_batch_launch_all(susp_batch *b, int64_t nsteps) {
+  if (!b) return set_error(SUSP_EINVAL, "NULL batch");
+  if (nsteps < 0) return set_error(SUSP_EINVAL, "negative step count");
+  // the previous lockstep run owns the clocks and tables until it has finished
+  if (hipEventSynchronize(b->gev) != hipSuccess) return set_error(SUSP_EDEVICE, "event wait failed");
+  std::vector<int> slots;
+  for (int k = 0; k < b->max_jobs; ++k) {
+    if (!b->job[k]) continue;
+    if (multi_ok(b->job[k])) {
+      slots.push_back(k);
+      continue;
+    }
+    // a job whose kernels have no multi-job form steps on its own stream
+    int rc = launch_steps(b->job[k], nsteps);
+    if (rc) return rc;
+    if (hipEventRecord(b->done[k], b->stream[k]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+  }
+  if (slots.empty()) return SUSP_OK;
+  int64_t left = nsteps;
+  while (left >= 2) {
+    const int m = (int)(left < CLK_CAP ? left : CLK_CAP) & ~1;
+    for (int k : slots) {
+      int rc = prepare_run(b->job[k], m);  // waits for the job's own stream
+      if (rc) return rc;
+    }
+    int rc = build_sequence(b, slots);
+    if (rc) return rc;
+    for (int p = 0; p < m / 2; ++p) {
+      for (const MultiLaunch &L : b->seq) {
+        const void *tab = b->mt + L.tab;
+        const int32_t *pre = (const int32_t *)(b->mt + L.pre);
+        int nj = L.nj;
+        void *kp[] = {(void *)&tab, (void *)&pre, (void *)&nj};
+        if (hipLaunchKernel(L.fn, dim3(L.total), dim3(L.blk), kp, 0, b->gstream) != hipSuccess)
+          return set_error(SUSP_EDEVICE, "lockstep launch failed");
+      }
+    }
+    for (int k : slots) advance_steps(b->job[k], m);
+    left -= m;
+  }
+  if (hipEventRecord(b->gev, b->gstream) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+  for (int k : slots) {
+    if (left) {  // an odd last step: on the job's own stream, after the lockstep run
+      if (hipStreamWaitEvent(b->stream[k], b->gev, 0) != hipSuccess) return set_error(SUSP_EDEVICE, "stream wait");
+      int rc = launch_steps(b->job[k], left);
+      if (rc) return rc;
+      if (hipEventRecord(b->done[k], b->stream[k]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+    } else if (hipEventRecord(b->done[k], b->gstream) != hipSuccess) {
+      return set_error(SUSP_EDEVICE, "event record");
+    }
+  }
   return SUSP_OK;
 }

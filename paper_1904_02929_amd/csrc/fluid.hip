@@ -1303,12 +1303,14 @@ __device__ __forceinline__ void lattice_rest(const LatticeArgs &P, int brick, Li
   lattice_sums<ST, OVF>(P.L, brick, sh, S, cnt, bad);
 }
 
+// bid: the work-group's index among its simulation's (a multiple of 8 apart from blockIdx.x
+// in multi-job launches, so the XCD of a brick is the same as in a launch of its own)
 template <class ST, int COLL>
-__global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(LatticeArgs P) {
+__device__ __forceinline__ void lattice_wg(const LatticeArgs &P, const int bid) {
   using CT = typename Store<ST>::CT;
   __shared__ LinksLDS sh;
   __shared__ CT sval[VLDS + 64];  // the slots and the lanes' spare slots
-  const int brick = (blockIdx.x & 7) * P.L.per_xcd + (blockIdx.x >> 3);
+  const int brick = (bid & 7) * P.L.per_xcd + (bid >> 3);
   if (brick >= P.L.nbricks) return;  // the whole work-group
   if (threadIdx.x < 64) sval[VLDS + threadIdx.x] = (CT)0;
   uint32_t bad = 0;
@@ -1321,6 +1323,16 @@ __global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(Lattic
   S.ovf = __builtin_amdgcn_readfirstlane(sh.vcount) > VLDS;
   if (S.ovf) lattice_rest<ST, COLL, true>(P, brick, sh, S, cnt, bad);
   else lattice_rest<ST, COLL, false>(P, brick, sh, S, cnt, bad);
+}
+
+template <class ST, int COLL>
+__global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice(LatticeArgs P) {
+  lattice_wg<ST, COLL>(P, (int)blockIdx.x);
+}
+template <class ST, int COLL>
+__global__ __launch_bounds__(256, sizeof(ST) <= 4 ? 4 : 1) void k_lattice_m(const LatticeArgs *__restrict__ tab,
+                                                                        const int32_t *__restrict__ pre, int nj) {
+  SUSP_MULTI_BODY(LatticeArgs, (lattice_wg<ST, COLL>));
 }
 
 static uint32_t pop_bytes(const Sim *s) {  // the populations and the link values after them
@@ -1399,18 +1411,17 @@ hipError_t launch_links(Sim *s, const Box &b) {
     P.L.lrec = nullptr;  // the stream phase takes the records from LDS
     P.L.lrow = nullptr;
     P.S = stream_args(s);
-    const dim3 grid(P.L.per_xcd * 8), blk(256);
+    const unsigned grid = P.L.per_xcd * 8;
     if (s->collision == 0) {
-      if (s->precision == 0) hipLaunchKernelGGL((k_lattice<double, 0>), grid, blk, 0, s->stream, P);
-      else if (s->precision == 1) hipLaunchKernelGGL((k_lattice<float, 0>), grid, blk, 0, s->stream, P);
-      else hipLaunchKernelGGL((k_lattice<__half, 0>), grid, blk, 0, s->stream, P);
-    } else {
-      if (s->precision == 0) hipLaunchKernelGGL((k_lattice<double, 1>), grid, blk, 0, s->stream, P);
-      else if (s->precision == 1) hipLaunchKernelGGL((k_lattice<float, 1>), grid, blk, 0, s->stream, P);
-      else hipLaunchKernelGGL((k_lattice<__half, 1>), grid, blk, 0, s->stream, P);
+      if (s->precision == 0) return dispatch(s, k_lattice<double, 0>, k_lattice_m<double, 0>, grid, 256, P);
+      if (s->precision == 1) return dispatch(s, k_lattice<float, 0>, k_lattice_m<float, 0>, grid, 256, P);
+      return dispatch(s, k_lattice<__half, 0>, k_lattice_m<__half, 0>, grid, 256, P);
     }
-    return hipGetLastError();
+    if (s->precision == 0) return dispatch(s, k_lattice<double, 1>, k_lattice_m<double, 1>, grid, 256, P);
+    if (s->precision == 1) return dispatch(s, k_lattice<float, 1>, k_lattice_m<float, 1>, grid, 256, P);
+    return dispatch(s, k_lattice<__half, 1>, k_lattice_m<__half, 1>, grid, 256, P);
   }
+  SUSP_NO_COLLECT(s);
   const LinksArgs A = links_args(s, b);
   const dim3 grid(A.per_xcd * 8), blk(256);
   if (s->precision == 0) hipLaunchKernelGGL(k_links<double>, grid, blk, 0, s->stream, A);
@@ -1423,6 +1434,7 @@ hipError_t launch_links(Sim *s, const Box &b) {
 hipError_t launch_lbm(Sim *s, const Box &b) {
   (void)b;
   if (fused(s)) return hipSuccess;
+  SUSP_NO_COLLECT(s);
   const StreamArgs A = stream_args(s);
   dim3 grid(A.per_xcd * 8), blk(256);
   if (s->collision == 0) {
@@ -1542,9 +1554,9 @@ __device__ inline void ghost_range(double c, double r, int L, int &lo, int &cnt)
   lo = a;
   cnt = b - a + 1;
 }
-__global__ __launch_bounds__(256) void k_ghost_raster(GhostArgs A) {
+__device__ __forceinline__ void ghost_raster_wg(const GhostArgs &A, const int bid) {
   const Box bx = clock_box(A.b, A.clk, 0);
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int p = bid * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (p >= A.n) return;  // the whole wave
   const double Rx = A.R[3 * p], Ry = A.R[3 * p + 1], Rz = A.R[3 * p + 2], am = A.amap[p];
@@ -1581,14 +1593,19 @@ __global__ __launch_bounds__(256) void k_ghost_raster(GhostArgs A) {
     }
   }
 }
+__global__ __launch_bounds__(256) void k_ghost_raster(GhostArgs A) { ghost_raster_wg(A, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void k_ghost_raster_m(const GhostArgs *__restrict__ tab,
+                                                        const int32_t *__restrict__ pre, int nj) {
+  SUSP_MULTI_BODY(GhostArgs, ghost_raster_wg);
+}
 
 // One thread per ghost point: -1 where no sphere covers it, an overlap where two do, and
 // (fluid points) the values.
 template <class ST>
-__global__ __launch_bounds__(256) void k_ghost_values(GhostArgs A) {
+__device__ __forceinline__ void ghost_values_wg(const GhostArgs &A, const int bid) {
   using CT = typename Store<ST>::CT;
   const Box bx = clock_box(A.b, A.clk, 0);
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = bid * 256 + threadIdx.x;
   const int npl = A.lx * A.lz;
   if (idx >= 2 * npl) return;
   const int cover = A.gcnt[idx];
@@ -1600,6 +1617,13 @@ __global__ __launch_bounds__(256) void k_ghost_values(GhostArgs A) {
   const int z = rem / A.lx, x = rem - z * A.lx;
   if (g == 0) ghost_values<0, ST, CT>(A, bx, x, z);
   else ghost_values<1, ST, CT>(A, bx, x, z);
+}
+template <class ST>
+__global__ __launch_bounds__(256) void k_ghost_values(GhostArgs A) { ghost_values_wg<ST>(A, (int)blockIdx.x); }
+template <class ST>
+__global__ __launch_bounds__(256) void k_ghost_values_m(const GhostArgs *__restrict__ tab,
+                                                        const int32_t *__restrict__ pre, int nj) {
+  SUSP_MULTI_BODY(GhostArgs, ghost_values_wg<ST>);
 }
 
 __global__ __launch_bounds__(256) void k_ghost_clear(int32_t *gown, int32_t *gcnt, int npts) {
@@ -1629,13 +1653,17 @@ hipError_t launch_ghosts(Sim *s, const Box &b, int32_t *gown_out, int32_t *gcnt,
   A.flags = s->flags;
   A.h16 = s->h16;
   const int tot = 2 * s->lx * s->lz;
-  dim3 grid((tot + 255) / 256), blk(256);
-  if (!cleared) hipLaunchKernelGGL(k_ghost_clear, grid, blk, 0, s->stream, gown_out, gcnt, tot);
-  if (s->n > 0) hipLaunchKernelGGL(k_ghost_raster, dim3((s->n + 3) / 4), blk, 0, s->stream, A);
-  if (s->precision == 0) hipLaunchKernelGGL(k_ghost_values<double>, grid, blk, 0, s->stream, A);
-  else if (s->precision == 1) hipLaunchKernelGGL(k_ghost_values<float>, grid, blk, 0, s->stream, A);
-  else hipLaunchKernelGGL(k_ghost_values<__half>, grid, blk, 0, s->stream, A);
-  return hipGetLastError();
+  const unsigned grid = (tot + 255) / 256;
+  if (!cleared) {
+    SUSP_NO_COLLECT(s);
+    hipLaunchKernelGGL(k_ghost_clear, dim3(grid), dim3(256), 0, s->stream, gown_out, gcnt, tot);
+  }
+  hipError_t e = hipSuccess;
+  if (s->n > 0) e = dispatch(s, k_ghost_raster, k_ghost_raster_m, (s->n + 3) / 4, 256, A);
+  if (e != hipSuccess) return e;
+  if (s->precision == 0) return dispatch(s, k_ghost_values<double>, k_ghost_values_m<double>, grid, 256, A);
+  if (s->precision == 1) return dispatch(s, k_ghost_values<float>, k_ghost_values_m<float>, grid, 256, A);
+  return dispatch(s, k_ghost_values<__half>, k_ghost_values_m<__half>, grid, 256, A);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1691,6 +1719,7 @@ __global__ __launch_bounds__(256) void k_walls(const void *fin, size_t plane, co
 }
 
 hipError_t launch_walls(Sim *s) {
+  SUSP_NO_COLLECT(s);
   const int tot = 2 * s->lx * s->lz;
   dim3 grid((tot + 255) / 256), blk(256);
   if (s->precision == 0)
@@ -1710,26 +1739,41 @@ hipError_t launch_walls(Sim *s) {
 // cursor after a new table upload).
 // The clock of the step (thread 0), and the cleared ghost owner planes for k_ghost_raster
 // (gown: no owner yet, INT32_MAX; gcnt: no cover), so that the step needs no launch for them.
-__global__ __launch_bounds__(256) void k_clock(const ClockEntry *tab, Clock *clk, int reset, int32_t *gown,
-                                               int32_t *gcnt, int npts) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < npts) { gown[g] = 0x7fffffff; gcnt[g] = 0; }
+struct ClockArgs {
+  const ClockEntry *tab;
+  Clock *clk;
+  int reset;
+  int32_t *gown, *gcnt;
+  int npts;
+};
+__device__ __forceinline__ void clock_wg(const ClockArgs &A, const int bid) {
+  const int g = bid * 256 + threadIdx.x;
+  if (g < A.npts) { A.gown[g] = 0x7fffffff; A.gcnt[g] = 0; }
   if (g != 0) return;
-  if (reset) {
-    clk->idx = 0;
+  if (A.reset) {
+    A.clk->idx = 0;
     return;
   }
-  const int i = clk->idx;
-  clk->cur = tab[i < CLK_CAP ? i : CLK_CAP - 1];
-  clk->idx = i + 1;
+  const int i = A.clk->idx;
+  A.clk->cur = A.tab[i < CLK_CAP ? i : CLK_CAP - 1];
+  A.clk->idx = i + 1;
+}
+__global__ __launch_bounds__(256) void k_clock(ClockArgs A) { clock_wg(A, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void k_clock_m(const ClockArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                 int nj) {
+  SUSP_MULTI_BODY(ClockArgs, clock_wg);
 }
 
 hipError_t launch_clock(Sim *s, int reset) {
   // the step's ghost planes are cleared here (Lees-Edwards steps)
-  const int npts = !reset && s->boundary == 0 ? 2 * s->lx * s->lz : 0;
-  hipLaunchKernelGGL(k_clock, dim3(npts > 0 ? (npts + 255) / 256 : 1), dim3(256), 0, s->stream, s->clk_tab, s->clk,
-                     reset, s->gown, s->gcnt, npts);
-  return hipGetLastError();
+  ClockArgs A;
+  A.tab = s->clk_tab;
+  A.clk = s->clk;
+  A.reset = reset;
+  A.gown = s->gown;
+  A.gcnt = s->gcnt;
+  A.npts = !reset && s->boundary == 0 ? 2 * s->lx * s->lz : 0;
+  return dispatch(s, k_clock, k_clock_m, A.npts > 0 ? (A.npts + 255) / 256 : 1, 256, A);
 }
 
 // ---------------------------------------------------------------------------------------

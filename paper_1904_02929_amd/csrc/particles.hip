@@ -46,9 +46,25 @@ __device__ inline int cell_of(const Cells &C, double x, double y, double z) {
   return a + C.nx * (b + C.ny * c);
 }
 
+// Arguments of the cell-list kernels (cnt: global counters of k_cells).
+struct CellArgs {
+  const double *R;
+  int n;
+  Cells C;
+  int ncell;
+  int32_t *start, *ids, *cnt;
+};
+#define SUSP_CELL_ARGS                                                                      \
+  const double *R = A.R;                                                                    \
+  const int n = A.n;                                                                        \
+  const Cells C = A.C;                                                                      \
+  const int ncell = A.ncell;                                                                \
+  int32_t *start = A.start, *ids = A.ids;
+
 // One work-group builds the whole cell list (counting sort, then ids sorted inside cells).
-__global__ __launch_bounds__(1024) void k_cells(const double *R, int n, Cells C, int ncell,
-                                                int32_t *start, int32_t *ids, int32_t *cnt) {
+__device__ __forceinline__ void cells_wg(const CellArgs &A, int) {
+  SUSP_CELL_ARGS
+  int32_t *cnt = A.cnt;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int c = t; c < ncell; c += nt) cnt[c] = 0;
   __syncthreads();
@@ -100,8 +116,8 @@ __global__ __launch_bounds__(1024) void k_cells(const double *R, int n, Cells C,
 // Same construction with the counters, the scan and the fill cursors in LDS (used when
 // the cell grid fits: ncell <= LDS_CELLS).
 constexpr int LDS_CELLS = 12288;
-__global__ __launch_bounds__(1024) void k_cells_lds(const double *R, int n, Cells C, int ncell,
-                                                    int32_t *start, int32_t *ids) {
+__device__ __forceinline__ void cells_lds_wg(const CellArgs &A, int) {
+  SUSP_CELL_ARGS
   __shared__ int32_t cnt[LDS_CELLS];
   __shared__ int32_t part[1024];
   const int t = threadIdx.x, nt = blockDim.x;
@@ -150,8 +166,8 @@ __global__ __launch_bounds__(1024) void k_cells_lds(const double *R, int n, Cell
 // of its (at most 16) spheres in registers, so positions are read once, and the fill and the
 // sort inside each cell work in LDS; the ids are written out once at the end.
 constexpr int LDS_IDS = 16 * 1024;
-__global__ __launch_bounds__(1024) void k_cells_lds_ids(const double *R, int n, Cells C, int ncell,
-                                                        int32_t *start, int32_t *ids) {
+__device__ __forceinline__ void cells_lds_ids_wg(const CellArgs &A, int) {
+  SUSP_CELL_ARGS
   __shared__ int32_t cnt[LDS_CELLS];
   __shared__ int32_t part[1024];
   __shared__ int32_t sid[LDS_IDS];
@@ -209,17 +225,34 @@ __global__ __launch_bounds__(1024) void k_cells_lds_ids(const double *R, int n, 
   for (int i = t; i < n; i += nt) ids[i] = sid[i];
 }
 
+__global__ __launch_bounds__(1024) void k_cells(CellArgs A) { cells_wg(A, 0); }
+__global__ __launch_bounds__(1024) void k_cells_m(const CellArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                  int nj) {
+  SUSP_MULTI_BODY(CellArgs, cells_wg);
+}
+__global__ __launch_bounds__(1024) void k_cells_lds(CellArgs A) { cells_lds_wg(A, 0); }
+__global__ __launch_bounds__(1024) void k_cells_lds_m(const CellArgs *__restrict__ tab,
+                                                      const int32_t *__restrict__ pre, int nj) {
+  SUSP_MULTI_BODY(CellArgs, cells_lds_wg);
+}
+__global__ __launch_bounds__(1024) void k_cells_lds_ids(CellArgs A) { cells_lds_ids_wg(A, 0); }
+__global__ __launch_bounds__(1024) void k_cells_lds_ids_m(const CellArgs *__restrict__ tab,
+                                                          const int32_t *__restrict__ pre, int nj) {
+  SUSP_MULTI_BODY(CellArgs, cells_lds_ids_wg);
+}
+
 hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t *scratch) {
-  if (s->ncell <= LDS_CELLS && s->n <= LDS_IDS)
-    hipLaunchKernelGGL(k_cells_lds_ids, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n,
-                       s->cells, s->ncell, cell_start, cell_ids);
-  else if (s->ncell <= LDS_CELLS)
-    hipLaunchKernelGGL(k_cells_lds, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n,
-                       s->cells, s->ncell, cell_start, cell_ids);
-  else
-    hipLaunchKernelGGL(k_cells, dim3(1), dim3(1024), 0, s->stream, s->R[s->pcur], s->n, s->cells,
-                       s->ncell, cell_start, cell_ids, scratch);
-  return hipGetLastError();
+  CellArgs A;
+  A.R = s->R[s->pcur];
+  A.n = s->n;
+  A.C = s->cells;
+  A.ncell = s->ncell;
+  A.start = cell_start;
+  A.ids = cell_ids;
+  A.cnt = scratch;
+  if (s->ncell <= LDS_CELLS && s->n <= LDS_IDS) return dispatch(s, k_cells_lds_ids, k_cells_lds_ids_m, 1, 1024, A);
+  if (s->ncell <= LDS_CELLS) return dispatch(s, k_cells_lds, k_cells_lds_m, 1, 1024, A);
+  return dispatch(s, k_cells, k_cells_m, 1, 1024, A);
 }
 
 // Visit the distinct cells that can hold spheres within one cell width of (px,py,pz).
@@ -286,10 +319,10 @@ struct PairArgs {
 // raise flag 4), and each kept partner goes to its rank among them, so the list ascends in
 // partner id.  A pair that stays listed carries its spring history over from the previous
 // list, where the lower id holds it.
-__global__ __launch_bounds__(256) void k_pairs(PairArgs A) {
+__device__ __forceinline__ void pairs_wg(const PairArgs &A, const int bid) {
   __shared__ int32_t s_cs[4][32], s_pre[4][32], s_js[4][NCAP], s_srt[4][NCAP], s_old[4][NCAP];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wv;
+  const int i = bid * 4 + wv;
   const bool ok = i < A.n;  // waves past the last sphere still reach the barriers
   if (ok && lane < HYD) {  // the sphere's force, torque, stresslet and link count of the step
     const size_t k = (size_t)i * HYD + lane;
@@ -391,6 +424,12 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs A) {
   A.hstart[e] = (sqrt(r2) - A.a[i] - A.a[j]) < 0.0 ? 1 : 0;
 }
 
+__global__ __launch_bounds__(256) void k_pairs(PairArgs A) { pairs_wg(A, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void k_pairs_m(const PairArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                 int nj) {
+  SUSP_MULTI_BODY(PairArgs, pairs_wg);
+}
+
 hipError_t launch_pairs(Sim *s, const Box &b) {
   PairArgs A;
   A.R = s->R[s->pcur]; A.a = s->a; A.amap = s->amap;
@@ -405,9 +444,8 @@ hipError_t launch_pairs(Sim *s, const Box &b) {
   A.flags = s->flags;
   A.hacc = s->hacc;
   A.hyd = s->hyd[s->hcur];
-  if (s->n > 0)
-    hipLaunchKernelGGL(k_pairs, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, A);
-  return hipGetLastError();
+  if (s->n > 0) return dispatch(s, k_pairs, k_pairs_m, (s->n + 3) / 4, 256, A);
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -587,9 +625,16 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
 // Entry of each neighbour-list slot that holds the pair's spring history (the slot of the
 // lower id); one wave per sphere, lanes over its neighbour slots; the lower id's list
 // ascends, so its slot is found by bisection.
-__global__ __launch_bounds__(256) void k_pair_rev(const int32_t *cnt, const int32_t *nj, int32_t *rev,
-                                                  int n) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+struct RevArgs {
+  const int32_t *cnt, *nj;
+  int32_t *rev;
+  int n;
+};
+__device__ __forceinline__ void pair_rev_wg(const RevArgs &A, const int bid) {
+  const int32_t *cnt = A.cnt, *nj = A.nj;
+  int32_t *rev = A.rev;
+  const int n = A.n;
+  const int i = bid * 4 + (threadIdx.x >> 6);
   const int u = threadIdx.x & 63;
   if (i >= n || u >= NCAP) return;
   if (u >= cnt[i]) return;
@@ -609,11 +654,20 @@ __global__ __launch_bounds__(256) void k_pair_rev(const int32_t *cnt, const int3
   rev[e] = r;
 }
 
+__global__ __launch_bounds__(256) void k_pair_rev(RevArgs A) { pair_rev_wg(A, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void k_pair_rev_m(const RevArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                    int nj) {
+  SUSP_MULTI_BODY(RevArgs, pair_rev_wg);
+}
+
 hipError_t launch_pair_rev(Sim *s) {
-  if (s->n > 0)
-    hipLaunchKernelGGL(k_pair_rev, dim3((s->n + 3) / 4), dim3(256), 0, s->stream, s->ncnt[s->lcur],
-                       s->nj[s->lcur], s->rev, s->n);
-  return hipGetLastError();
+  RevArgs A;
+  A.cnt = s->ncnt[s->lcur];
+  A.nj = s->nj[s->lcur];
+  A.rev = s->rev;
+  A.n = s->n;
+  if (s->n > 0) return dispatch(s, k_pair_rev, k_pair_rev_m, (s->n + 3) / 4, 256, A);
+  return hipSuccess;
 }
 
 struct SubArgs {
@@ -683,11 +737,11 @@ __device__ inline void record_contact(const SubArgs &A, size_t e, bool keep, con
 // explicit first guess, and k_lub_advance moves the spheres.
 constexpr int SUB_L = 4;  // lanes per sphere in k_substep
 template <bool REC, bool IMP>
-__global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) {
+__device__ __forceinline__ void substep_wg(const SubArgs &A, const int bid) {
   const Box bx = clock_box(A.b, A.clk, 0);
   const double s1 = A.clk->cur.s1, ule1 = A.clk->cur.ule1;
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (256 / SUB_L) + threadIdx.x / SUB_L;
+  const int i = bid * (256 / SUB_L) + threadIdx.x / SUB_L;
   const int l = lane % SUB_L;
   const bool ok = i < A.n;
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0}, Fq[3] = {0, 0, 0}, st[PST];
@@ -916,6 +970,13 @@ __global__ __launch_bounds__(256) void k_lub_advance(SubArgs A, const double *Uf
     if (!ok) atomicOr(A.flags, 2);
   }
 }
+template <bool REC, bool IMP>
+__global__ __launch_bounds__(256, 2) void k_substep(SubArgs A) { substep_wg<REC, IMP>(A, (int)blockIdx.x); }
+template <bool REC, bool IMP>
+__global__ __launch_bounds__(256, 2) void k_substep_m(const SubArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                      int nj) {
+  SUSP_MULTI_BODY(SubArgs, (substep_wg<REC, IMP>));
+}
 
 hipError_t launch_substep(Sim *s, const Box &b, int sub) {
   SubArgs A;
@@ -949,9 +1010,10 @@ hipError_t launch_substep(Sim *s, const Box &b, int sub) {
     const dim3 gs((s->n + per - 1) / per), g((s->n + 15) / 16), blk(256);
     const bool rec = A.crec && A.last;
     if (s->lub_implicit == 0) {
-      if (rec) hipLaunchKernelGGL((k_substep<true, false>), gs, blk, 0, s->stream, A);
-      else hipLaunchKernelGGL((k_substep<false, false>), gs, blk, 0, s->stream, A);
+      if (rec) return dispatch(s, k_substep<true, false>, k_substep_m<true, false>, gs.x, 256, A);
+      return dispatch(s, k_substep<false, false>, k_substep_m<false, false>, gs.x, 256, A);
     } else {
+      SUSP_NO_COLLECT(s);
       if (rec) hipLaunchKernelGGL((k_substep<true, true>), gs, blk, 0, s->stream, A);
       else hipLaunchKernelGGL((k_substep<false, true>), gs, blk, 0, s->stream, A);
       // Jacobi sweeps between the new velocity buffer and the scratch buffer
@@ -1092,10 +1154,10 @@ __device__ inline bool inside_new(const MapArgs &A, const Box &bnew, int v, doub
 }
 
 template <class ST, int PHASE>
-__global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
+__device__ __forceinline__ void map_update_wg(const MapArgs &A, const int bid) {
   using CT = typename Store<ST>::CT;
   const Box bnew = clock_box(A.b, A.clk, 1), bold = clock_box(A.b, A.clk, 0);
-  const int p = blockIdx.x;
+  const int p = bid;
   const int lane = threadIdx.x;
   const double *Rn = &A.R[3 * p], *Ro = &A.R0[3 * p];
   if (!(isfinite(Rn[0]) && isfinite(Rn[1]) && isfinite(Rn[2]) && isfinite(Ro[0]) &&
@@ -1270,6 +1332,14 @@ __global__ __launch_bounds__(64) void k_map_update(MapArgs A) {
   for (int c = 0; c < 3; ++c) { A.Uw[3 * p + c] = U[c]; A.Ww[3 * p + c] = W[c]; }
 }
 
+template <class ST, int PHASE>
+__global__ __launch_bounds__(64) void k_map_update(MapArgs A) { map_update_wg<ST, PHASE>(A, (int)blockIdx.x); }
+template <class ST, int PHASE>
+__global__ __launch_bounds__(64) void k_map_update_m(const MapArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                     int nj) {
+  SUSP_MULTI_BODY(MapArgs, (map_update_wg<ST, PHASE>));
+}
+
 hipError_t launch_map_update(Sim *s, const Box &box, int phase) {
   MapArgs A;
   A.R = s->R[s->pcur]; A.U = s->U[s->pcur]; A.W = s->W[s->pcur];
@@ -1283,17 +1353,15 @@ hipError_t launch_map_update(Sim *s, const Box &box, int phase) {
   A.h16 = s->h16;
   A.wmem = s->boundary == 1 ? s->wmem : nullptr;
   if (s->n == 0) return hipSuccess;
-  dim3 g(s->n), b(64);
+  const unsigned g = s->n;
   if (phase == 1) {
-    if (s->precision == 0) hipLaunchKernelGGL((k_map_update<double, 1>), g, b, 0, s->stream, A);
-    else if (s->precision == 1) hipLaunchKernelGGL((k_map_update<float, 1>), g, b, 0, s->stream, A);
-    else hipLaunchKernelGGL((k_map_update<__half, 1>), g, b, 0, s->stream, A);
-  } else {
-    if (s->precision == 0) hipLaunchKernelGGL((k_map_update<double, 2>), g, b, 0, s->stream, A);
-    else if (s->precision == 1) hipLaunchKernelGGL((k_map_update<float, 2>), g, b, 0, s->stream, A);
-    else hipLaunchKernelGGL((k_map_update<__half, 2>), g, b, 0, s->stream, A);
+    if (s->precision == 0) return dispatch(s, k_map_update<double, 1>, k_map_update_m<double, 1>, g, 64, A);
+    if (s->precision == 1) return dispatch(s, k_map_update<float, 1>, k_map_update_m<float, 1>, g, 64, A);
+    return dispatch(s, k_map_update<__half, 1>, k_map_update_m<__half, 1>, g, 64, A);
   }
-  return hipGetLastError();
+  if (s->precision == 0) return dispatch(s, k_map_update<double, 2>, k_map_update_m<double, 2>, g, 64, A);
+  if (s->precision == 1) return dispatch(s, k_map_update<float, 2>, k_map_update_m<float, 2>, g, 64, A);
+  return dispatch(s, k_map_update<__half, 2>, k_map_update_m<__half, 2>, g, 64, A);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1312,6 +1380,7 @@ struct ReduceArgs {
   int split, has_particles;
   const Clock *clk;
   int32_t *flags;
+  int nred;  // work-groups of the reduction (<= RED_BLOCKS; one slice each)
 };
 
 // The fluid mass plus the ledger is conserved by the method (bounce-back links pair up along
@@ -1329,7 +1398,7 @@ __device__ void reduce_final(const ReduceArgs &A) {
     const int g = t / RED_N, c = t - g * RED_N;
     double x = 0.0;
 #pragma unroll 4
-    for (int b = g; b < RED_BLOCKS; b += RED_G) x += A.part[(size_t)b * RED_W + c];
+    for (int b = g; b < A.nred; b += RED_G) x += A.part[(size_t)b * RED_W + c];
     gs[g][c] = x;
   }
   __syncthreads();
@@ -1372,17 +1441,17 @@ __device__ void reduce_final(const ReduceArgs &A) {
   acc[64] += v[30];
 }
 
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs A) {
+__device__ __forceinline__ void reduce_wg(const ReduceArgs &A, const int bid) {
   double v[RED_N];
   for (int c = 0; c < RED_N; ++c) v[c] = 0.0;
-  const int b = blockIdx.x;
-  const int pb0 = (int)((int64_t)A.nblk * b / RED_BLOCKS), pb1 = (int)((int64_t)A.nblk * (b + 1) / RED_BLOCKS);
+  const int b = bid;
+  const int pb0 = (int)((int64_t)A.nblk * b / A.nred), pb1 = (int)((int64_t)A.nblk * (b + 1) / A.nred);
   for (int t = pb0 + threadIdx.x; t < pb1; t += blockDim.x) {
     for (int c = 0; c < 6; ++c) v[c] += A.pin[(size_t)t * 8 + c];
     v[31] += A.pin[(size_t)t * 8 + 6];
     v[32] += A.pin[(size_t)t * 8 + 7];
   }
-  const int s0 = (int)((int64_t)A.n * b / RED_BLOCKS), s1 = (int)((int64_t)A.n * (b + 1) / RED_BLOCKS);
+  const int s0 = (int)((int64_t)A.n * b / A.nred), s1 = (int)((int64_t)A.n * (b + 1) / A.nred);
   for (int p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
     for (int c = 0; c < 6; ++c) v[6 + c] += A.hyd[(size_t)p * HYD + 6 + c];
     for (int c = 0; c < PST; ++c) v[12 + c] += A.pst[(size_t)p * PST + c];
@@ -1404,12 +1473,17 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs A) {
   }
   __syncthreads();
   __shared__ int last;
-  if (threadIdx.x == 0) last = atomicAdd(A.flags + FL_REDCNT, 1) == RED_BLOCKS - 1;
+  if (threadIdx.x == 0) last = atomicAdd(A.flags + FL_REDCNT, 1) == A.nred - 1;
   __syncthreads();
   if (!last) return;  // the whole block
   __threadfence();  // every slice visible to this block's loads
   if (threadIdx.x == 0) A.flags[FL_REDCNT] = 0;  // for the next step's reduction
   reduce_final(A);
+}
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs A) { reduce_wg(A, (int)blockIdx.x); }
+__global__ __launch_bounds__(256) void k_reduce_m(const ReduceArgs *__restrict__ tab, const int32_t *__restrict__ pre,
+                                                  int nj) {
+  SUSP_MULTI_BODY(ReduceArgs, reduce_wg);
 }
 
 hipError_t launch_stress(Sim *s) {
@@ -1428,8 +1502,12 @@ hipError_t launch_stress(Sim *s) {
   A.has_particles = s->n > 0 ? 1 : 0;
   A.clk = s->clk;
   A.flags = s->flags;
-  hipLaunchKernelGGL(k_reduce, dim3(RED_BLOCKS), dim3(256), 0, s->stream, A);
-  return hipGetLastError();
+  // one work-group per 512 bricks or spheres: each one's fence writes back its L2, so the
+  // count is kept to what the data needs
+  const int64_t items = s->nbricks > s->n ? s->nbricks : s->n;
+  A.nred = (int)((items + 511) / 512);
+  A.nred = A.nred < 1 ? 1 : (A.nred > RED_BLOCKS ? RED_BLOCKS : A.nred);
+  return dispatch(s, k_reduce, k_reduce_m, (unsigned)A.nred, 256, A);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1512,6 +1590,7 @@ __global__ __launch_bounds__(64) void k_cstat_acc(const double *part, double *ca
 
 hipError_t launch_contact_sample(Sim *s) {
   if (s->cbins <= 0) return hipSuccess;
+  SUSP_NO_COLLECT(s);
   if (s->n > 0) {
     CstatArgs A;
     A.cnt = s->ncnt[s->lcur]; A.cflag = s->cflag; A.rec = s->crec; A.part = s->cpart;
@@ -1638,6 +1717,7 @@ __global__ __launch_bounds__(256) void k_wall_force(const double *wpart, int nbl
 }
 
 hipError_t launch_wall_force(Sim *s) {
+  SUSP_NO_COLLECT(s);
   const int nblk = (2 * s->lx * s->lz + 255) / 256;
   hipLaunchKernelGGL(k_wall_force, dim3(1), dim3(256), 0, s->stream, s->wpart, nblk, s->wmem, s->wfs, s->dp,
                      s->n, s->wacc);

@@ -17,6 +17,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <string.h>
 
 namespace susp {
 
@@ -167,6 +168,50 @@ struct Cells {
 
 struct Sim;
 
+// ---- multi-job launches ----
+// A step's kernels can run for many simulations at once: one launch whose work-groups
+// [pre[j], pre[j+1]) belong to job j, with job j's arguments in tab[j].  Each kernel body
+// takes its work-group index within its job; the one-job kernel passes blockIdx.x.
+// Work-group of a multi-job launch -> its job (pre ascends, pre[0] = 0, nj jobs).
+__device__ inline int multi_job(const int32_t *__restrict__ pre, int nj, int b) {
+  int lo = 0, hi = nj - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+// The multi-job kernel of a body: the job's arguments are read from its table entry.
+#define SUSP_MULTI_BODY(ARGS, BODY)                            \
+  const int mj_ = multi_job(pre, nj, (int)blockIdx.x);         \
+  BODY(tab[mj_], (int)blockIdx.x - pre[mj_])
+
+// Launches of one simulation recorded instead of issued (the batch builds its multi-job
+// launches from them): the multi-job kernel, the job's work-group count and block size,
+// and the argument bytes.
+struct Collect {
+  struct Rec {
+    const void *fn;
+    unsigned grid, blk;
+    size_t off, sz;
+  };
+  Rec rec[256];
+  int nrec;
+  char bytes[256 * 512];
+  size_t used;
+  int overflow;
+  void clear() { nrec = 0; used = 0; overflow = 0; }
+  hipError_t add(const void *fn, unsigned grid, unsigned blk, const void *a, size_t sz) {
+    const size_t al = (sz + 15) / 16 * 16;
+    if (nrec == 256 || used + al > sizeof bytes) { overflow = 1; return hipErrorInvalidValue; }
+    memcpy(bytes + used, a, sz);
+    rec[nrec++] = Rec{fn, grid, blk, used, sz};
+    used += al;
+    return hipSuccess;
+  }
+};
+
 // ---- launchers (fluid.hip) ----
 hipError_t launch_init_populations(Sim *s);
 // cleared: the planes were cleared by the step's clock kernel
@@ -282,10 +327,30 @@ struct Sim {
   int prof_on;
   int prof_used, prof_cap;
   hipEvent_t *prof_ev;  // [PROF_EV * prof_cap]: before k_links, before k_stream, after it
+  // non-null: launches of the step are recorded here (multi-job batches), not issued
+  Collect *col;
 };
+
+// Issue a kernel of one simulation, or record it for a multi-job launch.
+template <class A>
+inline hipError_t dispatch(Sim *s, void (*one)(A), void (*multi)(const A *, const int32_t *, int), unsigned grid,
+                           unsigned blk, const A &args) {
+  if (s->col) return s->col->add((const void *)multi, grid, blk, &args, sizeof(A));
+  void *kp[] = {(void *)&args};
+  return hipLaunchKernel((const void *)one, dim3(grid), dim3(blk), kp, 0, s->stream);
+}
+// Launchers of kernels that have no multi-job form refuse to record.
+#define SUSP_NO_COLLECT(s) \
+  do { if ((s)->col) return hipErrorNotSupported; } while (0)
 
 // ---- stepping helpers shared by the single-simulation and batch entry points (api.hip) ----
 int launch_steps(susp_sim *h, int64_t nsteps);
+Sim &sim_of(susp_sim *h);
+bool multi_ok(const susp_sim *h);
+int record_two_steps(susp_sim *h, Collect *c);
+int prepare_run(susp_sim *h, int m);
+void advance_steps(susp_sim *h, int m);
+int step_parity(const susp_sim *h);
 int check_flags(susp_sim *h);
 int set_error(int code, const char *msg);
 

@@ -216,6 +216,91 @@ class Server:
         return sorted(done, key=lambda d: d.jid)
 
 
+@dataclass
+class LockstepServer:
+    """Continuous batching in lockstep runs: every admitted job takes the same run of steps,
+    and each kernel of a step is one launch over all of them (``susp_batch_launch_all``).
+
+    The loop admits arrivals first come first served while their footprints fit; a job
+    admitted while a run is on the GPU joins the next run.  When a run has completed, the
+    jobs that finished (or failed: evicted without a result) leave at once and the next run
+    starts with everyone admitted meanwhile.  A run is ``chunk`` steps, or fewer if a job
+    needs fewer to finish.
+
+    executor: footprint(job) -> bytes, add(job) -> slot or None, launch_all(steps),
+              poll(slot) -> (done, status), result(slot) -> object, remove(slot)."""
+    executor: object
+    budget: int
+    chunk: int = 100
+    poll_s: float = 0.0005
+    clock: object = time.perf_counter
+    sleep: object = time.sleep
+    log: list = field(default_factory=list)
+    host_s: float = 0.0
+    progress: object = None
+    runs: list = field(default_factory=list)  # per run: [launched, queued, completed, jobs, steps]
+
+    def run(self, jobs):
+        ex = self.executor
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        pending = deque(sorted(jobs, key=lambda j: j.arrival))
+        queue = deque()
+        active = {}   # slot -> [job, admitted time, steps not yet run, worst status]
+        running = []  # slots of the run on the GPU
+        done = []
+        for j in jobs:
+            if ex.footprint(j) > self.budget:
+                raise ValueError("job %d can never fit in the budget" % j.jid)
+        while pending or queue or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                queue.append(pending.popleft())
+            while queue:
+                h0 = self.clock()
+                slot = ex.add(queue[0])
+                self.host_s += self.clock() - h0
+                if slot is None:
+                    break
+                j = queue.popleft()
+                active[slot] = [j, now(), j.steps, 0]
+            progressed = False
+            if running:
+                states = [ex.poll(s) for s in running]
+                if all(d for d, _ in states):
+                    progressed = True
+                    self.runs[-1][2] = now()
+                    for s, (_, status) in zip(running, states):
+                        v = active[s]
+                        v[3] = v[3] or status
+                        if v[2] > 0 and not status:
+                            continue
+                        del active[s]
+                        res = ex.result(s) if not status else None
+                        ex.remove(s)
+                        done.append(Done(v[0].jid, v[0].arrival, v[1], now(), res, v[3]))
+                        if self.progress is not None:
+                            self.progress(len(done), len(jobs))
+                    running = []
+            if not running and active:
+                n = min(self.chunk, min(v[2] for v in active.values()))
+                h0 = self.clock()
+                ex.launch_all(n)
+                self.host_s += self.clock() - h0
+                self.runs.append([h0 - t0, now(), None, len(active), n])
+                running = list(active)
+                for s in running:
+                    active[s][2] -= n
+                progressed = True
+            self.log.append((now(), len(active)))
+            if not progressed:
+                wait = self.poll_s
+                if not active and not queue and pending:
+                    wait = max(wait, pending[0].arrival - now())
+                self.sleep(wait)
+        return sorted(done, key=lambda d: d.jid)
+
+
 # ---------------------------------------------------------------------------------------
 # GPU executors (library calls only)
 
@@ -230,13 +315,15 @@ def job_params(spec, w, precision=1, brick=None):
 
 
 class BatchExecutor:
-    """Jobs in a susp_batch (autotuned brick shapes)."""
+    """Jobs in a susp_batch: autotuned brick shapes, one stream per job (``Server``), or
+    the default brick in lockstep runs (``LockstepServer``, autotune off)."""
 
     def __init__(self, workloads, budget, max_jobs=64, precision=1, autotune=True):
         from . import susp
         self.susp = susp
         self.w = workloads
         self.precision = precision
+        self.autotune = autotune
         self.batch = susp.Batch(max_jobs, budget, autotune=autotune)
         self._slot_job = {}
         self._fp = {}
@@ -254,7 +341,7 @@ class BatchExecutor:
 
     def add(self, spec):
         p = job_params(spec, self.w[spec.jid], self.precision)
-        self.bricks[spec.jid] = self.batch.tune(p)
+        self.bricks[spec.jid] = self.batch.tune(p) if self.autotune else None
         slot = self.batch.add(p)
         if slot is not None:
             self._slot_job[slot] = spec.jid
@@ -262,6 +349,9 @@ class BatchExecutor:
 
     def launch(self, slot, n):
         self.batch.launch(slot, n)
+
+    def launch_all(self, n):
+        self.batch.launch_all(n)
 
     def poll(self, slot):
         return self.batch.poll(slot)
@@ -299,8 +389,11 @@ def run_alone(spec, w, precision=1, brick=None, stream=None, graphs=0):
 
 
 def serve_benchmark(n_jobs=64, steps=3000, budget=32 << 30, seed=1904, workers=8, recheck=None,
-                    log=print):
+                    log=print, mode="lockstep"):
     """The plain loop and the batched server on the same requests; returns a summary.
+
+    mode "lockstep": ``LockstepServer`` (one launch per kernel over all jobs, default brick);
+    "streams": ``Server`` (one stream per job, autotuned bricks).
 
     The plain loop is timed twice, with every kernel launched one by one and with recorded
     step graphs replayed on a stream; the speedups are taken against the faster of the two.
@@ -332,19 +425,27 @@ def serve_benchmark(n_jobs=64, steps=3000, budget=32 << 30, seed=1904, workers=8
     fin_plain = fifo_schedule(arr, service)
     lat_plain = fin_plain - arr
     # batched server
-    ex = BatchExecutor(ws, budget, max_jobs=n_jobs)
-    t = time.perf_counter()
-    ex.tune(specs)
-    t_tune = time.perf_counter() - t
-    log("serving: autotuned %d lattice kinds in %.1f s" % (len(set((s.kind, s.L) for s in specs)), t_tune))
     every = lambda k, n: k % 8 == 0 and log("serving: batched %d/%d jobs done" % (k, n))
-    srv = Server(ex, budget, progress=every)
+    if mode == "lockstep":
+        ex = BatchExecutor(ws, budget, max_jobs=n_jobs, autotune=False)
+        t_tune = 0.0
+        make = lambda: LockstepServer(ex, budget, progress=every)
+    elif mode == "streams":
+        ex = BatchExecutor(ws, budget, max_jobs=n_jobs)
+        t = time.perf_counter()
+        ex.tune(specs)
+        t_tune = time.perf_counter() - t
+        log("serving: autotuned %d lattice kinds in %.1f s" % (len(set((s.kind, s.L) for s in specs)), t_tune))
+        make = lambda: Server(ex, budget, progress=every)
+    else:
+        raise ValueError("mode must be lockstep or streams")
+    srv = make()
     done = srv.run(specs)
     torch.cuda.synchronize()
     # capacity: the same requests all present at the start (the server never idles)
     sat = [JobSpec(**{**s.__dict__, "arrival": 0.0}) for s in specs]
     t = time.perf_counter()
-    srv_sat = Server(ex, budget, progress=every)
+    srv_sat = make()
     srv_sat.run(sat)
     torch.cuda.synchronize()
     t_sat = time.perf_counter() - t
@@ -363,6 +464,7 @@ def serve_benchmark(n_jobs=64, steps=3000, budget=32 << 30, seed=1904, workers=8
     peak = max((a for _, a in srv.log), default=0)
     peak_sat = max((a for _, a in srv_sat.log), default=0)
     return {
+        "server": mode,
         "jobs": n_jobs,
         "steps_per_job": steps,
         "budget_bytes": int(budget),

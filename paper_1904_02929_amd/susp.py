@@ -94,6 +94,7 @@ def lib():
         L.susp_batch_stress.argtypes = [vp, C.c_int32, _PD, _PD]
         L.susp_batch_launch.argtypes = [vp, C.c_int32, C.c_int64]
         L.susp_batch_poll.argtypes = [vp, C.c_int32, _PI]
+        L.susp_batch_launch_all.argtypes = [vp, C.c_int64]
         L.susp_batch_sim.argtypes = [vp, C.c_int32]
         L.susp_batch_sim.restype = vp
         L.susp_batch_bytes.argtypes = [vp]
@@ -388,6 +389,11 @@ class Batch:
     def launch(self, slot, n):
         """Queue n steps of one job and return at once."""
         _chk(lib().susp_batch_launch(self.h, int(slot), int(n)))
+
+    def launch_all(self, n):
+        """Queue n steps of every job in lockstep (one launch per kernel over all jobs) and
+        return at once; poll(slot) reports each job."""
+        _chk(lib().susp_batch_launch_all(self.h, int(n)))
 
     def poll(self, slot):
         """(done, status): done once the job's queued steps have completed."""

@@ -212,3 +212,109 @@ def test_failed_job_is_reported_alone(susp):
     alone.close()
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
+
+
+def _wait(batch, slots):
+    import time
+    for s in slots:
+        while True:
+            done, rc = batch.poll(s)
+            if done:
+                assert rc == 0, "job in slot %d reported %d" % (s, rc)
+                break
+            time.sleep(0.001)
+
+
+def test_lockstep_equals_alone(susp):
+    # lockstep runs (one launch per kernel over all jobs): jobs of different boxes and
+    # protocols, an FP16-storage job (a second kernel sequence), a job with another brick
+    # (steps on its own stream), a job joining and one leaving between runs, and an odd run
+    S = susp
+    jobs = _jobs(S)
+    specs = [(jobs[0], S.FP32, None), (jobs[1], S.FP32, None), (jobs[3], S.FP32, None),
+             (jobs[2], S.FP16STORE, None), (jobs[1], S.FP32, (8, 8))]
+    late = (jobs[2], S.FP32, None)
+
+    def params(spec):
+        j, prec, brick = spec
+        p = _params(S, j, brick)
+        p.precision = prec
+        return p
+
+    print("\n[batch] lockstep: %d jobs + 1 late" % len(specs), flush=True)
+    batch = S.Batch(8, 1 << 34, autotune=False)
+    slots = [batch.add(params(sp)) for sp in specs]
+    assert None not in slots
+    steps = {s: 0 for s in slots}
+    batch.launch_all(6)
+    _wait(batch, slots)
+    for s in slots:
+        steps[s] += 6
+    ls = batch.add(params(late))
+    slots.append(ls)
+    specs.append(late)
+    steps[ls] = 0
+    batch.launch_all(4)
+    _wait(batch, slots)
+    for s in slots:
+        steps[s] += 4
+    gone = slots[1]
+    batch.remove(gone)
+    keep = [(s, sp) for s, sp in zip(slots, specs) if s != gone]
+    batch.launch_all(3)
+    _wait(batch, [s for s, _ in keep])
+    for s, _ in keep:
+        steps[s] += 3
+    for s, sp in keep:
+        st = _state(batch.job(s))
+        sig, gg = batch.stress(s)
+        alone = S.Simulation(params(sp))
+        alone.step(steps[s])
+        ref = _state(alone)
+        print("[batch] slot %d box %s precision %d brick %s: %d steps" % (s, sp[0][0], sp[1], sp[2], steps[s]),
+              flush=True)
+        for k, (x, y) in enumerate(zip(st, ref)):
+            assert np.array_equal(x, y), "slot %d field %d differs" % (s, k)
+        sig_a, gg_a = alone.stress()
+        assert np.array_equal(sig, sig_a) and np.array_equal(gg, gg_a)
+        alone.close()
+    batch.close()
+
+
+def test_lockstep_job_matches_oracle(susp):
+    # a job stepped in lockstep beside another job, against the oracle: two steps from the
+    # oracle's state at the FP32 per-step tolerance
+    S = susp
+    box, pos, vel, om, rad, kw = PU.dense_workload(seed=21)
+    o = PU.oracle_for(box, kw, pos, vel, om, rad)
+    assert o.step(20) == 0
+    print("\n[batch] lockstep job vs oracle, box %s, n=%d" % (box, len(rad)), flush=True)
+    batch = S.Batch(4, 1 << 33, autotune=False)
+    other = batch.add(_params(S, _jobs(S)[1]))
+    slot = batch.add(S.make_params(box, radius=rad, pos=pos, vel=vel, omega=om, precision=S.FP32, **kw))
+    g = batch.job(slot)
+    PU.load_oracle_state(o, g, 1)
+    o.stress(); batch.stress(slot)
+    batch.launch_all(2)
+    _wait(batch, [other, slot])
+    assert o.step(2) == 0
+    tol = 1e-6
+    assert np.array_equal(g.lists(S.LIST_OWNER), o.own)
+    fluid = o.own == -1
+    wr = PU.weights()[:, None]
+    e_d = PU.rel(g.get_populations()[:, fluid] - wr, o.f[:, fluid] - wr)
+    F, T, Sg, nl = g.hydro()
+    Rg, Ug, Wg, Qg = g.get_particles()
+    errs = dict(d=e_d, F=PU.rel(F, o.part("Fh"), 1e-4), T=PU.rel(T, o.part("Th"), 1e-4),
+                U=PU.rel(Ug, o.part("U"), 1e-6), W=PU.rel(Wg, o.part("W"), 1e-7))
+    e_R = float(np.abs(Rg - o.part("R")).max())
+    print("[batch] " + " ".join("e_%s %.3e" % kv for kv in errs.items()) + " e_R %.3e" % e_R, flush=True)
+    assert np.array_equal(nl, o.nlinks)
+    # positions: the one-step bound (1e-10 lattice units) for each of the two steps, plus the
+    # first step's velocity error carried through the second step's displacement
+    assert max(errs.values()) <= tol and e_R <= 3e-10
+    sg, _ = batch.stress(slot)
+    so, _ = o.stress()
+    for k in range(5):
+        assert PU.rel(sg[k], so[k]) <= 1e-6
+    batch.close()

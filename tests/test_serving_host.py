@@ -183,3 +183,67 @@ def test_server_evicts_only_the_failed_job():
         if d.jid != 3:
             assert d.status == 0 and d.result == d.jid
     assert ex.used == 0
+
+
+class FakeLockstepExecutor(FakeExecutor):
+    """launch_all(n) runs every admitted job for n steps; records each run's jobs."""
+
+    def __init__(self, budget, clock, bad=None):
+        super().__init__(budget, clock)
+        self.runs = []
+        self.bad = bad
+
+    def launch_all(self, n):
+        self._advance()
+        assert all(v <= 1e-9 for v in self.left.values()), "a run started before the last ended"
+        for s in self.jobs:
+            self.left[s] = float(n)
+        self.runs.append((sorted(self.jobs), n))
+
+    def poll(self, slot):
+        ok, _ = super().poll(slot)
+        return ok, (-4 if ok and self.jobs[slot].jid == self.bad else 0)
+
+
+def test_lockstep_server_runs_every_admitted_job():
+    jobs = serve.mixed_jobs(16, seed=3, steps=1000)
+    arr = serve.poisson_arrivals(16, rate=0.01, seed=4)
+    for j, a in zip(jobs, arr):
+        j.arrival = float(a)
+    clock = Clock()
+    ex = FakeLockstepExecutor(budget=700, clock=clock)
+    srv = serve.LockstepServer(ex, budget=700, poll_s=1.0, clock=clock, sleep=clock.sleep)
+    done = srv.run(jobs)
+    assert sorted(d.jid for d in done) == list(range(16))
+    assert ex.peak <= 700 and ex.used == 0
+    by_arrival = [j.jid for j in sorted(jobs, key=lambda j: j.arrival)]
+    assert ex.order == by_arrival
+    # each job took exactly its own steps over the runs it was part of
+    slot_of = {}
+    for s, j in enumerate(ex.order):
+        slot_of[j] = s
+    for j in jobs:
+        took = sum(n for slots, n in ex.runs if slot_of[j.jid] in slots)
+        assert took == j.steps
+    for d in done:
+        assert d.result == d.jid and d.arrival <= d.admitted <= d.finished
+    assert max(len(slots) for slots, _ in ex.runs) > 1
+
+
+def test_lockstep_server_evicts_only_the_failed_job():
+    jobs = serve.mixed_jobs(8, seed=7, steps=500)
+    for j in jobs:
+        j.arrival = 0.0
+    clock = Clock()
+    ex = FakeLockstepExecutor(budget=10 ** 6, clock=clock, bad=3)
+    srv = serve.LockstepServer(ex, budget=10 ** 6, chunk=100, poll_s=1.0, clock=clock, sleep=clock.sleep)
+    done = srv.run(jobs)
+    assert sorted(d.jid for d in done) == list(range(8))
+    bad = [d for d in done if d.jid == 3][0]
+    assert bad.status == -4 and bad.result is None
+    for d in done:
+        if d.jid != 3:
+            assert d.status == 0 and d.result == d.jid
+    # the failed job left after the first run; the others ran all their steps
+    assert all(ex.order.index(3) not in slots for slots, _ in ex.runs[1:])
+    assert ex.used == 0
