@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <iterator>
 #include <map>
@@ -64,6 +65,10 @@ struct MultiLaunch {
   int nj;
 };
 
+// Lockstep runs use this many streams: the jobs are dealt to them by size, so that one
+// part's latency-bound particle kernels run beside another part's lattice kernel.
+constexpr int LS_STREAMS = 2;
+
 struct susp_batch {
   int max_jobs = 0;
   size_t budget = 0, used = 0;
@@ -74,12 +79,15 @@ struct susp_batch {
   std::vector<size_t> bytes, offset;
   std::vector<hipEvent_t> done;   // recorded after a job's queued steps
   std::map<std::array<int, 5>, std::pair<int, int>> shape;  // tuned brick per lattice kind
-  // lockstep runs (susp_batch_launch_all): one stream, the launches of two steps of every
-  // group of jobs with the same kernel sequence, built from each job's recorded launches
-  hipStream_t gstream = nullptr;
-  hipEvent_t gev = nullptr;                  // after the last lockstep run
+  // lockstep runs (susp_batch_launch_all): per part (stream), the launches of two steps of
+  // every group of its jobs with the same kernel sequence, built from each job's recorded
+  // launches
+  hipStream_t gstream[LS_STREAMS] = {};
+  hipEvent_t gjoin[LS_STREAMS] = {};         // end of a part's run (parts 1.. join part 0)
+  hipEvent_t gev = nullptr;                  // after the last lockstep run (all parts)
   std::vector<std::unique_ptr<Collect>> col;  // per slot
-  std::vector<MultiLaunch> seq;              // the groups' sequences, one after the other
+  std::vector<MultiLaunch> seq[LS_STREAMS];  // per part, the groups' sequences in turn
+  std::vector<int> part;                     // per slot: its part in the last build
   std::vector<std::array<int64_t, 3>> key;   // slot, parity, handle the sequence was built for
   std::vector<char> host;                    // staging of the tables
   char *mt = nullptr;                        // device tables
@@ -162,9 +170,16 @@ extern "C" int susp_batch_create(int32_t max_jobs, size_t hbm_budget, int32_t au
       return set_error(SUSP_EDEVICE, "stream or event creation failed");
     }
   }
-  if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->gev, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(b->gev, b->gstream) != hipSuccess) {
+  b->part.assign(max_jobs, 0);
+  for (int g = 0; g < LS_STREAMS; ++g) {
+    if (hipStreamCreateWithFlags(&b->gstream[g], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->gjoin[g], hipEventDisableTiming) != hipSuccess) {
+      susp_batch_destroy(b);
+      return set_error(SUSP_EDEVICE, "stream or event creation failed");
+    }
+  }
+  if (hipEventCreateWithFlags(&b->gev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(b->gev, b->gstream[0]) != hipSuccess) {
     susp_batch_destroy(b);
     return set_error(SUSP_EDEVICE, "stream or event creation failed");
   }
@@ -202,7 +217,6 @@ extern "C" int susp_batch_add(susp_batch *b, const susp_params *p, int32_t *slot
   }
   b->job[k] = h;
   b->key.clear();  // the lockstep sequence is rebuilt for the new set of jobs
-  b->seq.clear();
   b->bytes[k] = need;
   b->offset[k] = off;
   b->used += need;
@@ -216,7 +230,6 @@ extern "C" int susp_batch_remove(susp_batch *b, int32_t slot) {
   susp_destroy(b->job[slot]);  // waits for the job's stream only; its block is the arena's
   b->job[slot] = nullptr;
   b->key.clear();
-  b->seq.clear();
   b->arena.give(b->offset[slot], b->bytes[slot]);
   b->used -= b->bytes[slot];
   b->bytes[slot] = 0;
@@ -280,14 +293,18 @@ extern "C" size_t susp_batch_bytes(const susp_batch *b) { return b ? b->used : 0
 
 extern "C" int susp_batch_destroy(susp_batch *b) {
   if (!b) return SUSP_OK;
-  if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+  for (hipStream_t st : b->gstream)
+    if (st) (void)hipStreamSynchronize(st);
   for (int k = 0; k < b->max_jobs; ++k)
     if (b->job[k]) susp_destroy(b->job[k]);
   for (hipStream_t st : b->stream)
     if (st) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->done)
     if (ev) (void)hipEventDestroy(ev);
-  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  for (hipStream_t st : b->gstream)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->gjoin)
+    if (ev) (void)hipEventDestroy(ev);
   if (b->gev) (void)hipEventDestroy(b->gev);
   if (b->mt) (void)hipFree(b->mt);
   if (b->arena.base) (void)hipFree(b->arena.base);
@@ -302,16 +319,28 @@ extern "C" int susp_batch_destroy(susp_batch *b) {
 // The kernels are the ones a job runs alone, with its own arguments, so its results are the
 // same bit for bit.
 
-// (Re)build the multi-job launch sequence of two steps for the jobs now in the batch, if the
-// jobs or their buffer parities differ from the last build.  The lockstep stream is idle.
+// (Re)build the multi-job launch sequences of two steps for the jobs now in the batch, if the
+// jobs or their buffer parities differ from the last build.  The lockstep streams are idle.
+// The jobs are dealt to the parts largest first, each to the part with the fewest nodes.
 static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
   std::vector<std::array<int64_t, 3>> key;
   for (int k : slots) key.push_back({k, step_parity(b->job[k]), (int64_t)(intptr_t)b->job[k]});
-  if (key == b->key && !b->seq.empty()) return SUSP_OK;
+  if (key == b->key) return SUSP_OK;
   b->key.clear();
-  b->seq.clear();
-  // each job's launches of two steps, grouped by kernel sequence
-  std::map<std::vector<std::pair<const void *, unsigned>>, std::vector<int>> groups;
+  for (auto &q : b->seq) q.clear();
+  std::vector<int> order(slots);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return sim_of(b->job[x]).nodes > sim_of(b->job[y]).nodes; });
+  int64_t load[LS_STREAMS] = {};
+  for (int k : order) {
+    int g = 0;
+    for (int u = 1; u < LS_STREAMS; ++u)
+      if (load[u] < load[g]) g = u;
+    b->part[k] = g;
+    load[g] += sim_of(b->job[k]).nodes;
+  }
+  // each job's launches of two steps, grouped by part and kernel sequence
+  std::map<std::pair<int, std::vector<std::pair<const void *, unsigned>>>, std::vector<int>> groups;
   for (int k : slots) {
     if (!b->col[k]) b->col[k].reset(new Collect);
     Collect *c = b->col[k].get();
@@ -319,18 +348,19 @@ static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
     if (rc) return rc;
     std::vector<std::pair<const void *, unsigned>> sig;
     for (int r = 0; r < c->nrec; ++r) sig.push_back({c->rec[r].fn, c->rec[r].blk});
-    groups[sig].push_back(k);
+    groups[{b->part[k], sig}].push_back(k);
   }
   std::vector<char> &h = b->host;
   h.clear();
   auto align = [&](size_t a) { h.resize((h.size() + a - 1) / a * a); };
   for (auto &g : groups) {
     const std::vector<int> &js = g.second;
-    const int nrec = (int)g.first.size();
+    const auto &sig = g.first.second;
+    const int nrec = (int)sig.size();
     for (int r = 0; r < nrec; ++r) {
       MultiLaunch L;
-      L.fn = g.first[r].first;
-      L.blk = g.first[r].second;
+      L.fn = sig[r].first;
+      L.blk = sig[r].second;
       L.nj = (int)js.size();
       // the kernel indexes its table as an array of the argument struct: entries sizeof apart
       const size_t sz = b->col[js[0]]->rec[r].sz;
@@ -354,7 +384,7 @@ static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
       L.pre = h.size();
       h.resize(h.size() + pre.size() * sizeof(int32_t));
       memcpy(h.data() + L.pre, pre.data(), pre.size() * sizeof(int32_t));
-      b->seq.push_back(L);
+      b->seq[g.first.first].push_back(L);
     }
   }
   if (h.size() > b->mt_cap) {
@@ -364,13 +394,13 @@ static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
     const size_t cap = h.size() * 2 + 4096;
     if (hipMalloc((void **)&b->mt, cap) != hipSuccess) {
       b->mt = nullptr;
-      b->seq.clear();
+      for (auto &q : b->seq) q.clear();
       return set_error(SUSP_ENOMEM, "lockstep launch tables could not be allocated");
     }
     b->mt_cap = cap;
   }
   if (hipMemcpy(b->mt, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    b->seq.clear();
+    for (auto &q : b->seq) q.clear();
     return set_error(SUSP_EDEVICE, "upload of the lockstep launch tables failed");
   }
   b->key = key;
@@ -405,27 +435,35 @@ extern "C" int susp_batch_launch_all(susp_batch *b, int64_t nsteps) {
     int rc = build_sequence(b, slots);
     if (rc) return rc;
     for (int p = 0; p < m / 2; ++p) {
-      for (const MultiLaunch &L : b->seq) {
-        const void *tab = b->mt + L.tab;
-        const int32_t *pre = (const int32_t *)(b->mt + L.pre);
-        int nj = L.nj;
-        void *kp[] = {(void *)&tab, (void *)&pre, (void *)&nj};
-        if (hipLaunchKernel(L.fn, dim3(L.total), dim3(L.blk), kp, 0, b->gstream) != hipSuccess)
-          return set_error(SUSP_EDEVICE, "lockstep launch failed");
+      for (int g = 0; g < LS_STREAMS; ++g) {
+        for (const MultiLaunch &L : b->seq[g]) {
+          const void *tab = b->mt + L.tab;
+          const int32_t *pre = (const int32_t *)(b->mt + L.pre);
+          int nj = L.nj;
+          void *kp[] = {(void *)&tab, (void *)&pre, (void *)&nj};
+          if (hipLaunchKernel(L.fn, dim3(L.total), dim3(L.blk), kp, 0, b->gstream[g]) != hipSuccess)
+            return set_error(SUSP_EDEVICE, "lockstep launch failed");
+        }
       }
     }
     for (int k : slots) advance_steps(b->job[k], m);
     left -= m;
   }
-  if (hipEventRecord(b->gev, b->gstream) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
-  for (int k : slots) {
-    if (left) {  // an odd last step: on the job's own stream, after the lockstep run
+  for (int k : slots)
+    if (hipEventRecord(b->done[k], b->gstream[b->part[k]]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+  // the parts join on stream 0, whose event marks the end of the run
+  for (int g = 1; g < LS_STREAMS; ++g) {
+    if (hipEventRecord(b->gjoin[g], b->gstream[g]) != hipSuccess ||
+        hipStreamWaitEvent(b->gstream[0], b->gjoin[g], 0) != hipSuccess)
+      return set_error(SUSP_EDEVICE, "event record");
+  }
+  if (hipEventRecord(b->gev, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+  if (left) {  // an odd last step: on each job's own stream, after the lockstep run
+    for (int k : slots) {
       if (hipStreamWaitEvent(b->stream[k], b->gev, 0) != hipSuccess) return set_error(SUSP_EDEVICE, "stream wait");
       int rc = launch_steps(b->job[k], left);
       if (rc) return rc;
       if (hipEventRecord(b->done[k], b->stream[k]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
-    } else if (hipEventRecord(b->done[k], b->gstream) != hipSuccess) {
-      return set_error(SUSP_EDEVICE, "event record");
     }
   }
   return SUSP_OK;

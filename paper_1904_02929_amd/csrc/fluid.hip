@@ -185,8 +185,8 @@ template <> struct RowIO<__half> {
 
 // Minimum image of a node X against a sphere centre R, both inside the box (the particle
 // update keeps R in [0, L)): one sliding-plane crossing in y, then one wrap in x (after the
-// image's shift s) and z.  Agrees with minimage except exactly half a period apart, where
-// the links of the node take the per-link path anyway.
+// image's shift s) and z.  Agrees with minimage except exactly half a period apart; either
+// way the node's links are then checked against the image it gives (links_in_image).
 __device__ inline void node_image(const Box &b, double ilx, double ilz, double dx, double dy, double dz,
                                   double &ox, double &oy, double &oz, int &k) {
   k = dy > 0.5 * b.Ly ? 1 : (dy < -0.5 * b.Ly ? -1 : 0);
@@ -195,6 +195,34 @@ __device__ inline void node_image(const Box &b, double ilx, double ilz, double d
   ox = dx - b.Lx * rint(dx * ilx);
   oy = dy;
   oz = dz - b.Lz * rint(dz * ilz);
+}
+
+// Masks (bit q) of the D3Q19 directions whose component along axis (0 x, 1 y, 2 z) is sgn.
+__host__ __device__ constexpr uint32_t dir_mask(int axis, int sgn) {
+  uint32_t m = 0;
+  for (int q = 1; q < NQ; ++q)
+    if ((axis == 0 ? cx(q) : axis == 1 ? cy(q) : cz(q)) == sgn) m |= 1u << q;
+  return m;
+}
+// Whether every link in m ends in the image whose centre gives the node's lever D: for each
+// linked q, each component of D - c_q (the solid end X - c_q minus that centre) lies inside the
+// half period, so the minimum image of the solid end is that image.  The node's links can then
+// be summed per node (eq. 8: u_b . c_q = u(X) . c_q, and each lever is D - c_q / 2).
+__device__ inline bool links_in_image(uint32_t m, const Box &bx, double Dx, double Dy, double Dz) {
+  const double hx = 0.5 * bx.Lx - 1e-6, hy = 0.5 * bx.Ly - 1e-6, hz = 0.5 * bx.Lz - 1e-6;
+  constexpr uint32_t XP = dir_mask(0, 1), XN = dir_mask(0, -1), YP = dir_mask(1, 1), YN = dir_mask(1, -1),
+                     ZP = dir_mask(2, 1), ZN = dir_mask(2, -1);
+  bool ok = true;
+  if (m & XP) ok = ok && fabs(Dx - 1.0) <= hx;
+  if (m & XN) ok = ok && fabs(Dx + 1.0) <= hx;
+  if (m & ~(XP | XN)) ok = ok && fabs(Dx) <= hx;
+  if (m & YP) ok = ok && fabs(Dy - 1.0) <= hy;
+  if (m & YN) ok = ok && fabs(Dy + 1.0) <= hy;
+  if (m & ~(YP | YN)) ok = ok && fabs(Dy) <= hy;
+  if (m & ZP) ok = ok && fabs(Dz - 1.0) <= hz;
+  if (m & ZN) ok = ok && fabs(Dz + 1.0) <= hz;
+  if (m & ~(ZP | ZN)) ok = ok && fabs(Dz) <= hz;
+  return ok;
 }
 
 // A wave-uniform value the compiler must treat as unknown at this point: what derives from
@@ -530,8 +558,6 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
     }
   };
   const double ilx = 1.0 / bx.Lx, ilz = 1.0 / bx.Lz;
-  // the links of a node within one unit of the half period may end in another image
-  const double hx = 0.5 * bx.Lx - 1.0 - 1e-6, hy = 0.5 * bx.Ly - 1.0 - 1e-6, hz = 0.5 * bx.Lz - 1.0 - 1e-6;
   for (int e = t; e < cnt; e += 256) {
     int2 en;
     int key, x, y, z;
@@ -543,7 +569,7 @@ __device__ __forceinline__ void links_body(const LinksArgs &A, int brick, LinksL
     int k;
     node_image(bx, ilx, ilz, (double)x - sphere(key, 0), (double)y - sphere(key, 1), (double)z - sphere(key, 2),
                Dx, Dy, Dz, k);
-    if (!(fabs(Dx) <= hx && fabs(Dy) <= hy && fabs(Dz) <= hz)) {
+    if (!links_in_image(m, bx, Dx, Dy, Dz)) {  // some link ends in another image
       list[e].y = en.y | (int)0x80000000;
       continue;
     }
@@ -712,15 +738,15 @@ __device__ inline double sph_state(const LinksArgs &A, const LinksLDS &sh, int k
   return c < 3 ? A.R[3 * p + c] : (c < 6 ? A.U[3 * p + c - 3] : A.W[3 * p + c - 6]);
 }
 // The node's lever D (node minus the nearest image of the centre) and the rigid-body velocity
-// there (eq. 8); false when some link may end in another image (the per-link path).
-__device__ inline bool entry_motion(const LinksArgs &A, const LinksLDS &sh, const Box &bx, int key, int x, int y,
-                                    int z, double &Dx, double &Dy, double &Dz, double &ux, double &uy, double &uz) {
+// there (eq. 8); false when some link of m ends in another image (the per-link path).
+__device__ inline bool entry_motion(const LinksArgs &A, const LinksLDS &sh, const Box &bx, int key, uint32_t m,
+                                    int x, int y, int z, double &Dx, double &Dy, double &Dz, double &ux, double &uy,
+                                    double &uz) {
   const double ilx = 1.0 / bx.Lx, ilz = 1.0 / bx.Lz;
-  const double hx = 0.5 * bx.Lx - 1.0 - 1e-6, hy = 0.5 * bx.Ly - 1.0 - 1e-6, hz = 0.5 * bx.Lz - 1.0 - 1e-6;
   int k;
   node_image(bx, ilx, ilz, (double)x - sph_state(A, sh, key, 0), (double)y - sph_state(A, sh, key, 1),
              (double)z - sph_state(A, sh, key, 2), Dx, Dy, Dz, k);
-  if (!(fabs(Dx) <= hx && fabs(Dy) <= hy && fabs(Dz) <= hz)) return false;
+  if (!links_in_image(m, bx, Dx, Dy, Dz)) return false;
   const double w0 = sph_state(A, sh, key, 6), w1 = sph_state(A, sh, key, 7), w2 = sph_state(A, sh, key, 8);
   ux = sph_state(A, sh, key, 3) + k * bx.ule + (w1 * Dz - w2 * Dy);
   uy = sph_state(A, sh, key, 4) + (w2 * Dx - w0 * Dz);
@@ -796,7 +822,7 @@ __device__ __forceinline__ void lattice_pre(const LinksArgs &A, int brick, Links
     const uint32_t m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
     const int x = x0 + (loc & 63), y = y0 + ((loc >> 6) & 3), z = z0 + ((loc >> 8) & 3);
     double Dx, Dy, Dz, ux, uy, uz;
-    if (!entry_motion(A, sh, bx, key, x, y, z, Dx, Dy, Dz, ux, uy, uz)) {
+    if (!entry_motion(A, sh, bx, key, m, x, y, z, Dx, Dy, Dz, ux, uy, uz)) {
       sh.list[e].y = en.y | (int)0x80000000;
       continue;
     }
@@ -861,7 +887,7 @@ __device__ __forceinline__ void lattice_sums(const LinksArgs &A, int brick, Link
     const uint32_t m = (((uint32_t)en.y >> 10) & 0x3ffffu) << 1;
     const int x = x0 + (loc & 63), y = y0 + ((loc >> 6) & 3), z = z0 + ((loc >> 8) & 3);
     double Dx, Dy, Dz, ux, uy, uz;
-    entry_motion(A, sh, bx, key, x, y, z, Dx, Dy, Dz, ux, uy, uz);  // true: not marked
+    entry_motion(A, sh, bx, key, m, x, y, z, Dx, Dy, Dz, ux, uy, uz);  // true: not marked
     const uint32_t rec = sh.srec[loc];
     const uint32_t v0 = sh.srow[(loc >> 6) & 15] + (rec >> REC_OFF);
     // the slot of the node's next link direction (a running count over the record's bits);
