@@ -4,6 +4,8 @@ Runs the FP64 oracle (and nothing else; inputs come from the seeded generators) 
 workloads and stores block averages of the stress (eq. 15) and the accumulated G', G''
 (eqs. 17-18):
 
+  bulk96_055  the same box at phi = 0.55 (inside the 0.50-0.56 range of the 3D bulk
+              configuration), 2,500 steps, blocks of 250 from step 500 (strain 0.5 to 2.5).
   bulk96      96^3 bidisperse (a = 4.5 / 6.3) suspension at phi = 0.45, simple shear
               gamma_dot = 1e-3, seed 1 (Sec. 4.1 parameters); 8,000 steps, the stress
               averaged over blocks of 500 steps from step 2,000 (strain 2 to 8).  (At
@@ -42,6 +44,9 @@ def workload(name):
     if name == "bulk96":
         w = synth.bulk3d(96, 0.45, 1e-3, seed=1)
         return w, dict(total=8000, start=2000, block=500, cycles=None)
+    if name == "bulk96_055":
+        w = synth.bulk3d(96, 0.55, 1e-3, seed=1)
+        return w, dict(total=2500, start=500, block=250, cycles=None)
     if name == "mono256":
         return [mono256(seed) for seed in MONO_SEEDS]
     raise ValueError(name)

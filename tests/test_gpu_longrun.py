@@ -1,12 +1,21 @@
-"""Long-run statistical parity: the library in FP32 against the FP64 oracle's stored averages.
+"""Long-run parity against the FP64 oracle's stored averages (tests/golden/longrun_*.json,
+written by tests/golden/make_longrun.py, which calls the oracle only).
 
-The trajectories of a sheared suspension separate after enough steps, so long runs are
-compared through statistics: the time-averaged shear stress <sigma_xy> (eq. 15, all five
-parts) of a 3D bulk suspension under simple shear, and G', G'' (eqs. 17-18) of a monolayer
-under oscillatory shear.  Bar: |gpu - oracle| <= 2 % of |oracle| + 2 standard errors, the
-standard errors from block averages (500-step blocks for the stress, one value per
-observation cycle for G', G'': three cycles in each of three packings).  The oracle's values are written by
-tests/golden/make_longrun.py (oracle only) into tests/golden/longrun_*.json.
+FP64: the library in FP64 sums the same terms as the oracle and differs only in the order of
+some roundings, so where the trajectories stay together the time averages are held to the
+2 % bar with no statistical allowance: the time-averaged shear stress <sigma_xy> (eq. 15, each
+of its five parts, every 500-step block) of the 3D bulk suspension at phi 0.45 over 8,000 steps
+(strain 2 to 8), and G', G'' (eqs. 17-18) of three monolayer packings over the first
+observation cycle of their oscillatory protocol.  At phi 0.55 (inside the 0.50-0.56 range of
+the 3D configuration; 2,500 steps) and in later monolayer cycles the trajectories separate even
+in FP64 (a dense sheared suspension is chaotic), and the phi 0.55 averages are compared with 2 %
+plus two paired standard errors of the block differences.
+
+FP32: the trajectories separate within the runs, so they are compared through statistics.
+Bar: |gpu - oracle| <= 2 % of |oracle| + 2 standard errors, the standard errors from block
+averages (500-step blocks for the stress, one value per observation cycle for G', G'':
+three cycles in each of three packings).  At strain amplitude 0.01 one cycle's G' scatters by
+tens of percent between realizations, so that bar is wide for G'.
 """
 import json
 import math
@@ -51,9 +60,9 @@ def _mean_se(x):
     return float(x.mean()), float(x.std(ddof=1) / math.sqrt(len(x))) if len(x) > 1 else 0.0
 
 
-def _run(S, w, plan):
+def _run(S, w, plan, precision=None):
     p = S.make_params(w.box, radius=w.radius, pos=w.pos, vel=w.vel, omega=w.omega,
-                      precision=S.FP32, **w.params)
+                      precision=S.FP32 if precision is None else precision, **w.params)
     sim = S.Simulation(p)
     sim.step(plan["start"])
     sim.stress()
@@ -121,3 +130,51 @@ def test_monolayer_moduli(susp):
     mo, _ = _mean_se(so_)
     mg, _ = _mean_se(sg_)
     print("[longrun] <sigma_xy> oracle %.6e, gpu %.6e" % (mo, mg), flush=True)
+
+
+def _parts_xy(blocks):
+    """Time average of sigma_xy of each of the five parts over the blocks."""
+    return np.array([[b[k][3] for k in range(5)] for b in blocks]).mean(axis=0)
+
+
+@pytest.mark.parametrize("name, tracks", [("bulk96", True), ("bulk96_055", False)])
+def test_bulk_fp64_against_the_oracle(susp, name, tracks):
+    # tracks: at phi 0.45 the FP64 trajectories stay together over the whole run (blocks
+    # agree to ~1e-5), so each block and each part of eq. 15 is held to 2 %; at phi 0.55,
+    # where contacts carry nearly all the stress, they separate within the run even in FP64,
+    # and the time averages are compared with the paired standard error of the block
+    # differences
+    gold = _golden(name)
+    w, plan = _workload(name)
+    print("\n[longrun] %s FP64 %s, %d spheres, %d steps" % (name, w.box, len(w.radius), plan["total"]), flush=True)
+    blocks, _ = _run(susp, w, plan, susp.FP64)
+    so, sg = np.array(_sxy(gold["block_stress"])), np.array(_sxy(blocks))
+    assert so.shape == sg.shape
+    d = sg - so
+    se = float(d.std(ddof=1) / math.sqrt(len(d)))
+    worst = float(np.max(np.abs(d) / np.abs(so)))
+    po, pg = _parts_xy(gold["block_stress"]), _parts_xy(blocks)
+    print("[longrun] <sigma_xy> oracle %.9e gpu %.9e (%.2f %% apart, paired se %.2f %%); worst block %.2e relative"
+          % (so.mean(), sg.mean(), 100 * abs(d.mean() / so.mean()), 100 * se / abs(so.mean()), worst), flush=True)
+    print("[longrun] parts oracle %s gpu %s" % (np.array2string(po, precision=6), np.array2string(pg, precision=6)),
+          flush=True)
+    if tracks:
+        assert abs(d.mean()) <= 0.02 * abs(so.mean())
+        assert np.all(np.abs(pg - po) <= 0.02 * abs(so.mean()))
+        assert worst <= 0.02
+    else:
+        assert abs(d.mean()) <= 0.02 * abs(so.mean()) + 2 * se
+
+
+def test_monolayer_fp64_first_cycle(susp):
+    gold = _golden("mono256")
+    for (w, plan), run in zip(_workload("mono256"), gold["runs"]):
+        cyc = plan["cycles"]
+        first = dict(plan, total=cyc[0] + cyc[1])  # the initial cycles and one observation cycle
+        print("\n[longrun] monolayer FP64 %s seed %d, %d steps" % (w.box, run["seed"], first["total"]), flush=True)
+        _, gg = _run(susp, w, first, susp.FP64)
+        go = np.asarray(run["gg_after_cycle"][0])
+        gg = np.asarray(gg[0])
+        print("[longrun] G', G'' oracle %s gpu %s" % (go, gg), flush=True)
+        assert abs(gg[0] - go[0]) <= 0.02 * abs(go[0])
+        assert abs(gg[1] - go[1]) <= 0.02 * abs(go[1])
