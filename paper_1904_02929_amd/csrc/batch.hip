@@ -67,7 +67,7 @@ struct MultiLaunch {
 
 // Lockstep runs use this many streams: the jobs are dealt to them by size, so that one
 // part's latency-bound particle kernels run beside another part's lattice kernel.
-constexpr int LS_STREAMS = 2;
+constexpr int LS_STREAMS = 4;
 
 struct susp_batch {
   int max_jobs = 0;
@@ -88,6 +88,8 @@ struct susp_batch {
   std::vector<std::unique_ptr<Collect>> col;  // per slot
   std::vector<MultiLaunch> seq[LS_STREAMS];  // per part, the groups' sequences in turn
   std::vector<int> part;                     // per slot: its part in the last build
+  hipEvent_t gfork = nullptr;                // fork of the parts inside the recorded pair
+  hipGraphExec_t gexec = nullptr;            // the pair of steps of all parts, recorded
   std::vector<std::array<int64_t, 3>> key;   // slot, parity, handle the sequence was built for
   std::vector<char> host;                    // staging of the tables
   char *mt = nullptr;                        // device tables
@@ -179,6 +181,7 @@ extern "C" int susp_batch_create(int32_t max_jobs, size_t hbm_budget, int32_t au
     }
   }
   if (hipEventCreateWithFlags(&b->gev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->gfork, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(b->gev, b->gstream[0]) != hipSuccess) {
     susp_batch_destroy(b);
     return set_error(SUSP_EDEVICE, "stream or event creation failed");
@@ -305,6 +308,8 @@ extern "C" int susp_batch_destroy(susp_batch *b) {
     if (st) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->gjoin)
     if (ev) (void)hipEventDestroy(ev);
+  if (b->gfork) (void)hipEventDestroy(b->gfork);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->gev) (void)hipEventDestroy(b->gev);
   if (b->mt) (void)hipFree(b->mt);
   if (b->arena.base) (void)hipFree(b->arena.base);
@@ -318,6 +323,57 @@ extern "C" int susp_batch_destroy(susp_batch *b) {
 // per kernel, its work-groups dealt to the jobs by the offsets table), instead of once per job.
 // The kernels are the ones a job runs alone, with its own arguments, so its results are the
 // same bit for bit.
+
+// Issue one pair of steps of every part: the parts' sequences on their streams, forked from
+// and joined back to stream 0 (recorded into a graph, or issued directly).
+static int issue_pair(susp_batch *b) {
+  if (hipEventRecord(b->gfork, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+  for (int g = 1; g < LS_STREAMS; ++g)
+    if (!b->seq[g].empty() && hipStreamWaitEvent(b->gstream[g], b->gfork, 0) != hipSuccess)
+      return set_error(SUSP_EDEVICE, "stream wait");
+  for (int g = 0; g < LS_STREAMS; ++g) {
+    for (const MultiLaunch &L : b->seq[g]) {
+      const void *tab = b->mt + L.tab;
+      const int32_t *pre = (const int32_t *)(b->mt + L.pre);
+      int nj = L.nj;
+      void *kp[] = {(void *)&tab, (void *)&pre, (void *)&nj};
+      if (hipLaunchKernel(L.fn, dim3(L.total), dim3(L.blk), kp, 0, b->gstream[g]) != hipSuccess)
+        return set_error(SUSP_EDEVICE, "lockstep launch failed");
+    }
+  }
+  for (int g = 1; g < LS_STREAMS; ++g) {
+    if (b->seq[g].empty()) continue;
+    if (hipEventRecord(b->gjoin[g], b->gstream[g]) != hipSuccess ||
+        hipStreamWaitEvent(b->gstream[0], b->gjoin[g], 0) != hipSuccess)
+      return set_error(SUSP_EDEVICE, "event record");
+  }
+  return SUSP_OK;
+}
+
+// Record one pair of steps of all parts as a graph (replayed once per pair: one host call
+// instead of a launch per kernel, part and job group).  Kernels and event nodes only.
+static int record_pair(susp_batch *b) {
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  hipGraph_t gr = nullptr;
+  if (hipStreamBeginCapture(b->gstream[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return set_error(SUSP_EDEVICE, "graph capture");
+  int rc = issue_pair(b);
+  const hipError_t e = hipStreamEndCapture(b->gstream[0], &gr);
+  if (rc || e != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc ? rc : set_error(SUSP_EDEVICE, "graph capture");
+  }
+  const hipError_t ei = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (ei != hipSuccess) {
+    b->gexec = nullptr;
+    return set_error(SUSP_EDEVICE, "graph instantiate");
+  }
+  return SUSP_OK;
+}
 
 // (Re)build the multi-job launch sequences of two steps for the jobs now in the batch, if the
 // jobs or their buffer parities differ from the last build.  The lockstep streams are idle.
@@ -403,6 +459,11 @@ static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
     for (auto &q : b->seq) q.clear();
     return set_error(SUSP_EDEVICE, "upload of the lockstep launch tables failed");
   }
+  int rc = record_pair(b);
+  if (rc) {
+    for (auto &q : b->seq) q.clear();
+    return rc;
+  }
   b->key = key;
   return SUSP_OK;
 }
@@ -434,29 +495,14 @@ extern "C" int susp_batch_launch_all(susp_batch *b, int64_t nsteps) {
     }
     int rc = build_sequence(b, slots);
     if (rc) return rc;
-    for (int p = 0; p < m / 2; ++p) {
-      for (int g = 0; g < LS_STREAMS; ++g) {
-        for (const MultiLaunch &L : b->seq[g]) {
-          const void *tab = b->mt + L.tab;
-          const int32_t *pre = (const int32_t *)(b->mt + L.pre);
-          int nj = L.nj;
-          void *kp[] = {(void *)&tab, (void *)&pre, (void *)&nj};
-          if (hipLaunchKernel(L.fn, dim3(L.total), dim3(L.blk), kp, 0, b->gstream[g]) != hipSuccess)
-            return set_error(SUSP_EDEVICE, "lockstep launch failed");
-        }
-      }
-    }
+    for (int p = 0; p < m / 2; ++p)
+      if (hipGraphLaunch(b->gexec, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "lockstep launch failed");
     for (int k : slots) advance_steps(b->job[k], m);
     left -= m;
   }
+  // every pair ends with the parts joined on stream 0, whose event marks the end of the run
   for (int k : slots)
-    if (hipEventRecord(b->done[k], b->gstream[b->part[k]]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
-  // the parts join on stream 0, whose event marks the end of the run
-  for (int g = 1; g < LS_STREAMS; ++g) {
-    if (hipEventRecord(b->gjoin[g], b->gstream[g]) != hipSuccess ||
-        hipStreamWaitEvent(b->gstream[0], b->gjoin[g], 0) != hipSuccess)
-      return set_error(SUSP_EDEVICE, "event record");
-  }
+    if (hipEventRecord(b->done[k], b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
   if (hipEventRecord(b->gev, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
   if (left) {  // an odd last step: on each job's own stream, after the lockstep run
     for (int k : slots) {

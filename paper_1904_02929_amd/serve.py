@@ -221,11 +221,12 @@ class LockstepServer:
     """Continuous batching in lockstep runs: every admitted job takes the same run of steps,
     and each kernel of a step is one launch over all of them (``susp_batch_launch_all``).
 
-    The loop admits arrivals first come first served while their footprints fit; a job
-    admitted while a run is on the GPU joins the next run.  When a run has completed, the
-    jobs that finished (or failed: evicted without a result) leave at once and the next run
-    starts with everyone admitted meanwhile.  A run is ``chunk`` steps, or fewer if a job
-    needs fewer to finish.
+    When a run has completed, the jobs that finished (or failed: evicted without a result)
+    leave at once, the arrivals waiting are admitted first come first served while their
+    footprints fit, and the next run starts with everyone admitted.  Admission waits for the
+    run boundary because creating a job makes synchronous calls on the job's stream, and a
+    stream can share a hardware queue with a lockstep stream: during a run they would wait
+    for the queued run.  A run is ``chunk`` steps, or fewer if a job needs fewer to finish.
 
     executor: footprint(job) -> bytes, add(job) -> slot or None, launch_all(steps),
               poll(slot) -> (done, status), result(slot) -> object, remove(slot)."""
@@ -256,14 +257,6 @@ class LockstepServer:
             t = now()
             while pending and pending[0].arrival <= t:
                 queue.append(pending.popleft())
-            while queue:
-                h0 = self.clock()
-                slot = ex.add(queue[0])
-                self.host_s += self.clock() - h0
-                if slot is None:
-                    break
-                j = queue.popleft()
-                active[slot] = [j, now(), j.steps, 0]
             progressed = False
             if running:
                 states = [ex.poll(s) for s in running]
@@ -282,6 +275,15 @@ class LockstepServer:
                         if self.progress is not None:
                             self.progress(len(done), len(jobs))
                     running = []
+            if not running:
+                while queue:
+                    h0 = self.clock()
+                    slot = ex.add(queue[0])
+                    self.host_s += self.clock() - h0
+                    if slot is None:
+                        break
+                    j = queue.popleft()
+                    active[slot] = [j, now(), j.steps, 0]
             if not running and active:
                 n = min(self.chunk, min(v[2] for v in active.values()))
                 h0 = self.clock()
