@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--serve-mode", default="lockstep", choices=["lockstep", "streams"],
                     help="batched server: lockstep runs with one launch per kernel over all jobs, "
                          "or one stream per job")
+    ap.add_argument("--mix-probe", action="store_true",
+                    help="only time the serving mix (--serve-jobs requests, 24 if 0): every job alone "
+                         "against one lockstep step of all of them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "reference kernel for scaling the HBM byte counters)")
@@ -247,6 +250,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": src.numel() * 4,
                           "copy_bytes_written_per_launch": src.numel() * 4, "launches": 5}))
+        return
+    if args.mix_probe:
+        from paper_1904_02929_amd import serve
+        print(json.dumps(serve.lockstep_probe(n_jobs=args.serve_jobs or 24, log=log)))
         return
     t = time.perf_counter()
     w, wname = workload(args.workload)

@@ -390,6 +390,47 @@ def run_alone(spec, w, precision=1, brick=None, stream=None, graphs=0):
     return dt, (sig, gg, R)
 
 
+def lockstep_probe(n_jobs=24, steps=100, seed=1904, budget=32 << 30, workers=8, log=print):
+    """Per-step time of the request mix: every job alone (recorded step graphs on a stream,
+    after 20 warm-up steps), summed, against one lockstep step of all of them together."""
+    import torch
+    from . import susp
+    specs = mixed_jobs(n_jobs, seed, 1000)
+    ws = build_workloads(specs, workers)
+    st = torch.cuda.Stream()
+    alone = []
+    for s in specs:
+        sim = susp.Simulation(job_params(s, ws[s.jid]), stream=st)
+        sim.use_graphs(5)
+        sim.step(20, check=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(steps, check=False)
+        torch.cuda.synchronize()
+        alone.append((time.perf_counter() - t) / steps * 1e3)
+        sim.close()
+    ex = BatchExecutor(ws, budget, max_jobs=n_jobs, autotune=False)
+    slots = [ex.add(s) for s in specs]
+    if None in slots:
+        raise RuntimeError("the mix does not fit in the budget")
+
+    def run(n):
+        ex.launch_all(n)
+        for k in slots:
+            while not ex.poll(k)[0]:
+                time.sleep(0.0002)
+    run(20)
+    t = time.perf_counter()
+    run(steps)
+    lock = (time.perf_counter() - t) / steps * 1e3
+    ex.close()
+    nodes = sum(int(np.prod(ws[s.jid].box)) for s in specs)
+    log("mix probe: %d jobs, %d nodes; alone %.3f ms per step summed, lockstep %.3f ms" % (n_jobs, nodes, sum(alone), lock))
+    return {"jobs": n_jobs, "nodes": nodes, "steps": steps, "alone_ms_per_step_sum": round(sum(alone), 4),
+            "alone_ms_per_step": [round(a, 4) for a in alone], "lockstep_ms_per_step": round(lock, 4),
+            "ratio": round(sum(alone) / lock, 3)}
+
+
 def serve_benchmark(n_jobs=64, steps=3000, budget=32 << 30, seed=1904, workers=8, recheck=None,
                     log=print, mode="lockstep"):
     """The plain loop and the batched server on the same requests; returns a summary.
