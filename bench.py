@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16-line", action="store_true",
                     help="skip the second run of the workload with FP16 storage")
-    ap.add_argument("--serve-jobs", type=int, default=48,
+    ap.add_argument("--serve-jobs", type=int, default=64,
                     help="requests in the serving comparison (0: skip it)")
     ap.add_argument("--serve-steps", type=int, default=1000, help="lattice steps per request")
     ap.add_argument("--serve-mode", default="lockstep", choices=["lockstep", "streams"],
