@@ -276,6 +276,10 @@ class Oracle:
         self._keep = (pos, vel, omega, radius)
         self.ptr = lib().orc_create(C.byref(params), n, _pd(pos), _pd(vel), _pd(omega), _pd(radius))
         self.s = self.ptr.contents
+        # the lattice loop is split over z-planes: no more threads than planes, and one thread
+        # per 4096 nodes at most (a tiny box otherwise spends its steps in thread barriers)
+        nodes = int(params.lx) * int(params.ly) * int(params.lz)
+        self.s.nthreads = max(1, min(int(self.s.nthreads), int(params.lz), nodes // 4096))
         if wall is not None:
             wall = np.ascontiguousarray(wall, np.int32).reshape(-1)
             if lib().orc_set_walls(self.ptr, _pi(wall)):

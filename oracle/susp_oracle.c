@@ -751,7 +751,7 @@ static void build_pairs(orc_sim *S, double s) {
   int32_t *cnt = (int32_t *)xcalloc((size_t)np + 1, sizeof(int32_t));
   int32_t **lst = (int32_t **)xcalloc((size_t)np, sizeof(int32_t *));
   int ovl = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(| : ovl)
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : ovl) if (np > 64)
   for (int i = 0; i < np; ++i) {
     int cap = 16, c = 0;
     int32_t *L = (int32_t *)malloc(cap * sizeof(int32_t));

@@ -11,6 +11,8 @@ workloads and stores block averages of the stress (eq. 15) and the accumulated G
               averaged over blocks of 500 steps from step 2,000 (strain 2 to 8).  (At
               phi = 0.55 and this rate the default contact stiffness lets mapped spheres
               overlap after about 3,000 steps.)
+  mono256_080 the same protocol at area fraction 0.80 (the other end of the monolayer
+              configuration's range).
   mono256     256^2 x 10 monolayers of a = 4.5 spheres at area fraction 0.70 under
               oscillatory shear (eq. 16), period 1,000 steps, 2 initial cycles at strain
               amplitude 0.05 then 3 observation cycles at 0.01, Theta = 0; an ensemble of
@@ -49,24 +51,26 @@ def workload(name):
         return w, dict(total=2500, start=500, block=250, cycles=None)
     if name == "mono256":
         return [mono256(seed) for seed in MONO_SEEDS]
+    if name == "mono256_080":
+        return [mono256(seed, 0.80) for seed in MONO_SEEDS]
     raise ValueError(name)
 
 
 MONO_SEEDS = (1, 2, 3)
 
 
-def mono256(seed):
-    w = synth.monolayer(256, 10, 0.70, seed=seed, g0_I=0.05, g0_F=0.01, theta=0.0, period=1000,
+def mono256(seed, phi=0.70):
+    w = synth.monolayer(256, 10, phi, seed=seed, g0_I=0.05, g0_F=0.01, theta=0.0, period=1000,
                         ncyc_I=2, ncyc_F=3)
     return w, dict(total=5000, start=2000, block=500, cycles=(2000, 1000, 3))
 
 
 def run(name):
-    if name == "mono256":
+    if name.startswith("mono256"):
         runs = [run_one("%s seed %d" % (name, sd), w, plan, sd)
                 for sd, (w, plan) in zip(MONO_SEEDS, workload(name))]
-        out = dict(name="monolayer_256_phi0.70", seeds=list(MONO_SEEDS), runs=runs,
-                   components=runs[0]["components"])
+        out = dict(name="monolayer_256_phi%s" % ("0.80" if name.endswith("080") else "0.70"),
+                   seeds=list(MONO_SEEDS), runs=runs, components=runs[0]["components"])
     else:
         w, plan = workload(name)
         out = run_one(name, w, plan, 1)

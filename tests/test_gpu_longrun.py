@@ -5,13 +5,15 @@ FP64: the library in FP64 sums the same terms as the oracle and differs only in 
 some roundings, so where the trajectories stay together the time averages are held to the
 2 % bar with no statistical allowance: the time-averaged shear stress <sigma_xy> (eq. 15, each
 of its five parts, every 500-step block) of the 3D bulk suspension at phi 0.45 over 8,000 steps
-(strain 2 to 8), and G', G'' (eqs. 17-18) of three monolayer packings over the first
+(strain 2 to 8), and G', G'' (eqs. 17-18) of three monolayer packings at area fraction 0.70
+and three at 0.80 (the two ends of the monolayer configuration's range) over the first
 observation cycle of their oscillatory protocol.  At phi 0.55 (inside the 0.50-0.56 range of
 the 3D configuration; 2,500 steps) and in later monolayer cycles the trajectories separate even
 in FP64 (a dense sheared suspension is chaotic), and the phi 0.55 averages are compared with 2 %
 plus two paired standard errors of the block differences.
 
-FP32: the trajectories separate within the runs, so they are compared through statistics.
+FP32 (and FP16 storage for the bulk stress): the trajectories separate within the runs, so
+they are compared through statistics.
 Bar: |gpu - oracle| <= 2 % of |oracle| + 2 standard errors, the standard errors from block
 averages (500-step blocks for the stress, one value per observation cycle for G', G'':
 three cycles in each of three packings).  At strain amplitude 0.01 one cycle's G' scatters by
@@ -91,11 +93,12 @@ def _per_cycle(avg):
     return np.concatenate([tot[:1], np.diff(tot, axis=0)])
 
 
-def test_bulk_shear_stress(susp):
+@pytest.mark.parametrize("precision", ["FP32", "FP16STORE"])
+def test_bulk_shear_stress(susp, precision):
     gold = _golden("bulk96")
     w, plan = _workload("bulk96")
-    print("\n[longrun] bulk %s, %d spheres, %d steps" % (w.box, len(w.radius), plan["total"]), flush=True)
-    blocks, _ = _run(susp, w, plan)
+    print("\n[longrun] bulk %s %s, %d spheres, %d steps" % (precision, w.box, len(w.radius), plan["total"]), flush=True)
+    blocks, _ = _run(susp, w, plan, getattr(susp, precision))
     mo, so = _mean_se(_sxy(gold["block_stress"]))
     mg, sg = _mean_se(_sxy(blocks))
     se = math.hypot(so, sg)
@@ -103,9 +106,10 @@ def test_bulk_shear_stress(susp):
     assert abs(mg - mo) <= 0.02 * abs(mo) + 2 * se
 
 
-def test_monolayer_moduli(susp):
-    gold = _golden("mono256")
-    ws = _workload("mono256")
+@pytest.mark.parametrize("name", ["mono256", "mono256_080"])
+def test_monolayer_moduli(susp, name):
+    gold = _golden(name)
+    ws = _workload(name)
     co, cg, so_, sg_ = [], [], [], []
     for (w, plan), run in zip(ws, gold["runs"]):
         print("\n[longrun] monolayer %s, %d spheres, %d steps, seed %d"
@@ -166,9 +170,10 @@ def test_bulk_fp64_against_the_oracle(susp, name, tracks):
         assert abs(d.mean()) <= 0.02 * abs(so.mean()) + 2 * se
 
 
-def test_monolayer_fp64_first_cycle(susp):
-    gold = _golden("mono256")
-    for (w, plan), run in zip(_workload("mono256"), gold["runs"]):
+@pytest.mark.parametrize("name", ["mono256", "mono256_080"])
+def test_monolayer_fp64_first_cycle(susp, name):
+    gold = _golden(name)
+    for (w, plan), run in zip(_workload(name), gold["runs"]):
         cyc = plan["cycles"]
         first = dict(plan, total=cyc[0] + cyc[1])  # the initial cycles and one observation cycle
         print("\n[longrun] monolayer FP64 %s seed %d, %d steps" % (w.box, run["seed"], first["total"]), flush=True)
