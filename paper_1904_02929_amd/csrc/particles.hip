@@ -250,6 +250,10 @@ hipError_t launch_cells(Sim *s, int32_t *cell_start, int32_t *cell_ids, int32_t 
   A.start = cell_start;
   A.ids = cell_ids;
   A.cnt = scratch;
+  // recorded for lockstep runs: the variant with its counters in global memory (4 KB of LDS),
+  // which finds room beside other jobs' lattice work-groups; every variant builds the same
+  // list (ids ascending within each cell)
+  if (s->col) return dispatch(s, k_cells, k_cells_m, 1, 1024, A);
   if (s->ncell <= LDS_CELLS && s->n <= LDS_IDS) return dispatch(s, k_cells_lds_ids, k_cells_lds_ids_m, 1, 1024, A);
   if (s->ncell <= LDS_CELLS) return dispatch(s, k_cells_lds, k_cells_lds_m, 1, 1024, A);
   return dispatch(s, k_cells, k_cells_m, 1, 1024, A);
