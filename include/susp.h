@@ -327,18 +327,22 @@ int susp_batch_step(susp_batch *b, int64_t nsteps);
 int susp_batch_launch(susp_batch *b, int32_t slot, int64_t nsteps);
 int susp_batch_poll(susp_batch *b, int32_t slot, int32_t *done);
 
-/* Queue nsteps steps of every job in the batch in lockstep and return at once (the batched
- * step of the scope table, row a13: one launch per kernel over all jobs).  Jobs whose steps
- * have the same kernel sequence share each kernel's launch: its work-groups are dealt to the
- * jobs by a table of offsets, and each job's arguments come from a device table that the
- * batch builds from the job's own launches (rebuilt when jobs join or leave).  A job gets
- * exactly the kernels and arguments it would get alone, so its results are the same bit for
- * bit.  Jobs with moving walls, contact statistics, implicit lubrication, profiling, no
- * spheres or a brick other than 64 x 4 x 4 step on their own streams instead.  Waits for the
- * previous lockstep run before it queues anything; an odd step count ends with one step per
- * job on its own stream.  susp_batch_poll reports each job as before.  A job's state must
- * not be read (susp_batch_sim getters) before its poll reports it done; susp_batch_stress
- * and susp_batch_remove wait for the run themselves.
+/* Queue nsteps steps of every job in the batch in lockstep and return at once (a batched
+ * step with one launch per kernel over all jobs; the paper steps one suspension at a time).
+ * Jobs whose steps have the same kernel sequence share each kernel's launch: its work-groups
+ * are dealt to the jobs by a table of offsets, and each job's arguments come from a device
+ * table that the batch builds from the job's own launches.  The jobs are split over four
+ * streams by size; one pair of steps of all of them is recorded as a HIP graph and replayed
+ * (tables and graph rebuilt when jobs join or leave).  A job gets exactly the kernels and
+ * arguments it would get alone, so its results are the same bit for bit.  Jobs with moving
+ * walls, contact statistics, implicit lubrication, profiling, no spheres or a brick other
+ * than 64 x 4 x 4 step on their own streams instead.  Waits for the previous lockstep run
+ * before it queues anything; an odd step count ends with one step per job on its own stream.
+ * susp_batch_poll reports each job as before.  A job's state must not be read
+ * (susp_batch_sim getters) before its poll reports it done; susp_batch_stress and
+ * susp_batch_remove wait for the run themselves.  Adding a job while a run is in flight is
+ * allowed but its creation may wait behind the run (its stream can share a hardware queue
+ * with the lockstep streams).
  * Errors: SUSP_EINVAL (NULL batch, negative count), SUSP_ENOMEM (launch tables),
  * SUSP_EDEVICE.                                                                            */
 int susp_batch_launch_all(susp_batch *b, int64_t nsteps);
