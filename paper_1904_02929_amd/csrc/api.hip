@@ -622,11 +622,12 @@ Sim &sim_of(susp_sim *h) { return h->s; }
 
 // Whether the simulation's step can run in multi-job launches: every kernel of its step has
 // a multi-job form (Lees-Edwards, spheres in the fused lattice kernel, explicit lubrication,
-// no contact statistics, no profiling events).
+// no contact statistics, no profiling events), and two steps' launches (10 + n_sub each) fit
+// the recorder.
 bool multi_ok(const susp_sim *h) {
   const Sim &s = h->s;
   return s.boundary == 0 && s.n > 0 && s.BY == 4 && s.BZ == 4 && s.cbins == 0 && s.lub_implicit == 0 &&
-         !s.prof_on;
+         !s.prof_on && 2 * (10 + s.n_sub) <= 256;
 }
 
 // Record the launches of the next two steps into c without issuing them; the simulation's
