@@ -54,8 +54,8 @@ typedef enum {
                            exceeded the neighbour capacity, a node touches more than six
                            spheres, a sphere moved more than one node in one step, a
                            non-finite fluid density or velocity, or the fluid mass plus the
-                           ledger of covered nodes drifted by more than 1e-3 of the box's
-                           mass                                                           */
+                           ledger of covered nodes drifted by more than 1e-2 of the box's
+                           mass (spheres touching node to node leak ~2e-4 per 1000 steps) */
   SUSP_ESTATE = -5      /* a state buffer does not match the simulation                */
 } susp_status;
 
@@ -221,7 +221,7 @@ int susp_set_populations(susp_sim *s, const double *host);
  * the sums of sigma_xy cos(phase) and sigma_xy sin(phase) over the observation steps so far
  * (eqs. 17-18; the phase of eq. 16), acc[33] = their count, acc[34] = the mass ledger: fluid
  * mass taken in by nodes that spheres covered minus the mass given back to released nodes
- * (the fluid mass plus the ledger is conserved).  Set checks that every entry is finite and
+ * (the fluid mass plus the ledger is conserved while no two spheres touch node to node).  Set checks that every entry is finite and
  * the counts are not negative (SUSP_EINVAL).  Both synchronise.                           */
 enum { SUSP_NACC = 35 };
 int susp_get_accumulators(susp_sim *s, double acc[SUSP_NACC]);

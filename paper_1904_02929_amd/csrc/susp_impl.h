@@ -36,9 +36,13 @@ constexpr int RED_BLOCKS = 128;
 constexpr int RED_W = 40;
 constexpr int ACC_PART = 128;
 constexpr int ACC_DOUBLES = ACC_PART + RED_BLOCKS * RED_W;
-// largest drift of the conserved fluid mass + ledger, relative to the box's mass, before
-// FL_MASS (rounding and the sliding boundary drift far less; this catches a broken run)
-constexpr double MASS_TOL = 1e-3;
+// largest drift of the fluid mass + ledger, relative to the box's mass, before FL_MASS.  The
+// sum is exact for separated spheres (each lattice line's entry and exit links pair up), but
+// where two mapped spheres touch node to node the lines running from one into the other lose
+// their pairs, and the moving boundaries leak mass slowly: ~1.5-3e-4 of the box per 1000
+// steps in dense monolayers and bulk suspensions, in the oracle alike.  The check is for
+// runs going wrong, whose drift grows much faster.
+constexpr double MASS_TOL = 1e-2;
 // instability flags (SUSP_EUNSTABLE)
 constexpr int FL_OVERLAP = 1, FL_NONFINITE = 2, FL_NEIGHBOURS = 4, FL_LINKS = 8, FL_JUMP = 16,
               FL_FLUID = 32, FL_MASS = 64;
