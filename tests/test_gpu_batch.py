@@ -227,12 +227,15 @@ def _wait(batch, slots):
 
 def test_lockstep_equals_alone(susp):
     # lockstep runs (one launch per kernel over all jobs): jobs of different boxes and
-    # protocols, an FP16-storage job (a second kernel sequence), a job with another brick
-    # (steps on its own stream), a job joining and one leaving between runs, and an odd run
+    # protocols, FP16-storage, FP64 and multi-eigenvalue-collision jobs (other kernel
+    # sequences), a job with another brick (steps on its own stream), a job joining and one
+    # leaving between runs, and an odd run
     S = susp
     jobs = _jobs(S)
+    multi = dict(collision=1, tau_bulk=0.65, tau_ghost=1.25, tau=0.8)
     specs = [(jobs[0], S.FP32, None), (jobs[1], S.FP32, None), (jobs[3], S.FP32, None),
-             (jobs[2], S.FP16STORE, None), (jobs[1], S.FP32, (8, 8))]
+             (jobs[2], S.FP16STORE, None), (jobs[1], S.FP32, (8, 8)), (jobs[0], S.FP64, None),
+             (jobs[3], S.FP64, None), ((jobs[1][:5] + ({**jobs[1][5], **multi},)), S.FP32, None)]
     late = (jobs[2], S.FP32, None)
 
     def params(spec):
@@ -242,7 +245,7 @@ def test_lockstep_equals_alone(susp):
         return p
 
     print("\n[batch] lockstep: %d jobs + 1 late" % len(specs), flush=True)
-    batch = S.Batch(8, 1 << 34, autotune=False)
+    batch = S.Batch(12, 1 << 34, autotune=False)
     slots = [batch.add(params(sp)) for sp in specs]
     assert None not in slots
     steps = {s: 0 for s in slots}
