@@ -226,6 +226,15 @@ int susp_set_populations(susp_sim *s, const double *host);
 enum { SUSP_NACC = 35 };
 int susp_get_accumulators(susp_sim *s, double acc[SUSP_NACC]);
 int susp_set_accumulators(susp_sim *s, const double acc[SUSP_NACC]);
+/* The whole state of a simulation in one host buffer, a checkpoint: its step, the populations
+ * exactly as stored (deviations from the rest state in the storage type, so a restart is bit
+ * for bit in every precision), positions, velocities, spins, orientations, the spring history
+ * and the running sums above.  Get: host NULL sets *bytes to the size needed (it varies with
+ * the number of pairs in contact); otherwise *bytes must be at least that, and receives it.
+ * Set: the buffer must come from a simulation of the same precision, box and sphere count
+ * (SUSP_ESTATE otherwise, nothing changed); the caller owns the buffer.  Both synchronise.  */
+int susp_get_state(susp_sim *s, void *host, size_t *bytes);
+int susp_set_state(susp_sim *s, const void *host, size_t bytes);
 /* Particle state: positions, velocities, angular velocities [n][3], orientations [n][4]
  * (any pointer may be NULL on get).  Set re-maps the spheres (no cover/uncover).         */
 int susp_get_particles(susp_sim *s, double *pos, double *vel, double *omega, double *quat);

@@ -848,6 +848,106 @@ extern "C" int susp_set_populations(susp_sim *h, const double *host) {
   return SUSP_OK;
 }
 
+// ---- whole-state checkpoint: header, populations as stored, particles, history, running sums
+namespace {
+struct StateHeader {
+  char magic[8];  // "SUSPSTA1"
+  int32_t precision, lx, ly, lz, n, npairs;
+  int64_t step;
+  int64_t nodes, es;  // nodes and bytes per stored population element
+};
+// bytes of the stored populations, padded so that the FP64 parts after them stay aligned
+size_t state_pop_bytes(const Sim &s) {
+  const size_t es = s.precision == 0 ? 8 : s.precision == 1 ? 4 : 2;
+  return ((size_t)NQ * s.nodes * es + 7) / 8 * 8;
+}
+size_t state_bytes(const Sim &s, int npairs) {
+  return sizeof(StateHeader) + state_pop_bytes(s) + (size_t)s.n * 13 * 8 + (size_t)npairs * (8 + 24) +
+         (size_t)SUSP_NACC * 8;
+}
+}  // namespace
+
+extern "C" int susp_get_state(susp_sim *h, void *host, size_t *bytes) {
+  if (!h || !bytes) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  int32_t np = 0;
+  int rc = susp_get_history(h, 0, &np, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  const size_t need = state_bytes(s, np);
+  if (!host) {
+    *bytes = need;
+    return SUSP_OK;
+  }
+  if (*bytes < need) return fail(SUSP_EINVAL, "state buffer of %zu bytes, %zu needed", *bytes, need);
+  char *p = (char *)host;
+  StateHeader hd;
+  memset(&hd, 0, sizeof hd);
+  memcpy(hd.magic, "SUSPSTA1", 8);
+  hd.precision = s.precision; hd.lx = s.lx; hd.ly = s.ly; hd.lz = s.lz; hd.n = s.n; hd.npairs = np;
+  hd.step = s.step;
+  hd.nodes = s.nodes;
+  hd.es = s.precision == 0 ? 8 : s.precision == 1 ? 4 : 2;
+  memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  // the populations exactly as stored (deviations from the rest state in the storage type)
+  HIPCHK(hipStreamSynchronize(s.stream));
+  memset(p, 0, state_pop_bytes(s));
+  for (int q = 0; q < NQ; ++q)
+    HIPCHK(hipMemcpy(p + (size_t)q * s.nodes * hd.es, (const char *)s.f[s.cur] + (size_t)q * s.plane * hd.es,
+                     (size_t)s.nodes * hd.es, hipMemcpyDeviceToHost));
+  p += state_pop_bytes(s);
+  double *d = (double *)p;
+  rc = susp_get_particles(h, d, d + 3 * (size_t)s.n, d + 6 * (size_t)s.n, d + 9 * (size_t)s.n);
+  if (rc) return rc;
+  p += (size_t)s.n * 13 * 8;
+  int32_t got = 0;
+  std::vector<int32_t> pi(np > 0 ? np : 1), pj(np > 0 ? np : 1);
+  rc = susp_get_history(h, np, &got, pi.data(), pj.data(), (double *)(p + (size_t)np * 8));
+  if (rc) return rc;
+  if (got != np) return fail(SUSP_ESTATE, "spring history changed while it was read");
+  memcpy(p, pi.data(), (size_t)np * 4);
+  memcpy(p + (size_t)np * 4, pj.data(), (size_t)np * 4);
+  p += (size_t)np * (8 + 24);
+  rc = susp_get_accumulators(h, (double *)p);
+  if (rc) return rc;
+  *bytes = need;
+  return SUSP_OK;
+}
+
+extern "C" int susp_set_state(susp_sim *h, const void *host, size_t bytes) {
+  if (!h || !host) return fail(SUSP_EINVAL, "NULL argument");
+  Sim &s = h->s;
+  StateHeader hd;
+  if (bytes < sizeof hd) return fail(SUSP_ESTATE, "state buffer too short");
+  memcpy(&hd, host, sizeof hd);
+  if (memcmp(hd.magic, "SUSPSTA1", 8) != 0) return fail(SUSP_ESTATE, "not a state buffer");
+  if (hd.precision != s.precision || hd.lx != s.lx || hd.ly != s.ly || hd.lz != s.lz || hd.n != s.n ||
+      hd.nodes != s.nodes || hd.npairs < 0)
+    return fail(SUSP_ESTATE, "state of another simulation (precision, box or sphere count differ)");
+  if (bytes != state_bytes(s, hd.npairs)) return fail(SUSP_ESTATE, "state buffer has the wrong size");
+  const char *p = (const char *)host + sizeof hd;
+  const char *pop = p;
+  p += state_pop_bytes(s);
+  const double *d = (const double *)p;
+  int rc = susp_set_clock(h, hd.step);
+  if (!rc) rc = susp_set_particles(h, d, d + 3 * (size_t)s.n, d + 6 * (size_t)s.n, d + 9 * (size_t)s.n);
+  if (rc) return rc;
+  p += (size_t)s.n * 13 * 8;
+  HIPCHK(hipStreamSynchronize(s.stream));
+  for (int q = 0; q < NQ; ++q)
+    HIPCHK(hipMemcpy((char *)s.f[s.cur] + (size_t)q * s.plane * hd.es, pop + (size_t)q * s.nodes * hd.es,
+                     (size_t)s.nodes * hd.es, hipMemcpyHostToDevice));
+  rc = reset_mass_reference(s);
+  if (rc) return rc;
+  std::vector<int32_t> pi(hd.npairs > 0 ? hd.npairs : 1), pj(hd.npairs > 0 ? hd.npairs : 1);
+  memcpy(pi.data(), p, (size_t)hd.npairs * 4);
+  memcpy(pj.data(), p + (size_t)hd.npairs * 4, (size_t)hd.npairs * 4);
+  rc = susp_set_history(h, hd.npairs, pi.data(), pj.data(), (const double *)(p + (size_t)hd.npairs * 8));
+  if (rc) return rc;
+  p += (size_t)hd.npairs * (8 + 24);
+  return susp_set_accumulators(h, (const double *)p);
+}
+
 // acc layout on the device: [0,30) stress of the last step, [30,60) stress sums, 60 their
 // count, 61 sum sigma_xy cos, 62 sum sigma_xy sin, 63 observation steps, 64 mass ledger
 extern "C" int susp_get_accumulators(susp_sim *h, double out[SUSP_NACC]) {

@@ -83,6 +83,8 @@ def lib():
         L.susp_profile_read_parts.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
         L.susp_health.argtypes = [vp, _PD]
         L.susp_set_accumulators.argtypes = [vp, _PD]
+        L.susp_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.susp_set_state.argtypes = [vp, vp, C.c_size_t]
         L.susp_use_graphs.argtypes = [vp, C.c_int32]
         L.susp_profile.argtypes = [vp, C.c_int32]
         L.susp_profile_read.argtypes = [vp, _PD, C.POINTER(C.c_int64)]
@@ -275,6 +277,18 @@ class Simulation:
     def set_accumulators(self, a):
         a = np.ascontiguousarray(a, np.float64).reshape(35)
         _chk(lib().susp_set_accumulators(self.h, _pd(a)))
+
+    def get_state(self):
+        """The whole state as bytes (susp_get_state): a checkpoint."""
+        nb = C.c_size_t(0)
+        _chk(lib().susp_get_state(self.h, None, C.byref(nb)))
+        buf = np.zeros(nb.value, np.uint8)
+        _chk(lib().susp_get_state(self.h, buf.ctypes.data_as(C.c_void_p), C.byref(nb)))
+        return buf[:nb.value].tobytes()
+
+    def set_state(self, state: bytes):
+        buf = np.frombuffer(state, np.uint8).copy()
+        _chk(lib().susp_set_state(self.h, buf.ctypes.data_as(C.c_void_p), len(buf)))
 
     def get_particles(self):
         n = self.n

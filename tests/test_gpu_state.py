@@ -99,3 +99,41 @@ def test_checkpoint_continues_the_run_bitwise(susp, prec):
     assert same(sa, sb) and same(ga, gb)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_whole_state_checkpoint_is_bitwise(susp, prec):
+    # susp_get_state / susp_set_state: the populations travel as stored, so the continued run
+    # is bit for bit the same in every precision, FP64 included
+    S = susp
+    box, pos, vel, om, rad, _ = PU.dense_workload((48, 41, 36), 0.35, 9, 0.0)
+    kw = dict(shear_kind=2, g0_I=0.004, g0_F=0.002, period=20, ncyc_I=1, ncyc_F=2, theta=0.5)
+    print("\n[state] whole-state checkpoint, precision %d, box %s, %d spheres" % (prec, box, len(rad)), flush=True)
+    a = PU.gpu_for(box, kw, pos, vel, om, rad, prec)
+    a.step(23)
+    st = a.get_state()
+    a.step(17)
+    b = PU.gpu_for(box, kw, pos, vel, om, rad, prec)
+    b.set_state(st)
+    b.step(17)
+    ra, rb = _snapshot(a), _snapshot(b)
+    assert ra["clock"] == rb["clock"] == 40
+    for x, y in zip(ra["particles"], rb["particles"]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(ra["populations"], rb["populations"])
+    for x, y in zip(ra["history"], rb["history"]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(ra["acc"], rb["acc"])
+    sa, ga = a.stress()
+    sb, gb = b.stress()
+    assert np.array_equal(sa, sb) and np.array_equal(ga, gb)
+    assert a.get_state() == b.get_state()
+    # a state of another box is refused and changes nothing
+    c = PU.gpu_for((48, 41, 40), kw, pos, vel, om, rad, prec)  # the same spheres, a taller box
+    before = c.get_state()
+    with pytest.raises(S.SuspError) as ei:
+        c.set_state(st)
+    assert ei.value.code == S.ESTATE
+    assert c.get_state() == before
+    for g in (a, b, c):
+        g.close()
