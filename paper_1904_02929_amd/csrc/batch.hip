@@ -378,10 +378,12 @@ static int record_pair(susp_batch *b) {
 // (Re)build the multi-job launch sequences of two steps for the jobs now in the batch, if the
 // jobs or their buffer parities differ from the last build.  The lockstep streams are idle.
 // The jobs are dealt to the parts largest first, each to the part with the fewest nodes.
-static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
+static int build_sequence(susp_batch *b, const std::vector<int> &slots, bool *built) {
   std::vector<std::array<int64_t, 3>> key;
   for (int k : slots) key.push_back({k, step_parity(b->job[k]), (int64_t)(intptr_t)b->job[k]});
+  *built = false;
   if (key == b->key) return SUSP_OK;
+  *built = true;
   b->key.clear();
   for (auto &q : b->seq) q.clear();
   std::vector<int> order(slots);
@@ -459,10 +461,9 @@ static int build_sequence(susp_batch *b, const std::vector<int> &slots) {
     for (auto &q : b->seq) q.clear();
     return set_error(SUSP_EDEVICE, "upload of the lockstep launch tables failed");
   }
-  int rc = record_pair(b);
-  if (rc) {
-    for (auto &q : b->seq) q.clear();
-    return rc;
+  if (b->gexec) {  // recorded for the jobs before; recorded again once these jobs stay
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
   }
   b->key = key;
   return SUSP_OK;
@@ -489,14 +490,33 @@ extern "C" int susp_batch_launch_all(susp_batch *b, int64_t nsteps) {
   int64_t left = nsteps;
   while (left >= 2) {
     const int m = (int)(left < CLK_CAP ? left : CLK_CAP) & ~1;
+    if (left < nsteps) {  // the clock tables are rewritten: the run before must have read them
+      if (hipEventRecord(b->gev, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "event record");
+      for (int k : slots)
+        if (hipStreamWaitEvent(b->stream[k], b->gev, 0) != hipSuccess) return set_error(SUSP_EDEVICE, "stream wait");
+    }
     for (int k : slots) {
       int rc = prepare_run(b->job[k], m);  // waits for the job's own stream
       if (rc) return rc;
     }
-    int rc = build_sequence(b, slots);
+    bool built = false;
+    int rc = build_sequence(b, slots, &built);
     if (rc) return rc;
-    for (int p = 0; p < m / 2; ++p)
-      if (hipGraphLaunch(b->gexec, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "lockstep launch failed");
+    // the first run after the jobs changed issues its kernels directly (recording and
+    // instantiating the graph would keep the GPU waiting); a run of the same jobs again
+    // records the pair once and replays it
+    if (!built && !b->gexec) {
+      rc = record_pair(b);
+      if (rc) return rc;
+    }
+    for (int p = 0; p < m / 2; ++p) {
+      if (b->gexec) {
+        if (hipGraphLaunch(b->gexec, b->gstream[0]) != hipSuccess) return set_error(SUSP_EDEVICE, "lockstep launch failed");
+      } else {
+        rc = issue_pair(b);
+        if (rc) return rc;
+      }
+    }
     for (int k : slots) advance_steps(b->job[k], m);
     left -= m;
   }

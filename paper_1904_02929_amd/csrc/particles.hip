@@ -2,8 +2,10 @@
 //
 //  k_cells_lds_ids cell list: cell of each sphere, counting sort, ascending ids per cell
 //  k_pairs         Lees-Edwards cell search -> neighbour list (ascending ids, both
-//                  directions), contact-at-start flags, spring history carried over; also
-//                  the step's per-sphere link sums into F, T, S (a wave per sphere)
+//                  directions), contact-at-start flags, spring history carried over (a wave
+//                  per sphere; needs only the positions, so it can run beside the lattice)
+//  k_pair_rev      each list entry's mirror entry; also the step's per-sphere link sums
+//                  into F, T, S
 //  k_substep       one DEM substep per sphere: contact (spring-dashpot + Cundall-Strack with
 //                  Coulomb cap, Sec. 2), DLVO (eq. 13), lubrication (App. A), eq. (1)
 //  k_map_update<1> new mapped-sphere footprints; fluid nodes covered by a sphere give it
@@ -313,8 +315,6 @@ struct PairArgs {
   double *xi;                        // carried history for this step
   int32_t *on, *hstart;
   int32_t *flags;
-  unsigned long long *hacc;          // the step's fixed-point link sums [n][HYD][2] (cleared here)
-  double *hyd;                       // their values [n][HYD]
 };
 
 // Neighbour list of one sphere per wave, four spheres per work-group.  The lanes take the
@@ -328,13 +328,6 @@ __device__ __forceinline__ void pairs_wg(const PairArgs &A, const int bid) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = bid * 4 + wv;
   const bool ok = i < A.n;  // waves past the last sphere still reach the barriers
-  if (ok && lane < HYD) {  // the sphere's force, torque, stresslet and link count of the step
-    const size_t k = (size_t)i * HYD + lane;
-    const long long h = (long long)A.hacc[2 * k], l = (long long)A.hacc[2 * k + 1];
-    A.hyd[k] = ldexp((double)h, -FXH) + ldexp((double)l, -FXL);
-    A.hacc[2 * k] = 0ull;
-    A.hacc[2 * k + 1] = 0ull;
-  }
   const Box bx = clock_box(A.b, A.clk, 0);
   const double *R = A.R;
   // the near cells: lane k takes the k-th cell visited (at most 27)
@@ -446,8 +439,6 @@ hipError_t launch_pairs(Sim *s, const Box &b) {
   A.xi = s->hxi[1 - s->hfin]; A.on = s->hon[1 - s->hfin];
   A.hstart = s->hstart;
   A.flags = s->flags;
-  A.hacc = s->hacc;
-  A.hyd = s->hyd[s->hcur];
   if (s->n > 0) return dispatch(s, k_pairs, k_pairs_m, (s->n + 3) / 4, 256, A);
   return hipSuccess;
 }
@@ -632,6 +623,8 @@ __device__ void pair_forces(const Phys &P, double ai, double aj, const double d[
 struct RevArgs {
   const int32_t *cnt, *nj;
   int32_t *rev;
+  unsigned long long *hacc;  // the step's fixed-point link sums [n][HYD][2] (cleared here)
+  double *hyd;               // their values [n][HYD]
   int n;
 };
 __device__ __forceinline__ void pair_rev_wg(const RevArgs &A, const int bid) {
@@ -640,6 +633,13 @@ __device__ __forceinline__ void pair_rev_wg(const RevArgs &A, const int bid) {
   const int n = A.n;
   const int i = bid * 4 + (threadIdx.x >> 6);
   const int u = threadIdx.x & 63;
+  if (i < n && u < HYD) {  // the sphere's force, torque, stresslet and link count of the step
+    const size_t k = (size_t)i * HYD + u;
+    const long long h = (long long)A.hacc[2 * k], l = (long long)A.hacc[2 * k + 1];
+    A.hyd[k] = ldexp((double)h, -FXH) + ldexp((double)l, -FXL);
+    A.hacc[2 * k] = 0ull;
+    A.hacc[2 * k + 1] = 0ull;
+  }
   if (i >= n || u >= NCAP) return;
   if (u >= cnt[i]) return;
   const size_t e = (size_t)i * NCAP + u;
@@ -669,6 +669,8 @@ hipError_t launch_pair_rev(Sim *s) {
   A.cnt = s->ncnt[s->lcur];
   A.nj = s->nj[s->lcur];
   A.rev = s->rev;
+  A.hacc = s->hacc;
+  A.hyd = s->hyd[s->hcur];
   A.n = s->n;
   if (s->n > 0) return dispatch(s, k_pair_rev, k_pair_rev_m, (s->n + 3) / 4, 256, A);
   return hipSuccess;

@@ -284,6 +284,31 @@ def test_lockstep_equals_alone(susp):
     batch.close()
 
 
+def test_lockstep_long_run_equals_alone(susp):
+    # a lockstep run longer than one clock table (two uploads, the second after the first
+    # part has run), issued directly after the jobs changed and then replayed from the
+    # recorded pair; then a run of the same jobs again (replay only)
+    S = susp
+    jobs = [PU.dense_workload(box, phi, seed, gd)
+            for box, phi, seed, gd in (((44, 42, 40), 0.15, 31, 5e-4), ((36, 44, 41), 0.12, 32, 4e-4))]
+    print("\n[batch] lockstep long run: 2 jobs, 4100 + 4 steps", flush=True)
+    batch = S.Batch(4, 1 << 33, autotune=False)
+    slots = [batch.add(_params(S, j)) for j in jobs]
+    assert None not in slots
+    batch.launch_all(4100)
+    _wait(batch, slots)
+    batch.launch_all(4)
+    _wait(batch, slots)
+    for s, j in zip(slots, jobs):
+        alone = S.Simulation(_params(S, j))
+        alone.step(4104)
+        st, ref = _state(batch.job(s)), _state(alone)
+        for k, (x, y) in enumerate(zip(st, ref)):
+            assert np.array_equal(x, y), "slot %d field %d differs" % (s, k)
+        alone.close()
+    batch.close()
+
+
 def test_lockstep_job_matches_oracle(susp):
     # a job stepped in lockstep beside another job, against the oracle: two steps from the
     # oracle's state at the FP32 per-step tolerance
