@@ -365,14 +365,6 @@ static int read_flags(Sim &s, int32_t *out) {
   return SUSP_OK;
 }
 
-static void drop_side(Sim &s) {
-  if (s.efork) (void)hipEventDestroy(s.efork);
-  if (s.ejoin) (void)hipEventDestroy(s.ejoin);
-  if (s.side) (void)hipStreamDestroy(s.side);
-  s.efork = s.ejoin = nullptr;
-  s.side = nullptr;
-}
-
 extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, size_t ws_bytes,
                            susp_sim **out) {
   if (!out) return fail(SUSP_EINVAL, "out is NULL");
@@ -478,12 +470,6 @@ extern "C" int susp_create(const susp_params *p, void *stream, void *workspace, 
   rc = read_flags(s, &fl);
   if (rc) return bail(rc);
   if (fl & 1) return bail(fail(SUSP_EUNSTABLE, "mapped spheres overlap in the initial state"));
-  if (n && s.stream && (int64_t)s.nodes >= SIDE_NODES) {  // without it: one stream, same results
-    if (hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking) != hipSuccess) s.side = nullptr;
-    if (s.side && (hipEventCreateWithFlags(&s.efork, hipEventDisableTiming) != hipSuccess ||
-                   hipEventCreateWithFlags(&s.ejoin, hipEventDisableTiming) != hipSuccess))
-      drop_side(s);
-  }
   *out = h;
   return SUSP_OK;
 }
@@ -493,7 +479,6 @@ extern "C" int susp_destroy(susp_sim *h) {
   for (int i = 0; i < PROF_EV * h->s.prof_cap; ++i) (void)hipEventDestroy(h->s.prof_ev[i]);
   free(h->s.prof_ev);
   (void)hipStreamSynchronize(h->s.stream);
-  drop_side(h->s);
   if (h->s.gexec) (void)hipGraphExecDestroy(h->s.gexec);
   free(h->s.clk_host);
   if (h->s.owns_block && h->s.block) (void)hipFree(h->s.block);
@@ -538,25 +523,11 @@ static int one_step(Sim &s) {
   const Box b = make_box(s, 0.0, 0.0);  // dimensions only
   HIPCHK(launch_clock(&s, 0));
   s.hcur ^= 1;
-  if (s.n) HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
-  // the pair search reads only the positions at the start of the step and the cell list:
-  // on the second stream, if there is one, beside the ghost planes and the lattice
-  const bool fork = s.n && s.side && !s.col && !s.prof_on;
-  if (fork) {
-    HIPCHK(hipEventRecord(s.efork, s.stream));
-    HIPCHK(hipStreamWaitEvent(s.side, s.efork, 0));
-    std::swap(s.stream, s.side);
-  }
-  hipError_t e = hipSuccess;
-  if (s.n) {
-    e = launch_pairs(&s, b);
+  if (s.n) {  // the pair search needs only the positions at the start of the step
+    HIPCHK(launch_cells(&s, s.cell_start, s.cell_ids, s.cell_scr));
+    HIPCHK(launch_pairs(&s, b));
     s.lcur ^= 1;
   }
-  if (fork) {
-    std::swap(s.stream, s.side);
-    if (e == hipSuccess) e = hipEventRecord(s.ejoin, s.side);
-  }
-  HIPCHK(e);
   if (s.boundary == 1) HIPCHK(launch_walls(&s));
   else HIPCHK(launch_ghosts(&s, b, s.gown, s.gcnt, s.gval, 1, s.clk, 1));
   hipEvent_t *ev = nullptr;
@@ -577,7 +548,6 @@ static int one_step(Sim &s) {
   HIPCHK(launch_lbm(&s, b));
   if (ev) HIPCHK(hipEventRecord(ev[2], s.stream));
   s.cur ^= 1;
-  if (fork) HIPCHK(hipStreamWaitEvent(s.stream, s.ejoin, 0));
   if (s.n) {
     HIPCHK(launch_pair_rev(&s));
     for (int k = 0; k < s.n_sub; ++k) {

@@ -3,7 +3,7 @@
 //  k_cells_lds_ids cell list: cell of each sphere, counting sort, ascending ids per cell
 //  k_pairs         Lees-Edwards cell search -> neighbour list (ascending ids, both
 //                  directions), contact-at-start flags, spring history carried over (a wave
-//                  per sphere; needs only the positions, so it can run beside the lattice)
+//                  per sphere; needs only the positions and the cell list)
 //  k_pair_rev      each list entry's mirror entry; also the step's per-sphere link sums
 //                  into F, T, S
 //  k_substep       one DEM substep per sphere: contact (spring-dashpot + Cundall-Strack with

@@ -333,14 +333,7 @@ struct Sim {
   hipEvent_t *prof_ev;  // [PROF_EV * prof_cap]: before k_links, before k_stream, after it
   // non-null: launches of the step are recorded here (multi-job batches), not issued
   Collect *col;
-  // lattices of SIDE_NODES nodes or more on a stream of their own: the pair search (which
-  // needs only the positions and the cell list) runs on this second stream beside the ghost
-  // planes and the lattice kernel, forked after the cell list and joined before the substeps
-  // (null: one stream)
-  hipStream_t side;
-  hipEvent_t efork, ejoin;
 };
-constexpr int64_t SIDE_NODES = int64_t(1) << 22;
 
 // Issue a kernel of one simulation, or record it for a multi-job launch.
 template <class A>
