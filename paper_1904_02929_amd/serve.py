@@ -419,7 +419,8 @@ def lockstep_probe(n_jobs=24, steps=100, seed=1904, budget=32 << 30, workers=8, 
         for k in slots:
             while not ex.poll(k)[0]:
                 time.sleep(0.0002)
-    run(20)
+    run(20)  # issued directly (the jobs are new)
+    run(20)  # records the pair of steps as a graph
     t = time.perf_counter()
     run(steps)
     lock = (time.perf_counter() - t) / steps * 1e3
