@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=64,
                     help="requests in the serving comparison (0: skip it)")
     ap.add_argument("--serve-steps", type=int, default=1000, help="lattice steps per request")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0,
+                    help="HBM budget of the batched server (GiB)")
     ap.add_argument("--serve-mode", default="lockstep", choices=["lockstep", "streams"],
                     help="batched server: lockstep runs with one launch per kernel over all jobs, "
                          "or one stream per job")
@@ -291,7 +293,7 @@ def main():
         log("serving %d requests of %d steps: plain loop, then the batched server"
             % (args.serve_jobs, args.serve_steps))
         serving = serve.serve_benchmark(n_jobs=args.serve_jobs, steps=args.serve_steps, log=log,
-                                        mode=args.serve_mode)
+                                        mode=args.serve_mode, budget=int(args.serve_budget_gib * (1 << 30)))
         serving["workload"] = ("mixed requests: half quasi-2D monolayers L x L x 10 (L 128-384, "
                                "area fraction 0.70-0.80, oscillatory), half 3D bulk L^3 "
                                "(L 64-128, phi 0.50-0.56, simple shear); Poisson arrivals at "
