@@ -341,8 +341,10 @@ int susp_batch_poll(susp_batch *b, int32_t slot, int32_t *done);
  * Jobs whose steps have the same kernel sequence share each kernel's launch: its work-groups
  * are dealt to the jobs by a table of offsets, and each job's arguments come from a device
  * table that the batch builds from the job's own launches.  The jobs are split over four
- * streams by size; one pair of steps of all of them is recorded as a HIP graph and replayed
- * (tables and graph rebuilt when jobs join or leave).  A job gets exactly the kernels and
+ * streams by size.  Tables are rebuilt when jobs join or leave; the first run after that
+ * issues its kernels one by one, and a run of the same jobs again records one pair of steps
+ * of all of them as a HIP graph and replays it.  A run longer than 4096 steps uploads each
+ * job's next clock table only after the lockstep work before it.  A job gets exactly the kernels and
  * arguments it would get alone, so its results are the same bit for bit.  Jobs with moving
  * walls, contact statistics, implicit lubrication, profiling, no spheres or a brick other
  * than 64 x 4 x 4 step on their own streams instead.  Waits for the previous lockstep run
